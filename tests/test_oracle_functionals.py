@@ -1,0 +1,137 @@
+"""Pins of the oracle's pointwise functionals (Sec. III, Sec. IV PZ XC)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import fermi_dirac as fd
+from oracle import functionals as fn
+
+T = 0.15834   # 50 kK in hartree
+RNG = np.random.default_rng(7)
+
+
+def test_tf_potential_is_T_eta():
+    # the ftTF potential is the chemical potential of the uniform gas, v = T eta
+    n = np.array([1e-3, 0.05, 0.3, 2.0])
+    f, v, ts = fn.tf_point(n, T)
+    eta = fd.eta_of_t(fd.reduced_temperature(n, T))
+    assert np.allclose(v, T * eta, rtol=1e-12)
+
+
+def test_tf_zero_T_limit_and_entropy():
+    n = np.array([0.5])
+    Tlow = 1e-6
+    f, v, ts = fn.tf_point(n, Tlow)
+    assert f[0] == pytest.approx(0.3 * (3 * math.pi ** 2) ** (2 / 3) * 0.5 ** (5 / 3), rel=1e-9)
+    assert v[0] == pytest.approx(0.5 * (3 * math.pi ** 2 * 0.5) ** (2 / 3), rel=1e-9)
+
+
+def test_sga_equals_tf_plus_gradient_correction():
+    n = 10 ** RNG.uniform(-2.5, 0.5, 20)
+    sigma = (RNG.uniform(0, 3, 20) * n ** (4 / 3)) ** 2
+    f, dfdn, dfds, ts = fn.gga_point(n, sigma, T, "SGA")
+    ftf, vtf, _ = fn.tf_point(n, T)
+    tfac = fd.t_factors(fd.reduced_temperature(n, T))
+    assert np.allclose(f, ftf + tfac["h"] / 72 * sigma / n, rtol=1e-11)
+    assert np.allclose(dfds, tfac["h"] / (72 * n), rtol=1e-11)
+    # df/dn|sigma = v_TF + sigma/(72 n^2) (-(2/3) t h~' - h~)
+    t = fd.reduced_temperature(n, T)
+    ref = vtf + sigma / (72 * n * n) * (-(2 / 3) * t * tfac["dh"] - tfac["h"])
+    assert np.allclose(dfdn, ref, rtol=1e-10)
+
+
+def test_vwtf_zero_T_is_tf_plus_von_weizsaecker():
+    n = np.array([0.02, 0.3, 1.5])
+    sigma = np.array([0.001, 0.2, 4.0])
+    f, _, _, _ = fn.gga_point(n, sigma, 1e-7, "VWTF")
+    ref = 0.3 * (3 * math.pi ** 2) ** (2 / 3) * n ** (5 / 3) + sigma / (8 * n)
+    assert np.allclose(f, ref, rtol=1e-8)
+
+
+def test_vt84f_enhancement_limits():
+    xs0 = np.array([1e-8, 1e-7, 1e-6])
+    F, dF = fn.enh_vt84f(xs0)
+    slope = fn.VT84F_ALPHA - fn.VT84F_MU + 5 / 3
+    assert slope == pytest.approx(0.185167, abs=1e-6)
+    # (F-1)/s^2 -> alpha - mu + 5/3 ~ 5/27 (the gradient-expansion coefficient)
+    assert np.allclose((F - 1) / xs0, slope, rtol=1e-4)
+    assert np.allclose(dF[:1], slope, rtol=1e-5)
+    x = np.array([40.0, 200.0])
+    F, _ = fn.enh_vt84f(x)
+    assert np.allclose(F, 5 / 3 * x + 1 / x, rtol=1e-12)
+    # continuity across the small-x series switch
+    xs = np.array([1e-4 * (1 - 1e-9), 1e-4 * (1 + 1e-9)])
+    F, dF = fn.enh_vt84f(xs)
+    assert abs(F[1] - F[0]) < 1e-12 and abs(dF[1] - dF[0]) < 1e-9
+
+
+@pytest.mark.parametrize("name", ["VT84F", "KST2", "TW", "APBEF", "SGA", "VWTF"])
+def test_enhancement_derivative_fd(name):
+    enh = fn.enhancement(name)
+    x = np.array([1e-3, 0.05, 0.7, 3.0, 20.0])
+    h = 1e-6 * np.maximum(x, 1e-2)
+    num = (enh(x + h)[0] - enh(x - h)[0]) / (2 * h)
+    assert np.allclose(num, enh(x)[1], rtol=1e-7, atol=1e-9)
+
+
+@pytest.mark.parametrize("name", ["VT84F", "KST2", "SGA", "TW"])
+@pytest.mark.parametrize("temp", [0.0063336, 0.15834, 3.16681])
+def test_gga_partial_derivatives_fd(name, temp):
+    n = 10 ** RNG.uniform(-2.0, 0.5, 6)
+    sigma = (RNG.uniform(0.05, 2.5, 6) * n ** (4 / 3)) ** 2
+    f, dfdn, dfds, _ = fn.gga_point(n, sigma, temp, name)
+    hn = 1e-5 * n
+    num_n = (fn.gga_point(n + hn, sigma, temp, name)[0] - fn.gga_point(n - hn, sigma, temp, name)[0]) / (2 * hn)
+    hs = 1e-5 * sigma
+    num_s = (fn.gga_point(n, sigma + hs, temp, name)[0] - fn.gga_point(n, sigma - hs, temp, name)[0]) / (2 * hs)
+    assert np.allclose(num_n, dfdn, rtol=1e-6, atol=1e-10 * np.max(np.abs(dfdn)))
+    assert np.allclose(num_s, dfds, rtol=1e-6)
+
+
+def test_gga_entropy_density_is_T_times_minus_dF_dT():
+    # T s_s = -T dF_s/dT at fixed n and grad n; check the pointwise entropic term
+    n = np.array([0.05, 0.4])
+    sigma = (np.array([0.3, 1.1]) * n ** (4 / 3)) ** 2
+    for name in ("SGA", "VT84F"):
+        f, _, _, ts = fn.gga_point(n, sigma, T, name)
+        h = 1e-5 * T
+        dfdT = (fn.gga_point(n, sigma, T + h, name)[0] - fn.gga_point(n, sigma, T - h, name)[0]) / (2 * h)
+        if name == "SGA":
+            # exact for SGA: the free energy is f_TF + (h~/72) sigma/n
+            assert np.allclose(ts, -T * dfdT, rtol=1e-6)
+        else:
+            # VT84F is a different split; only the sign and scale are physical
+            assert np.all(ts > 0)
+
+
+def test_pz81_exchange_and_continuity():
+    n = np.array([0.01, 0.2, 3.0])
+    rs = (3 / (4 * math.pi * n)) ** (1 / 3)
+    eps, v = fn.pz81(n)
+    ex = -0.458165293283143 / rs
+    # correlation is the difference; check exchange via a tiny-rs scaling
+    assert np.allclose(fn.EX_COEF * n ** (1 / 3), ex, rtol=1e-12)
+    n1 = 3 / (4 * math.pi)
+    e_lo, _ = fn.pz81(np.array([n1 * (1 + 1e-12)]))
+    e_hi, _ = fn.pz81(np.array([n1 * (1 - 1e-12)]))
+    # the PZ81 fit is continuous at rs = 1 to about 1e-5 hartree by construction
+    assert abs(e_lo[0] - e_hi[0]) < 5e-5
+
+
+def test_pz81_potential_fd():
+    n = np.array([0.003, 0.1, 0.5, 5.0])
+    h = 1e-6 * n
+    E = lambda x: x * fn.pz81(x)[0]
+    num = (E(n + h) - E(n - h)) / (2 * h)
+    assert np.allclose(num, fn.pz81(n)[1], rtol=1e-8)
+
+
+def test_pz81_correlation_reference_values():
+    # PZ81 unpolarised correlation at rs = 2 (high branch) and rs = 0.5 (low branch)
+    for rs, ref in ((2.0, -0.1423 / (1 + 1.0529 * math.sqrt(2.0) + 0.3334 * 2.0)),
+                    (0.5, 0.0311 * math.log(0.5) - 0.048 + 0.0020 * 0.5 * math.log(0.5) - 0.0116 * 0.5)):
+        n = 3 / (4 * math.pi * rs ** 3)
+        eps, _ = fn.pz81(np.array([n]))
+        ex = -0.458165293283143 / rs
+        assert eps[0] - ex == pytest.approx(ref, abs=1e-14)
