@@ -1,0 +1,848 @@
+// C ABI of the MI355X finite-temperature OF-DFT library: argument checks,
+// context state machine, the host side of the minimisers (scalar decisions;
+// every vector operation and evaluation runs on the device) and the Ewald
+// ion-ion term.
+//
+// Minimisers (the direct minimisation at constant int n of Sec. II; the CG and
+// truncated-Newton optimisers named in Sec. I): phi lives on the sphere
+// dv sum phi^2 = N_e; the projected gradient is g = 2 dv phi (v - mu) with
+// mu = int n v / N_e (Eq. E10); steps are rotations
+// phi(theta) = cos(theta) phi + sin(theta) |phi| d/|d| along a tangent d.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <thread>
+#include <vector>
+
+#include "ofdft_internal.h"
+
+using namespace ofdft;
+
+namespace {
+
+constexpr double kPiD = 3.141592653589793238462643383279502884;
+constexpr double kKelvinToHartree = 3.1668115634556e-6;   // k_B / E_h (CODATA 2018)
+
+thread_local std::string g_last_error;
+
+int fail(ofdft_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  g_last_error = msg;
+  return code;
+}
+
+bool grid_ok(int n) {
+  static const int allowed[] = {8, 12, 16, 24, 32, 48, 64, 96, 128, 256};
+  for (int a : allowed)
+    if (a == n) return true;
+  return false;
+}
+
+int largest_pow2_divisor_upto(int n, int cap) {
+  int t = cap;
+  while (t > 1 && n % t) t >>= 1;
+  return t;
+}
+
+// ---------------------------------------------------------------- Ewald (host FP64)
+void ewald_sum(const double lat[9], int nat, const double* pos, const double* Z, double& E,
+               std::vector<double>& F) {
+  const double* a1 = lat;
+  const double* a2 = lat + 3;
+  const double* a3 = lat + 6;
+  const double V = std::fabs(a1[0] * (a2[1] * a3[2] - a2[2] * a3[1]) - a1[1] * (a2[0] * a3[2] - a2[2] * a3[0]) +
+                             a1[2] * (a2[0] * a3[1] - a2[1] * a3[0]));
+  // reciprocal rows b_i = 2 pi (a_j x a_k) / V
+  double b[9];
+  auto cross = [](const double* u, const double* v, double* w) {
+    w[0] = u[1] * v[2] - u[2] * v[1];
+    w[1] = u[2] * v[0] - u[0] * v[2];
+    w[2] = u[0] * v[1] - u[1] * v[0];
+  };
+  cross(a2, a3, b);
+  cross(a3, a1, b + 3);
+  cross(a1, a2, b + 6);
+  const double det = a1[0] * b[0] + a1[1] * b[1] + a1[2] * b[2];
+  for (int k = 0; k < 9; ++k) b[k] *= 2.0 * kPiD / det;
+  const double split = std::sqrt(kPiD) * std::pow(nat / (V * V), 1.0 / 6.0);
+  const double cfac = std::sqrt(-std::log(1e-16));
+  const double rcut = cfac / split, gcut = 2.0 * split * cfac;
+  F.assign(3 * (size_t)nat, 0.0);
+  double Q = 0.0, Q2 = 0.0;
+  for (int i = 0; i < nat; ++i) {
+    Q += Z[i];
+    Q2 += Z[i] * Z[i];
+  }
+  // real space: images n with |n . lat| possibly < rcut + cell diagonal
+  const double diag = std::sqrt(a1[0] * a1[0] + a1[1] * a1[1] + a1[2] * a1[2]) +
+                      std::sqrt(a2[0] * a2[0] + a2[1] * a2[1] + a2[2] * a2[2]) +
+                      std::sqrt(a3[0] * a3[0] + a3[1] * a3[1] + a3[2] * a3[2]);
+  int nmax[3];
+  for (int k = 0; k < 3; ++k) {
+    const double bn = std::sqrt(b[3 * k] * b[3 * k] + b[3 * k + 1] * b[3 * k + 1] + b[3 * k + 2] * b[3 * k + 2]);
+    nmax[k] = (int)std::ceil((rcut + diag) * bn / (2.0 * kPiD)) + 1;
+  }
+  std::vector<double> imgs;
+  for (int i = -nmax[0]; i <= nmax[0]; ++i)
+    for (int j = -nmax[1]; j <= nmax[1]; ++j)
+      for (int k = -nmax[2]; k <= nmax[2]; ++k) {
+        const double L[3] = {i * a1[0] + j * a2[0] + k * a3[0], i * a1[1] + j * a2[1] + k * a3[1],
+                             i * a1[2] + j * a2[2] + k * a3[2]};
+        if (std::sqrt(L[0] * L[0] + L[1] * L[1] + L[2] * L[2]) < rcut + diag) {
+          imgs.push_back(L[0]);
+          imgs.push_back(L[1]);
+          imgs.push_back(L[2]);
+        }
+      }
+  const size_t nimg = imgs.size() / 3;
+  double Er = 0.0;
+  const double c2 = 2.0 * split / std::sqrt(kPiD);
+  for (int i = 0; i < nat; ++i) {
+    for (int j = i; j < nat; ++j) {
+      const double w = (i == j) ? 0.5 : 1.0;
+      double fx = 0, fy = 0, fz = 0, e = 0;
+      for (size_t m = 0; m < nimg; ++m) {
+        const double dx = pos[3 * i] - pos[3 * j] + imgs[3 * m];
+        const double dy = pos[3 * i + 1] - pos[3 * j + 1] + imgs[3 * m + 1];
+        const double dz = pos[3 * i + 2] - pos[3 * j + 2] + imgs[3 * m + 2];
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 < 1e-20 || r2 >= rcut * rcut) continue;
+        const double r = std::sqrt(r2);
+        const double ec = std::erfc(split * r) / r;
+        e += ec;
+        const double fm = (ec + c2 * std::exp(-split * split * r2)) / r2;
+        fx += fm * dx;
+        fy += fm * dy;
+        fz += fm * dz;
+      }
+      Er += w * Z[i] * Z[j] * e;
+      if (i != j) {
+        const double zz = Z[i] * Z[j];
+        F[3 * i] += zz * fx; F[3 * i + 1] += zz * fy; F[3 * i + 2] += zz * fz;
+        F[3 * j] -= zz * fx; F[3 * j + 1] -= zz * fy; F[3 * j + 2] -= zz * fz;
+      }
+    }
+  }
+  // reciprocal space
+  int gmax[3];
+  for (int k = 0; k < 3; ++k) {
+    const double an = std::sqrt(lat[3 * k] * lat[3 * k] + lat[3 * k + 1] * lat[3 * k + 1] + lat[3 * k + 2] * lat[3 * k + 2]);
+    gmax[k] = (int)std::ceil(gcut * an / (2.0 * kPiD)) + 1;
+  }
+  double Eg = 0.0;
+  std::vector<double> cs(nat), sn(nat);
+  for (int h = -gmax[0]; h <= gmax[0]; ++h)
+    for (int k = -gmax[1]; k <= gmax[1]; ++k)
+      for (int l = -gmax[2]; l <= gmax[2]; ++l) {
+        if (!h && !k && !l) continue;
+        const double G[3] = {h * b[0] + k * b[3] + l * b[6], h * b[1] + k * b[4] + l * b[7],
+                             h * b[2] + k * b[5] + l * b[8]};
+        const double G2 = G[0] * G[0] + G[1] * G[1] + G[2] * G[2];
+        if (G2 > gcut * gcut) continue;
+        const double wgt = std::exp(-G2 / (4.0 * split * split)) / G2;
+        double Sr = 0.0, Si = 0.0;
+        for (int i = 0; i < nat; ++i) {
+          const double ph = G[0] * pos[3 * i] + G[1] * pos[3 * i + 1] + G[2] * pos[3 * i + 2];
+          cs[i] = std::cos(ph);
+          sn[i] = std::sin(ph);
+          Sr += Z[i] * cs[i];
+          Si += Z[i] * sn[i];
+        }
+        Eg += wgt * (Sr * Sr + Si * Si);
+        for (int i = 0; i < nat; ++i) {
+          // Im[e^{iG.R_i} conj(S)]
+          const double im = sn[i] * Sr - cs[i] * Si;
+          const double f = 4.0 * kPiD / V * Z[i] * wgt * im;
+          F[3 * i] += f * G[0];
+          F[3 * i + 1] += f * G[1];
+          F[3 * i + 2] += f * G[2];
+        }
+      }
+  Eg *= 2.0 * kPiD / V;
+  const double Es = -split / std::sqrt(kPiD) * Q2;
+  const double Eb = -kPiD * Q * Q / (2.0 * V * split * split);
+  E = Er + Eg + Es + Eb;
+}
+
+double alpha_of(const ofdft_options& o, double Z, double V) {
+  if (o.lpp == OFDFT_LPP_HA) return 2.0 * kPiD / V * (Z * o.lpp_rc * o.lpp_rc - 2.0 / 3.0 * o.lpp_A * std::pow(o.lpp_rc, 3));
+  return kPiD * Z * o.lpp_rc * o.lpp_rc / V;
+}
+
+bool is_fin(double x) { return std::isfinite(x); }
+
+// ---------------------------------------------------------------- evaluation helpers
+struct Point {
+  double F;     // F_tot
+  double Ne;    // measured int n
+};
+
+int eval_at(ofdft_ctx* c, const double* phi, void* v, double* sc, Point& p) {
+  int rc = dev_eval(c, phi, v, sc);
+  if (rc) return rc;
+  double h[SC_COUNT];
+  rc = dev_read(c, sc, SC_COUNT, h);
+  if (rc) return rc;
+  p.F = h[SC_FTOT];
+  p.Ne = h[SC_NE];
+  if (!is_fin(p.F)) return fail(c, OFDFT_E_NONFINITE, "non-finite free energy");
+  return OFDFT_OK;
+}
+
+void fill_report(ofdft_ctx* c, const double* h, double resid, ofdft_report* rep, int iters, int evals, int conv) {
+  ofdft_report r{};
+  r.iterations = iters;
+  r.evaluations = evals;
+  r.converged = conv;
+  r.F_total = h[SC_FTOT];
+  r.F_s = h[SC_FS];
+  r.TS_s = h[SC_TS];
+  r.E_internal = h[SC_FTOT] + h[SC_TS];
+  r.E_xc = h[SC_EXC];
+  r.E_H = h[SC_EH];
+  r.E_ext = h[SC_EEXT];
+  r.E_alphaZ = h[SC_EAZ];
+  r.E_ion = h[SC_EION];
+  r.N_e = h[SC_NE];
+  r.mu = h[SC_MU];
+  r.residual = resid;
+  c->last = r;
+  if (rep) *rep = r;
+}
+
+// Line search along the rotation phi(theta) = ca phi + sb d (ca, sb from theta).
+// On success the accepted state is in phi_t / v_t / scalars_t.
+struct LS {
+  double theta;
+  double F;
+  bool ok;
+};
+
+int line_search(ofdft_ctx* c, double F0, double dF0, double r, double phinorm, double dn, double theta1,
+                int& nevals, LS& out) {
+  const double ratio = r / phinorm;   // renormalises phi to the exact sphere
+  double lo = 0.0, dlo = dF0, hi = -1.0, dhi = 0.0;
+  double theta = theta1;
+  double best_theta = -1.0, best_F = F0;
+  double last_theta = -1.0;
+  for (int trial = 0; trial < 14; ++trial) {
+    const double ct = std::cos(theta), st = std::sin(theta);
+    int rc = dev_rotate(c, c->phi_t, c->phi, ct * ratio, c->d, st * r / dn);
+    if (rc) return rc;
+    rc = dev_eval(c, c->phi_t, c->v_t, c->scalars_t);
+    if (rc) return rc;
+    rc = dev_dtheta(c, c->phi_t, c->v_t, c->scalars_t, c->phi, c->d, -st * ratio, ct * r / dn);
+    if (rc) return rc;
+    ++nevals;
+    double h[SC_COUNT], dth;
+    if ((rc = dev_read(c, c->scalars_t, SC_COUNT, h))) return rc;
+    if ((rc = dev_read(c, c->vout, 1, &dth))) return rc;
+    const double Ft = h[SC_FTOT];
+    if (!is_fin(Ft) || !is_fin(dth)) return fail(c, OFDFT_E_NONFINITE, "non-finite energy in line search");
+    last_theta = theta;
+    if (Ft <= F0 && (best_theta < 0 || Ft < best_F)) {
+      best_theta = theta;
+      best_F = Ft;
+    }
+    const bool armijo = Ft <= F0 + 1e-4 * theta * dF0;
+    if (armijo && std::fabs(dth) <= 0.1 * std::fabs(dF0)) {
+      out = {theta, Ft, true};
+      return OFDFT_OK;
+    }
+    if (dth > 0.0 || !armijo) {
+      hi = theta;
+      dhi = dth;
+    } else {
+      lo = theta;
+      dlo = dth;
+    }
+    double next;
+    if (hi < 0.0) {
+      next = (dth <= dF0) ? 2.0 * theta : theta - dth * theta / (dth - dF0);
+      next = std::min(std::max(next, 1.5 * theta), 4.0 * theta);
+    } else {
+      next = (dth > 0.0 && dhi > dlo) ? lo - dlo * (hi - lo) / (dhi - dlo) : 0.5 * (lo + hi);
+      const double w = hi - lo;
+      next = std::min(std::max(next, lo + 0.1 * w), hi - 0.1 * w);
+    }
+    theta = next;
+  }
+  if (best_theta < 0.0) {
+    out = {0.0, F0, false};
+    return OFDFT_OK;
+  }
+  if (best_theta != last_theta) {
+    const double ct = std::cos(best_theta), st = std::sin(best_theta);
+    int rc = dev_rotate(c, c->phi_t, c->phi, ct * ratio, c->d, st * r / dn);
+    if (rc) return rc;
+    rc = dev_eval(c, c->phi_t, c->v_t, c->scalars_t);
+    if (rc) return rc;
+    ++nevals;
+  }
+  out = {best_theta, best_F, true};
+  return OFDFT_OK;
+}
+
+void accept_trial(ofdft_ctx* c) {
+  std::swap(c->phi, c->phi_t);
+  std::swap(c->v, c->v_t);
+  std::swap(c->scalars, c->scalars_t);
+}
+
+int ensure_phi(ofdft_ctx* c) {
+  if (c->have_phi) return OFDFT_OK;
+  std::vector<double> h(c->g.N, std::sqrt(c->Ne / c->g.volume));
+  if (hipMemcpy(c->phi, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+    return fail(c, OFDFT_E_DEVICE, "upload phi");
+  c->have_phi = true;
+  return OFDFT_OK;
+}
+
+int check_ready(ofdft_ctx* c) {
+  if (!c) return fail(nullptr, OFDFT_E_ARG, "null context");
+  if (!c->have_cell) return fail(c, OFDFT_E_STATE, "set_cell has not been called");
+  if (!c->have_ions) return fail(c, OFDFT_E_STATE, "set_ions has not been called (after the last set_cell)");
+  if (!c->have_T) return fail(c, OFDFT_E_STATE, "set_temperature has not been called");
+  if (hipSetDevice(c->opt.device) != hipSuccess) return fail(c, OFDFT_E_DEVICE, "hipSetDevice");
+  return ensure_phi(c);
+}
+
+bool stop_rule(const ofdft_ctx* c, int small, double resid) {
+  return small >= 2 && (c->opt.tol_residual <= 0.0 || resid < c->opt.tol_residual);
+}
+
+double first_step(double F0, double Fprev, bool have_prev, double dF0) {
+  if (have_prev && dF0 < 0.0 && Fprev > F0) return std::min(std::max(2.0 * (Fprev - F0) / (-dF0), 1e-6), 0.3);
+  return 0.05;
+}
+
+// ---------------------------------------------------------------- CG
+int minimize_cg(ofdft_ctx* c, ofdft_report* rep) {
+  const double norm2 = c->Ne / c->g.dv;   // target sum phi^2
+  const double r = std::sqrt(norm2);
+  const double two_dv = 2.0 * c->g.dv;
+  (void)two_dv;
+  int nevals = 0, rc;
+  Point p;
+  if ((rc = eval_at(c, c->phi, c->v, c->scalars, p))) return rc;
+  ++nevals;
+  double F = p.F, Fprev = 0.0, gg_prev = 0.0, dn_prev = 0.0, theta_prev = 0.0;
+  bool have_prev = false;
+  int small = 0, it = 0;
+  bool converged = false;
+  double resid = 0.0;
+  for (it = 1; it <= c->opt.max_iter; ++it) {
+    double dots[4];
+    if ((rc = dev_grad_dots(c, c->phi, c->v, c->scalars, have_prev ? c->gprev : nullptr, have_prev ? c->d : nullptr)))
+      return rc;
+    if ((rc = dev_read(c, c->vout, 4, dots))) return rc;
+    const double phinorm2 = p.Ne / c->g.dv;
+    resid = std::sqrt(dots[3] / phinorm2);
+    const double gg = dots[0];
+    if (gg == 0.0) { converged = true; break; }
+    double beta = 0.0, cproj = 0.0;
+    if (have_prev) {
+      beta = std::max(0.0, (gg - dots[1]) / gg_prev);
+      // d_old . phi_new = sin(theta) |phi| |d_old| (d_old is tangent at phi_old)
+      cproj = std::sin(theta_prev) * dn_prev / r;
+    }
+    if ((rc = dev_cg_direction(c, beta, cproj))) return rc;
+    double dd_dg[2];
+    if ((rc = dev_read(c, c->vout, 2, dd_dg))) return rc;
+    if (dd_dg[1] >= 0.0) {   // not a descent direction: restart along -g
+      if ((rc = dev_cg_direction(c, 0.0, 0.0))) return rc;
+      if ((rc = dev_read(c, c->vout, 2, dd_dg))) return rc;
+    }
+    const double dn = std::sqrt(dd_dg[0]);
+    const double dF0 = r * dd_dg[1] / dn;
+    LS ls;
+    if ((rc = line_search(c, F, dF0, r, std::sqrt(phinorm2), dn, first_step(F, Fprev, have_prev, dF0), nevals, ls)))
+      return rc;
+    if (!ls.ok) {
+      converged = small >= 1 || (c->opt.tol_residual > 0 && resid < c->opt.tol_residual);
+      break;
+    }
+    accept_trial(c);
+    double h[SC_COUNT];
+    if ((rc = dev_read(c, c->scalars, SC_COUNT, h))) return rc;
+    p.F = h[SC_FTOT];
+    p.Ne = h[SC_NE];
+    const double dF = F - p.F;
+    Fprev = F;
+    F = p.F;
+    gg_prev = gg;
+    dn_prev = dn;
+    theta_prev = ls.theta;
+    have_prev = true;
+    small = std::fabs(dF) < c->opt.tol_energy ? small + 1 : 0;
+    if (small >= 2) {
+      double d4[4];
+      if ((rc = dev_grad_dots(c, c->phi, c->v, c->scalars, nullptr, nullptr))) return rc;
+      if ((rc = dev_read(c, c->vout, 4, d4))) return rc;
+      resid = std::sqrt(d4[3] / (p.Ne / c->g.dv));
+      if (stop_rule(c, small, resid)) { converged = true; break; }
+    }
+  }
+  double h[SC_COUNT];
+  if ((rc = dev_read(c, c->scalars, SC_COUNT, h))) return rc;
+  fill_report(c, h, resid, rep, std::min(it, c->opt.max_iter), nevals, converged ? 1 : 0);
+  c->converged = converged;
+  return converged ? OFDFT_OK : fail(c, OFDFT_E_NOT_CONVERGED, "minimisation did not converge");
+}
+
+// ---------------------------------------------------------------- truncated Newton
+int minimize_tn(ofdft_ctx* c, ofdft_report* rep) {
+  const double norm2 = c->Ne / c->g.dv;
+  const double r = std::sqrt(norm2);
+  const double two_dv = 2.0 * c->g.dv;
+  double* P = c->tn[0];
+  double* RES = c->tn[1];
+  double* S = c->tn[2];
+  double* HS = c->tn[3];
+  int nevals = 0, rc;
+  Point p;
+  if ((rc = eval_at(c, c->phi, c->v, c->scalars, p))) return rc;
+  ++nevals;
+  double F = p.F;
+  int small = 0, it = 0;
+  bool converged = false;
+  double resid = 0.0;
+  const int max_inner = 20;
+  for (it = 1; it <= c->opt.max_iter; ++it) {
+    double dots[4];
+    if ((rc = dev_grad_dots(c, c->phi, c->v, c->scalars, nullptr, nullptr))) return rc;
+    if ((rc = dev_read(c, c->vout, 4, dots))) return rc;
+    const double phinorm2 = p.Ne / c->g.dv;
+    resid = std::sqrt(dots[3] / phinorm2);
+    const double gnorm = std::sqrt(dots[0]);
+    if (gnorm == 0.0) { converged = true; break; }
+    double hsc[SC_COUNT];
+    if ((rc = dev_read(c, c->scalars, SC_COUNT, hsc))) return rc;
+    const double mu = hsc[SC_MU];
+    // d = -g, gprev = g
+    if ((rc = dev_cg_direction(c, 0.0, 0.0))) return rc;
+    // inner CG on H p = -g: P = 0, RES = -g, S = RES
+    if ((rc = dev_axpby(c, P, 0.0, c->d, 0.0))) return rc;
+    if ((rc = dev_axpby(c, RES, 0.0, c->d, 1.0))) return rc;
+    if ((rc = dev_axpby(c, S, 0.0, c->d, 1.0))) return rc;
+    double rr = dots[0];
+    const double tol_in = std::min(0.5, std::sqrt(gnorm)) * gnorm;
+    bool any = false;
+    for (int k = 0; k < max_inner; ++k) {
+      double ss;
+      if ((rc = dev_dot(c, S, S))) return rc;
+      if ((rc = dev_read(c, c->vout, 1, &ss))) return rc;
+      const double eps = 1e-6 * r / std::sqrt(ss);
+      // central difference of the unconstrained gradient along S
+      if ((rc = dev_rotate(c, c->phi_t, c->phi, 1.0, S, eps))) return rc;
+      if ((rc = dev_eval(c, c->phi_t, c->v_t, c->scalars_t))) return rc;
+      if ((rc = dev_full_grad_acc(c, HS, c->phi_t, c->v_t, +1.0))) return rc;
+      if ((rc = dev_rotate(c, c->phi_t, c->phi, 1.0, S, -eps))) return rc;
+      if ((rc = dev_eval(c, c->phi_t, c->v_t, c->scalars_t))) return rc;
+      if ((rc = dev_full_grad_acc(c, HS, c->phi_t, c->v_t, -1.0))) return rc;
+      nevals += 2;
+      // HS = P[(g+ - g-)/(2 eps)] - 2 dv mu S
+      if ((rc = dev_tn_hess_finish(c, HS, c->phi, S, 0.5 / eps, 0.0))) return rc;
+      double hphi;
+      if ((rc = dev_read(c, c->vout, 1, &hphi))) return rc;
+      if ((rc = dev_axpby(c, HS, 1.0, c->phi, -hphi / phinorm2))) return rc;
+      if ((rc = dev_axpby(c, HS, 1.0, S, -two_dv * mu))) return rc;
+      double curv;
+      if ((rc = dev_dot(c, S, HS))) return rc;
+      if ((rc = dev_read(c, c->vout, 1, &curv))) return rc;
+      if (!is_fin(curv)) return fail(c, OFDFT_E_NONFINITE, "non-finite curvature");
+      if (curv <= 0.0) break;
+      const double alpha = rr / curv;
+      if ((rc = dev_axpby(c, P, 1.0, S, alpha))) return rc;
+      any = true;
+      if ((rc = dev_axpby(c, RES, 1.0, HS, -alpha))) return rc;
+      double rr_new;
+      if ((rc = dev_dot(c, RES, RES))) return rc;
+      if ((rc = dev_read(c, c->vout, 1, &rr_new))) return rc;
+      if (std::sqrt(rr_new) < tol_in) break;
+      if ((rc = dev_axpby(c, S, rr_new / rr, RES, 1.0))) return rc;
+      rr = rr_new;
+    }
+    // search direction d = P projected onto the tangent space (or -g)
+    if (any) {
+      double pphi;
+      if ((rc = dev_dot(c, P, c->phi))) return rc;
+      if ((rc = dev_read(c, c->vout, 1, &pphi))) return rc;
+      if ((rc = dev_axpby(c, c->d, 0.0, P, 1.0))) return rc;
+      if ((rc = dev_axpby(c, c->d, 1.0, c->phi, -pphi / phinorm2))) return rc;
+    }
+    double dd, dg;
+    if ((rc = dev_dot(c, c->d, c->d))) return rc;
+    if ((rc = dev_read(c, c->vout, 1, &dd))) return rc;
+    if ((rc = dev_dot(c, c->d, c->gprev))) return rc;
+    if ((rc = dev_read(c, c->vout, 1, &dg))) return rc;
+    if (dg >= 0.0) {
+      if ((rc = dev_cg_direction(c, 0.0, 0.0))) return rc;
+      double t2[2];
+      if ((rc = dev_read(c, c->vout, 2, t2))) return rc;
+      dd = t2[0];
+      dg = t2[1];
+    }
+    const double dn = std::sqrt(dd);
+    const double dF0 = r * dg / dn;
+    const double theta1 = std::min(std::max(dn / r, 1e-8), 0.5);
+    LS ls;
+    if ((rc = line_search(c, F, dF0, r, std::sqrt(phinorm2), dn, theta1, nevals, ls))) return rc;
+    if (!ls.ok) {
+      converged = small >= 1 || (c->opt.tol_residual > 0 && resid < c->opt.tol_residual);
+      break;
+    }
+    accept_trial(c);
+    double h[SC_COUNT];
+    if ((rc = dev_read(c, c->scalars, SC_COUNT, h))) return rc;
+    p.F = h[SC_FTOT];
+    p.Ne = h[SC_NE];
+    const double dF = F - p.F;
+    F = p.F;
+    small = std::fabs(dF) < c->opt.tol_energy ? small + 1 : 0;
+    if (small >= 2) {
+      double d4[4];
+      if ((rc = dev_grad_dots(c, c->phi, c->v, c->scalars, nullptr, nullptr))) return rc;
+      if ((rc = dev_read(c, c->vout, 4, d4))) return rc;
+      resid = std::sqrt(d4[3] / (p.Ne / c->g.dv));
+      if (stop_rule(c, small, resid)) { converged = true; break; }
+    }
+  }
+  double h[SC_COUNT];
+  if ((rc = dev_read(c, c->scalars, SC_COUNT, h))) return rc;
+  fill_report(c, h, resid, rep, std::min(it, c->opt.max_iter), nevals, converged ? 1 : 0);
+  c->converged = converged;
+  return converged ? OFDFT_OK : fail(c, OFDFT_E_NOT_CONVERGED, "minimisation did not converge");
+}
+
+}  // namespace
+
+// ==================================================================== C ABI
+extern "C" {
+
+void ofdft_default_options(ofdft_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->functional = OFDFT_TF;
+  o->mu_sga = 5.0 / 27.0;
+  o->xc = OFDFT_XC_PZ81;
+  o->lpp = OFDFT_LPP_GAUSS;
+  o->lpp_rc = 0.5;
+  o->lpp_A = 0.0;
+  o->lpp_qc = 1e30;
+  o->precision = OFDFT_FP64;
+  o->minimizer = OFDFT_CG;
+  o->tol_energy = 1e-8;
+  o->tol_residual = 0.0;
+  o->max_iter = 1000;
+  o->device = 0;
+  o->stream = nullptr;
+}
+
+int ofdft_create(const ofdft_options* opt, ofdft_ctx** out) {
+  if (!out) return fail(nullptr, OFDFT_E_ARG, "out is NULL");
+  *out = nullptr;
+  ofdft_options o;
+  if (opt) o = *opt;
+  else ofdft_default_options(&o);
+  if (o.functional < OFDFT_TF || o.functional > OFDFT_APBEF) return fail(nullptr, OFDFT_E_ARG, "unknown functional");
+  if (o.xc != OFDFT_XC_NONE && o.xc != OFDFT_XC_PZ81) return fail(nullptr, OFDFT_E_ARG, "unknown xc");
+  if (o.lpp != OFDFT_LPP_GAUSS && o.lpp != OFDFT_LPP_HA) return fail(nullptr, OFDFT_E_ARG, "unknown pseudopotential");
+  if (!(o.lpp_rc > 0.0)) return fail(nullptr, OFDFT_E_ARG, "lpp_rc must be > 0");
+  if (o.lpp == OFDFT_LPP_HA && !(o.lpp_qc > 0.0)) return fail(nullptr, OFDFT_E_ARG, "lpp_qc must be > 0");
+  if (o.precision != OFDFT_FP64 && o.precision != OFDFT_MIXED) return fail(nullptr, OFDFT_E_ARG, "unknown precision");
+  if (o.minimizer != OFDFT_CG && o.minimizer != OFDFT_TN) return fail(nullptr, OFDFT_E_ARG, "unknown minimizer");
+  if (!(o.tol_energy > 0.0) || o.tol_residual < 0.0 || o.max_iter < 1)
+    return fail(nullptr, OFDFT_E_ARG, "tolerances must be positive and max_iter >= 1");
+  if (o.functional == OFDFT_SGA && !(o.mu_sga >= 0.0)) return fail(nullptr, OFDFT_E_ARG, "mu_sga must be >= 0");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(nullptr, OFDFT_E_DEVICE, "no HIP device");
+  if (o.device < 0 || o.device >= ndev) return fail(nullptr, OFDFT_E_ARG, "device ordinal out of range");
+  if (hipSetDevice(o.device) != hipSuccess) return fail(nullptr, OFDFT_E_DEVICE, "hipSetDevice failed");
+  if (dev_upload_tables() != OFDFT_OK) return fail(nullptr, OFDFT_E_DEVICE, "uploading Fermi-Dirac tables failed");
+  ofdft_ctx* c = new ofdft_ctx();
+  c->opt = o;
+  c->rsize = (o.precision == OFDFT_MIXED) ? 4 : 8;
+  if (o.stream) {
+    c->stream = (hipStream_t)o.stream;
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete c;
+      return fail(nullptr, OFDFT_E_DEVICE, "stream creation failed");
+    }
+    c->own_stream = true;
+  }
+  *out = c;
+  return OFDFT_OK;
+}
+
+int ofdft_destroy(ofdft_ctx* c) {
+  if (!c) return fail(nullptr, OFDFT_E_ARG, "null context");
+  (void)hipSetDevice(c->opt.device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  dev_free_grid(c);
+  if (c->phase) (void)hipFree(c->phase);
+  if (c->dZ) (void)hipFree(c->dZ);
+  if (c->fpart) (void)hipFree(c->fpart);
+  if (c->dforces) (void)hipFree(c->dforces);
+  if (c->hbuf) (void)hipHostFree(c->hbuf);
+  for (hipEvent_t e : c->timing.events) (void)hipEventDestroy(e);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+  return OFDFT_OK;
+}
+
+int ofdft_set_cell(ofdft_ctx* c, const double lattice[9], double cell_scale, const int grid[3]) {
+  if (!c) return fail(nullptr, OFDFT_E_ARG, "null context");
+  if (!lattice || !grid) return fail(c, OFDFT_E_ARG, "lattice and grid must not be NULL");
+  if (!(cell_scale > 0.0) || !is_fin(cell_scale)) return fail(c, OFDFT_E_ARG, "cell_scale must be > 0");
+  for (int k = 0; k < 9; ++k)
+    if (!is_fin(lattice[k])) return fail(c, OFDFT_E_ARG, "non-finite lattice");
+  for (int k = 0; k < 3; ++k)
+    if (!grid_ok(grid[k])) return fail(c, OFDFT_E_GRID, "grid sizes must be one of 8,12,16,24,32,48,64,96,128,256");
+  double lat[9];
+  for (int k = 0; k < 9; ++k) lat[k] = lattice[k] * cell_scale;
+  const double* a1 = lat;
+  const double* a2 = lat + 3;
+  const double* a3 = lat + 6;
+  const double det = a1[0] * (a2[1] * a3[2] - a2[2] * a3[1]) - a1[1] * (a2[0] * a3[2] - a2[2] * a3[0]) +
+                     a1[2] * (a2[0] * a3[1] - a2[1] * a3[0]);
+  const double scale = std::pow(std::fabs(a1[0]) + std::fabs(a2[1]) + std::fabs(a3[2]) + 1e-300, 3.0);
+  if (!(std::fabs(det) > 1e-10 * scale)) return fail(c, OFDFT_E_ARG, "singular lattice");
+  if (hipSetDevice(c->opt.device) != hipSuccess) return fail(c, OFDFT_E_DEVICE, "hipSetDevice");
+  GridDesc g{};
+  g.n1 = grid[0];
+  g.n2 = grid[1];
+  g.n3 = grid[2];
+  g.n3h = g.n3 / 2 + 1;
+  g.N = (long long)g.n1 * g.n2 * g.n3;
+  g.NS = (long long)g.n3h * g.n1 * g.n2;
+  // b_i = 2 pi (a_j x a_k)/det
+  auto cross = [](const double* u, const double* v, double* w) {
+    w[0] = u[1] * v[2] - u[2] * v[1];
+    w[1] = u[2] * v[0] - u[0] * v[2];
+    w[2] = u[0] * v[1] - u[1] * v[0];
+  };
+  cross(a2, a3, g.b);
+  cross(a3, a1, g.b + 3);
+  cross(a1, a2, g.b + 6);
+  for (int k = 0; k < 9; ++k) g.b[k] *= 2.0 * kPiD / det;
+  g.volume = std::fabs(det);
+  g.dv = g.volume / (double)g.N;
+  g.inv_n = 1.0 / (double)g.N;
+  g.tr = std::max(2, largest_pow2_divisor_upto(g.n2, g.n3 >= 256 ? 8 : 16));
+  const int tc_cap = (g.n1 >= 256) ? 8 : 16;
+  g.tc = largest_pow2_divisor_upto(g.n2, tc_cap);
+  g.rb = std::max(1, 1024 / g.n2);
+  std::memcpy(c->lat, lat, sizeof(lat));
+  c->cell_scale = cell_scale;
+  c->g = g;
+  c->have_cell = false;
+  c->have_ions = false;
+  c->have_phi = false;
+  c->converged = false;
+  int rc = dev_alloc_grid(c);
+  if (rc) return fail(c, rc, c->err.empty() ? "device allocation failed" : c->err);
+  c->have_cell = true;
+  return OFDFT_OK;
+}
+
+int ofdft_set_ions(ofdft_ctx* c, int nat, const double* tau, const double* Z) {
+  if (!c) return fail(nullptr, OFDFT_E_ARG, "null context");
+  if (!c->have_cell) return fail(c, OFDFT_E_STATE, "set_cell must come first");
+  if (nat <= 0 || !tau || !Z) return fail(c, OFDFT_E_ARG, "nat must be >= 1 and tau, Z non-NULL");
+  for (int i = 0; i < nat; ++i) {
+    if (!(Z[i] > 0.0) || !is_fin(Z[i])) return fail(c, OFDFT_E_ARG, "charges must be finite and > 0");
+    for (int a = 0; a < 3; ++a)
+      if (!is_fin(tau[3 * i + a])) return fail(c, OFDFT_E_ARG, "non-finite ion position");
+  }
+  if (hipSetDevice(c->opt.device) != hipSuccess) return fail(c, OFDFT_E_DEVICE, "hipSetDevice");
+  // positions are given in the frame of the unscaled lattice (cellScale, Sec. V B)
+  const double Ne_old = c->Ne;
+  c->nat = nat;
+  c->tau.assign(tau, tau + 3 * (size_t)nat);
+  for (double& x : c->tau) x *= c->cell_scale;
+  c->Z.assign(Z, Z + nat);
+  double Ne = 0.0, asum = 0.0;
+  for (int i = 0; i < nat; ++i) {
+    Ne += Z[i];
+    asum += alpha_of(c->opt, Z[i], c->g.volume);
+  }
+  c->Ne = Ne;
+  c->alpha_sum = asum;
+  ewald_sum(c->lat, nat, c->tau.data(), c->Z.data(), c->E_ion, c->F_ion);
+  int rc = dev_structure_factor(c);
+  if (rc) return fail(c, rc, c->err.empty() ? "structure factor failed" : c->err);
+  if (c->have_phi && Ne_old > 0.0 && Ne_old != Ne) {
+    // keep the shape of the warm start, rescale to the new electron count
+    if ((rc = dev_axpby(c, c->phi, std::sqrt(Ne / Ne_old), c->phi, 0.0))) return fail(c, rc, c->err);
+  }
+  c->have_ions = true;
+  c->converged = false;
+  return OFDFT_OK;
+}
+
+int ofdft_set_temperature(ofdft_ctx* c, double T_kelvin) {
+  if (!c) return fail(nullptr, OFDFT_E_ARG, "null context");
+  if (!(T_kelvin > 0.0) || !is_fin(T_kelvin)) return fail(c, OFDFT_E_ARG, "temperature must be finite and > 0");
+  c->T_ha = T_kelvin * kKelvinToHartree;
+  c->have_T = true;
+  c->converged = false;
+  return OFDFT_OK;
+}
+
+int ofdft_minimize_density(ofdft_ctx* c, ofdft_report* rep) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  c->converged = false;
+  return c->opt.minimizer == OFDFT_TN ? minimize_tn(c, rep) : minimize_cg(c, rep);
+}
+
+int ofdft_free_energy_and_forces(ofdft_ctx* c, double* F_total, double* E_internal, double* forces,
+                                 double* pressure) {
+  if (!c) return fail(nullptr, OFDFT_E_ARG, "null context");
+  if (pressure) return fail(c, OFDFT_E_ARG, "pressure must be NULL: the stress tensor is not provided");
+  if (!c->converged) return fail(c, OFDFT_E_STATE, "no converged density: call ofdft_minimize_density first");
+  if (hipSetDevice(c->opt.device) != hipSuccess) return fail(c, OFDFT_E_DEVICE, "hipSetDevice");
+  if (F_total) *F_total = c->last.F_total;
+  if (E_internal) *E_internal = c->last.E_internal;
+  if (forces) {
+    int rc = dev_forces(c, forces);
+    if (rc) return fail(c, rc, c->err);
+    for (int k = 0; k < 3 * c->nat; ++k) {
+      forces[k] += c->F_ion[k];
+      if (!is_fin(forces[k])) return fail(c, OFDFT_E_NONFINITE, "non-finite force");
+    }
+  }
+  return OFDFT_OK;
+}
+
+int ofdft_get_density(ofdft_ctx* c, double* phi_out) {
+  if (!c) return fail(nullptr, OFDFT_E_ARG, "null context");
+  if (!phi_out) return fail(c, OFDFT_E_ARG, "phi_out is NULL");
+  if (!c->have_cell) return fail(c, OFDFT_E_STATE, "set_cell has not been called");
+  if (!c->have_phi) return fail(c, OFDFT_E_STATE, "no density yet");
+  (void)hipSetDevice(c->opt.device);
+  if (hipMemcpyAsync(phi_out, c->phi, c->g.N * sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    return fail(c, OFDFT_E_DEVICE, "copy phi");
+  return OFDFT_OK;
+}
+
+int ofdft_set_density(ofdft_ctx* c, const double* phi) {
+  if (!c) return fail(nullptr, OFDFT_E_ARG, "null context");
+  if (!phi) return fail(c, OFDFT_E_ARG, "phi is NULL");
+  if (!c->have_cell) return fail(c, OFDFT_E_STATE, "set_cell has not been called");
+  if (!c->have_ions) return fail(c, OFDFT_E_STATE, "set_ions has not been called");
+  double s = 0.0;
+  for (long long i = 0; i < c->g.N; ++i) {
+    if (!is_fin(phi[i])) return fail(c, OFDFT_E_ARG, "non-finite phi");
+    s += phi[i] * phi[i];
+  }
+  if (!(s > 0.0)) return fail(c, OFDFT_E_ARG, "phi is zero");
+  const double k = std::sqrt(c->Ne / (c->g.dv * s));
+  std::vector<double> h(phi, phi + c->g.N);
+  for (double& x : h) x *= k;
+  (void)hipSetDevice(c->opt.device);
+  if (hipMemcpy(c->phi, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+    return fail(c, OFDFT_E_DEVICE, "upload phi");
+  c->have_phi = true;
+  c->converged = false;
+  return OFDFT_OK;
+}
+
+int ofdft_eval(ofdft_ctx* c, ofdft_report* rep, double* potential_out) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  Point p;
+  if ((rc = eval_at(c, c->phi, c->v, c->scalars, p))) return rc;
+  double d4[4];
+  if ((rc = dev_grad_dots(c, c->phi, c->v, c->scalars, nullptr, nullptr))) return rc;
+  if ((rc = dev_read(c, c->vout, 4, d4))) return rc;
+  double h[SC_COUNT];
+  if ((rc = dev_read(c, c->scalars, SC_COUNT, h))) return rc;
+  fill_report(c, h, std::sqrt(d4[3] / (p.Ne / c->g.dv)), rep, 0, 1, 0);
+  if (potential_out) {
+    if (c->rsize == 8) {
+      if (hipMemcpy(potential_out, c->v, c->g.N * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(c, OFDFT_E_DEVICE, "copy potential");
+    } else {
+      std::vector<float> tmp(c->g.N);
+      if (hipMemcpy(tmp.data(), c->v, c->g.N * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(c, OFDFT_E_DEVICE, "copy potential");
+      for (long long i = 0; i < c->g.N; ++i) potential_out[i] = tmp[i];
+    }
+  }
+  return OFDFT_OK;
+}
+
+int ofdft_time_evals(ofdft_ctx* c, int n_evals, double* total_ms, int max_kernels, const char** kernel_names,
+                     double* kernel_ms, int* n_kernels) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (n_evals < 1 || !total_ms || max_kernels < 0 || (max_kernels > 0 && (!kernel_names || !kernel_ms)) || !n_kernels)
+    return fail(c, OFDFT_E_ARG, "invalid timing arguments");
+  Timing& t = c->timing;
+  const size_t need = (size_t)n_evals * 16 + 2;
+  while (t.events.size() < need) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return fail(c, OFDFT_E_DEVICE, "hipEventCreate");
+    t.events.push_back(e);
+  }
+  t.names.clear();
+  t.used = 0;
+  t.on = true;
+  for (int k = 0; k < n_evals; ++k) {
+    rc = dev_eval(c, c->phi, c->v, c->scalars);
+    if (rc) {
+      t.on = false;
+      return fail(c, rc, c->err);
+    }
+  }
+  t.on = false;
+  if ((rc = dev_sync(c))) return fail(c, rc, c->err);
+  const int per = t.used / n_evals;   // marks per evaluation (kernels + end)
+  float ms = 0.0f;
+  (void)hipEventElapsedTime(&ms, t.events[0], t.events[t.used - 1]);
+  *total_ms = ms;
+  const int nk = std::min(per - 1, max_kernels);
+  for (int k = 0; k < nk; ++k) {
+    double acc = 0.0;
+    for (int e = 0; e < n_evals; ++e) {
+      float d = 0.0f;
+      (void)hipEventElapsedTime(&d, t.events[e * per + k], t.events[e * per + k + 1]);
+      acc += d;
+    }
+    kernel_ms[k] = acc / n_evals;
+    kernel_names[k] = t.names[k];
+  }
+  *n_kernels = nk;
+  return OFDFT_OK;
+}
+
+int ofdft_batch_minimize(ofdft_ctx* const* ctxs, int n, ofdft_report* reps) {
+  if (!ctxs || n < 0) return fail(nullptr, OFDFT_E_ARG, "invalid batch");
+  for (int i = 0; i < n; ++i)
+    if (!ctxs[i]) return fail(nullptr, OFDFT_E_ARG, "null context in batch");
+  std::vector<int> rcs(n, OFDFT_OK);
+  std::vector<std::thread> th;
+  th.reserve(n);
+  for (int i = 0; i < n; ++i)
+    th.emplace_back([&, i]() { rcs[i] = ofdft_minimize_density(ctxs[i], reps ? reps + i : nullptr); });
+  for (auto& t : th) t.join();
+  for (int i = 0; i < n; ++i)
+    if (rcs[i]) {
+      g_last_error = "batch member " + std::to_string(i) + ": " + ctxs[i]->err;
+      return rcs[i];
+    }
+  return OFDFT_OK;
+}
+
+const char* ofdft_last_error(const ofdft_ctx* c) {
+  if (c) return c->err.c_str();
+  return g_last_error.c_str();
+}
+
+}  // extern "C"

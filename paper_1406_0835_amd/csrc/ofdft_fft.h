@@ -1,0 +1,184 @@
+// LDS-resident FFT building blocks for CDNA4 (wave64).
+//
+// The 3D R2C/C2R transforms of the density, its gradient and the divergence
+// term (the reciprocal-space parts of arXiv:1406.0835 Sec. III B, Eqs. E2,
+// E4A, vftGGA) are assembled from three passes; each pass stages a tile of
+// rows in LDS and runs a Stockham auto-sort FFT over them:
+//   * a contiguous-axis pass that packs two real rows into one complex row,
+//   * passes along the two other axes on the transposed half spectrum
+//     S[k3][i1][i2] (k3 slowest), so both are rows of N1 or N2 points.
+// Plans are compile-time (radix 8, 4, 2, 3 in that order of preference), so
+// every index division in the butterflies is by a constant.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace ofdft {
+
+template <typename R>
+struct cplx {
+  R x, y;
+};
+
+template <typename R>
+__device__ __forceinline__ cplx<R> mk(R a, R b) { return cplx<R>{a, b}; }
+template <typename R>
+__device__ __forceinline__ cplx<R> operator+(cplx<R> a, cplx<R> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename R>
+__device__ __forceinline__ cplx<R> operator-(cplx<R> a, cplx<R> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename R>
+__device__ __forceinline__ cplx<R> cmul(cplx<R> a, cplx<R> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename R>
+__device__ __forceinline__ cplx<R> cconj(cplx<R> a) { return {a.x, -a.y}; }
+template <typename R>
+__device__ __forceinline__ cplx<R> cscale(cplx<R> a, R s) { return {a.x * s, a.y * s}; }
+// multiply by SIGN * i
+template <typename R, int SIGN>
+__device__ __forceinline__ cplx<R> mul_si(cplx<R> a) {
+  return SIGN > 0 ? cplx<R>{-a.y, a.x} : cplx<R>{a.y, -a.x};
+}
+
+// ---------------------------------------------------------------- plans
+__host__ __device__ constexpr int first_radix(int L) {
+  return (L % 8 == 0) ? 8 : (L % 4 == 0) ? 4 : (L % 2 == 0) ? 2 : (L % 3 == 0) ? 3 : 0;
+}
+// radix of stage s for length L: stages peel the preferred radix off L
+__host__ __device__ constexpr int radix_at(int L, int s) {
+  int rem = L;
+  for (int i = 0; i < s; ++i) rem /= first_radix(rem);
+  return first_radix(rem);
+}
+__host__ __device__ constexpr int n_stages(int L) {
+  int s = 0;
+  for (int rem = L; rem > 1; rem /= first_radix(rem)) ++s;
+  return s;
+}
+__host__ __device__ constexpr bool supported_length(int L) {
+  if (L < 2) return false;
+  int rem = L;
+  while (rem % 2 == 0) rem /= 2;
+  while (rem % 3 == 0) rem /= 3;
+  return rem == 1;
+}
+
+// ---------------------------------------------------------------- butterflies
+template <typename R, int SIGN, int RAD>
+struct Bfly;
+
+template <typename R, int SIGN>
+struct Bfly<R, SIGN, 2> {
+  __device__ __forceinline__ static void run(cplx<R>* v) {
+    cplx<R> a = v[0];
+    v[0] = a + v[1];
+    v[1] = a - v[1];
+  }
+};
+
+template <typename R, int SIGN>
+struct Bfly<R, SIGN, 3> {
+  __device__ __forceinline__ static void run(cplx<R>* v) {
+    const R c = R(-0.5);
+    const R s = R(SIGN) * R(0.86602540378443864676372317075294);
+    cplx<R> t1 = v[1] + v[2];
+    cplx<R> t2 = v[1] - v[2];
+    cplx<R> m = {v[0].x + c * t1.x, v[0].y + c * t1.y};
+    v[0] = v[0] + t1;
+    v[1] = {m.x - s * t2.y, m.y + s * t2.x};
+    v[2] = {m.x + s * t2.y, m.y - s * t2.x};
+  }
+};
+
+template <typename R, int SIGN>
+struct Bfly<R, SIGN, 4> {
+  __device__ __forceinline__ static void run(cplx<R>* v) {
+    cplx<R> a = v[0] + v[2], b = v[0] - v[2];
+    cplx<R> c = v[1] + v[3], d = mul_si<R, SIGN>(v[1] - v[3]);
+    v[0] = a + c;
+    v[2] = a - c;
+    v[1] = b + d;
+    v[3] = b - d;
+  }
+};
+
+template <typename R, int SIGN>
+struct Bfly<R, SIGN, 8> {
+  __device__ __forceinline__ static void run(cplx<R>* v) {
+    cplx<R> e[4] = {v[0], v[2], v[4], v[6]};
+    cplx<R> o[4] = {v[1], v[3], v[5], v[7]};
+    Bfly<R, SIGN, 4>::run(e);
+    Bfly<R, SIGN, 4>::run(o);
+    const R h = R(0.70710678118654752440084436210485);
+    // W^k, W = exp(SIGN 2 pi i / 8)
+    cplx<R> o1 = {h * (o[1].x - R(SIGN) * o[1].y), h * (o[1].y + R(SIGN) * o[1].x)};
+    cplx<R> o2 = mul_si<R, SIGN>(o[2]);
+    cplx<R> o3 = {h * (-o[3].x - R(SIGN) * o[3].y), h * (-o[3].y + R(SIGN) * o[3].x)};
+    v[0] = e[0] + o[0];
+    v[4] = e[0] - o[0];
+    v[1] = e[1] + o1;
+    v[5] = e[1] - o1;
+    v[2] = e[2] + o2;
+    v[6] = e[2] - o2;
+    v[3] = e[3] + o3;
+    v[7] = e[3] - o3;
+  }
+};
+
+// ---------------------------------------------------------------- Stockham stages
+// nrows rows of length L, contiguous (row stride L) in LDS; NT threads.
+// tw[m] = exp(-2 pi i m / L) in LDS; the inverse uses its conjugate.
+template <typename R, int SIGN, int L, int NT, int S, int NS>
+struct Stages {
+  __device__ __forceinline__ static cplx<R>* run(cplx<R>* src, cplx<R>* dst, const cplx<R>* tw,
+                                                 int nrows, int tid) {
+    if constexpr (NS >= L) {
+      return src;
+    } else {
+      constexpr int RAD = radix_at(L, S);
+      constexpr int LR = L / RAD;
+      constexpr int TWSTEP = L / (NS * RAD);
+      const int total = nrows * LR;
+      for (int b = tid; b < total; b += NT) {
+        const int row = b / LR;
+        const int j = b - row * LR;
+        const cplx<R>* in = src + row * L;
+        cplx<R>* out = dst + row * L;
+        const int k = j % NS;
+        cplx<R> v[RAD];
+#pragma unroll
+        for (int q = 0; q < RAD; ++q) v[q] = in[j + q * LR];
+        if constexpr (NS > 1) {
+#pragma unroll
+          for (int q = 1; q < RAD; ++q) {
+            cplx<R> w = tw[q * k * TWSTEP];
+            if constexpr (SIGN > 0) w.y = -w.y;
+            v[q] = cmul(v[q], w);
+          }
+        }
+        Bfly<R, SIGN, RAD>::run(v);
+        const int base = (j / NS) * NS * RAD + k;
+#pragma unroll
+        for (int q = 0; q < RAD; ++q) out[base + q * NS] = v[q];
+      }
+      __syncthreads();
+      return Stages<R, SIGN, L, NT, S + 1, NS * RAD>::run(dst, src, tw, nrows, tid);
+    }
+  }
+};
+
+// In-LDS FFT of nrows contiguous rows of length L; returns the buffer that
+// holds the result (a or b).  Callers __syncthreads() before (data and
+// twiddles in place); the routine ends with a barrier.
+template <typename R, int SIGN, int L, int NT>
+__device__ __forceinline__ cplx<R>* lds_fft(cplx<R>* a, cplx<R>* b, const cplx<R>* tw, int nrows,
+                                            int tid) {
+  return Stages<R, SIGN, L, NT, 0, 1>::run(a, b, tw, nrows, tid);
+}
+
+// Twiddles exp(-2 pi i m / L), m < L, copied from global to LDS.
+template <typename R, int L, int NT>
+__device__ __forceinline__ void load_twiddles(cplx<R>* tw_lds, const cplx<R>* tw_glob, int tid) {
+  for (int m = tid; m < L; m += NT) tw_lds[m] = tw_glob[m];
+}
+
+}  // namespace ofdft

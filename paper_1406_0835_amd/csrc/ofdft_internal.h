@@ -1,0 +1,133 @@
+// Internal context shared by the kernel file and the host API.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/ofdft.h"
+
+namespace ofdft {
+
+// Slots of the per-block partial sums written by the evaluation kernels.
+enum Slot { SL_PHI2 = 0, SL_FS, SL_TS, SL_EXC, SL_EH, SL_EEXT, SL_NV, SL_COUNT };
+// Reduced scalars of one evaluation (double[16] on the device).
+enum Scal {
+  SC_NE = 0, SC_FS, SC_TS, SC_EXC, SC_EH, SC_EEXT, SC_NV, SC_MU, SC_EAZ, SC_EION, SC_FTOT,
+  SC_COUNT = 16
+};
+
+struct GridDesc {
+  int n1, n2, n3, n3h;
+  long long N;    // n1 n2 n3 real points
+  long long NS;   // n3h n1 n2 half-spectrum points (layout [k3][k1][k2])
+  double b[9];    // reciprocal lattice rows b1, b2, b3 (a_i . b_j = 2 pi delta_ij)
+  double volume, dv, inv_n;
+  int tr;         // rows per block in the contiguous-axis pass (divides n2, even)
+  int tc;         // columns per block in the strided pass (divides n2)
+  int rb;         // rows per block in the x2 pass
+};
+
+struct LppParams {
+  int kind;       // 0 Gaussian, 1 Heine-Abarenkov
+  double rc, A, qc;
+};
+
+struct EvalParams {
+  int functional;
+  int xc;
+  double T;           // hartree
+  double alpha_sum;   // sum_I alpha_I (G = 0 remainder of the pseudopotential)
+  double E_ion;
+  double enh_kind, enh_c1, enh_a1;   // enhancement-factor parameters (kind as double)
+};
+
+struct Timing {
+  bool on = false;
+  std::vector<hipEvent_t> events;   // one before each kernel, one at the end
+  std::vector<const char*> names;
+  int used = 0;
+};
+
+}  // namespace ofdft
+
+struct ofdft_ctx {
+  ofdft_options opt{};
+  std::string err;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  bool have_cell = false, have_ions = false, have_T = false, have_phi = false, converged = false;
+
+  // cell and grid
+  double lat[9] = {0};
+  double cell_scale = 1.0;
+  ofdft::GridDesc g{};
+  double T_ha = 0.0;
+
+  // ions
+  int nat = 0;
+  std::vector<double> tau, Z;
+  double Ne = 0.0, alpha_sum = 0.0, E_ion = 0.0;
+  std::vector<double> F_ion;
+
+  // device buffers (R = float or double by precision)
+  size_t rsize = 8;
+  double* phi = nullptr;     // current amplitude
+  double* phi_t = nullptr;   // trial amplitude
+  void* v = nullptr;         // potential at phi (R)
+  void* v_t = nullptr;       // potential at phi_t (R)
+  void* vloc = nullptr;      // local part df/dn + v_xc (R)
+  void* A = nullptr;         // spectra, cplx<R>[NS]
+  void* B[3] = {nullptr, nullptr, nullptr};
+  void* S0 = nullptr;
+  void* D = nullptr;
+  void* Vext = nullptr;
+  void* tw[3] = {nullptr, nullptr, nullptr};   // twiddles per axis, cplx<R>[n_a]
+  double* partials = nullptr;  // [SL_COUNT][max_blocks]
+  int max_blocks = 0;
+  double* scalars = nullptr;   // current point, double[SC_COUNT]
+  double* scalars_t = nullptr; // trial point
+  // minimiser vectors
+  double* d = nullptr;
+  double* gprev = nullptr;
+  double* tn[4] = {nullptr, nullptr, nullptr, nullptr};
+  double* vpart = nullptr;     // vector-reduction partials
+  double* vout = nullptr;      // vector-reduction results
+  double* hbuf = nullptr;      // pinned host mirror for small readbacks
+  // ions on the device
+  double* phase = nullptr;     // [nat][n1 + n2 + n3h] complex doubles
+  double* dZ = nullptr;
+  double* fpart = nullptr;
+  double* dforces = nullptr;
+  int phase_cap = 0;
+
+  ofdft::Timing timing;
+  ofdft_report last{};
+};
+
+namespace ofdft {
+
+// kernels (ofdft_kernels.hip)
+int dev_upload_tables();
+int dev_alloc_grid(ofdft_ctx* c);
+void dev_free_grid(ofdft_ctx* c);
+int dev_alloc_ions(ofdft_ctx* c);
+int dev_structure_factor(ofdft_ctx* c);
+int dev_eval(ofdft_ctx* c, const double* phi, void* v_out, double* scalars_out);
+int dev_forces(ofdft_ctx* c, double* forces_host);
+// vector operations for the minimisers; results land in c->vout (device)
+int dev_grad_dots(ofdft_ctx* c, const double* phi, const void* v, const double* sc, const double* gprev,
+                  const double* d);
+int dev_cg_direction(ofdft_ctx* c, double beta, double cproj);
+int dev_rotate(ofdft_ctx* c, double* dst, const double* phi, double ca, const double* dir, double sb);
+int dev_dtheta(ofdft_ctx* c, const double* phi_t, const void* v_t, const double* sc_t, const double* phi,
+               const double* d, double ms, double mc);
+int dev_full_grad_acc(ofdft_ctx* c, double* out, const double* phi_t, const void* v_t, double sign);
+int dev_dot(ofdft_ctx* c, const double* a, const double* b);
+int dev_axpby(ofdft_ctx* c, double* y, double a, const double* x, double b);
+int dev_tn_hess_finish(ofdft_ctx* c, double* hs, const double* phi, const double* s, double inv2e,
+                       double mu_term);
+int dev_read(ofdft_ctx* c, const double* dptr, int n, double* host);
+int dev_sync(ofdft_ctx* c);
+
+}  // namespace ofdft

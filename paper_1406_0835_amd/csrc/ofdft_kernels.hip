@@ -1,0 +1,1204 @@
+// HIP kernels of the finite-T orbital-free DFT hot path (CDNA4, wave64).
+//
+// One F[n] + gradient evaluation with n = phi^2 (arXiv:1406.0835 Sec. II-IV)
+// is a fixed sequence of fused passes over a real grid [N1][N2][N3] and its
+// transposed half spectrum S[k3][k1][k2] (k3 = 0..N3/2 slowest):
+//
+//   rpass_fwd_density   n = phi^2, real FFT along x3 (two rows per complex
+//                       row), transposed store; sum phi^2
+//   cpass x2            FFT along x2: contiguous rows of the transposed layout
+//   x1_density_*        FFT along x1 on column tiles, then in reciprocal space:
+//                       Hartree (Eq. E2) and pseudopotential energies, the
+//                       potential 4 pi n/G^2 + v_ext(G), and for gradient
+//                       functionals i G_a n(G) (Eq. s_0defn), inverse x1 FFT
+//   cpass x2 (inverse)
+//   rpass_gga_pointwise inverse x3 FFT of grad n, pointwise ftGGA + PZ81
+//                       (Eqs. FGGA..vftGGA), W = 2 df/dsigma grad n, forward
+//                       x3 FFT of W
+//   cpass x2, x1_divergence   S = v_H + v_ext - i G.W(G) (last line of
+//                       Eq. vftGGA in reciprocal space), inverse x1 FFT
+//   cpass x2 (inverse)
+//   rpass_final         inverse x3 FFT, v = df/dn + v_xc + S + alpha, sum n v
+//   reduce_scalars      fixed-order sums of the per-block partials (FP64)
+//
+// Reciprocal-space operators act on the G set without Nyquist components
+// (closed under G -> -G), so the potential is the exact gradient of the
+// discrete energy.  All energy and dot-product sums are FP64 wave-shuffle +
+// LDS block reductions written per block and summed in a fixed order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "ofdft_fd.h"
+#include "ofdft_fft.h"
+#include "ofdft_internal.h"
+
+namespace ofdft {
+
+constexpr int NT = 256;
+constexpr double kFourPi = 12.566370614359172953850573533118;
+
+// ---------------------------------------------------------------- helpers
+struct Smem {
+  char* p;
+  __device__ explicit Smem(char* base) : p(base) {}
+  template <typename T>
+  __device__ T* take(size_t n) {
+    T* r = reinterpret_cast<T*>(p);
+    p += ((n * sizeof(T) + 15) / 16) * 16;
+    return r;
+  }
+};
+
+template <typename T>
+__host__ __device__ constexpr size_t pad16(size_t n) { return ((n * sizeof(T) + 15) / 16) * 16; }
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Block sum of K values; the result is valid in thread 0. red: LDS of K*NT/64 doubles.
+template <int K>
+__device__ __forceinline__ void block_sum(double* v, double* red) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const double s = wave_sum(v[k]);
+    if (lane == 0) red[k * (NT / 64) + w] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double s = 0.0;
+      for (int i = 0; i < NT / 64; ++i) s += red[k * (NT / 64) + i];
+      v[k] = s;
+    }
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ int signed_freq(int k, int n) { return (2 * k <= n) ? k : k - n; }
+
+// Cartesian G of spectrum element (k1, k2, k3) and whether it is kept.
+__device__ __forceinline__ bool gvec(const GridDesc& g, int k1, int k2, int k3, double& gx, double& gy,
+                                     double& gz) {
+  const int m1 = signed_freq(k1, g.n1), m2 = signed_freq(k2, g.n2);
+  const double m3 = k3;
+  gx = m1 * g.b[0] + m2 * g.b[3] + m3 * g.b[6];
+  gy = m1 * g.b[1] + m2 * g.b[4] + m3 * g.b[7];
+  gz = m1 * g.b[2] + m2 * g.b[5] + m3 * g.b[8];
+  return (2 * k1 != g.n1) && (2 * k2 != g.n2) && (2 * k3 != g.n3);
+}
+
+// ---------------------------------------------------------------- contiguous-axis helpers
+// Separate two real rows packed as z = x_a + i x_b (after a forward FFT) into
+// their half spectra and store them transposed: S[k3][i1][i2_0 + r].
+template <typename R, int L>
+__device__ __forceinline__ void store_half_spectra(const cplx<R>* res, cplx<R>* out, const GridDesc& g,
+                                                   int i1, int i2_0, int tr) {
+  constexpr int LH = L / 2 + 1;
+  for (int e = threadIdx.x; e < LH * tr; e += NT) {
+    const int k3 = e / tr, r = e - k3 * tr, p = r >> 1;
+    const cplx<R> z = res[p * L + k3];
+    const cplx<R> zc = cconj(res[p * L + ((L - k3) % L)]);
+    cplx<R> X;
+    if ((r & 1) == 0) {
+      X = {R(0.5) * (z.x + zc.x), R(0.5) * (z.y + zc.y)};
+    } else {
+      X = {R(0.5) * (z.y - zc.y), R(-0.5) * (z.x - zc.x)};
+    }
+    out[((size_t)k3 * g.n1 + i1) * g.n2 + i2_0 + r] = X;
+  }
+}
+
+// Load a transposed half-spectrum tile S[k3][i1][i2_0 + r] (staging in LDS)
+// and build z_p[k] = X_{2p}[k] + i X_{2p+1}[k] over the full k range using
+// Hermitian symmetry.  stage must hold (L/2+1)*tr elements; z holds tr/2 rows.
+template <typename R, int L>
+__device__ __forceinline__ void load_pack_half_spectra(const cplx<R>* in, cplx<R>* stage, cplx<R>* z,
+                                                       const GridDesc& g, int i1, int i2_0, int tr) {
+  constexpr int LH = L / 2 + 1;
+  for (int e = threadIdx.x; e < LH * tr; e += NT) {
+    const int k3 = e / tr, r = e - k3 * tr;
+    stage[e] = in[((size_t)k3 * g.n1 + i1) * g.n2 + i2_0 + r];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < (tr / 2) * L; e += NT) {
+    const int p = e / L, k = e - p * L;
+    cplx<R> xa, xb;
+    if (2 * k <= L) {
+      xa = stage[k * tr + 2 * p];
+      xb = stage[k * tr + 2 * p + 1];
+    } else {
+      xa = cconj(stage[(L - k) * tr + 2 * p]);
+      xb = cconj(stage[(L - k) * tr + 2 * p + 1]);
+    }
+    z[e] = {xa.x - xb.y, xa.y + xb.x};
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------- K1: density, x3 forward
+template <typename R, int L>
+__global__ void __launch_bounds__(NT) k_rpass_fwd_density(const double* __restrict__ phi, cplx<R>* __restrict__ out,
+                                                          const cplx<R>* __restrict__ tw_g, GridDesc g,
+                                                          double* __restrict__ partials, int maxb) {
+  extern __shared__ __align__(16) char smem_raw[];
+  const int tr = g.tr;
+  Smem sm(smem_raw);
+  cplx<R>* za = sm.take<cplx<R>>((tr / 2) * L);
+  cplx<R>* zb = sm.take<cplx<R>>((tr / 2) * L);
+  cplx<R>* tw = sm.take<cplx<R>>(L);
+  double* red = sm.take<double>(NT / 64);
+  const int i1 = blockIdx.y, i2_0 = blockIdx.x * tr;
+  const size_t base = ((size_t)i1 * g.n2 + i2_0) * L;
+  R* zr = reinterpret_cast<R*>(za);
+  double acc = 0.0;
+  for (int e = threadIdx.x; e < tr * L; e += NT) {
+    const int r = e / L, i3 = e - r * L;
+    const double p = phi[base + e];
+    const double n = p * p;
+    acc += n;
+    zr[2 * ((r >> 1) * L + i3) + (r & 1)] = R(n);
+  }
+  for (int m = threadIdx.x; m < L; m += NT) tw[m] = tw_g[m];
+  __syncthreads();
+  const cplx<R>* res = lds_fft<R, -1, L, NT>(za, zb, tw, tr / 2, threadIdx.x);
+  store_half_spectra<R, L>(res, out, g, i1, i2_0, tr);
+  double v[1] = {acc};
+  block_sum<1>(v, red);
+  if (threadIdx.x == 0) partials[SL_PHI2 * maxb + blockIdx.y * gridDim.x + blockIdx.x] = v[0];
+}
+
+// ---------------------------------------------------------------- K2: x2 pass (contiguous rows)
+struct Arr3 {
+  void* p[3];
+};
+
+template <typename R, int L, int SIGN>
+__global__ void __launch_bounds__(NT) k_cpass_x2(Arr3 arrs, const cplx<R>* __restrict__ tw_g, long long nrows,
+                                                 int rb) {
+  extern __shared__ __align__(16) char smem_raw[];
+  Smem sm(smem_raw);
+  cplx<R>* a = sm.take<cplx<R>>(rb * L);
+  cplx<R>* b = sm.take<cplx<R>>(rb * L);
+  cplx<R>* tw = sm.take<cplx<R>>(L);
+  cplx<R>* x = reinterpret_cast<cplx<R>*>(arrs.p[blockIdx.y]);
+  const long long row0 = (long long)blockIdx.x * rb;
+  const int nr = (int)min<long long>(rb, nrows - row0);
+  cplx<R>* base = x + row0 * L;
+  for (int e = threadIdx.x; e < rb * L; e += NT) a[e] = (e < nr * L) ? base[e] : cplx<R>{R(0), R(0)};
+  for (int m = threadIdx.x; m < L; m += NT) tw[m] = tw_g[m];
+  __syncthreads();
+  const cplx<R>* res = lds_fft<R, SIGN, L, NT>(a, b, tw, rb, threadIdx.x);
+  for (int e = threadIdx.x; e < nr * L; e += NT) base[e] = res[e];
+}
+
+// ---------------------------------------------------------------- K3: x1 pass + density ops
+enum { X1_TF = 0, X1_GGA = 1, X1_NHAT = 2 };
+
+template <typename R, int L, int MODE>
+__global__ void __launch_bounds__(NT) k_x1_density(const cplx<R>* __restrict__ A, const cplx<R>* __restrict__ vext,
+                                                   cplx<R>* __restrict__ out0, cplx<R>* __restrict__ out1,
+                                                   cplx<R>* __restrict__ out2, cplx<R>* __restrict__ s0,
+                                                   const cplx<R>* __restrict__ tw_g, GridDesc g,
+                                                   double* __restrict__ partials, int maxb) {
+  extern __shared__ __align__(16) char smem_raw[];
+  const int tc = g.tc;
+  Smem sm(smem_raw);
+  cplx<R>* b0 = sm.take<cplx<R>>(tc * L);
+  cplx<R>* b1 = sm.take<cplx<R>>(tc * L);
+  cplx<R>* b2 = sm.take<cplx<R>>(tc * L);
+  cplx<R>* tw = sm.take<cplx<R>>(L);
+  double* red = sm.take<double>(2 * NT / 64);
+  const int k3 = blockIdx.y, i2_0 = blockIdx.x * tc;
+  const size_t plane = (size_t)k3 * g.n1 * g.n2;
+  for (int e = threadIdx.x; e < L * tc; e += NT) {
+    const int i1 = e / tc, c = e - i1 * tc;
+    b0[c * L + i1] = A[plane + (size_t)i1 * g.n2 + i2_0 + c];
+  }
+  for (int m = threadIdx.x; m < L; m += NT) tw[m] = tw_g[m];
+  __syncthreads();
+  cplx<R>* res = lds_fft<R, -1, L, NT>(b0, b1, tw, tc, threadIdx.x);
+  cplx<R>* fa = (res == b0) ? b1 : b0;   // free buffers
+  cplx<R>* fb = b2;
+  const R inv_n = R(g.inv_n);
+  const double wk = (k3 == 0) ? 1.0 : 2.0;
+  double eh = 0.0, ee = 0.0;
+  for (int e = threadIdx.x; e < L * tc; e += NT) {
+    const int k1 = e / tc, c = e - k1 * tc;
+    const int k2 = i2_0 + c;
+    const int idx = c * L + k1;
+    const size_t gi = plane + (size_t)k1 * g.n2 + k2;
+    double gx, gy, gz;
+    const bool keep = gvec(g, k1, k2, k3, gx, gy, gz);
+    const double G2 = gx * gx + gy * gy + gz * gz;
+    cplx<R> nh = cscale(res[idx], inv_n);
+    cplx<R> S = {R(0), R(0)};
+    if (keep && G2 > 0.0) {
+      const double nx = nh.x, ny = nh.y;
+      const double kern = kFourPi / G2;
+      if constexpr (MODE != X1_NHAT) {
+        const cplx<R> ve = vext[gi];
+        eh += wk * kern * (nx * nx + ny * ny);
+        ee += wk * (nx * double(ve.x) + ny * double(ve.y));
+        S = {R(kern * nx + double(ve.x)), R(kern * ny + double(ve.y))};
+      }
+    }
+    if (!keep) nh = {R(0), R(0)};
+    if constexpr (MODE == X1_TF) {
+      res[idx] = S;
+    } else if constexpr (MODE == X1_GGA) {
+      s0[gi] = S;
+      res[idx] = nh;
+    } else {
+      out0[gi] = nh;
+    }
+  }
+  if constexpr (MODE != X1_NHAT) {
+    double v[2] = {eh, ee};
+    block_sum<2>(v, red);
+    if (threadIdx.x == 0) {
+      const int blk = blockIdx.y * gridDim.x + blockIdx.x;
+      partials[SL_EH * maxb + blk] = v[0];
+      partials[SL_EEXT * maxb + blk] = v[1];
+    }
+  } else {
+    __syncthreads();
+  }
+  if constexpr (MODE == X1_TF) {
+    const cplx<R>* o = lds_fft<R, +1, L, NT>(res, fa, tw, tc, threadIdx.x);
+    for (int e = threadIdx.x; e < L * tc; e += NT) {
+      const int i1 = e / tc, c = e - i1 * tc;
+      out0[plane + (size_t)i1 * g.n2 + i2_0 + c] = o[c * L + i1];
+    }
+  } else if constexpr (MODE == X1_GGA) {
+    cplx<R>* outs[3] = {out0, out1, out2};
+#pragma unroll 1
+    for (int a = 0; a < 3; ++a) {
+      for (int e = threadIdx.x; e < L * tc; e += NT) {
+        const int c = e / L, k1 = e - c * L;
+        double gv[3];
+        gvec(g, k1, i2_0 + c, k3, gv[0], gv[1], gv[2]);
+        const R ga = R(gv[a]);
+        const cplx<R> z = res[e];
+        fa[e] = {-ga * z.y, ga * z.x};
+      }
+      __syncthreads();
+      const cplx<R>* o = lds_fft<R, +1, L, NT>(fa, fb, tw, tc, threadIdx.x);
+      cplx<R>* dst = outs[a];
+      for (int e = threadIdx.x; e < L * tc; e += NT) {
+        const int i1 = e / tc, c = e - i1 * tc;
+        dst[plane + (size_t)i1 * g.n2 + i2_0 + c] = o[c * L + i1];
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------- K4: gradient functional pointwise
+template <typename R, int L>
+__global__ void __launch_bounds__(NT) k_rpass_gga(cplx<R>* __restrict__ B0, cplx<R>* __restrict__ B1,
+                                                  cplx<R>* __restrict__ B2, const double* __restrict__ phi,
+                                                  R* __restrict__ vloc, const cplx<R>* __restrict__ tw_g,
+                                                  GridDesc g, EvalParams ep, double* __restrict__ partials,
+                                                  int maxb) {
+  extern __shared__ __align__(16) char smem_raw[];
+  const int tr = g.tr;
+  constexpr int LH = L / 2 + 1;
+  Smem sm(smem_raw);
+  cplx<R>* za = sm.take<cplx<R>>((tr / 2) * L);
+  cplx<R>* zb = sm.take<cplx<R>>((tr / 2) * L + tr);
+  cplx<R>* tw = sm.take<cplx<R>>(L);
+  R* gr = sm.take<R>(3 * tr * L);
+  double* red = sm.take<double>(3 * NT / 64);
+  (void)LH;
+  const int i1 = blockIdx.y, i2_0 = blockIdx.x * tr;
+  const size_t base = ((size_t)i1 * g.n2 + i2_0) * L;
+  for (int m = threadIdx.x; m < L; m += NT) tw[m] = tw_g[m];
+  cplx<R>* Bs[3] = {B0, B1, B2};
+#pragma unroll 1
+  for (int a = 0; a < 3; ++a) {
+    load_pack_half_spectra<R, L>(Bs[a], zb, za, g, i1, i2_0, tr);
+    const cplx<R>* res = lds_fft<R, +1, L, NT>(za, zb, tw, tr / 2, threadIdx.x);
+    R* ga = gr + a * tr * L;
+    for (int e = threadIdx.x; e < (tr / 2) * L; e += NT) {
+      const int p = e / L, i3 = e - p * L;
+      const cplx<R> z = res[e];
+      ga[(2 * p) * L + i3] = z.x;
+      ga[(2 * p + 1) * L + i3] = z.y;
+    }
+    __syncthreads();
+  }
+  EnhParams enh{(int)ep.enh_kind, ep.enh_c1, ep.enh_a1};
+  double fs = 0.0, ts = 0.0, exc = 0.0;
+  for (int e = threadIdx.x; e < tr * L; e += NT) {
+    const double p = phi[base + e];
+    const double n = p * p;
+    const double nf = n > kDensityFloor ? n : kDensityFloor;
+    const R gx = gr[e], gy = gr[tr * L + e], gz = gr[2 * tr * L + e];
+    const R sigma = gx * gx + gy * gy + gz * gz;
+    double f, tsl;
+    R dfdn, dfds;
+    gga_point<R>(nf, sigma, ep.T, enh, f, dfdn, dfds, tsl);
+    R vl = dfdn;
+    if (ep.xc) {
+      double eps, vxc;
+      pz81<double>(nf, eps, vxc);
+      vl += R(vxc);
+      exc += n * eps;
+    }
+    vloc[base + e] = vl;
+    fs += f;
+    ts += tsl;
+    const R w2 = R(2) * dfds;
+    gr[e] = w2 * gx;
+    gr[tr * L + e] = w2 * gy;
+    gr[2 * tr * L + e] = w2 * gz;
+  }
+  __syncthreads();
+  R* zr = reinterpret_cast<R*>(za);
+#pragma unroll 1
+  for (int a = 0; a < 3; ++a) {
+    const R* wa = gr + a * tr * L;
+    for (int e = threadIdx.x; e < tr * L; e += NT) {
+      const int r = e / L, i3 = e - r * L;
+      zr[2 * ((r >> 1) * L + i3) + (r & 1)] = wa[e];
+    }
+    __syncthreads();
+    const cplx<R>* res = lds_fft<R, -1, L, NT>(za, zb, tw, tr / 2, threadIdx.x);
+    store_half_spectra<R, L>(res, Bs[a], g, i1, i2_0, tr);
+    __syncthreads();
+  }
+  double v[3] = {fs, ts, exc};
+  block_sum<3>(v, red);
+  if (threadIdx.x == 0) {
+    const int blk = blockIdx.y * gridDim.x + blockIdx.x;
+    partials[SL_FS * maxb + blk] = v[0];
+    partials[SL_TS * maxb + blk] = v[1];
+    partials[SL_EXC * maxb + blk] = v[2];
+  }
+}
+
+// ---------------------------------------------------------------- K5: x1 pass + divergence term
+template <typename R, int L>
+__global__ void __launch_bounds__(NT) k_x1_divergence(const cplx<R>* __restrict__ C0, const cplx<R>* __restrict__ C1,
+                                                      const cplx<R>* __restrict__ C2, const cplx<R>* __restrict__ s0,
+                                                      cplx<R>* __restrict__ out, const cplx<R>* __restrict__ tw_g,
+                                                      GridDesc g) {
+  extern __shared__ __align__(16) char smem_raw[];
+  const int tc = g.tc;
+  Smem sm(smem_raw);
+  cplx<R>* acc = sm.take<cplx<R>>(tc * L);
+  cplx<R>* b0 = sm.take<cplx<R>>(tc * L);
+  cplx<R>* b1 = sm.take<cplx<R>>(tc * L);
+  cplx<R>* tw = sm.take<cplx<R>>(L);
+  const int k3 = blockIdx.y, i2_0 = blockIdx.x * tc;
+  const size_t plane = (size_t)k3 * g.n1 * g.n2;
+  for (int e = threadIdx.x; e < L * tc; e += NT) {
+    const int i1 = e / tc, c = e - i1 * tc;
+    acc[c * L + i1] = s0[plane + (size_t)i1 * g.n2 + i2_0 + c];
+  }
+  for (int m = threadIdx.x; m < L; m += NT) tw[m] = tw_g[m];
+  const cplx<R>* Cs[3] = {C0, C1, C2};
+  const R inv_n = R(g.inv_n);
+#pragma unroll 1
+  for (int a = 0; a < 3; ++a) {
+    for (int e = threadIdx.x; e < L * tc; e += NT) {
+      const int i1 = e / tc, c = e - i1 * tc;
+      b0[c * L + i1] = Cs[a][plane + (size_t)i1 * g.n2 + i2_0 + c];
+    }
+    __syncthreads();
+    const cplx<R>* res = lds_fft<R, -1, L, NT>(b0, b1, tw, tc, threadIdx.x);
+    for (int e = threadIdx.x; e < L * tc; e += NT) {
+      const int c = e / L, k1 = e - c * L;
+      double gv[3];
+      const bool keep = gvec(g, k1, i2_0 + c, k3, gv[0], gv[1], gv[2]);
+      if (keep) {
+        const R ga = R(gv[a]) * inv_n;
+        const cplx<R> z = res[e];
+        // acc -= i G_a W_a(G)
+        acc[e].x += ga * z.y;
+        acc[e].y -= ga * z.x;
+      }
+    }
+    __syncthreads();
+  }
+  const cplx<R>* o = lds_fft<R, +1, L, NT>(acc, b0, tw, tc, threadIdx.x);
+  for (int e = threadIdx.x; e < L * tc; e += NT) {
+    const int i1 = e / tc, c = e - i1 * tc;
+    out[plane + (size_t)i1 * g.n2 + i2_0 + c] = o[c * L + i1];
+  }
+}
+
+// ---------------------------------------------------------------- K6: final potential
+template <typename R, int L, bool TF>
+__global__ void __launch_bounds__(NT) k_rpass_final(const cplx<R>* __restrict__ D, const double* __restrict__ phi,
+                                                    const R* __restrict__ vloc, R* __restrict__ vout,
+                                                    const cplx<R>* __restrict__ tw_g, GridDesc g, EvalParams ep,
+                                                    double* __restrict__ partials, int maxb) {
+  extern __shared__ __align__(16) char smem_raw[];
+  const int tr = g.tr;
+  Smem sm(smem_raw);
+  cplx<R>* za = sm.take<cplx<R>>((tr / 2) * L);
+  cplx<R>* zb = sm.take<cplx<R>>((tr / 2) * L + tr);
+  cplx<R>* tw = sm.take<cplx<R>>(L);
+  double* red = sm.take<double>(4 * NT / 64);
+  const int i1 = blockIdx.y, i2_0 = blockIdx.x * tr;
+  const size_t base = ((size_t)i1 * g.n2 + i2_0) * L;
+  for (int m = threadIdx.x; m < L; m += NT) tw[m] = tw_g[m];
+  load_pack_half_spectra<R, L>(D, zb, za, g, i1, i2_0, tr);
+  const cplx<R>* res = lds_fft<R, +1, L, NT>(za, zb, tw, tr / 2, threadIdx.x);
+  double fs = 0.0, ts = 0.0, exc = 0.0, nv = 0.0;
+  for (int e = threadIdx.x; e < tr * L; e += NT) {
+    const int r = e / L, i3 = e - r * L;
+    const cplx<R> z = res[(r >> 1) * L + i3];
+    const double S = (r & 1) ? double(z.y) : double(z.x);
+    const double p = phi[base + e];
+    const double n = p * p;
+    double vl;
+    if constexpr (TF) {
+      const double nf = n > kDensityFloor ? n : kDensityFloor;
+      double f, vt, tsl;
+      tf_point(nf, ep.T, f, vt, tsl);
+      vl = vt;
+      fs += f;
+      ts += tsl;
+      if (ep.xc) {
+        double eps, vxc;
+        pz81<double>(nf, eps, vxc);
+        vl += vxc;
+        exc += n * eps;
+      }
+    } else {
+      vl = double(vloc[base + e]);
+    }
+    const R vv = R(vl + S + ep.alpha_sum);
+    vout[base + e] = vv;
+    nv += n * double(vv);
+  }
+  if constexpr (TF) {
+    double v[4] = {fs, ts, exc, nv};
+    block_sum<4>(v, red);
+    if (threadIdx.x == 0) {
+      const int blk = blockIdx.y * gridDim.x + blockIdx.x;
+      partials[SL_FS * maxb + blk] = v[0];
+      partials[SL_TS * maxb + blk] = v[1];
+      partials[SL_EXC * maxb + blk] = v[2];
+      partials[SL_NV * maxb + blk] = v[3];
+    }
+  } else {
+    double v[1] = {nv};
+    block_sum<1>(v, red);
+    if (threadIdx.x == 0) partials[SL_NV * maxb + blockIdx.y * gridDim.x + blockIdx.x] = v[0];
+  }
+}
+
+// ---------------------------------------------------------------- K7: scalar reduction
+struct ReduceParams {
+  int nb_r, nb_x1;   // partial counts of the row-pass and x1-pass kernels
+  double dv, volume, alpha_sum, E_ion;
+};
+
+__global__ void __launch_bounds__(NT) k_reduce_scalars(const double* __restrict__ partials, int maxb,
+                                                       ReduceParams rp, double* __restrict__ sc) {
+  __shared__ double red[NT / 64];
+  __shared__ double raw[SL_COUNT];
+  for (int s = 0; s < SL_COUNT; ++s) {
+    const int cnt = (s == SL_EH || s == SL_EEXT) ? rp.nb_x1 : rp.nb_r;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < cnt; i += NT) acc += partials[s * maxb + i];
+    double v[1] = {acc};
+    block_sum<1>(v, red);
+    if (threadIdx.x == 0) raw[s] = v[0];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double Ne = rp.dv * raw[SL_PHI2];
+    sc[SC_NE] = Ne;
+    sc[SC_FS] = rp.dv * raw[SL_FS];
+    sc[SC_TS] = rp.dv * raw[SL_TS];
+    sc[SC_EXC] = rp.dv * raw[SL_EXC];
+    sc[SC_EH] = 0.5 * rp.volume * raw[SL_EH];
+    sc[SC_EEXT] = rp.volume * raw[SL_EEXT];
+    sc[SC_NV] = rp.dv * raw[SL_NV];
+    sc[SC_MU] = raw[SL_NV] / raw[SL_PHI2];
+    sc[SC_EAZ] = Ne * rp.alpha_sum;
+    sc[SC_EION] = rp.E_ion;
+    sc[SC_FTOT] = sc[SC_FS] + sc[SC_EXC] + sc[SC_EH] + sc[SC_EEXT] + sc[SC_EAZ] + rp.E_ion;
+    for (int k = SC_FTOT + 1; k < SC_COUNT; ++k) sc[k] = 0.0;
+  }
+}
+
+// ---------------------------------------------------------------- vector reductions
+constexpr int VEC_BLOCKS = 512;
+
+template <int K, class Op>
+__global__ void __launch_bounds__(NT) k_vec(long long n, Op op, double* __restrict__ part) {
+  __shared__ double red[(K > 0 ? K : 1) * NT / 64];
+  double acc[K > 0 ? K : 1];
+#pragma unroll
+  for (int k = 0; k < (K > 0 ? K : 1); ++k) acc[k] = 0.0;
+  for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT) op(i, acc);
+  if constexpr (K > 0) {
+    block_sum<K>(acc, red);
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) part[k * gridDim.x + blockIdx.x] = acc[k];
+    }
+  }
+}
+
+template <int K>
+__global__ void __launch_bounds__(NT) k_vec_final(const double* __restrict__ part, int nb, double* __restrict__ out) {
+  __shared__ double red[NT / 64];
+  for (int k = 0; k < K; ++k) {
+    double a = 0.0;
+    for (int i = threadIdx.x; i < nb; i += NT) a += part[k * nb + i];
+    double v[1] = {a};
+    block_sum<1>(v, red);
+    if (threadIdx.x == 0) out[k] = v[0];
+  }
+}
+
+// g = 2 dv phi (v - mu): dots g.g, g.gprev, g.d and sum n (v - mu)^2
+template <typename R>
+struct OpGradDots {
+  const double* phi; const R* v; const double* sc; const double* gprev; const double* d; double two_dv;
+  __device__ void operator()(long long i, double* acc) const {
+    const double mu = sc[SC_MU];
+    const double p = phi[i];
+    const double dvm = double(v[i]) - mu;
+    const double gi = two_dv * p * dvm;
+    acc[0] += gi * gi;
+    acc[1] += gprev ? gi * gprev[i] : 0.0;
+    acc[2] += d ? gi * d[i] : 0.0;
+    acc[3] += p * p * dvm * dvm;
+  }
+};
+
+// d = -g + beta (d - c phi); gprev = g; dots d.d and d.g
+template <typename R>
+struct OpDirection {
+  const double* phi; const R* v; const double* sc; double* gprev; double* d; double two_dv, beta, cproj;
+  __device__ void operator()(long long i, double* acc) const {
+    const double p = phi[i];
+    const double gi = two_dv * p * (double(v[i]) - sc[SC_MU]);
+    const double di = -gi + beta * (d[i] - cproj * p);
+    d[i] = di;
+    gprev[i] = gi;
+    acc[0] += di * di;
+    acc[1] += di * gi;
+  }
+};
+
+struct OpRotate {
+  double* dst; const double* phi; const double* dir; double ca, sb;
+  __device__ void operator()(long long i, double*) const { dst[i] = ca * phi[i] + sb * dir[i]; }
+};
+
+// dF/dtheta = g_t . (ms phi + mc d)
+template <typename R>
+struct OpDtheta {
+  const double* phi_t; const R* v_t; const double* sc_t; const double* phi; const double* d;
+  double two_dv, ms, mc;
+  __device__ void operator()(long long i, double* acc) const {
+    const double gt = two_dv * phi_t[i] * (double(v_t[i]) - sc_t[SC_MU]);
+    acc[0] += gt * (ms * phi[i] + mc * d[i]);
+  }
+};
+
+// out += sign * 2 dv phi_t v_t  (unconstrained gradient)
+template <typename R>
+struct OpFullGradAcc {
+  double* out; const double* phi_t; const R* v_t; double two_dv, sign; int init;
+  __device__ void operator()(long long i, double*) const {
+    const double gfull = sign * two_dv * phi_t[i] * double(v_t[i]);
+    out[i] = init ? gfull : out[i] + gfull;
+  }
+};
+
+struct OpDot {
+  const double* a; const double* b;
+  __device__ void operator()(long long i, double* acc) const { acc[0] += a[i] * b[i]; }
+};
+
+struct OpAxpby {
+  double* y; const double* x; double a, b;
+  __device__ void operator()(long long i, double*) const { y[i] = (a == 0.0 ? 0.0 : a * y[i]) + b * x[i]; }
+};
+
+// hs = hs * inv2e - c phi - mu_term s, with c chosen later; first pass: hs *= inv2e; dot hs.phi
+struct OpHessScale {
+  double* hs; const double* phi; double inv2e;
+  __device__ void operator()(long long i, double* acc) const {
+    const double h = hs[i] * inv2e;
+    hs[i] = h;
+    acc[0] += h * phi[i];
+  }
+};
+
+// ---------------------------------------------------------------- ions: phase tables, structure factor, forces
+__global__ void __launch_bounds__(NT) k_phase_tables(int nat, const double* __restrict__ frac, GridDesc g,
+                                                     double2* __restrict__ tab) {
+  const int M = g.n1 + g.n2 + g.n3h;
+  const long long total = (long long)nat * M;
+  for (long long idx = (long long)blockIdx.x * NT + threadIdx.x; idx < total; idx += (long long)gridDim.x * NT) {
+    const int I = (int)(idx / M), j = (int)(idx - (long long)I * M);
+    int axis, m;
+    if (j < g.n1) { axis = 0; m = signed_freq(j, g.n1); }
+    else if (j < g.n1 + g.n2) { axis = 1; m = signed_freq(j - g.n1, g.n2); }
+    else { axis = 2; m = j - g.n1 - g.n2; }
+    double s, c;
+    sincospi(-2.0 * m * frac[3 * I + axis], &s, &c);
+    tab[idx] = make_double2(c, s);
+  }
+}
+
+__device__ __forceinline__ double2 zmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// form factor v_I(q) = Z_I a(q) + b(q) of the local pseudopotential (q > 0)
+__device__ __forceinline__ void form_ab(const LppParams& lp, double q, double volume, double& a, double& b) {
+  const double pre = -kFourPi / (volume * q * q);
+  if (lp.kind == 0) {
+    a = pre * exp(-0.25 * q * q * lp.rc * lp.rc);
+    b = 0.0;
+  } else {
+    double s, c;
+    sincos(q * lp.rc, &s, &c);
+    const double x = q / lp.qc;
+    const double x2 = x * x;
+    const double f = exp(-x2 * x2 * x2);
+    a = pre * c * f;
+    b = pre * (-lp.A * lp.rc * c + lp.A / q * s) * f;
+  }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(NT) k_structure_factor(int nat, const double* __restrict__ Z,
+                                                         const double2* __restrict__ tab, GridDesc g, LppParams lp,
+                                                         cplx<R>* __restrict__ vext) {
+  const int M = g.n1 + g.n2 + g.n3h;
+  const long long plane = (long long)g.n1 * g.n2;
+  for (long long gi = (long long)blockIdx.x * NT + threadIdx.x; gi < g.NS; gi += (long long)gridDim.x * NT) {
+    const int k3 = (int)(gi / plane);
+    const long long rem = gi - k3 * plane;
+    const int k1 = (int)(rem / g.n2), k2 = (int)(rem - (long long)k1 * g.n2);
+    double gx, gy, gz;
+    const bool keep = gvec(g, k1, k2, k3, gx, gy, gz);
+    const double G2 = gx * gx + gy * gy + gz * gz;
+    double2 out = make_double2(0.0, 0.0);
+    if (keep && G2 > 0.0) {
+      double a, b;
+      form_ab(lp, sqrt(G2), g.volume, a, b);
+      double2 sz = make_double2(0.0, 0.0), s1 = make_double2(0.0, 0.0);
+      for (int I = 0; I < nat; ++I) {
+        const double2* t = tab + (size_t)I * M;
+        const double2 e = zmul(zmul(t[k1], t[g.n1 + k2]), t[g.n1 + g.n2 + k3]);
+        sz.x += Z[I] * e.x;
+        sz.y += Z[I] * e.y;
+        s1.x += e.x;
+        s1.y += e.y;
+      }
+      out = make_double2(a * sz.x + b * s1.x, a * sz.y + b * s1.y);
+    }
+    vext[gi] = cplx<R>{R(out.x), R(out.y)};
+  }
+}
+
+constexpr int FORCE_IONS = 8;
+
+// F_I partial sums: sum_G w G Im[conj(n(G)) e^{-iG.R_I}] (Z_I a + b)
+template <typename R>
+__global__ void __launch_bounds__(NT) k_forces(int nat, const double* __restrict__ Z, const double2* __restrict__ tab,
+                                               const cplx<R>* __restrict__ nhat, GridDesc g, LppParams lp,
+                                               double* __restrict__ part) {
+  __shared__ double red[3 * FORCE_IONS * NT / 64];
+  const int M = g.n1 + g.n2 + g.n3h;
+  const long long plane = (long long)g.n1 * g.n2;
+  const int I0 = blockIdx.y * FORCE_IONS;
+  double acc[3 * FORCE_IONS];
+#pragma unroll
+  for (int k = 0; k < 3 * FORCE_IONS; ++k) acc[k] = 0.0;
+  for (long long gi = (long long)blockIdx.x * NT + threadIdx.x; gi < g.NS; gi += (long long)gridDim.x * NT) {
+    const int k3 = (int)(gi / plane);
+    const long long rem = gi - k3 * plane;
+    const int k1 = (int)(rem / g.n2), k2 = (int)(rem - (long long)k1 * g.n2);
+    double gx, gy, gz;
+    const bool keep = gvec(g, k1, k2, k3, gx, gy, gz);
+    const double G2 = gx * gx + gy * gy + gz * gz;
+    if (!keep || G2 == 0.0) continue;
+    double a, b;
+    form_ab(lp, sqrt(G2), g.volume, a, b);
+    const double wk = (k3 == 0) ? 1.0 : 2.0;
+    const cplx<R> nh = nhat[gi];
+    const double cx = wk * double(nh.x), cy = -wk * double(nh.y);   // w conj(n)
+#pragma unroll
+    for (int j = 0; j < FORCE_IONS; ++j) {
+      const int I = I0 + j;
+      if (I < nat) {
+        const double2* t = tab + (size_t)I * M;
+        const double2 e = zmul(zmul(t[k1], t[g.n1 + k2]), t[g.n1 + g.n2 + k3]);
+        const double im = (cx * e.y + cy * e.x) * (Z[I] * a + b);
+        acc[3 * j + 0] += gx * im;
+        acc[3 * j + 1] += gy * im;
+        acc[3 * j + 2] += gz * im;
+      }
+    }
+  }
+  block_sum<3 * FORCE_IONS>(acc, red);
+  if (threadIdx.x == 0) {
+    for (int j = 0; j < FORCE_IONS; ++j) {
+      const int I = I0 + j;
+      if (I < nat)
+        for (int c = 0; c < 3; ++c) part[((size_t)I * 3 + c) * gridDim.x + blockIdx.x] = acc[3 * j + c];
+    }
+  }
+}
+
+__global__ void __launch_bounds__(NT) k_forces_final(int nat, const double* __restrict__ part, int nb, double scale,
+                                                     double* __restrict__ out) {
+  const int k = blockIdx.x * NT + threadIdx.x;
+  if (k >= 3 * nat) return;
+  double s = 0.0;
+  for (int i = 0; i < nb; ++i) s += part[(size_t)k * nb + i];
+  out[k] = scale * s;
+}
+
+// ---------------------------------------------------------------- host side
+#define OFDFT_LENGTHS(X) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(256)
+
+static inline bool hip_ok(ofdft_ctx* c, hipError_t e, const char* what) {
+  if (e == hipSuccess) return true;
+  c->err = std::string(what) + ": " + hipGetErrorString(e);
+  return false;
+}
+
+int dev_upload_tables() {
+  static bool done = false;
+  if (done) return OFDFT_OK;
+  if (hipMemcpyToSymbol(HIP_SYMBOL(c_fd_cheb), kFdCheb, sizeof(kFdCheb)) != hipSuccess) return OFDFT_E_DEVICE;
+  if (hipMemcpyToSymbol(HIP_SYMBOL(c_guess_cheb), kGuessCheb, sizeof(kGuessCheb)) != hipSuccess)
+    return OFDFT_E_DEVICE;
+  done = true;
+  return OFDFT_OK;
+}
+
+template <typename R>
+static size_t lds_rpass_fwd(int L, int tr) {
+  return 2 * pad16<cplx<R>>((tr / 2) * L) + pad16<cplx<R>>(L) + pad16<double>(NT / 64);
+}
+template <typename R>
+static size_t lds_rpass_inv(int L, int tr, int extra_real, int nred) {
+  return pad16<cplx<R>>((tr / 2) * L) + pad16<cplx<R>>((tr / 2) * L + tr) + pad16<cplx<R>>(L) +
+         pad16<R>((size_t)extra_real * tr * L) + pad16<double>((size_t)nred * NT / 64);
+}
+template <typename R>
+static size_t lds_x1(int L, int tc, int nred) {
+  return 3 * pad16<cplx<R>>((size_t)tc * L) + pad16<cplx<R>>(L) + pad16<double>((size_t)nred * NT / 64);
+}
+template <typename R>
+static size_t lds_x2(int L, int rb) {
+  return 2 * pad16<cplx<R>>((size_t)rb * L) + pad16<cplx<R>>(L);
+}
+
+// Timing hook: record an event before each launch when enabled.
+static inline void tmark(ofdft_ctx* c, const char* name) {
+  if (!c->timing.on) return;
+  Timing& t = c->timing;
+  if (t.used >= (int)t.events.size()) return;
+  if (t.used < (int)t.names.size()) t.names[t.used] = name;
+  else t.names.push_back(name);
+  (void)hipEventRecord(t.events[t.used++], c->stream);
+}
+
+template <typename R>
+static void set_lds_limits() {
+  // allow large dynamic LDS (gfx950: 160 KB per workgroup)
+}
+
+template <typename R, int L>
+static void launch_rpass_fwd(ofdft_ctx* c, const double* phi, void* out) {
+  const GridDesc& g = c->g;
+  dim3 grid(g.n2 / g.tr, g.n1);
+  hipLaunchKernelGGL((k_rpass_fwd_density<R, L>), grid, dim3(NT), lds_rpass_fwd<R>(L, g.tr), c->stream, phi,
+                     (cplx<R>*)out, (const cplx<R>*)c->tw[2], g, c->partials, c->max_blocks);
+}
+
+template <typename R, int L, int SIGN>
+static void launch_x2(ofdft_ctx* c, void* a0, void* a1, void* a2, int narr) {
+  const GridDesc& g = c->g;
+  const long long nrows = (long long)g.n3h * g.n1;
+  dim3 grid((unsigned)((nrows + g.rb - 1) / g.rb), narr);
+  Arr3 arr{{a0, a1, a2}};
+  hipLaunchKernelGGL((k_cpass_x2<R, L, SIGN>), grid, dim3(NT), lds_x2<R>(L, g.rb), c->stream, arr,
+                     (const cplx<R>*)c->tw[1], nrows, g.rb);
+}
+
+template <typename R, int L, int MODE>
+static void launch_x1_density(ofdft_ctx* c, void* out0, void* out1, void* out2) {
+  const GridDesc& g = c->g;
+  dim3 grid(g.n2 / g.tc, g.n3h);
+  hipLaunchKernelGGL((k_x1_density<R, L, MODE>), grid, dim3(NT), lds_x1<R>(L, g.tc, 2), c->stream,
+                     (const cplx<R>*)c->A, (const cplx<R>*)c->Vext, (cplx<R>*)out0, (cplx<R>*)out1,
+                     (cplx<R>*)out2, (cplx<R>*)c->S0, (const cplx<R>*)c->tw[0], g, c->partials, c->max_blocks);
+}
+
+template <typename R, int L>
+static void launch_rpass_gga(ofdft_ctx* c, const double* phi, const EvalParams& ep) {
+  const GridDesc& g = c->g;
+  dim3 grid(g.n2 / g.tr, g.n1);
+  hipLaunchKernelGGL((k_rpass_gga<R, L>), grid, dim3(NT), lds_rpass_inv<R>(L, g.tr, 3, 3), c->stream,
+                     (cplx<R>*)c->B[0], (cplx<R>*)c->B[1], (cplx<R>*)c->B[2], phi, (R*)c->vloc,
+                     (const cplx<R>*)c->tw[2], g, ep, c->partials, c->max_blocks);
+}
+
+template <typename R, int L>
+static void launch_x1_div(ofdft_ctx* c) {
+  const GridDesc& g = c->g;
+  dim3 grid(g.n2 / g.tc, g.n3h);
+  hipLaunchKernelGGL((k_x1_divergence<R, L>), grid, dim3(NT), lds_x1<R>(L, g.tc, 0), c->stream,
+                     (const cplx<R>*)c->B[0], (const cplx<R>*)c->B[1], (const cplx<R>*)c->B[2],
+                     (const cplx<R>*)c->S0, (cplx<R>*)c->D, (const cplx<R>*)c->tw[0], g);
+}
+
+template <typename R, int L, bool TF>
+static void launch_rpass_final(ofdft_ctx* c, const double* phi, void* v_out, const EvalParams& ep) {
+  const GridDesc& g = c->g;
+  dim3 grid(g.n2 / g.tr, g.n1);
+  hipLaunchKernelGGL((k_rpass_final<R, L, TF>), grid, dim3(NT), lds_rpass_inv<R>(L, g.tr, 0, 4), c->stream,
+                     (const cplx<R>*)c->D, phi, (const R*)c->vloc, (R*)v_out, (const cplx<R>*)c->tw[2], g, ep,
+                     c->partials, c->max_blocks);
+}
+
+// Dispatch on a runtime length.
+#define OFDFT_DISPATCH(LEN, CALL)                        \
+  switch (LEN) {                                         \
+    case 8: { constexpr int L_ = 8; CALL; } break;       \
+    case 12: { constexpr int L_ = 12; CALL; } break;     \
+    case 16: { constexpr int L_ = 16; CALL; } break;     \
+    case 24: { constexpr int L_ = 24; CALL; } break;     \
+    case 32: { constexpr int L_ = 32; CALL; } break;     \
+    case 48: { constexpr int L_ = 48; CALL; } break;     \
+    case 64: { constexpr int L_ = 64; CALL; } break;     \
+    case 96: { constexpr int L_ = 96; CALL; } break;     \
+    case 128: { constexpr int L_ = 128; CALL; } break;   \
+    case 256: { constexpr int L_ = 256; CALL; } break;   \
+    default: return OFDFT_E_GRID;                        \
+  }
+
+static EvalParams make_params(ofdft_ctx* c) {
+  EvalParams ep{};
+  ep.functional = c->opt.functional;
+  ep.xc = c->opt.xc == OFDFT_XC_PZ81 ? 1 : 0;
+  ep.T = c->T_ha;
+  ep.alpha_sum = c->alpha_sum;
+  ep.E_ion = c->E_ion;
+  switch (c->opt.functional) {
+    case OFDFT_SGA: ep.enh_kind = 0; ep.enh_c1 = c->opt.mu_sga; break;
+    case OFDFT_VWTF: ep.enh_kind = 0; ep.enh_c1 = 5.0 / 3.0; break;
+    case OFDFT_VT84F: ep.enh_kind = 2; break;
+    case OFDFT_KST2: ep.enh_kind = 1; ep.enh_c1 = 2.03087; ep.enh_a1 = 0.29424; break;
+    case OFDFT_TW: ep.enh_kind = 1; ep.enh_c1 = 0.2319; ep.enh_a1 = 0.2748; break;
+    case OFDFT_APBEF: ep.enh_kind = 1; ep.enh_c1 = 0.23889; ep.enh_a1 = 0.23889 / 0.804; break;
+    default: break;
+  }
+  return ep;
+}
+
+template <typename R>
+static int eval_impl(ofdft_ctx* c, const double* phi, void* v_out, double* sc) {
+  const GridDesc& g = c->g;
+  const EvalParams ep = make_params(c);
+  const bool tf = c->opt.functional == OFDFT_TF;
+  tmark(c, "rpass_fwd_density");
+  OFDFT_DISPATCH(g.n3, (launch_rpass_fwd<R, L_>(c, phi, c->A)));
+  tmark(c, "cpass_x2_fwd");
+  OFDFT_DISPATCH(g.n2, (launch_x2<R, L_, -1>(c, c->A, nullptr, nullptr, 1)));
+  if (tf) {
+    tmark(c, "x1_density_hartree");
+    OFDFT_DISPATCH(g.n1, (launch_x1_density<R, L_, X1_TF>(c, c->D, nullptr, nullptr)));
+  } else {
+    tmark(c, "x1_density_gradient");
+    OFDFT_DISPATCH(g.n1, (launch_x1_density<R, L_, X1_GGA>(c, c->B[0], c->B[1], c->B[2])));
+    tmark(c, "cpass_x2_inv3");
+    OFDFT_DISPATCH(g.n2, (launch_x2<R, L_, +1>(c, c->B[0], c->B[1], c->B[2], 3)));
+    tmark(c, "rpass_gga_pointwise");
+    OFDFT_DISPATCH(g.n3, (launch_rpass_gga<R, L_>(c, phi, ep)));
+    tmark(c, "cpass_x2_fwd3");
+    OFDFT_DISPATCH(g.n2, (launch_x2<R, L_, -1>(c, c->B[0], c->B[1], c->B[2], 3)));
+    tmark(c, "x1_divergence");
+    OFDFT_DISPATCH(g.n1, (launch_x1_div<R, L_>(c)));
+  }
+  tmark(c, "cpass_x2_inv");
+  OFDFT_DISPATCH(g.n2, (launch_x2<R, L_, +1>(c, c->D, nullptr, nullptr, 1)));
+  if (tf) {
+    tmark(c, "rpass_tf_final");
+    OFDFT_DISPATCH(g.n3, (launch_rpass_final<R, L_, true>(c, phi, v_out, ep)));
+  } else {
+    tmark(c, "rpass_final");
+    OFDFT_DISPATCH(g.n3, (launch_rpass_final<R, L_, false>(c, phi, v_out, ep)));
+  }
+  ReduceParams rp{(g.n2 / g.tr) * g.n1, (g.n2 / g.tc) * g.n3h, g.dv, g.volume, c->alpha_sum, c->E_ion};
+  tmark(c, "reduce_scalars");
+  hipLaunchKernelGGL(k_reduce_scalars, dim3(1), dim3(NT), 0, c->stream, c->partials, c->max_blocks, rp, sc);
+  tmark(c, "end");
+  hipError_t e = hipGetLastError();
+  return hip_ok(c, e, "eval launch") ? OFDFT_OK : OFDFT_E_DEVICE;
+}
+
+int dev_eval(ofdft_ctx* c, const double* phi, void* v_out, double* sc) {
+  return c->rsize == 4 ? eval_impl<float>(c, phi, v_out, sc) : eval_impl<double>(c, phi, v_out, sc);
+}
+
+// ---------------------------------------------------------------- allocation
+template <typename T>
+static bool dalloc(ofdft_ctx* c, T** p, size_t n) {
+  *p = nullptr;
+  if (n == 0) n = 1;
+  return hip_ok(c, hipMalloc((void**)p, n * sizeof(T)), "hipMalloc");
+}
+static bool dalloc_bytes(ofdft_ctx* c, void** p, size_t bytes) {
+  *p = nullptr;
+  return hip_ok(c, hipMalloc(p, bytes ? bytes : 1), "hipMalloc");
+}
+
+template <typename R>
+static bool upload_twiddles(ofdft_ctx* c) {
+  const int ns[3] = {c->g.n1, c->g.n2, c->g.n3};
+  for (int a = 0; a < 3; ++a) {
+    std::vector<cplx<R>> h(ns[a]);
+    for (int m = 0; m < ns[a]; ++m) {
+      const long double ang = -2.0L * 3.141592653589793238462643383279502884L * m / ns[a];
+      h[m] = cplx<R>{R(cosl(ang)), R(sinl(ang))};
+    }
+    if (!dalloc_bytes(c, &c->tw[a], ns[a] * sizeof(cplx<R>))) return false;
+    if (!hip_ok(c, hipMemcpy(c->tw[a], h.data(), ns[a] * sizeof(cplx<R>), hipMemcpyHostToDevice), "twiddles"))
+      return false;
+  }
+  return true;
+}
+
+template <typename R>
+static void configure_lds() {
+  // Opt every kernel into the large CDNA4 LDS.
+  auto allow = [](const void* f) { (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024); };
+#define OFDFT_ALLOW(LEN)                                                             \
+  allow((const void*)k_rpass_fwd_density<R, LEN>);                                   \
+  allow((const void*)k_cpass_x2<R, LEN, -1>);                                        \
+  allow((const void*)k_cpass_x2<R, LEN, +1>);                                        \
+  allow((const void*)k_x1_density<R, LEN, X1_TF>);                                   \
+  allow((const void*)k_x1_density<R, LEN, X1_GGA>);                                  \
+  allow((const void*)k_x1_density<R, LEN, X1_NHAT>);                                 \
+  allow((const void*)k_rpass_gga<R, LEN>);                                           \
+  allow((const void*)k_x1_divergence<R, LEN>);                                       \
+  allow((const void*)k_rpass_final<R, LEN, true>);                                   \
+  allow((const void*)k_rpass_final<R, LEN, false>);
+  OFDFT_LENGTHS(OFDFT_ALLOW)
+#undef OFDFT_ALLOW
+}
+
+int dev_alloc_grid(ofdft_ctx* c) {
+  dev_free_grid(c);
+  const GridDesc& g = c->g;
+  const size_t rs = c->rsize;
+  const size_t N = g.N, NS = g.NS;
+  bool ok = dalloc(c, &c->phi, N) && dalloc(c, &c->phi_t, N) && dalloc(c, &c->d, N) && dalloc(c, &c->gprev, N);
+  for (int k = 0; k < 4 && ok; ++k) ok = dalloc(c, &c->tn[k], N);
+  ok = ok && dalloc_bytes(c, &c->v, N * rs) && dalloc_bytes(c, &c->v_t, N * rs) && dalloc_bytes(c, &c->vloc, N * rs);
+  ok = ok && dalloc_bytes(c, &c->A, NS * 2 * rs) && dalloc_bytes(c, &c->S0, NS * 2 * rs) &&
+       dalloc_bytes(c, &c->D, NS * 2 * rs) && dalloc_bytes(c, &c->Vext, NS * 2 * rs);
+  for (int k = 0; k < 3 && ok; ++k) ok = dalloc_bytes(c, &c->B[k], NS * 2 * rs);
+  const int nb_r = (g.n2 / g.tr) * g.n1, nb_x1 = (g.n2 / g.tc) * g.n3h;
+  c->max_blocks = nb_r > nb_x1 ? nb_r : nb_x1;
+  ok = ok && dalloc(c, &c->partials, (size_t)SL_COUNT * c->max_blocks) && dalloc(c, &c->scalars, SC_COUNT) &&
+       dalloc(c, &c->scalars_t, SC_COUNT) && dalloc(c, &c->vpart, 8 * VEC_BLOCKS) && dalloc(c, &c->vout, 16);
+  if (ok && !c->hbuf) ok = hip_ok(c, hipHostMalloc((void**)&c->hbuf, 64 * sizeof(double)), "hipHostMalloc");
+  ok = ok && (rs == 4 ? upload_twiddles<float>(c) : upload_twiddles<double>(c));
+  if (ok) {
+    static bool lds_f = false, lds_d = false;
+    if (rs == 4 && !lds_f) { configure_lds<float>(); lds_f = true; }
+    if (rs == 8 && !lds_d) { configure_lds<double>(); lds_d = true; }
+    ok = hip_ok(c, hipMemsetAsync(c->Vext, 0, NS * 2 * rs, c->stream), "memset");
+  }
+  if (!ok) {
+    dev_free_grid(c);
+    return OFDFT_E_DEVICE;
+  }
+  return OFDFT_OK;
+}
+
+void dev_free_grid(ofdft_ctx* c) {
+  void** ps[] = {(void**)&c->phi, (void**)&c->phi_t, (void**)&c->d, (void**)&c->gprev, (void**)&c->tn[0],
+                 (void**)&c->tn[1], (void**)&c->tn[2], (void**)&c->tn[3], &c->v, &c->v_t, &c->vloc, &c->A,
+                 &c->S0, &c->D, &c->Vext, &c->B[0], &c->B[1], &c->B[2], &c->tw[0], &c->tw[1], &c->tw[2],
+                 (void**)&c->partials, (void**)&c->scalars, (void**)&c->scalars_t, (void**)&c->vpart,
+                 (void**)&c->vout};
+  for (void** p : ps) {
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+  }
+}
+
+int dev_alloc_ions(ofdft_ctx* c) {
+  const int M = c->g.n1 + c->g.n2 + c->g.n3h;
+  if (c->phase_cap < c->nat * M) {
+    if (c->phase) (void)hipFree(c->phase);
+    if (c->dZ) (void)hipFree(c->dZ);
+    if (c->fpart) (void)hipFree(c->fpart);
+    if (c->dforces) (void)hipFree(c->dforces);
+    c->phase = nullptr; c->dZ = nullptr; c->fpart = nullptr; c->dforces = nullptr;
+    const int cap = c->nat * M;
+    bool ok = dalloc(c, &c->phase, 2 * (size_t)cap) && dalloc(c, &c->dZ, c->nat + 4 * (size_t)c->nat) &&
+              dalloc(c, &c->fpart, (size_t)3 * c->nat * 1024) && dalloc(c, &c->dforces, 3 * (size_t)c->nat);
+    if (!ok) return OFDFT_E_DEVICE;
+    c->phase_cap = cap;
+  }
+  return OFDFT_OK;
+}
+
+static LppParams lpp_of(const ofdft_ctx* c) {
+  return LppParams{c->opt.lpp == OFDFT_LPP_HA ? 1 : 0, c->opt.lpp_rc, c->opt.lpp_A, c->opt.lpp_qc};
+}
+
+// fractional coordinates f = tau . inv(lattice) (row vectors)
+static void fractional(const ofdft_ctx* c, std::vector<double>& f) {
+  const GridDesc& g = c->g;
+  f.resize(3 * c->nat);
+  for (int I = 0; I < c->nat; ++I)
+    for (int a = 0; a < 3; ++a) {
+      // b_a . tau / (2 pi)
+      const double* t = &c->tau[3 * I];
+      f[3 * I + a] = (g.b[3 * a] * t[0] + g.b[3 * a + 1] * t[1] + g.b[3 * a + 2] * t[2]) /
+                     (2.0 * 3.141592653589793238462643383279502884);
+    }
+}
+
+int dev_structure_factor(ofdft_ctx* c) {
+  int rc = dev_alloc_ions(c);
+  if (rc) return rc;
+  std::vector<double> f;
+  fractional(c, f);
+  // upload fractional coordinates into the tail of dZ (nat + 3 nat)
+  std::vector<double> zf(c->nat + 3 * (size_t)c->nat);
+  for (int I = 0; I < c->nat; ++I) zf[I] = c->Z[I];
+  for (size_t k = 0; k < f.size(); ++k) zf[c->nat + k] = f[k];
+  if (!hip_ok(c, hipMemcpyAsync(c->dZ, zf.data(), zf.size() * sizeof(double), hipMemcpyHostToDevice, c->stream),
+              "ions"))
+    return OFDFT_E_DEVICE;
+  const GridDesc& g = c->g;
+  const long long M = g.n1 + g.n2 + g.n3h;
+  const int nb1 = (int)std::min<long long>(4096, ((long long)c->nat * M + NT - 1) / NT);
+  hipLaunchKernelGGL(k_phase_tables, dim3(nb1), dim3(NT), 0, c->stream, c->nat, c->dZ + c->nat, g,
+                     (double2*)c->phase);
+  const int nb2 = (int)std::min<long long>(8192, (g.NS + NT - 1) / NT);
+  if (c->rsize == 4)
+    hipLaunchKernelGGL(k_structure_factor<float>, dim3(nb2), dim3(NT), 0, c->stream, c->nat, c->dZ,
+                       (const double2*)c->phase, g, lpp_of(c), (cplx<float>*)c->Vext);
+  else
+    hipLaunchKernelGGL(k_structure_factor<double>, dim3(nb2), dim3(NT), 0, c->stream, c->nat, c->dZ,
+                       (const double2*)c->phase, g, lpp_of(c), (cplx<double>*)c->Vext);
+  hipError_t e = hipStreamSynchronize(c->stream);
+  return hip_ok(c, e, "structure factor") ? OFDFT_OK : OFDFT_E_DEVICE;
+}
+
+template <typename R>
+static int forces_impl(ofdft_ctx* c, double* out_host) {
+  const GridDesc& g = c->g;
+  // n(G) of the current density into A (forward transform, kept modes, 1/N)
+  OFDFT_DISPATCH(g.n3, (launch_rpass_fwd<R, L_>(c, c->phi, c->A)));
+  OFDFT_DISPATCH(g.n2, (launch_x2<R, L_, -1>(c, c->A, nullptr, nullptr, 1)));
+  OFDFT_DISPATCH(g.n1, (launch_x1_density<R, L_, X1_NHAT>(c, c->D, nullptr, nullptr)));
+  const int nbx = 1024;
+  const int nby = (c->nat + FORCE_IONS - 1) / FORCE_IONS;
+  hipLaunchKernelGGL(k_forces<R>, dim3(nbx, nby), dim3(NT), 0, c->stream, c->nat, c->dZ, (const double2*)c->phase,
+                     (const cplx<R>*)c->D, g, lpp_of(c), c->fpart);
+  hipLaunchKernelGGL(k_forces_final, dim3((3 * c->nat + NT - 1) / NT), dim3(NT), 0, c->stream, c->nat, c->fpart,
+                     nbx, -g.volume, c->dforces);
+  if (!hip_ok(c, hipMemcpyAsync(out_host, c->dforces, 3 * (size_t)c->nat * sizeof(double), hipMemcpyDeviceToHost,
+                                c->stream),
+              "forces copy"))
+    return OFDFT_E_DEVICE;
+  hipError_t e = hipStreamSynchronize(c->stream);
+  return hip_ok(c, e, "forces") ? OFDFT_OK : OFDFT_E_DEVICE;
+}
+
+int dev_forces(ofdft_ctx* c, double* forces_host) {
+  return c->rsize == 4 ? forces_impl<float>(c, forces_host) : forces_impl<double>(c, forces_host);
+}
+
+// ---------------------------------------------------------------- vector-op launchers
+template <int K, class Op>
+static int run_vec(ofdft_ctx* c, const Op& op) {
+  hipLaunchKernelGGL((k_vec<K, Op>), dim3(VEC_BLOCKS), dim3(NT), 0, c->stream, c->g.N, op, c->vpart);
+  if constexpr (K > 0)
+    hipLaunchKernelGGL((k_vec_final<K>), dim3(1), dim3(NT), 0, c->stream, c->vpart, VEC_BLOCKS, c->vout);
+  return hip_ok(c, hipGetLastError(), "vector op") ? OFDFT_OK : OFDFT_E_DEVICE;
+}
+
+int dev_grad_dots(ofdft_ctx* c, const double* phi, const void* v, const double* sc, const double* gprev,
+                  const double* d) {
+  const double two_dv = 2.0 * c->g.dv;
+  if (c->rsize == 4) return run_vec<4>(c, OpGradDots<float>{phi, (const float*)v, sc, gprev, d, two_dv});
+  return run_vec<4>(c, OpGradDots<double>{phi, (const double*)v, sc, gprev, d, two_dv});
+}
+
+int dev_cg_direction(ofdft_ctx* c, double beta, double cproj) {
+  const double two_dv = 2.0 * c->g.dv;
+  if (c->rsize == 4)
+    return run_vec<2>(c, OpDirection<float>{c->phi, (const float*)c->v, c->scalars, c->gprev, c->d, two_dv, beta, cproj});
+  return run_vec<2>(c, OpDirection<double>{c->phi, (const double*)c->v, c->scalars, c->gprev, c->d, two_dv, beta, cproj});
+}
+
+int dev_rotate(ofdft_ctx* c, double* dst, const double* phi, double ca, const double* dir, double sb) {
+  return run_vec<0>(c, OpRotate{dst, phi, dir, ca, sb});
+}
+
+int dev_dtheta(ofdft_ctx* c, const double* phi_t, const void* v_t, const double* sc_t, const double* phi,
+               const double* d, double ms, double mc) {
+  const double two_dv = 2.0 * c->g.dv;
+  if (c->rsize == 4)
+    return run_vec<1>(c, OpDtheta<float>{phi_t, (const float*)v_t, sc_t, phi, d, two_dv, ms, mc});
+  return run_vec<1>(c, OpDtheta<double>{phi_t, (const double*)v_t, sc_t, phi, d, two_dv, ms, mc});
+}
+
+int dev_full_grad_acc(ofdft_ctx* c, double* out, const double* phi_t, const void* v_t, double sign) {
+  const double two_dv = 2.0 * c->g.dv;
+  const int init = sign > 0 ? 1 : 0;
+  if (c->rsize == 4) return run_vec<0>(c, OpFullGradAcc<float>{out, phi_t, (const float*)v_t, two_dv, sign, init});
+  return run_vec<0>(c, OpFullGradAcc<double>{out, phi_t, (const double*)v_t, two_dv, sign, init});
+}
+
+int dev_dot(ofdft_ctx* c, const double* a, const double* b) { return run_vec<1>(c, OpDot{a, b}); }
+
+int dev_axpby(ofdft_ctx* c, double* y, double a, const double* x, double b) {
+  return run_vec<0>(c, OpAxpby{y, x, a, b});
+}
+
+int dev_tn_hess_finish(ofdft_ctx* c, double* hs, const double* phi, const double* s, double inv2e, double mu_term) {
+  (void)s;
+  (void)mu_term;
+  return run_vec<1>(c, OpHessScale{hs, phi, inv2e});
+}
+
+int dev_read(ofdft_ctx* c, const double* dptr, int n, double* host) {
+  if (!hip_ok(c, hipMemcpyAsync(c->hbuf, dptr, n * sizeof(double), hipMemcpyDeviceToHost, c->stream), "readback"))
+    return OFDFT_E_DEVICE;
+  if (!hip_ok(c, hipStreamSynchronize(c->stream), "sync")) return OFDFT_E_DEVICE;
+  std::memcpy(host, c->hbuf, n * sizeof(double));
+  return OFDFT_OK;
+}
+
+int dev_sync(ofdft_ctx* c) {
+  return hip_ok(c, hipStreamSynchronize(c->stream), "sync") ? OFDFT_OK : OFDFT_E_DEVICE;
+}
+
+}  // namespace ofdft
