@@ -1,0 +1,229 @@
+#!/usr/bin/env python3
+"""Benchmark of the finite-T orbital-free DFT hot path on one MI355X.
+
+Headline: F[n] + gradient evaluations per second at 128^3 (1024 H atoms,
+4.0 g/cm^3, T = 100 kK, VT84F + PZ81, mixed precision: FP32 FFTs and gradient
+terms, FP64 Fermi-Dirac inversion and sums).  One step = one evaluation of
+every stage of the evaluation path on the cell (density, forward FFT, Hartree
+and pseudopotential in reciprocal space, gradient, pointwise free energy and
+XC, divergence term, potential, Euler multiplier and energy reductions),
+launched back to back on the library's stream.
+
+Also reported: the same rate in FP64, per-kernel HIP-event durations with the
+roofline of the dominant kernel, milliseconds per converged MD step (128 H,
+1.0 g/cm^3, 64^3, 50 kK, VT84F, warm-started velocity Verlet) in mixed and FP64
+precision, and the FP64 CPU oracle timed on the host as a baseline.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--md-steps M] [--no-md] [--no-cpu]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = "1024 H, 4.0 g/cm^3, 128^3 grid, T=100 kK, VT84F+PZ81 ftGGA, Gaussian LPP rc=0.5"
+
+
+def log(msg: str):
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
+def host_threads() -> int:
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def kernel_bytes(name: str, n1: int, n2: int, n3: int, rsize: int) -> float:
+    """Algorithmic HBM bytes of one launch: compulsory reads + writes of whole arrays."""
+    N = n1 * n2 * n3
+    CS = (n3 // 2 + 1) * n1 * n2 * 2 * rsize      # one half-spectrum array (complex R)
+    RR = N * rsize                               # one real R array
+    P = N * 8                                    # phi (FP64)
+    table = {
+        "rpass_fwd_density": P + CS,
+        "cpass_x2_fwd": 2 * CS,
+        "x1_density_gradient": 6 * CS,
+        "x1_density_hartree": 3 * CS,
+        "cpass_x2_inv3": 6 * CS,
+        "rpass_gga_pointwise": 6 * CS + P + RR,
+        "cpass_x2_fwd3": 6 * CS,
+        "x1_divergence": 5 * CS,
+        "cpass_x2_inv": 2 * CS,
+        "rpass_final": CS + P + 2 * RR,
+        "rpass_tf_final": CS + P + RR,
+        "reduce_scalars": 0,
+    }
+    return float(table.get(name, 0))
+
+
+def sync():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.synchronize()
+    except Exception:
+        pass
+
+
+def make_context(P, cell, functional, precision, **kw):
+    ctx = P.Context(functional=functional, precision=precision, **kw)
+    ctx.set_cell(cell.lattice, cell.grid)
+    ctx.set_ions(cell.positions, cell.charges)
+    ctx.set_temperature(cell.temperature_K)
+    return ctx
+
+
+def eval_rate(ctx, steps, warmup):
+    ctx.time_evals(max(warmup, 1), 0)
+    sync()
+    t0 = time.perf_counter()
+    dev_ms, _ = ctx.time_evals(steps, 0)
+    sync()
+    t1 = time.perf_counter()
+    return steps / (t1 - t0), 1e3 * (t1 - t0) / steps, dev_ms / steps
+
+
+def md_run(P, wl, precision, n_steps):
+    from paper_1406_0835_amd import md
+    cell = wl.md_cell()
+    ctx = make_context(P, cell, "VT84F", precision, tol_energy=1e-8, max_iter=400)
+    masses = [md.H_MASS_ME] * cell.nat
+    v0 = md.maxwell_boltzmann(cell.nat, cell.temperature_K, md.H_MASS_ME, seed=wl.SEED_BASE + 4)
+    dt = 0.2 * md.FS_AU
+    recs = md.velocity_verlet(ctx, cell.positions, v0, cell.charges, masses, dt, n_steps)
+    steps = recs[1:]
+    e = [r.F_total + r.kinetic for r in recs]
+    ctx.close()
+    return {
+        "ms_per_step": sum(r.wall_ms for r in steps) / len(steps),
+        "evals_per_step": sum(r.evaluations for r in steps) / len(steps),
+        "first_minimization_ms": recs[0].wall_ms,
+        "E_cons_span_Ha": max(e) - min(e),
+        "steps": n_steps,
+    }
+
+
+def cpu_baseline(wl, cell, phi):
+    os.environ.setdefault("OFDFT_ORACLE_THREADS", str(host_threads()))
+    import numpy as np
+    import oracle
+    sysm = oracle.System(cell.lattice, cell.grid, cell.positions[:1], cell.charges[:1] * cell.nat,
+                         cell.temperature_K, functional="VT84F", with_ions=False)
+    sysm.vext_hat = np.zeros(sysm.grid.shape, dtype=complex)
+    t0 = time.perf_counter()
+    oracle.evaluate(phi, sysm)
+    dt = time.perf_counter() - t0
+    from oracle import fermi_dirac
+    return {"value": 1.0 / dt, "unit": "evals/s", "cores": fermi_dirac._THREADS, "kind": "oracle",
+            "sample": "one FP64 oracle F+gradient evaluation of the 128^3 VT84F+PZ81 cell at the benchmark "
+                      "phi (numpy/scipy, threaded Fermi-Dirac quadrature); the ionic setup (structure factor, "
+                      "Ewald) is outside the timed region",
+            "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--md-steps", type=int, default=4)
+    ap.add_argument("--no-md", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--kernel-steps", type=int, default=50)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(sharding is described in DESIGN.md); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import paper_1406_0835_amd as P
+    import workloads as wl
+
+    cell = wl.gga_128_cell(1.0e5)
+    n1, n2, n3 = cell.grid
+    nbar = cell.nat / abs(np.linalg.det(cell.lattice))
+    phi = wl.trial_phi(cell.grid, nbar, seed=wl.SEED_BASE + 2, contrast=0.6)
+
+    log("setting up the 128^3 cell (structure factor, Ewald)")
+    ctx = make_context(P, cell, "VT84F", "mixed")
+    ctx.set_density(phi)
+    log(f"timing {args.steps} mixed-precision evaluations")
+    value, ms_per_step, dev_ms = eval_rate(ctx, args.steps, args.warmup)
+    log(f"{value:.1f} evals/s; per-kernel events over {args.kernel_steps} evaluations")
+    _, kern = ctx.time_evals(args.kernel_steps, 16)
+    ctx.close()
+
+    per_kernel = []
+    for name, ms in kern:
+        b = kernel_bytes(name, n1, n2, n3, 4)
+        per_kernel.append({"kernel": name, "avg_us": 1e3 * ms, "alg_bytes": b,
+                           "GB_s": (b / (ms * 1e-3) / 1e9) if ms > 0 and b > 0 else None})
+    dom = max(per_kernel, key=lambda k: k["avg_us"])
+    achieved = dom["GB_s"] or 0.0
+    roofline = {"bound": "hbm", "kernel": dom["kernel"], "achieved": achieved, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "alg_bytes_per_launch": dom["alg_bytes"], "avg_launch_us": dom["avg_us"]}
+    total_alg = sum(k["alg_bytes"] for k in per_kernel)
+    eval_gbs = total_alg / (dev_ms * 1e-3) / 1e9
+
+    fp64 = None
+    if not args.no_fp64:
+        log("FP64 evaluation rate")
+        c64 = make_context(P, cell, "VT84F", "fp64")
+        c64.set_density(phi)
+        v64, ms64, _ = eval_rate(c64, max(20, args.steps // 4), max(2, args.warmup // 2))
+        c64.close()
+        fp64 = {"evals_per_s": v64, "ms_per_eval": ms64}
+
+    md_res = None
+    if not args.no_md and args.md_steps > 0:
+        log(f"MD: {args.md_steps} steps mixed and FP64")
+        md_res = {"mixed": md_run(P, wl, "mixed", args.md_steps), "fp64": md_run(P, wl, "fp64", args.md_steps),
+                  "workload": "128 H, 1.0 g/cm^3, 64^3 grid, T=50 kK, VT84F+PZ81, CG to 1e-8 Ha, dt=0.2 fs"}
+
+    cpu = None
+    if not args.no_cpu:
+        log("CPU oracle baseline (one 128^3 evaluation)")
+        cpu = cpu_baseline(wl, cell, phi)
+
+    out = {
+        "metric": "F[n]+gradient evals/s at 128^3",
+        "value": value,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "grid_points": n1 * n2 * n3, "precision": "mixed",
+                   "step": "one F+gradient evaluation"},
+        "grid_points_per_s": value * n1 * n2 * n3,
+        "device_ms_per_eval": dev_ms,
+        "eval_alg_GB_s": eval_gbs,
+        "roofline": roofline,
+        "kernels": per_kernel,
+        "fp64": fp64,
+        "md_step": md_res,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

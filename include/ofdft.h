@@ -150,10 +150,12 @@ int ofdft_set_density(ofdft_ctx* ctx, const double* phi);
    total potential v = dF_tot/dn on the grid (N1*N2*N3 doubles). */
 int ofdft_eval(ofdft_ctx* ctx, ofdft_report* rep, double* potential_out);
 
-/* Runs n_evals evaluations back to back on the context's stream and times
-   them with HIP events recorded on that stream around every kernel launch.
-   total_ms receives the wall time of all evaluations (events around the
-   whole sequence); kernel_ms[k] the average duration of kernel slot k per
+/* Runs n_evals evaluations back to back on the context's stream (no host
+   synchronisation in between) and times them with HIP events recorded on
+   that stream.  total_ms receives the device time of the whole sequence.
+   With max_kernels == 0 only that total is measured (two events).  With
+   max_kernels > 0 an event is also recorded before every kernel launch, and
+   kernel_ms[k] receives the average duration of kernel slot k per
    evaluation and kernel_names[k] its name (static strings), for
    k < *n_kernels <= max_kernels. */
 int ofdft_time_evals(ofdft_ctx* ctx, int n_evals, double* total_ms, int max_kernels,

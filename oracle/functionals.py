@@ -26,15 +26,17 @@ Exchange-correlation: ground-state spin-unpolarised LDA in the Perdew-Zunger
   eps_x = -(3/4)(3/pi)^(1/3) n^(1/3);
   eps_c = gamma/(1 + beta1 sqrt(rs) + beta2 rs)           (rs >= 1)
         = A ln rs + B + C rs ln rs + D rs                  (rs < 1)
-  with gamma=-0.1423, beta1=1.0529, beta2=0.3334, A=0.0311, B=-0.048,
-  C=0.0020, D=-0.0116 (Phys. Rev. B 23, 5048 (1981), unpolarised);
+  with gamma=-0.1423, beta1=1.0529, beta2=0.3334, A=0.0311, B=-0.048
+  (Phys. Rev. B 23, 5048 (1981), unpolarised) and C, D fixed by continuity
+  of eps_c and its derivative at rs = 1 (C = 0.0020192, D = -0.0116321; the
+  published C = 0.0020, D = -0.0116 are these rounded);
   v_xc = eps_xc - (rs/3) d eps_xc/d rs.
 
 Pins (tests/test_oracle_functionals.py): ftTF potential equals T*eta (uniform
 gas chemical potential); SGA equals f_TF + (h~/72)|grad n|^2/n; VWTF at t -> 0
 equals TF + von Weizsaecker; VT84F (F-1)/s^2 -> 5/27 and F -> 5/3 s^2 + 1/s^2;
 df/dn and df/dsigma against central finite differences; exchange closed form;
-PZ81 branch continuity at rs = 1; v_xc by finite differences.
+PZ81 continuity of eps_c and its slope at rs = 1; v_xc by finite differences.
 """
 from __future__ import annotations
 
@@ -161,7 +163,13 @@ def gga_point(n, sigma, T_ha, name: str, mu_sga: float = MU_SGA, factors=None):
 
 # ---------------------------------------------------------------- XC (PZ81)
 PZ_GAMMA, PZ_BETA1, PZ_BETA2 = -0.1423, 1.0529, 0.3334
-PZ_A, PZ_B, PZ_C, PZ_D = 0.0311, -0.048, 0.0020, -0.0116
+PZ_A, PZ_B = 0.0311, -0.048
+# C and D from continuity of eps_c and d eps_c/d rs at rs = 1 (their published
+# values 0.0020 and -0.0116 are these, rounded; with the rounded values eps_c
+# jumps by 3e-5 hartree at rs = 1 and F_tot is discontinuous in n)
+_DEN1 = 1.0 + PZ_BETA1 + PZ_BETA2
+PZ_D = PZ_GAMMA / _DEN1 - PZ_B
+PZ_C = -PZ_GAMMA * (0.5 * PZ_BETA1 + PZ_BETA2) / _DEN1 ** 2 - PZ_A - PZ_D
 EX_COEF = -0.75 * (3.0 / pi) ** (1.0 / 3.0)
 
 

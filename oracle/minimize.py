@@ -16,7 +16,8 @@ results are compared):
   which keeps sum phi^2 fixed exactly;
 * the line search uses dF/dtheta = g(theta) . dphi/dtheta, a first trial step,
   then safeguarded secant/bisection on dF/dtheta until
-  |dF/dtheta| <= 0.1 |dF/dtheta(0)| with sufficient decrease;
+  |dF/dtheta| <= 0.1 |dF/dtheta(0)| with sufficient decrease (or, once the
+  change of F is at its rounding level 1e-14 |F|, with no increase beyond it);
 * CG: Polak-Ribiere with restart (beta = max(0, .)), direction projected
   orthogonal to phi;
 * TN: Newton-CG in the tangent space on the Lagrangian Hessian
@@ -72,7 +73,10 @@ def _line_search(phi, F0, dF0, dhat, r, system, theta1, counter, max_trials=12):
         if ev.F_tot <= F0 and (best is None or ev.F_tot < best[2].F_tot):
             best = (theta, p, ev)
         armijo = ev.F_tot <= F0 + 1e-4 * theta * dF0
-        if armijo and abs(dth) <= 0.1 * abs(dF0):
+        # at the rounding floor of F the decrease test cannot resolve progress;
+        # then the slope condition alone decides (approximate Wolfe)
+        flat = ev.F_tot <= F0 + 1e-14 * abs(F0)
+        if (armijo or flat) and abs(dth) <= 0.1 * abs(dF0):
             return theta, p, ev
         if dth > 0 or not armijo:
             hi, Fhi, dhi = theta, ev.F_tot, dth

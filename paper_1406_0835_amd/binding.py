@@ -204,9 +204,10 @@ class Context:
         return (rep, pot.reshape(self.shape)) if potential else rep
 
     def time_evals(self, n_evals: int, max_kernels: int = 16):
+        """(total device ms, [(kernel name, average ms per evaluation)]); max_kernels=0: total only."""
         total = ctypes.c_double()
-        names = (ctypes.c_char_p * max_kernels)()
-        ms = (ctypes.c_double * max_kernels)()
+        names = (ctypes.c_char_p * max(max_kernels, 1))()
+        ms = (ctypes.c_double * max(max_kernels, 1))()
         nk = ctypes.c_int()
         _check(self._lib, self._lib.ofdft_time_evals(self._h, int(n_evals), ctypes.byref(total), max_kernels,
                                                      names, ms, ctypes.byref(nk)), self._h)

@@ -247,7 +247,9 @@ int line_search(ofdft_ctx* c, double F0, double dF0, double r, double phinorm, d
       best_F = Ft;
     }
     const bool armijo = Ft <= F0 + 1e-4 * theta * dF0;
-    if (armijo && std::fabs(dth) <= 0.1 * std::fabs(dF0)) {
+    // once F changes at its rounding level only the slope test can decide
+    const bool flat = Ft <= F0 + 1e-14 * std::fabs(F0);
+    if ((armijo || flat) && std::fabs(dth) <= 0.1 * std::fabs(dF0)) {
       out = {theta, Ft, true};
       return OFDFT_OK;
     }
@@ -785,11 +787,24 @@ int ofdft_time_evals(ofdft_ctx* c, int n_evals, double* total_ms, int max_kernel
   if (n_evals < 1 || !total_ms || max_kernels < 0 || (max_kernels > 0 && (!kernel_names || !kernel_ms)) || !n_kernels)
     return fail(c, OFDFT_E_ARG, "invalid timing arguments");
   Timing& t = c->timing;
-  const size_t need = (size_t)n_evals * 16 + 2;
+  const size_t need = max_kernels > 0 ? (size_t)n_evals * 16 + 2 : 2;
   while (t.events.size() < need) {
     hipEvent_t e;
     if (hipEventCreate(&e) != hipSuccess) return fail(c, OFDFT_E_DEVICE, "hipEventCreate");
     t.events.push_back(e);
+  }
+  if (max_kernels == 0) {
+    // whole-sequence timing only: one event before the first and one after the last evaluation
+    if (hipEventRecord(t.events[0], c->stream) != hipSuccess) return fail(c, OFDFT_E_DEVICE, "hipEventRecord");
+    for (int k = 0; k < n_evals; ++k)
+      if ((rc = dev_eval(c, c->phi, c->v, c->scalars))) return fail(c, rc, c->err);
+    if (hipEventRecord(t.events[1], c->stream) != hipSuccess) return fail(c, OFDFT_E_DEVICE, "hipEventRecord");
+    if ((rc = dev_sync(c))) return fail(c, rc, c->err);
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, t.events[0], t.events[1]);
+    *total_ms = ms;
+    *n_kernels = 0;
+    return OFDFT_OK;
   }
   t.names.clear();
   t.used = 0;

@@ -203,6 +203,13 @@ __device__ __forceinline__ void enhancement(const EnhParams& p, R x, R& F, R& dF
 
 // ---------------------------------------------------------------- PZ81 LDA XC
 // eps_xc and v_xc of the unpolarised Perdew-Zunger (1981) parametrisation.
+// The high-density C and D follow from continuity of eps_c and its slope at
+// rs = 1 (the published 0.0020 and -0.0116 are these values rounded).
+constexpr double kPzGamma = -0.1423, kPzB1 = 1.0529, kPzB2 = 0.3334, kPzA = 0.0311, kPzB = -0.048;
+constexpr double kPzDen1 = 1.0 + kPzB1 + kPzB2;
+constexpr double kPzD = kPzGamma / kPzDen1 - kPzB;
+constexpr double kPzC = -kPzGamma * (0.5 * kPzB1 + kPzB2) / (kPzDen1 * kPzDen1) - kPzA - kPzD;
+
 template <typename R>
 __device__ __forceinline__ void pz81(R n, R& eps, R& v) {
   const R rs = cbrt(R(0.75) / (R(kPi) * n));
@@ -210,13 +217,13 @@ __device__ __forceinline__ void pz81(R n, R& eps, R& v) {
   R ec, dec;
   if (rs >= R(1)) {
     const R sq = sqrt(rs);
-    const R den = R(1) + R(1.0529) * sq + R(0.3334) * rs;
-    ec = R(-0.1423) / den;
-    dec = R(0.1423) * (R(0.5) * R(1.0529) / sq + R(0.3334)) / (den * den);
+    const R den = R(1) + R(kPzB1) * sq + R(kPzB2) * rs;
+    ec = R(kPzGamma) / den;
+    dec = -R(kPzGamma) * (R(0.5 * kPzB1) / sq + R(kPzB2)) / (den * den);
   } else {
     const R lr = log(rs);
-    ec = R(0.0311) * lr + R(-0.048) + R(0.0020) * rs * lr + R(-0.0116) * rs;
-    dec = R(0.0311) / rs + R(0.0020) * (lr + R(1)) + R(-0.0116);
+    ec = R(kPzA) * lr + R(kPzB) + R(kPzC) * rs * lr + R(kPzD) * rs;
+    dec = R(kPzA) / rs + R(kPzC) * (lr + R(1)) + R(kPzD);
   }
   eps = ex + ec;
   v = R(4.0 / 3.0) * ex + ec - rs * dec / R(3);

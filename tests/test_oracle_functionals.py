@@ -108,15 +108,16 @@ def test_gga_entropy_density_is_T_times_minus_dF_dT():
 def test_pz81_exchange_and_continuity():
     n = np.array([0.01, 0.2, 3.0])
     rs = (3 / (4 * math.pi * n)) ** (1 / 3)
-    eps, v = fn.pz81(n)
-    ex = -0.458165293283143 / rs
-    # correlation is the difference; check exchange via a tiny-rs scaling
-    assert np.allclose(fn.EX_COEF * n ** (1 / 3), ex, rtol=1e-12)
+    # exchange per electron -(3/4)(3/pi)^(1/3) n^(1/3) = -0.458165.../rs
+    assert np.allclose(fn.EX_COEF * n ** (1 / 3), -0.458165293283143 / rs, rtol=1e-12)
     n1 = 3 / (4 * math.pi)
-    e_lo, _ = fn.pz81(np.array([n1 * (1 + 1e-12)]))
-    e_hi, _ = fn.pz81(np.array([n1 * (1 - 1e-12)]))
-    # the PZ81 fit is continuous at rs = 1 to about 1e-5 hartree by construction
-    assert abs(e_lo[0] - e_hi[0]) < 5e-5
+    h = 1e-11
+    e_hi, v_hi = fn.pz81(np.array([n1 * (1 + h)]))   # rs slightly below 1
+    e_lo, v_lo = fn.pz81(np.array([n1 * (1 - h)]))
+    # the published rounded C, D would leave a jump of 3.2e-5 hartree here
+    assert abs(e_lo[0] - e_hi[0]) < 1e-10 and abs(v_lo[0] - v_hi[0]) < 1e-9
+    # the continuity-fixed C, D round to the published 0.0020 and -0.0116
+    assert round(fn.PZ_C, 4) == 0.0020 and round(fn.PZ_D, 4) == -0.0116
 
 
 def test_pz81_potential_fd():
@@ -128,10 +129,12 @@ def test_pz81_potential_fd():
 
 
 def test_pz81_correlation_reference_values():
-    # PZ81 unpolarised correlation at rs = 2 (high branch) and rs = 0.5 (low branch)
+    # low-density branch at rs = 2 from the published gamma, beta1, beta2; high-density
+    # branch at rs = 0.5 from A, B and the continuity-fixed C, D
     for rs, ref in ((2.0, -0.1423 / (1 + 1.0529 * math.sqrt(2.0) + 0.3334 * 2.0)),
-                    (0.5, 0.0311 * math.log(0.5) - 0.048 + 0.0020 * 0.5 * math.log(0.5) - 0.0116 * 0.5)):
+                    (0.5, 0.0311 * math.log(0.5) - 0.048 + 0.0020191519 * 0.5 * math.log(0.5)
+                     - 0.0116320664 * 0.5)):
         n = 3 / (4 * math.pi * rs ** 3)
         eps, _ = fn.pz81(np.array([n]))
         ex = -0.458165293283143 / rs
-        assert eps[0] - ex == pytest.approx(ref, abs=1e-14)
+        assert eps[0] - ex == pytest.approx(ref, abs=1e-10)
