@@ -130,6 +130,18 @@ def cpu_baseline(wl, cell, phi):
             "seconds": dt}
 
 
+def copy_probe(mib: float):
+    """A plain device-to-device copy kernel of known size (FETCH_SIZE/WRITE_SIZE calibration)."""
+    import torch
+    n = int(mib * 1024 * 1024 / 4)
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_MiB": mib, "bytes_read_per_copy": 4 * n, "bytes_written_per_copy": 4 * n}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -140,7 +152,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--kernel-steps", type=int, default=50)
+    ap.add_argument("--copy-probe", type=float, default=0.0,
+                    help="only run a plain device copy of this many MiB (counter calibration) and exit")
     args = ap.parse_args()
+    if args.copy_probe > 0:
+        copy_probe(args.copy_probe)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "

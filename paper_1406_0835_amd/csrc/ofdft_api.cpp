@@ -233,12 +233,13 @@ int line_search(ofdft_ctx* c, double F0, double dF0, double r, double phinorm, d
     if (rc) return rc;
     rc = dev_eval(c, c->phi_t, c->v_t, c->scalars_t);
     if (rc) return rc;
-    rc = dev_dtheta(c, c->phi_t, c->v_t, c->scalars_t, c->phi, c->d, -st * ratio, ct * r / dn);
+    rc = dev_dtheta(c, c->phi_t, c->v_t, c->scalars_t, c->phi, c->d, -st * ratio, ct * r / dn,
+                    c->scalars_t + SC_DOT0);
     if (rc) return rc;
     ++nevals;
-    double h[SC_COUNT], dth;
+    double h[SC_COUNT];
     if ((rc = dev_read(c, c->scalars_t, SC_COUNT, h))) return rc;
-    if ((rc = dev_read(c, c->vout, 1, &dth))) return rc;
+    const double dth = h[SC_DOT0];
     const double Ft = h[SC_FTOT];
     if (!is_fin(Ft) || !is_fin(dth)) return fail(c, OFDFT_E_NONFINITE, "non-finite energy in line search");
     last_theta = theta;
@@ -315,6 +316,16 @@ bool stop_rule(const ofdft_ctx* c, int small, double resid) {
   return small >= 2 && (c->opt.tol_residual <= 0.0 || resid < c->opt.tol_residual);
 }
 
+// When no trial point lowers F, the iteration sits at the resolution of F:
+// converged if the last steps were already below the energy tolerance, or, in
+// the mixed path (FP32 terms summed in FP64), below 1e-6 |F| (its stated
+// accuracy).
+bool stalled_converged(const ofdft_ctx* c, int small, double last_dF, double F, double resid) {
+  if (small >= 1) return true;
+  if (c->opt.tol_residual > 0.0 && resid < c->opt.tol_residual) return true;
+  return c->rsize == 4 && std::fabs(last_dF) < 1e-6 * std::fabs(F);
+}
+
 double first_step(double F0, double Fprev, bool have_prev, double dF0) {
   if (have_prev && dF0 < 0.0 && Fprev > F0) return std::min(std::max(2.0 * (Fprev - F0) / (-dF0), 1e-6), 0.3);
   return 0.05;
@@ -330,20 +341,24 @@ int minimize_cg(ofdft_ctx* c, ofdft_report* rep) {
   Point p;
   if ((rc = eval_at(c, c->phi, c->v, c->scalars, p))) return rc;
   ++nevals;
-  double F = p.F, Fprev = 0.0, gg_prev = 0.0, dn_prev = 0.0, theta_prev = 0.0;
+  double F = p.F, Fprev = 0.0, gg_prev = 0.0, dn_prev = 0.0, theta_prev = 0.0, last_dF = 1e300;
   bool have_prev = false;
   int small = 0, it = 0;
   bool converged = false;
   double resid = 0.0;
   for (it = 1; it <= c->opt.max_iter; ++it) {
-    double dots[4];
-    if ((rc = dev_grad_dots(c, c->phi, c->v, c->scalars, have_prev ? c->gprev : nullptr, have_prev ? c->d : nullptr)))
+    double hs[SC_COUNT];
+    if ((rc = dev_grad_dots(c, c->phi, c->v, c->scalars, have_prev ? c->gprev : nullptr, have_prev ? c->d : nullptr,
+                            c->scalars + SC_DOT0)))
       return rc;
-    if ((rc = dev_read(c, c->vout, 4, dots))) return rc;
+    if ((rc = dev_read(c, c->scalars, SC_COUNT, hs))) return rc;
+    const double* dots = hs + SC_DOT0;
+    p.F = hs[SC_FTOT];
+    p.Ne = hs[SC_NE];
     const double phinorm2 = p.Ne / c->g.dv;
     resid = std::sqrt(dots[3] / phinorm2);
     const double gg = dots[0];
-    if (gg == 0.0) { converged = true; break; }
+    if (gg == 0.0 || stop_rule(c, small, resid)) { converged = true; break; }
     double beta = 0.0, cproj = 0.0;
     if (have_prev) {
       beta = std::max(0.0, (gg - dots[1]) / gg_prev);
@@ -363,29 +378,21 @@ int minimize_cg(ofdft_ctx* c, ofdft_report* rep) {
     if ((rc = line_search(c, F, dF0, r, std::sqrt(phinorm2), dn, first_step(F, Fprev, have_prev, dF0), nevals, ls)))
       return rc;
     if (!ls.ok) {
-      converged = small >= 1 || (c->opt.tol_residual > 0 && resid < c->opt.tol_residual);
+      converged = stalled_converged(c, small, last_dF, F, resid);
       break;
     }
     accept_trial(c);
-    double h[SC_COUNT];
-    if ((rc = dev_read(c, c->scalars, SC_COUNT, h))) return rc;
-    p.F = h[SC_FTOT];
-    p.Ne = h[SC_NE];
-    const double dF = F - p.F;
+    const double dF = F - ls.F;
+    last_dF = dF;
     Fprev = F;
-    F = p.F;
+    F = ls.F;
     gg_prev = gg;
     dn_prev = dn;
     theta_prev = ls.theta;
     have_prev = true;
     small = std::fabs(dF) < c->opt.tol_energy ? small + 1 : 0;
-    if (small >= 2) {
-      double d4[4];
-      if ((rc = dev_grad_dots(c, c->phi, c->v, c->scalars, nullptr, nullptr))) return rc;
-      if ((rc = dev_read(c, c->vout, 4, d4))) return rc;
-      resid = std::sqrt(d4[3] / (p.Ne / c->g.dv));
-      if (stop_rule(c, small, resid)) { converged = true; break; }
-    }
+    if (small >= 2 && c->opt.tol_residual <= 0.0) { converged = true; break; }
+    // with a residual target the next gradient pass measures it
   }
   double h[SC_COUNT];
   if ((rc = dev_read(c, c->scalars, SC_COUNT, h))) return rc;
@@ -407,21 +414,24 @@ int minimize_tn(ofdft_ctx* c, ofdft_report* rep) {
   Point p;
   if ((rc = eval_at(c, c->phi, c->v, c->scalars, p))) return rc;
   ++nevals;
-  double F = p.F;
+  double F = p.F, last_dF = 1e300;
   int small = 0, it = 0;
   bool converged = false;
   double resid = 0.0;
   const int max_inner = 20;
+  // finite-difference step of the Hessian products: ~sqrt of the gradient's relative precision
+  const double fd_rel = (c->rsize == 4) ? 3e-4 : 1e-6;
   for (it = 1; it <= c->opt.max_iter; ++it) {
-    double dots[4];
-    if ((rc = dev_grad_dots(c, c->phi, c->v, c->scalars, nullptr, nullptr))) return rc;
-    if ((rc = dev_read(c, c->vout, 4, dots))) return rc;
+    double hsc[SC_COUNT];
+    if ((rc = dev_grad_dots(c, c->phi, c->v, c->scalars, nullptr, nullptr, c->scalars + SC_DOT0))) return rc;
+    if ((rc = dev_read(c, c->scalars, SC_COUNT, hsc))) return rc;
+    const double* dots = hsc + SC_DOT0;
+    p.F = hsc[SC_FTOT];
+    p.Ne = hsc[SC_NE];
     const double phinorm2 = p.Ne / c->g.dv;
     resid = std::sqrt(dots[3] / phinorm2);
     const double gnorm = std::sqrt(dots[0]);
-    if (gnorm == 0.0) { converged = true; break; }
-    double hsc[SC_COUNT];
-    if ((rc = dev_read(c, c->scalars, SC_COUNT, hsc))) return rc;
+    if (gnorm == 0.0 || stop_rule(c, small, resid)) { converged = true; break; }
     const double mu = hsc[SC_MU];
     // d = -g, gprev = g
     if ((rc = dev_cg_direction(c, 0.0, 0.0))) return rc;
@@ -436,7 +446,7 @@ int minimize_tn(ofdft_ctx* c, ofdft_report* rep) {
       double ss;
       if ((rc = dev_dot(c, S, S))) return rc;
       if ((rc = dev_read(c, c->vout, 1, &ss))) return rc;
-      const double eps = 1e-6 * r / std::sqrt(ss);
+      const double eps = fd_rel * r / std::sqrt(ss);
       // central difference of the unconstrained gradient along S
       if ((rc = dev_rotate(c, c->phi_t, c->phi, 1.0, S, eps))) return rc;
       if ((rc = dev_eval(c, c->phi_t, c->v_t, c->scalars_t))) return rc;
@@ -493,24 +503,15 @@ int minimize_tn(ofdft_ctx* c, ofdft_report* rep) {
     LS ls;
     if ((rc = line_search(c, F, dF0, r, std::sqrt(phinorm2), dn, theta1, nevals, ls))) return rc;
     if (!ls.ok) {
-      converged = small >= 1 || (c->opt.tol_residual > 0 && resid < c->opt.tol_residual);
+      converged = stalled_converged(c, small, last_dF, F, resid);
       break;
     }
     accept_trial(c);
-    double h[SC_COUNT];
-    if ((rc = dev_read(c, c->scalars, SC_COUNT, h))) return rc;
-    p.F = h[SC_FTOT];
-    p.Ne = h[SC_NE];
-    const double dF = F - p.F;
-    F = p.F;
+    const double dF = F - ls.F;
+    last_dF = dF;
+    F = ls.F;
     small = std::fabs(dF) < c->opt.tol_energy ? small + 1 : 0;
-    if (small >= 2) {
-      double d4[4];
-      if ((rc = dev_grad_dots(c, c->phi, c->v, c->scalars, nullptr, nullptr))) return rc;
-      if ((rc = dev_read(c, c->vout, 4, d4))) return rc;
-      resid = std::sqrt(d4[3] / (p.Ne / c->g.dv));
-      if (stop_rule(c, small, resid)) { converged = true; break; }
-    }
+    if (small >= 2 && c->opt.tol_residual <= 0.0) { converged = true; break; }
   }
   double h[SC_COUNT];
   if ((rc = dev_read(c, c->scalars, SC_COUNT, h))) return rc;
@@ -760,12 +761,10 @@ int ofdft_eval(ofdft_ctx* c, ofdft_report* rep, double* potential_out) {
   if (rc) return rc;
   Point p;
   if ((rc = eval_at(c, c->phi, c->v, c->scalars, p))) return rc;
-  double d4[4];
-  if ((rc = dev_grad_dots(c, c->phi, c->v, c->scalars, nullptr, nullptr))) return rc;
-  if ((rc = dev_read(c, c->vout, 4, d4))) return rc;
   double h[SC_COUNT];
+  if ((rc = dev_grad_dots(c, c->phi, c->v, c->scalars, nullptr, nullptr, c->scalars + SC_DOT0))) return rc;
   if ((rc = dev_read(c, c->scalars, SC_COUNT, h))) return rc;
-  fill_report(c, h, std::sqrt(d4[3] / (p.Ne / c->g.dv)), rep, 0, 1, 0);
+  fill_report(c, h, std::sqrt(h[SC_DOT0 + 3] / (p.Ne / c->g.dv)), rep, 0, 1, 0);
   if (potential_out) {
     if (c->rsize == 8) {
       if (hipMemcpy(potential_out, c->v, c->g.N * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)

@@ -26,6 +26,22 @@ struct FD6 {
   double f32, f12, fm12, fm32, fm52, fm72;
 };
 
+// Six Chebyshev series at one x with a shared T_k recurrence.
+__device__ __forceinline__ void cheb6(const double* __restrict__ c, double x, double* s) {
+#pragma unroll
+  for (int j = 0; j < 6; ++j) s[j] = c[j * OFDFT_FD_NC] + c[j * OFDFT_FD_NC + 1] * x;
+  double t0 = 1.0, t1 = x;
+  const double x2 = 2.0 * x;
+#pragma unroll 4
+  for (int k = 2; k < OFDFT_FD_NC; ++k) {
+    const double t2 = x2 * t1 - t0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) s[j] = fma(c[j * OFDFT_FD_NC + k], t2, s[j]);
+    t0 = t1;
+    t1 = t2;
+  }
+}
+
 __device__ __forceinline__ FD6 fd6(double eta) {
   int r;
   double x;
@@ -42,19 +58,14 @@ __device__ __forceinline__ FD6 fd6(double eta) {
     const double a = kFdBreaks[r - 1], bb = kFdBreaks[r];
     x = (2.0 * eta - a - bb) / (bb - a);
   }
-  const double* c = c_fd_cheb + r * 6 * OFDFT_FD_NC;
   double s[6];
-#pragma unroll
-  for (int j = 0; j < 6; ++j) s[j] = c[j * OFDFT_FD_NC] + c[j * OFDFT_FD_NC + 1] * x;
-  double t0 = 1.0, t1 = x;
-  const double x2 = 2.0 * x;
-#pragma unroll 4
-  for (int k = 2; k < OFDFT_FD_NC; ++k) {
-    const double t2 = x2 * t1 - t0;
-#pragma unroll
-    for (int j = 0; j < 6; ++j) s[j] = fma(c[j * OFDFT_FD_NC + k], t2, s[j]);
-    t0 = t1;
-    t1 = t2;
+  // Neighbouring grid points usually share a region: then the region index is
+  // wave-uniform and the coefficients come through scalar loads.
+  const int r0 = __builtin_amdgcn_readfirstlane(r);
+  if (__all(r == r0)) {
+    cheb6(c_fd_cheb + r0 * 6 * OFDFT_FD_NC, x, s);
+  } else {
+    cheb6(c_fd_cheb + r * 6 * OFDFT_FD_NC, x, s);
   }
   FD6 F;
   if (r == 0) {

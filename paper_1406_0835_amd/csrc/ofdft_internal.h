@@ -14,6 +14,7 @@ enum Slot { SL_PHI2 = 0, SL_FS, SL_TS, SL_EXC, SL_EH, SL_EEXT, SL_NV, SL_COUNT }
 // Reduced scalars of one evaluation (double[16] on the device).
 enum Scal {
   SC_NE = 0, SC_FS, SC_TS, SC_EXC, SC_EH, SC_EEXT, SC_NV, SC_MU, SC_EAZ, SC_EION, SC_FTOT,
+  SC_DOT0 = 11,   // slots 11..15: minimiser dot products written after an evaluation
   SC_COUNT = 16
 };
 
@@ -116,12 +117,14 @@ int dev_structure_factor(ofdft_ctx* c);
 int dev_eval(ofdft_ctx* c, const double* phi, void* v_out, double* scalars_out);
 int dev_forces(ofdft_ctx* c, double* forces_host);
 // vector operations for the minimisers; results land in c->vout (device)
+// g = 2 dv phi (v - mu): writes g.g, g.gprev, g.d, sum n (v-mu)^2 into out[0..3]
 int dev_grad_dots(ofdft_ctx* c, const double* phi, const void* v, const double* sc, const double* gprev,
-                  const double* d);
+                  const double* d, double* out);
 int dev_cg_direction(ofdft_ctx* c, double beta, double cproj);
 int dev_rotate(ofdft_ctx* c, double* dst, const double* phi, double ca, const double* dir, double sb);
+// dF/dtheta at the trial point, written to out[0]
 int dev_dtheta(ofdft_ctx* c, const double* phi_t, const void* v_t, const double* sc_t, const double* phi,
-               const double* d, double ms, double mc);
+               const double* d, double ms, double mc, double* out);
 int dev_full_grad_acc(ofdft_ctx* c, double* out, const double* phi_t, const void* v_t, double sign);
 int dev_dot(ofdft_ctx* c, const double* a, const double* b);
 int dev_axpby(ofdft_ctx* c, double* y, double a, const double* x, double b);

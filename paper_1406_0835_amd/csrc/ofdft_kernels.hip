@@ -532,7 +532,7 @@ __global__ void __launch_bounds__(NT) k_reduce_scalars(const double* __restrict_
     sc[SC_EAZ] = Ne * rp.alpha_sum;
     sc[SC_EION] = rp.E_ion;
     sc[SC_FTOT] = sc[SC_FS] + sc[SC_EXC] + sc[SC_EH] + sc[SC_EEXT] + sc[SC_EAZ] + rp.E_ion;
-    for (int k = SC_FTOT + 1; k < SC_COUNT; ++k) sc[k] = 0.0;
+    for (int k = SC_FTOT + 1; k < SC_COUNT; ++k) sc[k] = 0.0;   // dot slots cleared
   }
 }
 
@@ -1137,18 +1137,19 @@ int dev_forces(ofdft_ctx* c, double* forces_host) {
 
 // ---------------------------------------------------------------- vector-op launchers
 template <int K, class Op>
-static int run_vec(ofdft_ctx* c, const Op& op) {
+static int run_vec(ofdft_ctx* c, const Op& op, double* out = nullptr) {
   hipLaunchKernelGGL((k_vec<K, Op>), dim3(VEC_BLOCKS), dim3(NT), 0, c->stream, c->g.N, op, c->vpart);
   if constexpr (K > 0)
-    hipLaunchKernelGGL((k_vec_final<K>), dim3(1), dim3(NT), 0, c->stream, c->vpart, VEC_BLOCKS, c->vout);
+    hipLaunchKernelGGL((k_vec_final<K>), dim3(1), dim3(NT), 0, c->stream, c->vpart, VEC_BLOCKS,
+                       out ? out : c->vout);
   return hip_ok(c, hipGetLastError(), "vector op") ? OFDFT_OK : OFDFT_E_DEVICE;
 }
 
 int dev_grad_dots(ofdft_ctx* c, const double* phi, const void* v, const double* sc, const double* gprev,
-                  const double* d) {
+                  const double* d, double* out) {
   const double two_dv = 2.0 * c->g.dv;
-  if (c->rsize == 4) return run_vec<4>(c, OpGradDots<float>{phi, (const float*)v, sc, gprev, d, two_dv});
-  return run_vec<4>(c, OpGradDots<double>{phi, (const double*)v, sc, gprev, d, two_dv});
+  if (c->rsize == 4) return run_vec<4>(c, OpGradDots<float>{phi, (const float*)v, sc, gprev, d, two_dv}, out);
+  return run_vec<4>(c, OpGradDots<double>{phi, (const double*)v, sc, gprev, d, two_dv}, out);
 }
 
 int dev_cg_direction(ofdft_ctx* c, double beta, double cproj) {
@@ -1163,11 +1164,11 @@ int dev_rotate(ofdft_ctx* c, double* dst, const double* phi, double ca, const do
 }
 
 int dev_dtheta(ofdft_ctx* c, const double* phi_t, const void* v_t, const double* sc_t, const double* phi,
-               const double* d, double ms, double mc) {
+               const double* d, double ms, double mc, double* out) {
   const double two_dv = 2.0 * c->g.dv;
   if (c->rsize == 4)
-    return run_vec<1>(c, OpDtheta<float>{phi_t, (const float*)v_t, sc_t, phi, d, two_dv, ms, mc});
-  return run_vec<1>(c, OpDtheta<double>{phi_t, (const double*)v_t, sc_t, phi, d, two_dv, ms, mc});
+    return run_vec<1>(c, OpDtheta<float>{phi_t, (const float*)v_t, sc_t, phi, d, two_dv, ms, mc}, out);
+  return run_vec<1>(c, OpDtheta<double>{phi_t, (const double*)v_t, sc_t, phi, d, two_dv, ms, mc}, out);
 }
 
 int dev_full_grad_acc(ofdft_ctx* c, double* out, const double* phi_t, const void* v_t, double sign) {

@@ -1,0 +1,76 @@
+"""Full-size (128^3, 1024 H) parity in the configuration bench.py times.
+
+The stored oracle results (tests/golden/c3eval_*.json, written by
+tests/golden/make_golden.py from oracle/ only) hold the energy components and
+the potential at 4096 seeded sample points for the benchmark phi.  FP64:
+1e-10 relative; mixed: 1e-6 in F, 1e-5 of the potential RMS.  A size-
+independent property is also checked: in FP64 the returned potential is the
+gradient of the discrete free energy (central differences at sampled points).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from paper_1406_0835_amd import binding as B
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _ctx(functional, precision, T):
+    cell = wl.gga_128_cell(T)
+    ctx = B.Context(functional=functional, precision=precision)
+    ctx.set_cell(cell.lattice, cell.grid)
+    ctx.set_ions(cell.positions, cell.charges)
+    ctx.set_temperature(cell.temperature_K)
+    V = abs(np.linalg.det(cell.lattice))
+    phi = wl.trial_phi(cell.grid, cell.nat / V, seed=wl.SEED_BASE + 2, contrast=0.6)
+    dv = V / np.prod(cell.grid)
+    phi *= np.sqrt(cell.nat / (dv * np.sum(phi * phi)))
+    ctx.set_density(phi)
+    return ctx, phi, dv
+
+
+@pytest.mark.parametrize("name", ["c3eval_VT84F_100000", "c3eval_SGA_4000000"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_128cubed_eval_matches_stored_oracle(name, precision):
+    path = os.path.join(GOLDEN, f"{name}.json")
+    if not os.path.exists(path):
+        pytest.skip(f"{name}.json not generated")
+    gold = json.load(open(path))
+    ctx, _, _ = _ctx(gold["functional"], precision, gold["temperature_K"])
+    rep, v = ctx.eval(potential=True)
+    tol = 1e-10 if precision == "fp64" else 1e-6
+    scale = abs(gold["F_tot"])
+    for k, g in (("F_total", "F_tot"), ("F_s", "F_s"), ("TS_s", "TS_s"), ("E_xc", "E_xc"), ("E_H", "E_H"),
+                 ("E_ext", "E_ext"), ("E_alphaZ", "E_alphaZ"), ("E_ion", "E_ion"), ("mu", "mu")):
+        ref = gold[g]
+        assert abs(getattr(rep, k) - ref) <= tol * max(abs(ref), 1e-3 * scale), (k, getattr(rep, k), ref)
+    vs = v.ravel()[np.array(gold["sample_index"])]
+    ref = np.array(gold["v_sample"])
+    if precision == "fp64":
+        assert np.max(np.abs(vs - ref)) <= 1e-10 * gold["v_rms"]
+    else:
+        assert np.sqrt(np.mean((vs - ref) ** 2)) <= 1e-5 * gold["v_rms"]
+
+
+def test_128cubed_potential_is_gradient_of_discrete_energy():
+    ctx, phi, dv = _ctx("VT84F", "fp64", 1.0e5)
+    rep, v = ctx.eval(potential=True)
+    rng = np.random.default_rng(5)
+    # the ABI keeps int phi^2 = N_e, so differentiate along a tangent rotation
+    # phi(t) = cos t phi + sin t u (u orthogonal to phi, |u| = |phi|): dF/dt = 2 dv sum phi v u
+    u = rng.normal(size=phi.shape)
+    u -= (np.sum(u * phi) / np.sum(phi * phi)) * phi
+    u *= np.sqrt(np.sum(phi * phi) / np.sum(u * u))
+    t = 1e-5
+    Fs = []
+    for s in (1, -1):
+        ctx.set_density(np.cos(t) * phi + np.sin(s * t) * u)
+        Fs.append(ctx.eval().F_total)
+    num = (Fs[0] - Fs[1]) / (2 * t)
+    ana = float(np.sum(2 * dv * phi * v * u))
+    assert num == pytest.approx(ana, rel=1e-6)
