@@ -112,6 +112,77 @@ def md_run(P, wl, precision, n_steps):
     }
 
 
+def batch_run(P, wl, n_cells, precision):
+    """Heterogeneous batch: all cells minimised concurrently vs one after another."""
+    cells = wl.batch_cells(n_cells)
+    def build():
+        out = []
+        for c in cells:
+            out.append(make_context(P, c, "VT84F", precision, tol_energy=1e-8, max_iter=2000))
+        return out
+    seq = build()
+    sync()
+    t0 = time.perf_counter()
+    seq_reps = [c.minimize_density() for c in seq]
+    sync()
+    t_seq = time.perf_counter() - t0
+    bat = build()
+    sync()
+    t0 = time.perf_counter()
+    bat_reps = P.batch_minimize(bat)
+    sync()
+    t_bat = time.perf_counter() - t0
+    pts = sum(int(np.prod(c.grid)) for c in cells)
+    evals = sum(r.evaluations for r in bat_reps)
+    pt_evals = sum(int(np.prod(c.grid)) * r.evaluations for c, r in zip(cells, bat_reps))
+    dF = max(abs(a.F_total - b.F_total) / abs(b.F_total) for a, b in zip(bat_reps, seq_reps))
+    for c in seq + bat:
+        c.close()
+    return {"cells": n_cells, "precision": precision, "batched_s": t_bat, "sequential_s": t_seq,
+            "speedup": t_seq / t_bat, "grid_points": pts, "evaluations": evals,
+            "grid_points_per_s": pt_evals / t_bat, "max_rel_dF_batch_vs_sequential": dF,
+            "all_converged": all(r.converged for r in bat_reps)}
+
+
+def md_long(P, wl, n_steps):
+    """NVE drift (Ha/atom/ps) of the mixed and FP64 paths, and mixed-vs-FP64 forces."""
+    from paper_1406_0835_amd import md
+    out = {}
+    cell = wl.md_cell()
+    check = make_context(P, cell, "VT84F", "fp64", tol_energy=1e-10, max_iter=2000)
+    for precision in ("mixed", "fp64"):
+        ctx = make_context(P, cell, "VT84F", precision, tol_energy=1e-8, max_iter=400)
+        masses = [md.H_MASS_ME] * cell.nat
+        v0 = md.maxwell_boltzmann(cell.nat, cell.temperature_K, md.H_MASS_ME, seed=wl.SEED_BASE + 4)
+        dt = 0.2 * md.FS_AU
+        ferr = {}
+
+        def cb(rec, x, v, f):
+            if precision == "mixed" and rec.step in (n_steps // 2, n_steps):
+                _, f64, _ = md.step_forces(check, x, cell.charges)
+                ferr[rec.step] = float(np.max(np.abs(f - f64)))
+            if rec.step % 20 == 0:
+                log(f"MD {precision} step {rec.step}")
+        recs = md.velocity_verlet(ctx, cell.positions, v0, cell.charges, masses, dt, n_steps, callback=cb)
+        if precision == "mixed":
+            ctx.set_ions(cell.positions, cell.charges)
+            ctx.minimize_density()
+            _, f0, _ = ctx.free_energy_and_forces()
+            _, f64, _ = md.step_forces(check, cell.positions, cell.charges)
+            ferr[0] = float(np.max(np.abs(f0 - f64)))
+        e = np.array([r.F_total + r.kinetic for r in recs])
+        tps = np.arange(len(recs)) * dt / md.FS_AU * 1e-3       # ps
+        slope = float(np.polyfit(tps, e, 1)[0]) / cell.nat
+        out[precision] = {"steps": n_steps, "ms_per_step": float(np.mean([r.wall_ms for r in recs[1:]])),
+                          "drift_Ha_per_atom_per_ps": slope, "E_cons_std_Ha": float(np.std(e)),
+                          "evals_per_step": float(np.mean([r.evaluations for r in recs[1:]]))}
+        if ferr:
+            out[precision]["max_force_diff_vs_fp64_Ha_bohr"] = ferr
+        ctx.close()
+    check.close()
+    return out
+
+
 def cpu_baseline(wl, cell, phi):
     os.environ.setdefault("OFDFT_ORACLE_THREADS", str(host_threads()))
     import numpy as np
@@ -152,6 +223,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--kernel-steps", type=int, default=50)
+    ap.add_argument("--no-tune", action="store_true", help="keep the default FFT tiles")
+    ap.add_argument("--batch", type=int, default=0, help="also run the heterogeneous batch of this many cells")
+    ap.add_argument("--md-long", type=int, default=0, help="also run an NVE trajectory of this many steps")
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="only run a plain device copy of this many MiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -176,6 +250,10 @@ def main():
     log("setting up the 128^3 cell (structure factor, Ewald)")
     ctx = make_context(P, cell, "VT84F", "mixed")
     ctx.set_density(phi)
+    tiles = None
+    if not args.no_tune:
+        tiles = ctx.autotune(5)
+        log(f"autotuned tiles (tr, tc, rb) = {tiles}")
     log(f"timing {args.steps} mixed-precision evaluations")
     value, ms_per_step, dev_ms = eval_rate(ctx, args.steps, args.warmup)
     log(f"{value:.1f} evals/s; per-kernel events over {args.kernel_steps} evaluations")
@@ -200,15 +278,25 @@ def main():
         log("FP64 evaluation rate")
         c64 = make_context(P, cell, "VT84F", "fp64")
         c64.set_density(phi)
+        tiles64 = c64.autotune(3) if not args.no_tune else None
         v64, ms64, _ = eval_rate(c64, max(20, args.steps // 4), max(2, args.warmup // 2))
         c64.close()
-        fp64 = {"evals_per_s": v64, "ms_per_eval": ms64}
+        fp64 = {"evals_per_s": v64, "ms_per_eval": ms64, "tiles": tiles64}
 
     md_res = None
     if not args.no_md and args.md_steps > 0:
         log(f"MD: {args.md_steps} steps mixed and FP64")
         md_res = {"mixed": md_run(P, wl, "mixed", args.md_steps), "fp64": md_run(P, wl, "fp64", args.md_steps),
                   "workload": "128 H, 1.0 g/cm^3, 64^3 grid, T=50 kK, VT84F+PZ81, CG to 1e-8 Ha, dt=0.2 fs"}
+
+    batch = None
+    if args.batch > 0:
+        log(f"batch of {args.batch} cells")
+        batch = batch_run(P, wl, args.batch, "mixed")
+
+    mdl = None
+    if args.md_long > 0:
+        mdl = md_long(P, wl, args.md_long)
 
     cpu = None
     if not args.no_cpu:
@@ -229,7 +317,7 @@ def main():
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "grid_points": n1 * n2 * n3, "precision": "mixed",
-                   "step": "one F+gradient evaluation"},
+                   "step": "one F+gradient evaluation", "fft_tiles_tr_tc_rb": tiles},
         "grid_points_per_s": value * n1 * n2 * n3,
         "device_ms_per_eval": dev_ms,
         "eval_alg_GB_s": eval_gbs,
@@ -237,6 +325,8 @@ def main():
         "kernels": per_kernel,
         "fp64": fp64,
         "md_step": md_res,
+        "batch": batch,
+        "md_trajectory": mdl,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -161,6 +161,17 @@ int ofdft_eval(ofdft_ctx* ctx, ofdft_report* rep, double* potential_out);
 int ofdft_time_evals(ofdft_ctx* ctx, int n_evals, double* total_ms, int max_kernels,
                      const char** kernel_names, double* kernel_ms, int* n_kernels);
 
+/* Picks the FFT tile sizes for the current cell by timing: the rows per block
+   of the contiguous-axis pass (tr), the columns per block of the strided pass
+   (tc) and the rows per block of the x2 pass (rb), one parameter at a time,
+   each candidate over n_evals evaluations (HIP events on the context's
+   stream).  Needs set_cell, set_ions and set_temperature.  The choice stays
+   in force until the next set_cell; tiles[3] (may be NULL) receives it.
+   ofdft_set_tiles sets the three values directly (E_ARG if invalid for the
+   grid). */
+int ofdft_autotune(ofdft_ctx* ctx, int n_evals, int tiles[3]);
+int ofdft_set_tiles(ofdft_ctx* ctx, const int tiles[3]);
+
 /* Minimises several independent contexts together: their evaluations are
    interleaved on the contexts' streams so that small cells overlap on the
    device.  reps[n] may be NULL.  Returns the first error, if any. */

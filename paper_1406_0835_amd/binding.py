@@ -83,6 +83,8 @@ def load_library() -> ctypes.CDLL:
         "ofdft_eval": [P, ctypes.POINTER(Report), dp],
         "ofdft_time_evals": [P, I, dp, I, ctypes.POINTER(ctypes.c_char_p), dp, ip],
         "ofdft_batch_minimize": [ctypes.POINTER(P), I, ctypes.POINTER(Report)],
+        "ofdft_autotune": [P, I, ip],
+        "ofdft_set_tiles": [P, ip],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -202,6 +204,16 @@ class Context:
         _check(self._lib, self._lib.ofdft_eval(self._h, ctypes.byref(rep), _dptr(pot) if potential else None),
                self._h)
         return (rep, pot.reshape(self.shape)) if potential else rep
+
+    def autotune(self, n_evals: int = 5):
+        """Pick FFT tiles (tr, tc, rb) by timing; returns the chosen triple."""
+        t = (ctypes.c_int * 3)()
+        _check(self._lib, self._lib.ofdft_autotune(self._h, int(n_evals), t), self._h)
+        return tuple(t)
+
+    def set_tiles(self, tiles):
+        t = (ctypes.c_int * 3)(*[int(x) for x in tiles])
+        _check(self._lib, self._lib.ofdft_set_tiles(self._h, t), self._h)
 
     def time_evals(self, n_evals: int, max_kernels: int = 16):
         """(total device ms, [(kernel name, average ms per evaluation)]); max_kernels=0: total only."""

@@ -836,6 +836,76 @@ int ofdft_time_evals(ofdft_ctx* c, int n_evals, double* total_ms, int max_kernel
   return OFDFT_OK;
 }
 
+static bool tiles_valid(const ofdft_ctx* c, int tr, int tc, int rb) {
+  const GridDesc& g = c->g;
+  if (tr < 2 || tr % 2 || g.n2 % tr || tc < 1 || g.n2 % tc || rb < 1 || rb * g.n2 > 8192) return false;
+  // the per-block partial sums were sized for tiles of at least 2
+  if ((long long)(g.n2 / tr) * g.n1 > c->max_blocks || (long long)(g.n2 / tc) * g.n3h > c->max_blocks) return false;
+  return true;
+}
+
+int ofdft_set_tiles(ofdft_ctx* c, const int tiles[3]) {
+  if (!c) return fail(nullptr, OFDFT_E_ARG, "null context");
+  if (!tiles) return fail(c, OFDFT_E_ARG, "tiles is NULL");
+  if (!c->have_cell) return fail(c, OFDFT_E_STATE, "set_cell has not been called");
+  if (!tiles_valid(c, tiles[0], tiles[1], tiles[2])) return fail(c, OFDFT_E_ARG, "invalid tiles for this grid");
+  const GridDesc old = c->g;
+  c->g.tr = tiles[0];
+  c->g.tc = tiles[1];
+  c->g.rb = tiles[2];
+  if (dev_max_lds(c) > 160 * 1024) {
+    c->g = old;
+    return fail(c, OFDFT_E_ARG, "tiles exceed the 160 KB LDS of a workgroup");
+  }
+  return OFDFT_OK;
+}
+
+int ofdft_autotune(ofdft_ctx* c, int n_evals, int tiles[3]) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (n_evals < 1) return fail(c, OFDFT_E_ARG, "n_evals must be >= 1");
+  auto time_cfg = [&](int tr, int tc, int rb, double& ms) -> int {
+    const int t[3] = {tr, tc, rb};
+    if (!tiles_valid(c, tr, tc, rb)) return OFDFT_E_ARG;
+    if (ofdft_set_tiles(c, t) != OFDFT_OK) return OFDFT_E_ARG;
+    double tot;
+    int nk = 0;
+    int r2 = ofdft_time_evals(c, 1, &tot, 0, nullptr, nullptr, &nk);   // warm-up
+    if (r2) return r2;
+    r2 = ofdft_time_evals(c, n_evals, &tot, 0, nullptr, nullptr, &nk);
+    ms = tot / n_evals;
+    return r2;
+  };
+  int best[3] = {c->g.tr, c->g.tc, c->g.rb};
+  double best_ms;
+  if ((rc = time_cfg(best[0], best[1], best[2], best_ms))) return rc;
+  const int cand[] = {1, 2, 4, 8, 16, 32, 64};
+  for (int param = 2; param >= 0; --param) {   // x2 rows, then columns, then rows
+    for (int v : cand) {
+      int t[3] = {best[0], best[1], best[2]};
+      t[param] = v;
+      if (t[0] == best[0] && t[1] == best[1] && t[2] == best[2]) continue;
+      double ms;
+      const int r2 = time_cfg(t[0], t[1], t[2], ms);
+      if (r2 == OFDFT_E_ARG) continue;
+      if (r2) return fail(c, r2, c->err);
+      if (ms < best_ms) {
+        best_ms = ms;
+        best[0] = t[0];
+        best[1] = t[1];
+        best[2] = t[2];
+      }
+    }
+  }
+  if ((rc = ofdft_set_tiles(c, best))) return rc;
+  if (tiles) {
+    tiles[0] = best[0];
+    tiles[1] = best[1];
+    tiles[2] = best[2];
+  }
+  return OFDFT_OK;
+}
+
 int ofdft_batch_minimize(ofdft_ctx* const* ctxs, int n, ofdft_report* reps) {
   if (!ctxs || n < 0) return fail(nullptr, OFDFT_E_ARG, "invalid batch");
   for (int i = 0; i < n; ++i)

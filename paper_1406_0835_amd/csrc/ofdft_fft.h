@@ -124,9 +124,20 @@ struct Bfly<R, SIGN, 8> {
   }
 };
 
+// ---------------------------------------------------------------- LDS row layout
+// FFT rows live in LDS with one padding slot after every 8 elements and one
+// more per row: element i of row r sits at r*RS + i + i/8.  Strided Stockham
+// accesses (stride 8 in the first stage, 8-element runs 64 apart in the
+// second) and column-wise tile loads then fall on distinct banks.
+template <int L>
+struct Lay {
+  static constexpr int RS = L + (L >> 3) + 1;   // padded row size in elements
+  __device__ __forceinline__ static int at(int row, int i) { return row * RS + i + (i >> 3); }
+};
+
 // ---------------------------------------------------------------- Stockham stages
-// nrows rows of length L, contiguous (row stride L) in LDS; NT threads.
-// tw[m] = exp(-2 pi i m / L) in LDS; the inverse uses its conjugate.
+// nrows rows of length L in the padded layout; NT threads.  tw[m] = exp(-2 pi i m/L)
+// in LDS; the inverse uses its conjugate.
 template <typename R, int SIGN, int L, int NT, int S, int NS>
 struct Stages {
   __device__ __forceinline__ static cplx<R>* run(cplx<R>* src, cplx<R>* dst, const cplx<R>* tw,
@@ -141,12 +152,15 @@ struct Stages {
       for (int b = tid; b < total; b += NT) {
         const int row = b / LR;
         const int j = b - row * LR;
-        const cplx<R>* in = src + row * L;
-        cplx<R>* out = dst + row * L;
+        const cplx<R>* in = src + row * Lay<L>::RS;
+        cplx<R>* out = dst + row * Lay<L>::RS;
         const int k = j % NS;
         cplx<R> v[RAD];
 #pragma unroll
-        for (int q = 0; q < RAD; ++q) v[q] = in[j + q * LR];
+        for (int q = 0; q < RAD; ++q) {
+          const int i = j + q * LR;
+          v[q] = in[i + (i >> 3)];
+        }
         if constexpr (NS > 1) {
 #pragma unroll
           for (int q = 1; q < RAD; ++q) {
@@ -158,7 +172,10 @@ struct Stages {
         Bfly<R, SIGN, RAD>::run(v);
         const int base = (j / NS) * NS * RAD + k;
 #pragma unroll
-        for (int q = 0; q < RAD; ++q) out[base + q * NS] = v[q];
+        for (int q = 0; q < RAD; ++q) {
+          const int i = base + q * NS;
+          out[i + (i >> 3)] = v[q];
+        }
       }
       __syncthreads();
       return Stages<R, SIGN, L, NT, S + 1, NS * RAD>::run(dst, src, tw, nrows, tid);
@@ -166,7 +183,7 @@ struct Stages {
   }
 };
 
-// In-LDS FFT of nrows contiguous rows of length L; returns the buffer that
+// In-LDS FFT of nrows rows of length L (padded layout); returns the buffer that
 // holds the result (a or b).  Callers __syncthreads() before (data and
 // twiddles in place); the routine ends with a barrier.
 template <typename R, int SIGN, int L, int NT>

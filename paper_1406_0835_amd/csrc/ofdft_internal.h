@@ -38,6 +38,7 @@ struct EvalParams {
   int functional;
   int xc;
   double T;           // hartree
+  double lt0;         // ln t = lt0 - (2/3) ln n
   double alpha_sum;   // sum_I alpha_I (G = 0 remainder of the pseudopotential)
   double E_ion;
   double enh_kind, enh_c1, enh_a1;   // enhancement-factor parameters (kind as double)
@@ -132,5 +133,7 @@ int dev_tn_hess_finish(ofdft_ctx* c, double* hs, const double* phi, const double
                        double mu_term);
 int dev_read(ofdft_ctx* c, const double* dptr, int n, double* host);
 int dev_sync(ofdft_ctx* c);
+// largest dynamic LDS (bytes) any evaluation kernel needs with the tiles in c->g
+size_t dev_max_lds(const ofdft_ctx* c);
 
 }  // namespace ofdft

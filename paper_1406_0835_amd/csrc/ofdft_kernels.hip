@@ -105,8 +105,8 @@ __device__ __forceinline__ void store_half_spectra(const cplx<R>* res, cplx<R>* 
   constexpr int LH = L / 2 + 1;
   for (int e = threadIdx.x; e < LH * tr; e += NT) {
     const int k3 = e / tr, r = e - k3 * tr, p = r >> 1;
-    const cplx<R> z = res[p * L + k3];
-    const cplx<R> zc = cconj(res[p * L + ((L - k3) % L)]);
+    const cplx<R> z = res[Lay<L>::at(p, k3)];
+    const cplx<R> zc = cconj(res[Lay<L>::at(p, (L - k3) % L)]);
     cplx<R> X;
     if ((r & 1) == 0) {
       X = {R(0.5) * (z.x + zc.x), R(0.5) * (z.y + zc.y)};
@@ -119,7 +119,8 @@ __device__ __forceinline__ void store_half_spectra(const cplx<R>* res, cplx<R>* 
 
 // Load a transposed half-spectrum tile S[k3][i1][i2_0 + r] (staging in LDS)
 // and build z_p[k] = X_{2p}[k] + i X_{2p+1}[k] over the full k range using
-// Hermitian symmetry.  stage must hold (L/2+1)*tr elements; z holds tr/2 rows.
+// Hermitian symmetry.  stage must hold (L/2+1)*tr elements; z holds tr/2 rows
+// in the padded row layout.
 template <typename R, int L>
 __device__ __forceinline__ void load_pack_half_spectra(const cplx<R>* in, cplx<R>* stage, cplx<R>* z,
                                                        const GridDesc& g, int i1, int i2_0, int tr) {
@@ -129,8 +130,9 @@ __device__ __forceinline__ void load_pack_half_spectra(const cplx<R>* in, cplx<R
     stage[e] = in[((size_t)k3 * g.n1 + i1) * g.n2 + i2_0 + r];
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < (tr / 2) * L; e += NT) {
-    const int p = e / L, k = e - p * L;
+  const int hp = tr >> 1;
+  for (int e = threadIdx.x; e < hp * L; e += NT) {
+    const int k = e / hp, p = e - k * hp;
     cplx<R> xa, xb;
     if (2 * k <= L) {
       xa = stage[k * tr + 2 * p];
@@ -139,9 +141,16 @@ __device__ __forceinline__ void load_pack_half_spectra(const cplx<R>* in, cplx<R
       xa = cconj(stage[(L - k) * tr + 2 * p]);
       xb = cconj(stage[(L - k) * tr + 2 * p + 1]);
     }
-    z[e] = {xa.x - xb.y, xa.y + xb.x};
+    z[Lay<L>::at(p, k)] = {xa.x - xb.y, xa.y + xb.x};
   }
   __syncthreads();
+}
+
+// LDS elements of the second row buffer of the contiguous-axis passes: it
+// also stages a transposed half-spectrum tile of (L/2+1)*tr elements.
+template <int L>
+__host__ __device__ constexpr int zb_elems(int tr) {
+  return ((tr / 2) * Lay<L>::RS > (L / 2 + 1) * tr) ? (tr / 2) * Lay<L>::RS : (L / 2 + 1) * tr;
 }
 
 // ---------------------------------------------------------------- K1: density, x3 forward
@@ -152,8 +161,8 @@ __global__ void __launch_bounds__(NT) k_rpass_fwd_density(const double* __restri
   extern __shared__ __align__(16) char smem_raw[];
   const int tr = g.tr;
   Smem sm(smem_raw);
-  cplx<R>* za = sm.take<cplx<R>>((tr / 2) * L);
-  cplx<R>* zb = sm.take<cplx<R>>((tr / 2) * L);
+  cplx<R>* za = sm.take<cplx<R>>((tr / 2) * Lay<L>::RS);
+  cplx<R>* zb = sm.take<cplx<R>>((tr / 2) * Lay<L>::RS);
   cplx<R>* tw = sm.take<cplx<R>>(L);
   double* red = sm.take<double>(NT / 64);
   const int i1 = blockIdx.y, i2_0 = blockIdx.x * tr;
@@ -165,7 +174,7 @@ __global__ void __launch_bounds__(NT) k_rpass_fwd_density(const double* __restri
     const double p = phi[base + e];
     const double n = p * p;
     acc += n;
-    zr[2 * ((r >> 1) * L + i3) + (r & 1)] = R(n);
+    zr[2 * Lay<L>::at(r >> 1, i3) + (r & 1)] = R(n);
   }
   for (int m = threadIdx.x; m < L; m += NT) tw[m] = tw_g[m];
   __syncthreads();
@@ -186,18 +195,24 @@ __global__ void __launch_bounds__(NT) k_cpass_x2(Arr3 arrs, const cplx<R>* __res
                                                  int rb) {
   extern __shared__ __align__(16) char smem_raw[];
   Smem sm(smem_raw);
-  cplx<R>* a = sm.take<cplx<R>>(rb * L);
-  cplx<R>* b = sm.take<cplx<R>>(rb * L);
+  cplx<R>* a = sm.take<cplx<R>>(rb * Lay<L>::RS);
+  cplx<R>* b = sm.take<cplx<R>>(rb * Lay<L>::RS);
   cplx<R>* tw = sm.take<cplx<R>>(L);
   cplx<R>* x = reinterpret_cast<cplx<R>*>(arrs.p[blockIdx.y]);
   const long long row0 = (long long)blockIdx.x * rb;
   const int nr = (int)min<long long>(rb, nrows - row0);
   cplx<R>* base = x + row0 * L;
-  for (int e = threadIdx.x; e < rb * L; e += NT) a[e] = (e < nr * L) ? base[e] : cplx<R>{R(0), R(0)};
+  for (int e = threadIdx.x; e < rb * L; e += NT) {
+    const int row = e / L, col = e - row * L;
+    a[Lay<L>::at(row, col)] = (e < nr * L) ? base[e] : cplx<R>{R(0), R(0)};
+  }
   for (int m = threadIdx.x; m < L; m += NT) tw[m] = tw_g[m];
   __syncthreads();
   const cplx<R>* res = lds_fft<R, SIGN, L, NT>(a, b, tw, rb, threadIdx.x);
-  for (int e = threadIdx.x; e < nr * L; e += NT) base[e] = res[e];
+  for (int e = threadIdx.x; e < nr * L; e += NT) {
+    const int row = e / L, col = e - row * L;
+    base[e] = res[Lay<L>::at(row, col)];
+  }
 }
 
 // ---------------------------------------------------------------- K3: x1 pass + density ops
@@ -212,16 +227,16 @@ __global__ void __launch_bounds__(NT) k_x1_density(const cplx<R>* __restrict__ A
   extern __shared__ __align__(16) char smem_raw[];
   const int tc = g.tc;
   Smem sm(smem_raw);
-  cplx<R>* b0 = sm.take<cplx<R>>(tc * L);
-  cplx<R>* b1 = sm.take<cplx<R>>(tc * L);
-  cplx<R>* b2 = sm.take<cplx<R>>(tc * L);
+  cplx<R>* b0 = sm.take<cplx<R>>(tc * Lay<L>::RS);
+  cplx<R>* b1 = sm.take<cplx<R>>(tc * Lay<L>::RS);
+  cplx<R>* b2 = sm.take<cplx<R>>(tc * Lay<L>::RS);
   cplx<R>* tw = sm.take<cplx<R>>(L);
   double* red = sm.take<double>(2 * NT / 64);
   const int k3 = blockIdx.y, i2_0 = blockIdx.x * tc;
   const size_t plane = (size_t)k3 * g.n1 * g.n2;
   for (int e = threadIdx.x; e < L * tc; e += NT) {
     const int i1 = e / tc, c = e - i1 * tc;
-    b0[c * L + i1] = A[plane + (size_t)i1 * g.n2 + i2_0 + c];
+    b0[Lay<L>::at(c, i1)] = A[plane + (size_t)i1 * g.n2 + i2_0 + c];
   }
   for (int m = threadIdx.x; m < L; m += NT) tw[m] = tw_g[m];
   __syncthreads();
@@ -234,7 +249,7 @@ __global__ void __launch_bounds__(NT) k_x1_density(const cplx<R>* __restrict__ A
   for (int e = threadIdx.x; e < L * tc; e += NT) {
     const int k1 = e / tc, c = e - k1 * tc;
     const int k2 = i2_0 + c;
-    const int idx = c * L + k1;
+    const int idx = Lay<L>::at(c, k1);
     const size_t gi = plane + (size_t)k1 * g.n2 + k2;
     double gx, gy, gz;
     const bool keep = gvec(g, k1, k2, k3, gx, gy, gz);
@@ -276,7 +291,7 @@ __global__ void __launch_bounds__(NT) k_x1_density(const cplx<R>* __restrict__ A
     const cplx<R>* o = lds_fft<R, +1, L, NT>(res, fa, tw, tc, threadIdx.x);
     for (int e = threadIdx.x; e < L * tc; e += NT) {
       const int i1 = e / tc, c = e - i1 * tc;
-      out0[plane + (size_t)i1 * g.n2 + i2_0 + c] = o[c * L + i1];
+      out0[plane + (size_t)i1 * g.n2 + i2_0 + c] = o[Lay<L>::at(c, i1)];
     }
   } else if constexpr (MODE == X1_GGA) {
     cplx<R>* outs[3] = {out0, out1, out2};
@@ -287,15 +302,16 @@ __global__ void __launch_bounds__(NT) k_x1_density(const cplx<R>* __restrict__ A
         double gv[3];
         gvec(g, k1, i2_0 + c, k3, gv[0], gv[1], gv[2]);
         const R ga = R(gv[a]);
-        const cplx<R> z = res[e];
-        fa[e] = {-ga * z.y, ga * z.x};
+        const int idx = Lay<L>::at(c, k1);
+        const cplx<R> z = res[idx];
+        fa[idx] = {-ga * z.y, ga * z.x};
       }
       __syncthreads();
       const cplx<R>* o = lds_fft<R, +1, L, NT>(fa, fb, tw, tc, threadIdx.x);
       cplx<R>* dst = outs[a];
       for (int e = threadIdx.x; e < L * tc; e += NT) {
         const int i1 = e / tc, c = e - i1 * tc;
-        dst[plane + (size_t)i1 * g.n2 + i2_0 + c] = o[c * L + i1];
+        dst[plane + (size_t)i1 * g.n2 + i2_0 + c] = o[Lay<L>::at(c, i1)];
       }
       __syncthreads();
     }
@@ -313,8 +329,8 @@ __global__ void __launch_bounds__(NT) k_rpass_gga(cplx<R>* __restrict__ B0, cplx
   const int tr = g.tr;
   constexpr int LH = L / 2 + 1;
   Smem sm(smem_raw);
-  cplx<R>* za = sm.take<cplx<R>>((tr / 2) * L);
-  cplx<R>* zb = sm.take<cplx<R>>((tr / 2) * L + tr);
+  cplx<R>* za = sm.take<cplx<R>>((tr / 2) * Lay<L>::RS);
+  cplx<R>* zb = sm.take<cplx<R>>(zb_elems<L>(tr));
   cplx<R>* tw = sm.take<cplx<R>>(L);
   R* gr = sm.take<R>(3 * tr * L);
   double* red = sm.take<double>(3 * NT / 64);
@@ -330,7 +346,7 @@ __global__ void __launch_bounds__(NT) k_rpass_gga(cplx<R>* __restrict__ B0, cplx
     R* ga = gr + a * tr * L;
     for (int e = threadIdx.x; e < (tr / 2) * L; e += NT) {
       const int p = e / L, i3 = e - p * L;
-      const cplx<R> z = res[e];
+      const cplx<R> z = res[Lay<L>::at(p, i3)];
       ga[(2 * p) * L + i3] = z.x;
       ga[(2 * p + 1) * L + i3] = z.y;
     }
@@ -346,13 +362,13 @@ __global__ void __launch_bounds__(NT) k_rpass_gga(cplx<R>* __restrict__ B0, cplx
     const R sigma = gx * gx + gy * gy + gz * gz;
     double f, tsl;
     R dfdn, dfds;
-    gga_point<R>(nf, sigma, ep.T, enh, f, dfdn, dfds, tsl);
+    gga_point<R>(nf, sigma, ep.lt0, enh, f, dfdn, dfds, tsl);
     R vl = dfdn;
     if (ep.xc) {
-      double eps, vxc;
-      pz81<double>(nf, eps, vxc);
-      vl += R(vxc);
-      exc += n * eps;
+      R eps, vxc;
+      pz81<R>(R(nf), eps, vxc);
+      vl += vxc;
+      exc += n * double(eps);
     }
     vloc[base + e] = vl;
     fs += f;
@@ -369,7 +385,7 @@ __global__ void __launch_bounds__(NT) k_rpass_gga(cplx<R>* __restrict__ B0, cplx
     const R* wa = gr + a * tr * L;
     for (int e = threadIdx.x; e < tr * L; e += NT) {
       const int r = e / L, i3 = e - r * L;
-      zr[2 * ((r >> 1) * L + i3) + (r & 1)] = wa[e];
+      zr[2 * Lay<L>::at(r >> 1, i3) + (r & 1)] = wa[e];
     }
     __syncthreads();
     const cplx<R>* res = lds_fft<R, -1, L, NT>(za, zb, tw, tr / 2, threadIdx.x);
@@ -395,15 +411,15 @@ __global__ void __launch_bounds__(NT) k_x1_divergence(const cplx<R>* __restrict_
   extern __shared__ __align__(16) char smem_raw[];
   const int tc = g.tc;
   Smem sm(smem_raw);
-  cplx<R>* acc = sm.take<cplx<R>>(tc * L);
-  cplx<R>* b0 = sm.take<cplx<R>>(tc * L);
-  cplx<R>* b1 = sm.take<cplx<R>>(tc * L);
+  cplx<R>* acc = sm.take<cplx<R>>(tc * Lay<L>::RS);
+  cplx<R>* b0 = sm.take<cplx<R>>(tc * Lay<L>::RS);
+  cplx<R>* b1 = sm.take<cplx<R>>(tc * Lay<L>::RS);
   cplx<R>* tw = sm.take<cplx<R>>(L);
   const int k3 = blockIdx.y, i2_0 = blockIdx.x * tc;
   const size_t plane = (size_t)k3 * g.n1 * g.n2;
   for (int e = threadIdx.x; e < L * tc; e += NT) {
     const int i1 = e / tc, c = e - i1 * tc;
-    acc[c * L + i1] = s0[plane + (size_t)i1 * g.n2 + i2_0 + c];
+    acc[Lay<L>::at(c, i1)] = s0[plane + (size_t)i1 * g.n2 + i2_0 + c];
   }
   for (int m = threadIdx.x; m < L; m += NT) tw[m] = tw_g[m];
   const cplx<R>* Cs[3] = {C0, C1, C2};
@@ -412,7 +428,7 @@ __global__ void __launch_bounds__(NT) k_x1_divergence(const cplx<R>* __restrict_
   for (int a = 0; a < 3; ++a) {
     for (int e = threadIdx.x; e < L * tc; e += NT) {
       const int i1 = e / tc, c = e - i1 * tc;
-      b0[c * L + i1] = Cs[a][plane + (size_t)i1 * g.n2 + i2_0 + c];
+      b0[Lay<L>::at(c, i1)] = Cs[a][plane + (size_t)i1 * g.n2 + i2_0 + c];
     }
     __syncthreads();
     const cplx<R>* res = lds_fft<R, -1, L, NT>(b0, b1, tw, tc, threadIdx.x);
@@ -422,10 +438,11 @@ __global__ void __launch_bounds__(NT) k_x1_divergence(const cplx<R>* __restrict_
       const bool keep = gvec(g, k1, i2_0 + c, k3, gv[0], gv[1], gv[2]);
       if (keep) {
         const R ga = R(gv[a]) * inv_n;
-        const cplx<R> z = res[e];
+        const int idx = Lay<L>::at(c, k1);
+        const cplx<R> z = res[idx];
         // acc -= i G_a W_a(G)
-        acc[e].x += ga * z.y;
-        acc[e].y -= ga * z.x;
+        acc[idx].x += ga * z.y;
+        acc[idx].y -= ga * z.x;
       }
     }
     __syncthreads();
@@ -433,7 +450,7 @@ __global__ void __launch_bounds__(NT) k_x1_divergence(const cplx<R>* __restrict_
   const cplx<R>* o = lds_fft<R, +1, L, NT>(acc, b0, tw, tc, threadIdx.x);
   for (int e = threadIdx.x; e < L * tc; e += NT) {
     const int i1 = e / tc, c = e - i1 * tc;
-    out[plane + (size_t)i1 * g.n2 + i2_0 + c] = o[c * L + i1];
+    out[plane + (size_t)i1 * g.n2 + i2_0 + c] = o[Lay<L>::at(c, i1)];
   }
 }
 
@@ -446,8 +463,8 @@ __global__ void __launch_bounds__(NT) k_rpass_final(const cplx<R>* __restrict__ 
   extern __shared__ __align__(16) char smem_raw[];
   const int tr = g.tr;
   Smem sm(smem_raw);
-  cplx<R>* za = sm.take<cplx<R>>((tr / 2) * L);
-  cplx<R>* zb = sm.take<cplx<R>>((tr / 2) * L + tr);
+  cplx<R>* za = sm.take<cplx<R>>((tr / 2) * Lay<L>::RS);
+  cplx<R>* zb = sm.take<cplx<R>>(zb_elems<L>(tr));
   cplx<R>* tw = sm.take<cplx<R>>(L);
   double* red = sm.take<double>(4 * NT / 64);
   const int i1 = blockIdx.y, i2_0 = blockIdx.x * tr;
@@ -458,7 +475,7 @@ __global__ void __launch_bounds__(NT) k_rpass_final(const cplx<R>* __restrict__ 
   double fs = 0.0, ts = 0.0, exc = 0.0, nv = 0.0;
   for (int e = threadIdx.x; e < tr * L; e += NT) {
     const int r = e / L, i3 = e - r * L;
-    const cplx<R> z = res[(r >> 1) * L + i3];
+    const cplx<R> z = res[Lay<L>::at(r >> 1, i3)];
     const double S = (r & 1) ? double(z.y) : double(z.x);
     const double p = phi[base + e];
     const double n = p * p;
@@ -466,15 +483,15 @@ __global__ void __launch_bounds__(NT) k_rpass_final(const cplx<R>* __restrict__ 
     if constexpr (TF) {
       const double nf = n > kDensityFloor ? n : kDensityFloor;
       double f, vt, tsl;
-      tf_point(nf, ep.T, f, vt, tsl);
+      tf_point(nf, ep.lt0, f, vt, tsl);
       vl = vt;
       fs += f;
       ts += tsl;
       if (ep.xc) {
-        double eps, vxc;
-        pz81<double>(nf, eps, vxc);
-        vl += vxc;
-        exc += n * eps;
+        R eps, vxc;
+        pz81<R>(R(nf), eps, vxc);
+        vl += double(vxc);
+        exc += n * double(eps);
       }
     } else {
       vl = double(vloc[base + e]);
@@ -506,18 +523,17 @@ struct ReduceParams {
   double dv, volume, alpha_sum, E_ion;
 };
 
-__global__ void __launch_bounds__(NT) k_reduce_scalars(const double* __restrict__ partials, int maxb,
-                                                       ReduceParams rp, double* __restrict__ sc) {
-  __shared__ double red[NT / 64];
+constexpr int RED_NT = 64 * SL_COUNT;   // one wavefront per slot
+
+__global__ void __launch_bounds__(RED_NT) k_reduce_scalars(const double* __restrict__ partials, int maxb,
+                                                           ReduceParams rp, double* __restrict__ sc) {
   __shared__ double raw[SL_COUNT];
-  for (int s = 0; s < SL_COUNT; ++s) {
-    const int cnt = (s == SL_EH || s == SL_EEXT) ? rp.nb_x1 : rp.nb_r;
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < cnt; i += NT) acc += partials[s * maxb + i];
-    double v[1] = {acc};
-    block_sum<1>(v, red);
-    if (threadIdx.x == 0) raw[s] = v[0];
-  }
+  const int s = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int cnt = (s == SL_EH || s == SL_EEXT) ? rp.nb_x1 : rp.nb_r;
+  double acc = 0.0;
+  for (int i = lane; i < cnt; i += 64) acc += partials[s * maxb + i];
+  acc = wave_sum(acc);
+  if (lane == 0) raw[s] = acc;
   __syncthreads();
   if (threadIdx.x == 0) {
     const double Ne = rp.dv * raw[SL_PHI2];
@@ -785,29 +801,30 @@ static inline bool hip_ok(ofdft_ctx* c, hipError_t e, const char* what) {
 int dev_upload_tables() {
   static bool done = false;
   if (done) return OFDFT_OK;
-  if (hipMemcpyToSymbol(HIP_SYMBOL(c_fd_cheb), kFdCheb, sizeof(kFdCheb)) != hipSuccess) return OFDFT_E_DEVICE;
-  if (hipMemcpyToSymbol(HIP_SYMBOL(c_guess_cheb), kGuessCheb, sizeof(kGuessCheb)) != hipSuccess)
-    return OFDFT_E_DEVICE;
+  if (hipMemcpyToSymbol(HIP_SYMBOL(c_t_gga), kTGga, sizeof(kTGga)) != hipSuccess) return OFDFT_E_DEVICE;
+  if (hipMemcpyToSymbol(HIP_SYMBOL(c_t_tf), kTTf, sizeof(kTTf)) != hipSuccess) return OFDFT_E_DEVICE;
+  if (hipMemcpyToSymbol(HIP_SYMBOL(c_t_cell), kTCell, sizeof(kTCell)) != hipSuccess) return OFDFT_E_DEVICE;
+  if (hipMemcpyToSymbol(HIP_SYMBOL(c_t_bound), kTBound, sizeof(kTBound)) != hipSuccess) return OFDFT_E_DEVICE;
   done = true;
   return OFDFT_OK;
 }
 
-template <typename R>
-static size_t lds_rpass_fwd(int L, int tr) {
-  return 2 * pad16<cplx<R>>((tr / 2) * L) + pad16<cplx<R>>(L) + pad16<double>(NT / 64);
+template <typename R, int L>
+static size_t lds_rpass_fwd(int tr) {
+  return 2 * pad16<cplx<R>>((tr / 2) * Lay<L>::RS) + pad16<cplx<R>>(L) + pad16<double>(NT / 64);
 }
-template <typename R>
-static size_t lds_rpass_inv(int L, int tr, int extra_real, int nred) {
-  return pad16<cplx<R>>((tr / 2) * L) + pad16<cplx<R>>((tr / 2) * L + tr) + pad16<cplx<R>>(L) +
+template <typename R, int L>
+static size_t lds_rpass_inv(int tr, int extra_real, int nred) {
+  return pad16<cplx<R>>((tr / 2) * Lay<L>::RS) + pad16<cplx<R>>(zb_elems<L>(tr)) + pad16<cplx<R>>(L) +
          pad16<R>((size_t)extra_real * tr * L) + pad16<double>((size_t)nred * NT / 64);
 }
-template <typename R>
-static size_t lds_x1(int L, int tc, int nred) {
-  return 3 * pad16<cplx<R>>((size_t)tc * L) + pad16<cplx<R>>(L) + pad16<double>((size_t)nred * NT / 64);
+template <typename R, int L>
+static size_t lds_x1(int tc, int nred) {
+  return 3 * pad16<cplx<R>>((size_t)tc * Lay<L>::RS) + pad16<cplx<R>>(L) + pad16<double>((size_t)nred * NT / 64);
 }
-template <typename R>
-static size_t lds_x2(int L, int rb) {
-  return 2 * pad16<cplx<R>>((size_t)rb * L) + pad16<cplx<R>>(L);
+template <typename R, int L>
+static size_t lds_x2(int rb) {
+  return 2 * pad16<cplx<R>>((size_t)rb * Lay<L>::RS) + pad16<cplx<R>>(L);
 }
 
 // Timing hook: record an event before each launch when enabled.
@@ -829,7 +846,7 @@ template <typename R, int L>
 static void launch_rpass_fwd(ofdft_ctx* c, const double* phi, void* out) {
   const GridDesc& g = c->g;
   dim3 grid(g.n2 / g.tr, g.n1);
-  hipLaunchKernelGGL((k_rpass_fwd_density<R, L>), grid, dim3(NT), lds_rpass_fwd<R>(L, g.tr), c->stream, phi,
+  hipLaunchKernelGGL((k_rpass_fwd_density<R, L>), grid, dim3(NT), (lds_rpass_fwd<R, L>(g.tr)), c->stream, phi,
                      (cplx<R>*)out, (const cplx<R>*)c->tw[2], g, c->partials, c->max_blocks);
 }
 
@@ -839,7 +856,7 @@ static void launch_x2(ofdft_ctx* c, void* a0, void* a1, void* a2, int narr) {
   const long long nrows = (long long)g.n3h * g.n1;
   dim3 grid((unsigned)((nrows + g.rb - 1) / g.rb), narr);
   Arr3 arr{{a0, a1, a2}};
-  hipLaunchKernelGGL((k_cpass_x2<R, L, SIGN>), grid, dim3(NT), lds_x2<R>(L, g.rb), c->stream, arr,
+  hipLaunchKernelGGL((k_cpass_x2<R, L, SIGN>), grid, dim3(NT), (lds_x2<R, L>(g.rb)), c->stream, arr,
                      (const cplx<R>*)c->tw[1], nrows, g.rb);
 }
 
@@ -847,7 +864,7 @@ template <typename R, int L, int MODE>
 static void launch_x1_density(ofdft_ctx* c, void* out0, void* out1, void* out2) {
   const GridDesc& g = c->g;
   dim3 grid(g.n2 / g.tc, g.n3h);
-  hipLaunchKernelGGL((k_x1_density<R, L, MODE>), grid, dim3(NT), lds_x1<R>(L, g.tc, 2), c->stream,
+  hipLaunchKernelGGL((k_x1_density<R, L, MODE>), grid, dim3(NT), (lds_x1<R, L>(g.tc, 2)), c->stream,
                      (const cplx<R>*)c->A, (const cplx<R>*)c->Vext, (cplx<R>*)out0, (cplx<R>*)out1,
                      (cplx<R>*)out2, (cplx<R>*)c->S0, (const cplx<R>*)c->tw[0], g, c->partials, c->max_blocks);
 }
@@ -856,7 +873,7 @@ template <typename R, int L>
 static void launch_rpass_gga(ofdft_ctx* c, const double* phi, const EvalParams& ep) {
   const GridDesc& g = c->g;
   dim3 grid(g.n2 / g.tr, g.n1);
-  hipLaunchKernelGGL((k_rpass_gga<R, L>), grid, dim3(NT), lds_rpass_inv<R>(L, g.tr, 3, 3), c->stream,
+  hipLaunchKernelGGL((k_rpass_gga<R, L>), grid, dim3(NT), (lds_rpass_inv<R, L>(g.tr, 3, 3)), c->stream,
                      (cplx<R>*)c->B[0], (cplx<R>*)c->B[1], (cplx<R>*)c->B[2], phi, (R*)c->vloc,
                      (const cplx<R>*)c->tw[2], g, ep, c->partials, c->max_blocks);
 }
@@ -865,7 +882,7 @@ template <typename R, int L>
 static void launch_x1_div(ofdft_ctx* c) {
   const GridDesc& g = c->g;
   dim3 grid(g.n2 / g.tc, g.n3h);
-  hipLaunchKernelGGL((k_x1_divergence<R, L>), grid, dim3(NT), lds_x1<R>(L, g.tc, 0), c->stream,
+  hipLaunchKernelGGL((k_x1_divergence<R, L>), grid, dim3(NT), (lds_x1<R, L>(g.tc, 0)), c->stream,
                      (const cplx<R>*)c->B[0], (const cplx<R>*)c->B[1], (const cplx<R>*)c->B[2],
                      (const cplx<R>*)c->S0, (cplx<R>*)c->D, (const cplx<R>*)c->tw[0], g);
 }
@@ -874,7 +891,7 @@ template <typename R, int L, bool TF>
 static void launch_rpass_final(ofdft_ctx* c, const double* phi, void* v_out, const EvalParams& ep) {
   const GridDesc& g = c->g;
   dim3 grid(g.n2 / g.tr, g.n1);
-  hipLaunchKernelGGL((k_rpass_final<R, L, TF>), grid, dim3(NT), lds_rpass_inv<R>(L, g.tr, 0, 4), c->stream,
+  hipLaunchKernelGGL((k_rpass_final<R, L, TF>), grid, dim3(NT), (lds_rpass_inv<R, L>(g.tr, 0, 4)), c->stream,
                      (const cplx<R>*)c->D, phi, (const R*)c->vloc, (R*)v_out, (const cplx<R>*)c->tw[2], g, ep,
                      c->partials, c->max_blocks);
 }
@@ -900,6 +917,7 @@ static EvalParams make_params(ofdft_ctx* c) {
   ep.functional = c->opt.functional;
   ep.xc = c->opt.xc == OFDFT_XC_PZ81 ? 1 : 0;
   ep.T = c->T_ha;
+  ep.lt0 = lt_offset(c->T_ha);
   ep.alpha_sum = c->alpha_sum;
   ep.E_ion = c->E_ion;
   switch (c->opt.functional) {
@@ -949,10 +967,42 @@ static int eval_impl(ofdft_ctx* c, const double* phi, void* v_out, double* sc) {
   }
   ReduceParams rp{(g.n2 / g.tr) * g.n1, (g.n2 / g.tc) * g.n3h, g.dv, g.volume, c->alpha_sum, c->E_ion};
   tmark(c, "reduce_scalars");
-  hipLaunchKernelGGL(k_reduce_scalars, dim3(1), dim3(NT), 0, c->stream, c->partials, c->max_blocks, rp, sc);
+  hipLaunchKernelGGL(k_reduce_scalars, dim3(1), dim3(RED_NT), 0, c->stream, c->partials, c->max_blocks, rp, sc);
   tmark(c, "end");
   hipError_t e = hipGetLastError();
   return hip_ok(c, e, "eval launch") ? OFDFT_OK : OFDFT_E_DEVICE;
+}
+
+template <typename R>
+static size_t max_lds_impl(const ofdft_ctx* c) {
+  const GridDesc& g = c->g;
+  size_t m = 0;
+  auto upd = [&](size_t v) { m = v > m ? v : m; };
+  switch (g.n3) {
+#define OFDFT_LDS3(LEN) \
+    case LEN: upd(lds_rpass_fwd<R, LEN>(g.tr)); upd(lds_rpass_inv<R, LEN>(g.tr, 3, 3)); \
+              upd(lds_rpass_inv<R, LEN>(g.tr, 0, 4)); break;
+    OFDFT_LENGTHS(OFDFT_LDS3)
+#undef OFDFT_LDS3
+    default: break;
+  }
+  switch (g.n2) {
+#define OFDFT_LDS2(LEN) case LEN: upd(lds_x2<R, LEN>(g.rb)); break;
+    OFDFT_LENGTHS(OFDFT_LDS2)
+#undef OFDFT_LDS2
+    default: break;
+  }
+  switch (g.n1) {
+#define OFDFT_LDS1(LEN) case LEN: upd(lds_x1<R, LEN>(g.tc, 2)); break;
+    OFDFT_LENGTHS(OFDFT_LDS1)
+#undef OFDFT_LDS1
+    default: break;
+  }
+  return m;
+}
+
+size_t dev_max_lds(const ofdft_ctx* c) {
+  return c->rsize == 4 ? max_lds_impl<float>(c) : max_lds_impl<double>(c);
 }
 
 int dev_eval(ofdft_ctx* c, const double* phi, void* v_out, double* sc) {
@@ -1017,7 +1067,8 @@ int dev_alloc_grid(ofdft_ctx* c) {
   ok = ok && dalloc_bytes(c, &c->A, NS * 2 * rs) && dalloc_bytes(c, &c->S0, NS * 2 * rs) &&
        dalloc_bytes(c, &c->D, NS * 2 * rs) && dalloc_bytes(c, &c->Vext, NS * 2 * rs);
   for (int k = 0; k < 3 && ok; ++k) ok = dalloc_bytes(c, &c->B[k], NS * 2 * rs);
-  const int nb_r = (g.n2 / g.tr) * g.n1, nb_x1 = (g.n2 / g.tc) * g.n3h;
+  // sized for the smallest tiles the tuner may pick (2 rows / 2 columns per block)
+  const int nb_r = (g.n2 / 2) * g.n1, nb_x1 = (g.n2 / 2) * g.n3h;
   c->max_blocks = nb_r > nb_x1 ? nb_r : nb_x1;
   ok = ok && dalloc(c, &c->partials, (size_t)SL_COUNT * c->max_blocks) && dalloc(c, &c->scalars, SC_COUNT) &&
        dalloc(c, &c->scalars_t, SC_COUNT) && dalloc(c, &c->vpart, 8 * VEC_BLOCKS) && dalloc(c, &c->vout, 16);
