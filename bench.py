@@ -54,7 +54,9 @@ def kernel_bytes(name: str, n1: int, n2: int, n3: int, rsize: int) -> float:
         "x1_density_gradient": 6 * CS,
         "x1_density_hartree": 3 * CS,
         "cpass_x2_inv3": 6 * CS,
-        "rpass_gga_pointwise": 6 * CS + P + RR,
+        "rpass_inv_grad3": 3 * CS + 3 * RR,
+        "pointwise_gga": P + 7 * RR,
+        "rpass_fwd_w3": 3 * CS + 3 * RR,
         "cpass_x2_fwd3": 6 * CS,
         "x1_divergence": 5 * CS,
         "cpass_x2_inv": 2 * CS,

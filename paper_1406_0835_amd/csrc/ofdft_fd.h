@@ -20,9 +20,9 @@ __constant__ double c_t_bound[2 * OFDFT_T_NP];
 constexpr double kPi = 3.14159265358979323846264338327950288;
 constexpr double kCTF = 2.87123400018819181594;       // (3/10)(3 pi^2)^(2/3)
 constexpr double kS2Den = 38.2831200025092242125;     // 4 (3 pi^2)^(2/3)
-constexpr double kThreePi2 = 29.6088132032680740;     // 3 pi^2
+constexpr double kThreePi2 = 29.6088132032680758565;  // 3 pi^2
 constexpr double kThreePi2_23 = 9.57078000062730605; // (3 pi^2)^(2/3)
-constexpr double kLn3Pi2 = 3.38808330116580843;       // ln(3 pi^2)
+constexpr double kLn3Pi2 = 3.38807206036691003968;     // ln(3 pi^2)
 constexpr double kDensityFloor = 1.0e-12;
 
 // NF Chebyshev series (coefficients c[f * NC + k]) at one x, sharing the T_k recurrence.
@@ -54,11 +54,20 @@ __device__ __forceinline__ void t_table(const double* __restrict__ table, double
   const int p = c_t_cell[cell];
   const double a = c_t_bound[2 * p], b = c_t_bound[2 * p + 1];
   const double x = (2.0 * l - a - b) / (b - a);
-  const int p0 = __builtin_amdgcn_readfirstlane(p);
-  if (__all(p == p0)) {
-    cheb_series<NF>(table + p0 * NF * OFDFT_T_NC, x, s);
-  } else {
-    cheb_series<NF>(table + p * NF * OFDFT_T_NC, x, s);
+  // Waterfall over the distinct pieces present in the wavefront: each pass
+  // serves the lanes of one piece with wave-uniform (scalar) coefficient loads.
+  bool done = false;
+  unsigned long long pending;
+  while ((pending = __ballot(!done)) != 0ull) {
+    const int first = __ffsll((long long)pending) - 1;
+    const int pm = __builtin_amdgcn_readlane(p, first);
+    double r[NF];
+    cheb_series<NF>(table + pm * NF * OFDFT_T_NC, x, r);
+    if (!done && p == pm) {
+#pragma unroll
+      for (int f = 0; f < NF; ++f) s[f] = r[f];
+      done = true;
+    }
   }
 }
 

@@ -83,6 +83,7 @@ struct ofdft_ctx {
   void* B[3] = {nullptr, nullptr, nullptr};
   void* S0 = nullptr;
   void* D = nullptr;
+  void* gr[3] = {nullptr, nullptr, nullptr};   // real grad n / W components (R)
   void* Vext = nullptr;
   void* tw[3] = {nullptr, nullptr, nullptr};   // twiddles per axis, cplx<R>[n_a]
   double* partials = nullptr;  // [SL_COUNT][max_blocks]

@@ -12,9 +12,10 @@
 //                       potential 4 pi n/G^2 + v_ext(G), and for gradient
 //                       functionals i G_a n(G) (Eq. s_0defn), inverse x1 FFT
 //   cpass x2 (inverse)
-//   rpass_gga_pointwise inverse x3 FFT of grad n, pointwise ftGGA + PZ81
-//                       (Eqs. FGGA..vftGGA), W = 2 df/dsigma grad n, forward
-//                       x3 FFT of W
+//   rpass_inv_grad3     inverse x3 FFT of the three components of grad n
+//   pointwise_gga       ftGGA + PZ81 at every point (Eqs. FGGA..vftGGA),
+//                       W = 2 df/dsigma grad n
+//   rpass_fwd_w3        forward x3 FFT of W
 //   cpass x2, x1_divergence   S = v_H + v_ext - i G.W(G) (last line of
 //                       Eq. vftGGA in reciprocal space), inverse x1 FFT
 //   cpass x2 (inverse)
@@ -318,47 +319,53 @@ __global__ void __launch_bounds__(NT) k_x1_density(const cplx<R>* __restrict__ A
   }
 }
 
-// ---------------------------------------------------------------- K4: gradient functional pointwise
+// ---------------------------------------------------------------- K4 split form
+// (a) inverse x3 FFT of one gradient component per block (blockIdx.z) into a
+// real array; (b) streaming pointwise functional; (c) forward x3 FFT of W.
+struct RealArr3 {
+  void* p[3];
+};
+
 template <typename R, int L>
-__global__ void __launch_bounds__(NT) k_rpass_gga(cplx<R>* __restrict__ B0, cplx<R>* __restrict__ B1,
-                                                  cplx<R>* __restrict__ B2, const double* __restrict__ phi,
-                                                  R* __restrict__ vloc, const cplx<R>* __restrict__ tw_g,
-                                                  GridDesc g, EvalParams ep, double* __restrict__ partials,
-                                                  int maxb) {
+__global__ void __launch_bounds__(NT) k_rpass_inv_real(Arr3 in, RealArr3 out, const cplx<R>* __restrict__ tw_g,
+                                                       GridDesc g) {
   extern __shared__ __align__(16) char smem_raw[];
   const int tr = g.tr;
-  constexpr int LH = L / 2 + 1;
   Smem sm(smem_raw);
   cplx<R>* za = sm.take<cplx<R>>((tr / 2) * Lay<L>::RS);
   cplx<R>* zb = sm.take<cplx<R>>(zb_elems<L>(tr));
   cplx<R>* tw = sm.take<cplx<R>>(L);
-  R* gr = sm.take<R>(3 * tr * L);
-  double* red = sm.take<double>(3 * NT / 64);
-  (void)LH;
   const int i1 = blockIdx.y, i2_0 = blockIdx.x * tr;
   const size_t base = ((size_t)i1 * g.n2 + i2_0) * L;
+  const cplx<R>* src = reinterpret_cast<const cplx<R>*>(in.p[blockIdx.z]);
+  R* dst = reinterpret_cast<R*>(out.p[blockIdx.z]);
   for (int m = threadIdx.x; m < L; m += NT) tw[m] = tw_g[m];
-  cplx<R>* Bs[3] = {B0, B1, B2};
-#pragma unroll 1
-  for (int a = 0; a < 3; ++a) {
-    load_pack_half_spectra<R, L>(Bs[a], zb, za, g, i1, i2_0, tr);
-    const cplx<R>* res = lds_fft<R, +1, L, NT>(za, zb, tw, tr / 2, threadIdx.x);
-    R* ga = gr + a * tr * L;
-    for (int e = threadIdx.x; e < (tr / 2) * L; e += NT) {
-      const int p = e / L, i3 = e - p * L;
-      const cplx<R> z = res[Lay<L>::at(p, i3)];
-      ga[(2 * p) * L + i3] = z.x;
-      ga[(2 * p + 1) * L + i3] = z.y;
-    }
-    __syncthreads();
+  load_pack_half_spectra<R, L>(src, zb, za, g, i1, i2_0, tr);
+  const cplx<R>* res = lds_fft<R, +1, L, NT>(za, zb, tw, tr / 2, threadIdx.x);
+  for (int e = threadIdx.x; e < tr * L; e += NT) {
+    const int r = e / L, i3 = e - r * L;
+    const cplx<R> z = res[Lay<L>::at(r >> 1, i3)];
+    dst[base + e] = (r & 1) ? z.y : z.x;
   }
+}
+
+constexpr int PW_BLOCKS = 2048;
+
+// Finite-T GGA + PZ81 at every point: v_loc = df/dn + v_xc, W = 2 df/dsigma grad n
+// (written over grad n), energy partial sums per block.
+template <typename R>
+__global__ void __launch_bounds__(NT) k_pointwise_gga(const double* __restrict__ phi, R* __restrict__ g0,
+                                                      R* __restrict__ g1, R* __restrict__ g2, R* __restrict__ vloc,
+                                                      long long npts, EvalParams ep, double* __restrict__ partials,
+                                                      int maxb) {
+  __shared__ double red[3 * NT / 64];
   EnhParams enh{(int)ep.enh_kind, ep.enh_c1, ep.enh_a1};
   double fs = 0.0, ts = 0.0, exc = 0.0;
-  for (int e = threadIdx.x; e < tr * L; e += NT) {
-    const double p = phi[base + e];
+  for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < npts; i += (long long)gridDim.x * NT) {
+    const double p = phi[i];
     const double n = p * p;
     const double nf = n > kDensityFloor ? n : kDensityFloor;
-    const R gx = gr[e], gy = gr[tr * L + e], gz = gr[2 * tr * L + e];
+    const R gx = g0[i], gy = g1[i], gz = g2[i];
     const R sigma = gx * gx + gy * gy + gz * gz;
     double f, tsl;
     R dfdn, dfds;
@@ -370,36 +377,45 @@ __global__ void __launch_bounds__(NT) k_rpass_gga(cplx<R>* __restrict__ B0, cplx
       vl += vxc;
       exc += n * double(eps);
     }
-    vloc[base + e] = vl;
+    vloc[i] = vl;
     fs += f;
     ts += tsl;
     const R w2 = R(2) * dfds;
-    gr[e] = w2 * gx;
-    gr[tr * L + e] = w2 * gy;
-    gr[2 * tr * L + e] = w2 * gz;
-  }
-  __syncthreads();
-  R* zr = reinterpret_cast<R*>(za);
-#pragma unroll 1
-  for (int a = 0; a < 3; ++a) {
-    const R* wa = gr + a * tr * L;
-    for (int e = threadIdx.x; e < tr * L; e += NT) {
-      const int r = e / L, i3 = e - r * L;
-      zr[2 * Lay<L>::at(r >> 1, i3) + (r & 1)] = wa[e];
-    }
-    __syncthreads();
-    const cplx<R>* res = lds_fft<R, -1, L, NT>(za, zb, tw, tr / 2, threadIdx.x);
-    store_half_spectra<R, L>(res, Bs[a], g, i1, i2_0, tr);
-    __syncthreads();
+    g0[i] = w2 * gx;
+    g1[i] = w2 * gy;
+    g2[i] = w2 * gz;
   }
   double v[3] = {fs, ts, exc};
   block_sum<3>(v, red);
   if (threadIdx.x == 0) {
-    const int blk = blockIdx.y * gridDim.x + blockIdx.x;
-    partials[SL_FS * maxb + blk] = v[0];
-    partials[SL_TS * maxb + blk] = v[1];
-    partials[SL_EXC * maxb + blk] = v[2];
+    partials[SL_FS * maxb + blockIdx.x] = v[0];
+    partials[SL_TS * maxb + blockIdx.x] = v[1];
+    partials[SL_EXC * maxb + blockIdx.x] = v[2];
   }
+}
+
+template <typename R, int L>
+__global__ void __launch_bounds__(NT) k_rpass_fwd_real(RealArr3 in, Arr3 out, const cplx<R>* __restrict__ tw_g,
+                                                       GridDesc g) {
+  extern __shared__ __align__(16) char smem_raw[];
+  const int tr = g.tr;
+  Smem sm(smem_raw);
+  cplx<R>* za = sm.take<cplx<R>>((tr / 2) * Lay<L>::RS);
+  cplx<R>* zb = sm.take<cplx<R>>((tr / 2) * Lay<L>::RS);
+  cplx<R>* tw = sm.take<cplx<R>>(L);
+  const int i1 = blockIdx.y, i2_0 = blockIdx.x * tr;
+  const size_t base = ((size_t)i1 * g.n2 + i2_0) * L;
+  const R* src = reinterpret_cast<const R*>(in.p[blockIdx.z]);
+  cplx<R>* dst = reinterpret_cast<cplx<R>*>(out.p[blockIdx.z]);
+  R* zr = reinterpret_cast<R*>(za);
+  for (int e = threadIdx.x; e < tr * L; e += NT) {
+    const int r = e / L, i3 = e - r * L;
+    zr[2 * Lay<L>::at(r >> 1, i3) + (r & 1)] = src[base + e];
+  }
+  for (int m = threadIdx.x; m < L; m += NT) tw[m] = tw_g[m];
+  __syncthreads();
+  const cplx<R>* res = lds_fft<R, -1, L, NT>(za, zb, tw, tr / 2, threadIdx.x);
+  store_half_spectra<R, L>(res, dst, g, i1, i2_0, tr);
 }
 
 // ---------------------------------------------------------------- K5: x1 pass + divergence term
@@ -520,6 +536,7 @@ __global__ void __launch_bounds__(NT) k_rpass_final(const cplx<R>* __restrict__ 
 // ---------------------------------------------------------------- K7: scalar reduction
 struct ReduceParams {
   int nb_r, nb_x1;   // partial counts of the row-pass and x1-pass kernels
+  int nb_fs;         // partial count of the free-energy slots (pointwise kernel or row pass)
   double dv, volume, alpha_sum, E_ion;
 };
 
@@ -529,7 +546,8 @@ __global__ void __launch_bounds__(RED_NT) k_reduce_scalars(const double* __restr
                                                            ReduceParams rp, double* __restrict__ sc) {
   __shared__ double raw[SL_COUNT];
   const int s = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int cnt = (s == SL_EH || s == SL_EEXT) ? rp.nb_x1 : rp.nb_r;
+  const int cnt = (s == SL_EH || s == SL_EEXT) ? rp.nb_x1
+                  : (s == SL_FS || s == SL_TS || s == SL_EXC) ? rp.nb_fs : rp.nb_r;
   double acc = 0.0;
   for (int i = lane; i < cnt; i += 64) acc += partials[s * maxb + i];
   acc = wave_sum(acc);
@@ -870,12 +888,29 @@ static void launch_x1_density(ofdft_ctx* c, void* out0, void* out1, void* out2) 
 }
 
 template <typename R, int L>
-static void launch_rpass_gga(ofdft_ctx* c, const double* phi, const EvalParams& ep) {
+static void launch_rpass_inv_real3(ofdft_ctx* c) {
   const GridDesc& g = c->g;
-  dim3 grid(g.n2 / g.tr, g.n1);
-  hipLaunchKernelGGL((k_rpass_gga<R, L>), grid, dim3(NT), (lds_rpass_inv<R, L>(g.tr, 3, 3)), c->stream,
-                     (cplx<R>*)c->B[0], (cplx<R>*)c->B[1], (cplx<R>*)c->B[2], phi, (R*)c->vloc,
-                     (const cplx<R>*)c->tw[2], g, ep, c->partials, c->max_blocks);
+  dim3 grid(g.n2 / g.tr, g.n1, 3);
+  Arr3 in{{c->B[0], c->B[1], c->B[2]}};
+  RealArr3 out{{c->gr[0], c->gr[1], c->gr[2]}};
+  hipLaunchKernelGGL((k_rpass_inv_real<R, L>), grid, dim3(NT), (lds_rpass_inv<R, L>(g.tr, 0, 0)), c->stream, in,
+                     out, (const cplx<R>*)c->tw[2], g);
+}
+
+template <typename R>
+static void launch_pointwise_gga(ofdft_ctx* c, const double* phi, const EvalParams& ep) {
+  hipLaunchKernelGGL((k_pointwise_gga<R>), dim3(PW_BLOCKS), dim3(NT), 0, c->stream, phi, (R*)c->gr[0],
+                     (R*)c->gr[1], (R*)c->gr[2], (R*)c->vloc, c->g.N, ep, c->partials, c->max_blocks);
+}
+
+template <typename R, int L>
+static void launch_rpass_fwd_real3(ofdft_ctx* c) {
+  const GridDesc& g = c->g;
+  dim3 grid(g.n2 / g.tr, g.n1, 3);
+  RealArr3 in{{c->gr[0], c->gr[1], c->gr[2]}};
+  Arr3 out{{c->B[0], c->B[1], c->B[2]}};
+  hipLaunchKernelGGL((k_rpass_fwd_real<R, L>), grid, dim3(NT), (lds_rpass_fwd<R, L>(g.tr)), c->stream, in, out,
+                     (const cplx<R>*)c->tw[2], g);
 }
 
 template <typename R, int L>
@@ -949,8 +984,12 @@ static int eval_impl(ofdft_ctx* c, const double* phi, void* v_out, double* sc) {
     OFDFT_DISPATCH(g.n1, (launch_x1_density<R, L_, X1_GGA>(c, c->B[0], c->B[1], c->B[2])));
     tmark(c, "cpass_x2_inv3");
     OFDFT_DISPATCH(g.n2, (launch_x2<R, L_, +1>(c, c->B[0], c->B[1], c->B[2], 3)));
-    tmark(c, "rpass_gga_pointwise");
-    OFDFT_DISPATCH(g.n3, (launch_rpass_gga<R, L_>(c, phi, ep)));
+    tmark(c, "rpass_inv_grad3");
+    OFDFT_DISPATCH(g.n3, (launch_rpass_inv_real3<R, L_>(c)));
+    tmark(c, "pointwise_gga");
+    launch_pointwise_gga<R>(c, phi, ep);
+    tmark(c, "rpass_fwd_w3");
+    OFDFT_DISPATCH(g.n3, (launch_rpass_fwd_real3<R, L_>(c)));
     tmark(c, "cpass_x2_fwd3");
     OFDFT_DISPATCH(g.n2, (launch_x2<R, L_, -1>(c, c->B[0], c->B[1], c->B[2], 3)));
     tmark(c, "x1_divergence");
@@ -965,7 +1004,8 @@ static int eval_impl(ofdft_ctx* c, const double* phi, void* v_out, double* sc) {
     tmark(c, "rpass_final");
     OFDFT_DISPATCH(g.n3, (launch_rpass_final<R, L_, false>(c, phi, v_out, ep)));
   }
-  ReduceParams rp{(g.n2 / g.tr) * g.n1, (g.n2 / g.tc) * g.n3h, g.dv, g.volume, c->alpha_sum, c->E_ion};
+  const int nb_r = (g.n2 / g.tr) * g.n1;
+  ReduceParams rp{nb_r, (g.n2 / g.tc) * g.n3h, tf ? nb_r : PW_BLOCKS, g.dv, g.volume, c->alpha_sum, c->E_ion};
   tmark(c, "reduce_scalars");
   hipLaunchKernelGGL(k_reduce_scalars, dim3(1), dim3(RED_NT), 0, c->stream, c->partials, c->max_blocks, rp, sc);
   tmark(c, "end");
@@ -980,7 +1020,7 @@ static size_t max_lds_impl(const ofdft_ctx* c) {
   auto upd = [&](size_t v) { m = v > m ? v : m; };
   switch (g.n3) {
 #define OFDFT_LDS3(LEN) \
-    case LEN: upd(lds_rpass_fwd<R, LEN>(g.tr)); upd(lds_rpass_inv<R, LEN>(g.tr, 3, 3)); \
+    case LEN: upd(lds_rpass_fwd<R, LEN>(g.tr)); upd(lds_rpass_inv<R, LEN>(g.tr, 0, 0)); \
               upd(lds_rpass_inv<R, LEN>(g.tr, 0, 4)); break;
     OFDFT_LENGTHS(OFDFT_LDS3)
 #undef OFDFT_LDS3
@@ -1048,10 +1088,11 @@ static void configure_lds() {
   allow((const void*)k_x1_density<R, LEN, X1_TF>);                                   \
   allow((const void*)k_x1_density<R, LEN, X1_GGA>);                                  \
   allow((const void*)k_x1_density<R, LEN, X1_NHAT>);                                 \
-  allow((const void*)k_rpass_gga<R, LEN>);                                           \
   allow((const void*)k_x1_divergence<R, LEN>);                                       \
   allow((const void*)k_rpass_final<R, LEN, true>);                                   \
-  allow((const void*)k_rpass_final<R, LEN, false>);
+  allow((const void*)k_rpass_final<R, LEN, false>);                                  \
+  allow((const void*)k_rpass_inv_real<R, LEN>);                                      \
+  allow((const void*)k_rpass_fwd_real<R, LEN>);
   OFDFT_LENGTHS(OFDFT_ALLOW)
 #undef OFDFT_ALLOW
 }
@@ -1069,7 +1110,8 @@ int dev_alloc_grid(ofdft_ctx* c) {
   for (int k = 0; k < 3 && ok; ++k) ok = dalloc_bytes(c, &c->B[k], NS * 2 * rs);
   // sized for the smallest tiles the tuner may pick (2 rows / 2 columns per block)
   const int nb_r = (g.n2 / 2) * g.n1, nb_x1 = (g.n2 / 2) * g.n3h;
-  c->max_blocks = nb_r > nb_x1 ? nb_r : nb_x1;
+  c->max_blocks = std::max(std::max(nb_r, nb_x1), PW_BLOCKS);
+  for (int k = 0; k < 3 && ok; ++k) ok = dalloc_bytes(c, &c->gr[k], N * rs);
   ok = ok && dalloc(c, &c->partials, (size_t)SL_COUNT * c->max_blocks) && dalloc(c, &c->scalars, SC_COUNT) &&
        dalloc(c, &c->scalars_t, SC_COUNT) && dalloc(c, &c->vpart, 8 * VEC_BLOCKS) && dalloc(c, &c->vout, 16);
   if (ok && !c->hbuf) ok = hip_ok(c, hipHostMalloc((void**)&c->hbuf, 64 * sizeof(double)), "hipHostMalloc");
@@ -1092,7 +1134,7 @@ void dev_free_grid(ofdft_ctx* c) {
                  (void**)&c->tn[1], (void**)&c->tn[2], (void**)&c->tn[3], &c->v, &c->v_t, &c->vloc, &c->A,
                  &c->S0, &c->D, &c->Vext, &c->B[0], &c->B[1], &c->B[2], &c->tw[0], &c->tw[1], &c->tw[2],
                  (void**)&c->partials, (void**)&c->scalars, (void**)&c->scalars_t, (void**)&c->vpart,
-                 (void**)&c->vout};
+                 (void**)&c->vout, &c->gr[0], &c->gr[1], &c->gr[2]};
   for (void** p : ps) {
     if (*p) (void)hipFree(*p);
     *p = nullptr;
