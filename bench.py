@@ -27,6 +27,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# Vector ALU peak for the pointwise kernel: 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz.
+# FP64 runs at this rate; FP32 without packed math (not used here) runs at the same lane rate.
+VALU_PEAK_TFLOPS = 78.6
+# Algorithmic flops per grid point of the pointwise GGA kernel (VT84F + PZ81), counting an FMA
+# as 2 and every add, multiply, reciprocal, square root, exp or log as 1, with one pass over
+# the t-factor tables: FP64 383 (ln n and l: 3; piece abscissa: 2; Chebyshev recurrence
+# T_2..T_21: 40; 8 series of 22 terms: 336; energy sums: 2) + FP32 151 (density powers and
+# s^2: 16; two VT84F enhancement factors: 64; f, df/dn, df/dsigma, T s: 37; PZ81: 24; W and
+# v_loc: 5; sums: 5).
+POINTWISE_GGA_FLOP_PER_POINT = 534
 WORKLOAD = "1024 H, 4.0 g/cm^3, 128^3 grid, T=100 kK, VT84F+PZ81 ftGGA, Gaussian LPP rc=0.5"
 
 
@@ -65,6 +75,39 @@ def kernel_bytes(name: str, n1: int, n2: int, n3: int, rsize: int) -> float:
         "reduce_scalars": 0,
     }
     return float(table.get(name, 0))
+
+
+def source_digest() -> str:
+    """SHA-256 over the HIP sources; a counter record applies only to the kernels it measured."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1406_0835_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary
+    (FETCH_SIZE + WRITE_SIZE, each scaled by the same counter on a copy kernel of known size),
+    or None when there is none or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_128cubed_counters.md")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("- ") and ":" in line:
+                k, v = line[2:].split(":", 1)
+                rec[k.strip()] = v.strip().strip("`")
+    if rec.get("source_sha256") != source_digest():
+        return None
+    try:
+        return float(rec["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def sync():
@@ -268,10 +311,19 @@ def main():
         per_kernel.append({"kernel": name, "avg_us": 1e3 * ms, "alg_bytes": b,
                            "GB_s": (b / (ms * 1e-3) / 1e9) if ms > 0 and b > 0 else None})
     dom = max(per_kernel, key=lambda k: k["avg_us"])
-    achieved = dom["GB_s"] or 0.0
-    roofline = {"bound": "hbm", "kernel": dom["kernel"], "achieved": achieved, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                "alg_bytes_per_launch": dom["alg_bytes"], "avg_launch_us": dom["avg_us"]}
+    traffic = measured_traffic(dom["kernel"])
+    if dom["kernel"] == "pointwise_gga":
+        flops = POINTWISE_GGA_FLOP_PER_POINT * n1 * n2 * n3
+        achieved = flops / (dom["avg_us"] * 1e-6) / 1e12
+        roofline = {"bound": "alu", "kernel": dom["kernel"], "achieved": achieved, "peak": VALU_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": achieved / VALU_PEAK_TFLOPS, "traffic": traffic,
+                    "alg_flop_per_launch": float(flops), "alg_bytes_per_launch": dom["alg_bytes"],
+                    "hbm_GB_s": dom["GB_s"], "avg_launch_us": dom["avg_us"]}
+    else:
+        achieved = dom["GB_s"] or 0.0
+        roofline = {"bound": "hbm", "kernel": dom["kernel"], "achieved": achieved, "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                    "alg_bytes_per_launch": dom["alg_bytes"], "avg_launch_us": dom["avg_us"]}
     total_alg = sum(k["alg_bytes"] for k in per_kernel)
     eval_gbs = total_alg / (dev_ms * 1e-3) / 1e9
 

@@ -14,11 +14,11 @@ integrals.  Reference values come from mpmath at 60 digits:
 Tabulated functions of l = ln t (t-derivatives multiplied by t):
   GGA: xi, zeta, t xi', t zeta', P_tau, P_sigma, t P_tau', t P_sigma'
   TF : kappa, zeta, t eta
-Pieces: l in [L_LO, L_HI] starts as equal pieces of width W0; a piece is
-halved (down to width W0/2^MAXDEPTH) until every function meets its error
-target (relative to the piece's largest value).  Each piece holds NC
-first-kind Chebyshev coefficients per function; the device finds the piece
-through a map from cells of width W0/2^MAXDEPTH.  Outside [L_LO, L_HI] the
+Pieces overlap: piece j covers [L_LO + j H, L_LO + j H + W] with W = 2 H, so
+any set of l values whose spread is at most H lies inside one piece (the
+piece of the smallest value), and a wavefront of neighbouring grid points is
+served by one piece with wave-uniform coefficients.  Each piece holds NC
+first-kind Chebyshev coefficients per function.  Outside [L_LO, L_HI] the
 device clamps l.
 
 Usage: python gen_t_tables.py > t_tables.h   (error report on stderr)
@@ -29,7 +29,8 @@ import sys
 import mpmath as mp
 
 mp.mp.dps = 60
-L_LO, L_HI, W0, NC, MAXDEPTH = -16.0, 24.0, 2.0, 22, 5
+L_LO, L_HI, H, NC = -16.0, 24.0, 0.5, 22
+W = 2 * H
 TOL = {"xi": 2e-15, "zeta": 4e-15, "t_dxi": 2e-14, "t_dzeta": 2e-14, "p_tau": 2e-14, "p_sig": 2e-14,
        "t_dp_tau": 1e-13, "t_dp_sig": 1e-13, "kappa": 2e-15, "t_eta": 4e-15}
 GGA_NAMES = ["xi", "zeta", "t_dxi", "t_dzeta", "p_tau", "p_sig", "t_dp_tau", "t_dp_sig"]
@@ -115,7 +116,7 @@ def fit_piece(a, b, nodes):
     vals = [factors(piece_l(a, b, x)) for x in nodes]
     gga = [[float(v) for v in cheb_coeffs([vv[0][f] for vv in vals])] for f in range(len(GGA_NAMES))]
     tf = [[float(v) for v in cheb_coeffs([vv[1][f] for vv in vals])] for f in range(len(TF_NAMES))]
-    xs = [mp.mpf(-0.97) + mp.mpf(1.94) * i / 12 for i in range(13)]
+    xs = [mp.mpf(-1) + mp.mpf(2) * i / 16 for i in range(17)]
     ref = [factors(piece_l(a, b, x)) for x in xs]
     errs = {}
     for f, n in enumerate(GGA_NAMES):
@@ -127,66 +128,42 @@ def fit_piece(a, b, nodes):
     return gga, tf, errs
 
 
-def build(a, b, depth, nodes, out):
-    gga, tf, errs = fit_piece(a, b, nodes)
-    bad = [n for n, e in errs.items() if e > TOL[n]]
-    if bad and depth < MAXDEPTH:
-        m = (a + b) / 2
-        print(f"split [{a}, {b}] ({', '.join(f'{n} {errs[n]:.1e}' for n in bad)})", file=sys.stderr, flush=True)
-        build(a, m, depth + 1, nodes, out)
-        build(m, b, depth + 1, nodes, out)
-        return
-    print(f"piece [{a}, {b}] max err {max(errs.values()):.1e}", file=sys.stderr, flush=True)
-    out.append((a, b, gga, tf, errs))
-
-
-def build_top(a):
+def build_piece(j):
     nodes = [mp.cos(mp.pi * (k + mp.mpf(1) / 2) / NC) for k in range(NC)]
-    out = []
-    build(a, a + W0, 0, nodes, out)
-    return out
+    a = L_LO + j * H
+    gga, tf, errs = fit_piece(a, a + W, nodes)
+    bad = [n for n, e in errs.items() if e > TOL[n]]
+    flag = (" ABOVE TOLERANCE: " + ", ".join(bad)) if bad else ""
+    print(f"piece {j} [{a}, {a + W}] max err {max(errs.values()):.1e}{flag}", file=sys.stderr, flush=True)
+    return gga, tf, errs
 
 
 def main():
     import multiprocessing as mpr
-    starts = []
-    a = L_LO
-    while a < L_HI - 1e-12:
-        starts.append(a)
-        a += W0
+    npieces = int(round((L_HI - L_LO) / H))
     with mpr.Pool(int(os.environ.get("GEN_PROCS", "6"))) as pool:
-        pieces = [p for part in pool.map(build_top, starts, chunksize=1) for p in part]
-    pieces.sort(key=lambda p: p[0])
-    cw = W0 / 2 ** MAXDEPTH
-    ncell = int(round((L_HI - L_LO) / cw))
-    cellmap = []
-    for c in range(ncell):
-        mid = L_LO + (c + 0.5) * cw
-        cellmap.append(next(i for i, p in enumerate(pieces) if p[0] <= mid < p[1]))
-    worst = {n: max(p[4][n] for p in pieces) for n in GGA_NAMES + TF_NAMES}
+        pieces = pool.map(build_piece, range(npieces), chunksize=1)
+    worst = {n: max(p[2][n] for p in pieces) for n in GGA_NAMES + TF_NAMES}
     for n, e in worst.items():
         print(f"{n}: max |err| / max|f| per piece = {e:.2e}", file=sys.stderr)
-    np_ = len(pieces)
     out = ["// Generated by gen_t_tables.py (mpmath, 60 digits). Do not edit.",
            "// max error / piece scale: " + ", ".join(f"{n} {e:.1e}" for n, e in worst.items()),
            "#pragma once",
            f"#define OFDFT_T_LLO ({L_LO!r})",
            f"#define OFDFT_T_LHI ({L_HI!r})",
-           f"#define OFDFT_T_NP {np_}",
+           f"#define OFDFT_T_H ({H!r})",
+           f"#define OFDFT_T_W ({W!r})",
+           f"#define OFDFT_T_NP {npieces}",
            f"#define OFDFT_T_NC {NC}",
-           f"#define OFDFT_T_NCELL {ncell}",
-           f"#define OFDFT_T_CELLW ({cw!r})",
-           "static const int kTCell[OFDFT_T_NCELL] = {" + ", ".join(str(i) for i in cellmap) + "};",
-           "static const double kTBound[2 * OFDFT_T_NP] = {" +
-           ", ".join(f"{p[0]!r}, {p[1]!r}" for p in pieces) + "};",
-           "// [piece][function][coefficient]; GGA functions: " + ", ".join(GGA_NAMES),
+           "// [piece][function][coefficient]; piece j spans l in [LLO + j H, LLO + j H + W]",
+           "// GGA functions: " + ", ".join(GGA_NAMES),
            f"static const double kTGga[OFDFT_T_NP * {len(GGA_NAMES)} * OFDFT_T_NC] = {{"]
-    flat = [v for p in pieces for f in range(len(GGA_NAMES)) for v in p[2][f]]
+    flat = [v for p in pieces for f in range(len(GGA_NAMES)) for v in p[0][f]]
     out += ["  " + ", ".join(f"{v:.17e}" for v in flat[i:i + 4]) + "," for i in range(0, len(flat), 4)]
     out.append("};")
     out.append("// TF functions: " + ", ".join(TF_NAMES))
     out.append(f"static const double kTTf[OFDFT_T_NP * {len(TF_NAMES)} * OFDFT_T_NC] = {{")
-    flat = [v for p in pieces for f in range(len(TF_NAMES)) for v in p[3][f]]
+    flat = [v for p in pieces for f in range(len(TF_NAMES)) for v in p[1][f]]
     out += ["  " + ", ".join(f"{v:.17e}" for v in flat[i:i + 4]) + "," for i in range(0, len(flat), 4)]
     out.append("};")
     print("\n".join(out))

@@ -564,7 +564,7 @@ int ofdft_create(const ofdft_options* opt, ofdft_ctx** out) {
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(nullptr, OFDFT_E_DEVICE, "no HIP device");
   if (o.device < 0 || o.device >= ndev) return fail(nullptr, OFDFT_E_ARG, "device ordinal out of range");
   if (hipSetDevice(o.device) != hipSuccess) return fail(nullptr, OFDFT_E_DEVICE, "hipSetDevice failed");
-  if (dev_upload_tables() != OFDFT_OK) return fail(nullptr, OFDFT_E_DEVICE, "uploading Fermi-Dirac tables failed");
+  if (dev_upload_tables(o.device) != OFDFT_OK) return fail(nullptr, OFDFT_E_DEVICE, "uploading the t-factor tables failed");
   ofdft_ctx* c = new ofdft_ctx();
   c->opt = o;
   c->rsize = (o.precision == OFDFT_MIXED) ? 4 : 8;
@@ -638,7 +638,7 @@ int ofdft_set_cell(ofdft_ctx* c, const double lattice[9], double cell_scale, con
   g.tr = std::max(2, largest_pow2_divisor_upto(g.n2, g.n3 >= 256 ? 8 : 16));
   const int tc_cap = (g.n1 >= 256) ? 8 : 16;
   g.tc = largest_pow2_divisor_upto(g.n2, tc_cap);
-  g.rb = std::max(1, 1024 / g.n2);
+  g.rb = std::max(1, 1024 / g.n2);   // rb * n2 <= 16 * 256 (register prefetch of the x2 pass)
   std::memcpy(c->lat, lat, sizeof(lat));
   c->cell_scale = cell_scale;
   c->g = g;
@@ -838,7 +838,8 @@ int ofdft_time_evals(ofdft_ctx* c, int n_evals, double* total_ms, int max_kernel
 
 static bool tiles_valid(const ofdft_ctx* c, int tr, int tc, int rb) {
   const GridDesc& g = c->g;
-  if (tr < 2 || tr % 2 || g.n2 % tr || tc < 1 || g.n2 % tc || rb < 1 || rb * g.n2 > 8192) return false;
+  // the x2 pass keeps rb * n2 / 256 elements per thread in registers (at most 16)
+  if (tr < 2 || tr % 2 || g.n2 % tr || tc < 1 || g.n2 % tc || rb < 1 || rb * g.n2 > 16 * 256) return false;
   // the per-block partial sums were sized for tiles of at least 2
   if ((long long)(g.n2 / tr) * g.n1 > c->max_blocks || (long long)(g.n2 / tc) * g.n3h > c->max_blocks) return false;
   return true;

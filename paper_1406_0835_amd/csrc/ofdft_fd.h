@@ -14,8 +14,6 @@ namespace ofdft {
 
 __constant__ double c_t_gga[OFDFT_T_NP * 8 * OFDFT_T_NC];
 __constant__ double c_t_tf[OFDFT_T_NP * 3 * OFDFT_T_NC];
-__constant__ int c_t_cell[OFDFT_T_NCELL];
-__constant__ double c_t_bound[2 * OFDFT_T_NP];
 
 constexpr double kPi = 3.14159265358979323846264338327950288;
 constexpr double kCTF = 2.87123400018819181594;       // (3/10)(3 pi^2)^(2/3)
@@ -42,32 +40,43 @@ __device__ __forceinline__ void cheb_series(const double* __restrict__ c, double
   }
 }
 
-// The t-dependent factors at l = ln t (clamped to the tabulated range).  A
-// cell map gives the Chebyshev piece; the piece index is usually the same
-// across a wavefront (neighbouring points have similar densities), and then
-// the coefficients arrive through scalar loads.
+// The t-dependent factors at l = ln t (clamped to the tabulated range).
+// Piece j spans [LLO + j H, LLO + j H + W] with W = 2 H.  Each pass takes the
+// smallest cell among the lanes still pending and evaluates that piece for the
+// whole wavefront with wave-uniform (scalar) coefficient loads; every pending
+// lane inside the piece takes the result.  Neighbouring points have similar
+// densities, so one pass usually serves the whole wavefront (always, when the
+// spread of l across the wavefront is at most H).
 template <int NF>
 __device__ __forceinline__ void t_table(const double* __restrict__ table, double l, double* s) {
   l = fmin(fmax(l, OFDFT_T_LLO), OFDFT_T_LHI);
-  int cell = (int)((l - OFDFT_T_LLO) * (1.0 / OFDFT_T_CELLW));
-  cell = cell < 0 ? 0 : (cell >= OFDFT_T_NCELL ? OFDFT_T_NCELL - 1 : cell);
-  const int p = c_t_cell[cell];
-  const double a = c_t_bound[2 * p], b = c_t_bound[2 * p + 1];
-  const double x = (2.0 * l - a - b) / (b - a);
-  // Waterfall over the distinct pieces present in the wavefront: each pass
-  // serves the lanes of one piece with wave-uniform (scalar) coefficient loads.
+  int cell = (int)((l - OFDFT_T_LLO) * (1.0 / OFDFT_T_H));
+  cell = cell < 0 ? 0 : (cell >= OFDFT_T_NP ? OFDFT_T_NP - 1 : cell);
   bool done = false;
-  unsigned long long pending;
-  while ((pending = __ballot(!done)) != 0ull) {
-    const int first = __ffsll((long long)pending) - 1;
-    const int pm = __builtin_amdgcn_readlane(p, first);
+  // Only lanes reported by __ballot (active and pending) are ever read, so a
+  // partly populated wavefront cannot contribute stale values.
+  // Both loops are bounded by the wavefront size: each inner step moves to a
+  // distinct pending lane, each outer pass completes at least one lane.
+  unsigned long long pending = __ballot(true);
+  for (int pass = 0; pending != 0ull && pass < 64; ++pass) {
+    // smallest cell among the pending lanes: start from the first pending lane
+    // and step to any pending lane with a smaller cell (strictly decreasing)
+    int pm = __builtin_amdgcn_readlane(cell, __ffsll((long long)pending) - 1);
+    unsigned long long lower;
+    for (int step = 0; step < 64 && (lower = __ballot(!done && cell < pm)) != 0ull; ++step)
+      pm = __builtin_amdgcn_readlane(cell, __ffsll((long long)lower) - 1);
+    const double a = OFDFT_T_LLO + pm * OFDFT_T_H;
+    const double x = (l - a) * (2.0 / OFDFT_T_W) - 1.0;
     double r[NF];
     cheb_series<NF>(table + pm * NF * OFDFT_T_NC, x, r);
-    if (!done && p == pm) {
+    // every pending lane of cell pm has l - a < H, i.e. x < 0, so each pass
+    // completes at least one lane
+    if (!done && x <= 1.0) {
 #pragma unroll
       for (int f = 0; f < NF; ++f) s[f] = r[f];
       done = true;
     }
+    pending = __ballot(!done);
   }
 }
 
@@ -84,6 +93,15 @@ struct EnhParams {
   double c1, a1; // mu for kind 0
 };
 
+// Reciprocal: the hardware v_rcp_f32 (1 ulp) in FP32, a correctly rounded
+// division in FP64.
+template <typename R>
+__device__ __forceinline__ R rcp(R x);
+template <>
+__device__ __forceinline__ float rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <>
+__device__ __forceinline__ double rcp<double>(double x) { return 1.0 / x; }
+
 // F(x) and dF/dx with x = s^2 (Eqs. VT84F, KST2F, SGA-F).
 template <typename R>
 __device__ __forceinline__ void enhancement(const EnhParams& p, R x, R& F, R& dF) {
@@ -91,28 +109,29 @@ __device__ __forceinline__ void enhancement(const EnhParams& p, R x, R& F, R& dF
     F = R(1) + R(p.c1) * x;
     dF = R(p.c1);
   } else if (p.kind == 1) {
-    const R den = R(1) + R(p.a1) * x;
-    F = R(1) + R(p.c1) * x / den;
-    dF = R(p.c1) / (den * den);
+    const R rden = rcp<R>(R(1) + R(p.a1) * x);
+    F = R(1) + R(p.c1) * x * rden;
+    dF = R(p.c1) * rden * rden;
   } else {
     const R mu = R(2.778), al = R(1.2965);
     const R ex = exp(-al * x);
-    const R den = R(1) + mu * x;
-    const R t1 = -mu * x * ex / den;
-    const R dt1 = -mu * ex * (R(1) - al * x - al * mu * x * x) / (den * den);
-    // (1 - exp(-al x^2)) (1/x - 1), with its small-x series
+    const R rden = rcp<R>(R(1) + mu * x);
+    const R t1 = -mu * x * ex * rden;
+    const R dt1 = -mu * ex * (R(1) - al * x - al * mu * x * x) * (rden * rden);
+    // q = 1 - exp(-al x^2) and the term q (1/x - 1), with its small-x series
     R q, qx, qx2;
     if (x < R(1e-4)) {
       qx = al * x - R(0.5) * al * al * x * x * x;
       qx2 = al - R(0.5) * al * al * x * x;
       q = qx * x;
     } else {
+      const R rx = rcp<R>(x);
       q = -expm1(-al * x * x);
-      qx = q / x;
-      qx2 = qx / x;
+      qx = q * rx;
+      qx2 = qx * rx;
     }
     F = R(1) + t1 + (qx - q) + R(5.0 / 3.0) * x;
-    dF = dt1 + R(2) * al * exp(-al * x * x) * (R(1) - x) - qx2 + R(5.0 / 3.0);
+    dF = dt1 + R(2) * al * (R(1) - q) * (R(1) - x) - qx2 + R(5.0 / 3.0);
   }
 }
 
@@ -127,21 +146,22 @@ constexpr double kPzC = -kPzGamma * (0.5 * kPzB1 + kPzB2) / (kPzDen1 * kPzDen1) 
 
 template <typename R>
 __device__ __forceinline__ void pz81(R n, R& eps, R& v) {
-  const R rs = cbrt(R(0.75) / (R(kPi) * n));
-  const R ex = R(-0.45816529328314287) / rs;
+  const R rs = cbrt(R(0.75 / kPi) * rcp<R>(n));
+  const R rrs = rcp<R>(rs);
+  const R ex = R(-0.45816529328314287) * rrs;
   R ec, dec;
   if (rs >= R(1)) {
     const R sq = sqrt(rs);
-    const R den = R(1) + R(kPzB1) * sq + R(kPzB2) * rs;
-    ec = R(kPzGamma) / den;
-    dec = -R(kPzGamma) * (R(0.5 * kPzB1) / sq + R(kPzB2)) / (den * den);
+    const R rden = rcp<R>(R(1) + R(kPzB1) * sq + R(kPzB2) * rs);
+    ec = R(kPzGamma) * rden;
+    dec = -R(kPzGamma) * (R(0.5 * kPzB1) * sq * rrs + R(kPzB2)) * (rden * rden);
   } else {
     const R lr = log(rs);
     ec = R(kPzA) * lr + R(kPzB) + R(kPzC) * rs * lr + R(kPzD) * rs;
-    dec = R(kPzA) / rs + R(kPzC) * (lr + R(1)) + R(kPzD);
+    dec = R(kPzA) * rrs + R(kPzC) * (lr + R(1)) + R(kPzD);
   }
   eps = ex + ec;
-  v = R(4.0 / 3.0) * ex + ec - rs * dec / R(3);
+  v = R(4.0 / 3.0) * ex + ec - rs * dec * R(1.0 / 3.0);
 }
 
 // ---------------------------------------------------------------- pointwise F_s
@@ -169,10 +189,10 @@ __device__ __forceinline__ void gga_point(double n, R sigma, double lt0, const E
   double a[8];   // xi, zeta, t xi', t zeta', P_tau, P_sigma, t P_tau', t P_sigma'
   t_table<8>(c_t_gga, lt0 - (2.0 / 3.0) * ln_n, a);
   const R nr = R(n);
-  const R n23 = R(exp((2.0 / 3.0) * ln_n));
+  const R n23 = exp(R((2.0 / 3.0) * ln_n));
   const R A = R(kCTF) * nr * n23;
-  const R rn = R(1) / nr;
-  const R invden = R(1.0 / kS2Den) * rn * rn / n23;
+  const R rn = rcp<R>(nr);
+  const R invden = R(1.0 / kS2Den) * rn * rn * rcp<R>(n23);
   const R s2 = sigma * invden;
   const R p_tau = R(a[4]), p_sig = R(a[5]);
   const R x_tau = s2 * p_tau;

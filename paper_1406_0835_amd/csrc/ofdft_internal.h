@@ -111,7 +111,7 @@ struct ofdft_ctx {
 namespace ofdft {
 
 // kernels (ofdft_kernels.hip)
-int dev_upload_tables();
+int dev_upload_tables(int device);
 int dev_alloc_grid(ofdft_ctx* c);
 void dev_free_grid(ofdft_ctx* c);
 int dev_alloc_ions(ofdft_ctx* c);

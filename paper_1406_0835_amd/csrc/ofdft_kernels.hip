@@ -31,6 +31,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "ofdft_fd.h"
@@ -191,6 +192,11 @@ struct Arr3 {
   void* p[3];
 };
 
+// Persistent blocks: each processes tiles blockIdx.x, blockIdx.x + gridDim.x, ...
+// and issues the global loads of its next tile into registers before it
+// transforms the current one, so the loads overlap the LDS work.
+constexpr int X2_PER_THREAD_MAX = 16;   // rb * L / NT elements held in registers
+
 template <typename R, int L, int SIGN>
 __global__ void __launch_bounds__(NT) k_cpass_x2(Arr3 arrs, const cplx<R>* __restrict__ tw_g, long long nrows,
                                                  int rb) {
@@ -200,19 +206,43 @@ __global__ void __launch_bounds__(NT) k_cpass_x2(Arr3 arrs, const cplx<R>* __res
   cplx<R>* b = sm.take<cplx<R>>(rb * Lay<L>::RS);
   cplx<R>* tw = sm.take<cplx<R>>(L);
   cplx<R>* x = reinterpret_cast<cplx<R>*>(arrs.p[blockIdx.y]);
-  const long long row0 = (long long)blockIdx.x * rb;
-  const int nr = (int)min<long long>(rb, nrows - row0);
-  cplx<R>* base = x + row0 * L;
-  for (int e = threadIdx.x; e < rb * L; e += NT) {
-    const int row = e / L, col = e - row * L;
-    a[Lay<L>::at(row, col)] = (e < nr * L) ? base[e] : cplx<R>{R(0), R(0)};
-  }
+  const long long ntiles = (nrows + rb - 1) / rb;
+  const int per = (rb * L + NT - 1) / NT;   // <= X2_PER_THREAD_MAX (checked on the host)
   for (int m = threadIdx.x; m < L; m += NT) tw[m] = tw_g[m];
-  __syncthreads();
-  const cplx<R>* res = lds_fft<R, SIGN, L, NT>(a, b, tw, rb, threadIdx.x);
-  for (int e = threadIdx.x; e < nr * L; e += NT) {
-    const int row = e / L, col = e - row * L;
-    base[e] = res[Lay<L>::at(row, col)];
+  cplx<R> reg[X2_PER_THREAD_MAX];
+  auto load_tile = [&](long long tile) {
+    const long long row0 = tile * rb;
+    const int nr = (int)min<long long>(rb, nrows - row0);
+    const cplx<R>* base = x + row0 * L;
+#pragma unroll
+    for (int u = 0; u < X2_PER_THREAD_MAX; ++u) {
+      const int e = threadIdx.x + u * NT;
+      if (u < per) reg[u] = (e < nr * L) ? base[e] : cplx<R>{R(0), R(0)};
+    }
+  };
+  long long tile = blockIdx.x;
+  if (tile < ntiles) load_tile(tile);
+  for (; tile < ntiles; tile += gridDim.x) {
+#pragma unroll
+    for (int u = 0; u < X2_PER_THREAD_MAX; ++u) {
+      const int e = threadIdx.x + u * NT;
+      if (u < per && e < rb * L) {
+        const int row = e / L, col = e - row * L;
+        a[Lay<L>::at(row, col)] = reg[u];
+      }
+    }
+    const long long next = tile + gridDim.x;
+    if (next < ntiles) load_tile(next);   // in flight during the transform below
+    __syncthreads();
+    const cplx<R>* res = lds_fft<R, SIGN, L, NT>(a, b, tw, rb, threadIdx.x);
+    const long long row0 = tile * rb;
+    const int nr = (int)min<long long>(rb, nrows - row0);
+    cplx<R>* base = x + row0 * L;
+    for (int e = threadIdx.x; e < nr * L; e += NT) {
+      const int row = e / L, col = e - row * L;
+      base[e] = res[Lay<L>::at(row, col)];
+    }
+    __syncthreads();
   }
 }
 
@@ -548,8 +578,16 @@ __global__ void __launch_bounds__(RED_NT) k_reduce_scalars(const double* __restr
   const int s = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int cnt = (s == SL_EH || s == SL_EEXT) ? rp.nb_x1
                   : (s == SL_FS || s == SL_TS || s == SL_EXC) ? rp.nb_fs : rp.nb_r;
-  double acc = 0.0;
-  for (int i = lane; i < cnt; i += 64) acc += partials[s * maxb + i];
+  // eight independent accumulators keep eight loads in flight per lane
+  const double* ps = partials + (size_t)s * maxb;
+  double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int i = lane;
+  for (; i + 7 * 64 < cnt; i += 8 * 64) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] += ps[i + u * 64];
+  }
+  for (; i < cnt; i += 64) a[0] += ps[i];
+  double acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   acc = wave_sum(acc);
   if (lane == 0) raw[s] = acc;
   __syncthreads();
@@ -816,14 +854,18 @@ static inline bool hip_ok(ofdft_ctx* c, hipError_t e, const char* what) {
   return false;
 }
 
-int dev_upload_tables() {
-  static bool done = false;
-  if (done) return OFDFT_OK;
+// The t-factor tables live in __constant__ memory, one copy per device: upload
+// once per device (the caller has made it current).
+int dev_upload_tables(int device) {
+  static std::mutex mtx;
+  static std::vector<char> uploaded;
+  std::lock_guard<std::mutex> lock(mtx);
+  if (device < 0) return OFDFT_E_ARG;
+  if ((int)uploaded.size() <= device) uploaded.resize(device + 1, 0);
+  if (uploaded[device]) return OFDFT_OK;
   if (hipMemcpyToSymbol(HIP_SYMBOL(c_t_gga), kTGga, sizeof(kTGga)) != hipSuccess) return OFDFT_E_DEVICE;
   if (hipMemcpyToSymbol(HIP_SYMBOL(c_t_tf), kTTf, sizeof(kTTf)) != hipSuccess) return OFDFT_E_DEVICE;
-  if (hipMemcpyToSymbol(HIP_SYMBOL(c_t_cell), kTCell, sizeof(kTCell)) != hipSuccess) return OFDFT_E_DEVICE;
-  if (hipMemcpyToSymbol(HIP_SYMBOL(c_t_bound), kTBound, sizeof(kTBound)) != hipSuccess) return OFDFT_E_DEVICE;
-  done = true;
+  uploaded[device] = 1;
   return OFDFT_OK;
 }
 
@@ -872,7 +914,10 @@ template <typename R, int L, int SIGN>
 static void launch_x2(ofdft_ctx* c, void* a0, void* a1, void* a2, int narr) {
   const GridDesc& g = c->g;
   const long long nrows = (long long)g.n3h * g.n1;
-  dim3 grid((unsigned)((nrows + g.rb - 1) / g.rb), narr);
+  const long long ntiles = (nrows + g.rb - 1) / g.rb;
+  // persistent blocks: a few per CU, each looping over tiles with prefetch
+  const long long cap = 2048 / narr;
+  dim3 grid((unsigned)(ntiles < cap ? ntiles : cap), narr);
   Arr3 arr{{a0, a1, a2}};
   hipLaunchKernelGGL((k_cpass_x2<R, L, SIGN>), grid, dim3(NT), (lds_x2<R, L>(g.rb)), c->stream, arr,
                      (const cplx<R>*)c->tw[1], nrows, g.rb);
