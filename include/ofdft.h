@@ -167,8 +167,11 @@ int ofdft_time_evals(ofdft_ctx* ctx, int n_evals, double* total_ms, int max_kern
    each candidate over n_evals evaluations (HIP events on the context's
    stream).  Needs set_cell, set_ions and set_temperature.  The choice stays
    in force until the next set_cell; tiles[3] (may be NULL) receives it.
-   ofdft_set_tiles sets the three values directly (E_ARG if invalid for the
-   grid). */
+   ofdft_set_tiles sets the three values directly.  Valid tiles are powers of
+   two with tr >= 2 dividing N2 and tc dividing N2, tr*N3 <= 2048,
+   (N3/2+1)*tr <= 2048, N1*tc <= 2048, rb*N2 <= 4096 (register-staged tiles),
+   and their LDS need fits the 160 KB of a workgroup; anything else is E_ARG.
+   The tiles change only the work split, not the result beyond rounding. */
 int ofdft_autotune(ofdft_ctx* ctx, int n_evals, int tiles[3]);
 int ofdft_set_tiles(ofdft_ctx* ctx, const int tiles[3]);
 

@@ -620,6 +620,7 @@ int ofdft_set_cell(ofdft_ctx* c, const double lattice[9], double cell_scale, con
   g.n2 = grid[1];
   g.n3 = grid[2];
   g.n3h = g.n3 / 2 + 1;
+  g.n3k = g.n3 / 2;   // grids are even: the k3 = n3/2 plane holds Nyquist modes only
   g.N = (long long)g.n1 * g.n2 * g.n3;
   g.NS = (long long)g.n3h * g.n1 * g.n2;
   // b_i = 2 pi (a_j x a_k)/det
@@ -638,7 +639,8 @@ int ofdft_set_cell(ofdft_ctx* c, const double lattice[9], double cell_scale, con
   g.tr = std::max(2, largest_pow2_divisor_upto(g.n2, g.n3 >= 256 ? 8 : 16));
   const int tc_cap = (g.n1 >= 256) ? 8 : 16;
   g.tc = largest_pow2_divisor_upto(g.n2, tc_cap);
-  g.rb = std::max(1, 1024 / g.n2);   // rb * n2 <= 16 * 256 (register prefetch of the x2 pass)
+  g.rb = 1;
+  while (2 * g.rb * g.n2 <= 1024) g.rb *= 2;   // largest power of two with rb * n2 <= 1024
   std::memcpy(c->lat, lat, sizeof(lat));
   c->cell_scale = cell_scale;
   c->g = g;
@@ -838,8 +840,12 @@ int ofdft_time_evals(ofdft_ctx* c, int n_evals, double* total_ms, int max_kernel
 
 static bool tiles_valid(const ofdft_ctx* c, int tr, int tc, int rb) {
   const GridDesc& g = c->g;
-  // the x2 pass keeps rb * n2 / 256 elements per thread in registers (at most 16)
-  if (tr < 2 || tr % 2 || g.n2 % tr || tc < 1 || g.n2 % tc || rb < 1 || rb * g.n2 > 16 * 256) return false;
+  auto pow2 = [](int v) { return v >= 1 && (v & (v - 1)) == 0; };
+  if (!pow2(tr) || tr < 2 || g.n2 % tr || !pow2(tc) || g.n2 % tc || !pow2(rb)) return false;
+  // tiles staged through registers
+  if (tr * g.n3 > kStageElems || (g.n3 / 2 + 1) * tr > kStageElems || g.n1 * tc > kStageElems ||
+      rb * g.n2 > kX2Elems)
+    return false;
   // the per-block partial sums were sized for tiles of at least 2
   if ((long long)(g.n2 / tr) * g.n1 > c->max_blocks || (long long)(g.n2 / tc) * g.n3h > c->max_blocks) return false;
   return true;

@@ -192,10 +192,4 @@ __device__ __forceinline__ cplx<R>* lds_fft(cplx<R>* a, cplx<R>* b, const cplx<R
   return Stages<R, SIGN, L, NT, 0, 1>::run(a, b, tw, nrows, tid);
 }
 
-// Twiddles exp(-2 pi i m / L), m < L, copied from global to LDS.
-template <typename R, int L, int NT>
-__device__ __forceinline__ void load_twiddles(cplx<R>* tw_lds, const cplx<R>* tw_glob, int tid) {
-  for (int m = tid; m < L; m += NT) tw_lds[m] = tw_glob[m];
-}
-
 }  // namespace ofdft

@@ -18,15 +18,23 @@ enum Scal {
   SC_COUNT = 16
 };
 
+// Largest tiles the kernels stage through registers: a contiguous-axis tile
+// (tr rows of N3 reals, or (N3/2+1) tr spectrum elements) and an x1 tile
+// (N1 tc elements) hold at most kStageElems elements; an x2 tile (rb rows of
+// N2) at most kX2Elems.  All tile sizes are powers of two.
+constexpr int kStageElems = 2048;
+constexpr int kX2Elems = 4096;
+
 struct GridDesc {
   int n1, n2, n3, n3h;
+  int n3k;        // k3 planes that carry kept modes: k3 < n3/2 (the k3 = n3/2 plane is all Nyquist)
   long long N;    // n1 n2 n3 real points
   long long NS;   // n3h n1 n2 half-spectrum points (layout [k3][k1][k2])
   double b[9];    // reciprocal lattice rows b1, b2, b3 (a_i . b_j = 2 pi delta_ij)
   double volume, dv, inv_n;
-  int tr;         // rows per block in the contiguous-axis pass (divides n2, even)
-  int tc;         // columns per block in the strided pass (divides n2)
-  int rb;         // rows per block in the x2 pass
+  int tr;         // rows per block in the contiguous-axis pass (power of two >= 2, divides n2)
+  int tc;         // columns per block in the strided pass (power of two, divides n2)
+  int rb;         // rows per block in the x2 pass (power of two)
 };
 
 struct LppParams {

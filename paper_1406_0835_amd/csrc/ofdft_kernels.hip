@@ -98,48 +98,115 @@ __device__ __forceinline__ bool gvec(const GridDesc& g, int k1, int k2, int k3, 
   return (2 * k1 != g.n1) && (2 * k2 != g.n2) && (2 * k3 != g.n3);
 }
 
-// ---------------------------------------------------------------- contiguous-axis helpers
-// Separate two real rows packed as z = x_a + i x_b (after a forward FFT) into
-// their half spectra and store them transposed: S[k3][i1][i2_0 + r].
-template <typename R, int L>
-__device__ __forceinline__ void store_half_spectra(const cplx<R>* res, cplx<R>* out, const GridDesc& g,
-                                                   int i1, int i2_0, int tr) {
-  constexpr int LH = L / 2 + 1;
-  for (int e = threadIdx.x; e < LH * tr; e += NT) {
-    const int k3 = e / tr, r = e - k3 * tr, p = r >> 1;
-    const cplx<R> z = res[Lay<L>::at(p, k3)];
-    const cplx<R> zc = cconj(res[Lay<L>::at(p, (L - k3) % L)]);
-    cplx<R> X;
-    if ((r & 1) == 0) {
-      X = {R(0.5) * (z.x + zc.x), R(0.5) * (z.y + zc.y)};
-    } else {
-      X = {R(0.5) * (z.y - zc.y), R(-0.5) * (z.x - zc.x)};
-    }
-    out[((size_t)k3 * g.n1 + i1) * g.n2 + i2_0 + r] = X;
+// ---------------------------------------------------------------- tile staging
+// Tile loads go through registers: each thread first issues all of its global
+// loads (elements e = tid + u NT, u < MAXU), then writes them to LDS, so its
+// loads are in flight together instead of paying one memory latency each.
+// Tile sizes are powers of two (indices by shift and mask) and a staged tile
+// holds at most MAXU * NT elements (both checked on the host).
+constexpr int MAXU = 8;
+static_assert(MAXU * NT == kStageElems, "staged tile size and the host check disagree");
+
+__device__ __forceinline__ int ilog2(int pow2) { return __ffs(pow2) - 1; }
+
+// Element u of this thread in a staged tile of cnt elements, clamped into the
+// tile: loads are issued for every u without branches (a clamped lane reads a
+// valid element it does not use), so none of them waits for another.
+__device__ __forceinline__ int tile_elem(int u, int cnt) {
+  const int e = threadIdx.x + u * NT;
+  return e < cnt ? e : cnt - 1;
+}
+
+// Offsets (elements, from the tile origin) of this thread's staged elements in
+// an x1 tile of the transposed spectrum: row k1 = e >> tcl, column c = e & (tc - 1).
+template <int U>
+__device__ __forceinline__ void x1_offsets(unsigned* off, int cnt, int n2, int tc, int tcl) {
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int e = tile_elem(u, cnt);
+    off[u] = (unsigned)((e >> tcl) * n2 + (e & (tc - 1)));
   }
 }
 
-// Load a transposed half-spectrum tile S[k3][i1][i2_0 + r] (staging in LDS)
-// and build z_p[k] = X_{2p}[k] + i X_{2p+1}[k] over the full k range using
-// Hermitian symmetry.  stage must hold (L/2+1)*tr elements; z holds tr/2 rows
-// in the padded row layout.
+// Twiddles of one transform length go to LDS once per block.  The global load
+// is issued before the tile loads and stored after them, so waiting for it
+// does not wait for the tile.
+template <typename R, int L>
+__device__ __forceinline__ cplx<R> twiddle_load(const cplx<R>* tw_g) {
+  static_assert(L <= NT, "one twiddle per thread");
+  return tw_g[threadIdx.x < L ? threadIdx.x : L - 1];
+}
+template <typename R, int L>
+__device__ __forceinline__ void twiddle_store(cplx<R>* tw, cplx<R> v) {
+  if (threadIdx.x < L) tw[threadIdx.x] = v;
+}
+
+// ---------------------------------------------------------------- contiguous-axis helpers
+// Separate two real rows packed as z = x_a + i x_b (after a forward FFT) into
+// their half spectra and store them transposed: S[k3][i1][i2_0 + r] for
+// k3 < L/2.  The k3 = L/2 plane holds only Nyquist modes, which every
+// reciprocal-space operator drops, so it is neither stored nor read.
+template <typename R, int L>
+__device__ __forceinline__ void store_half_spectra(const cplx<R>* res, cplx<R>* out, const GridDesc& g,
+                                                   int i1, int i2_0, int tr) {
+  const int trl = ilog2(tr);
+  const int plane = g.n1 * g.n2;
+  cplx<R>* ob = out + (size_t)i1 * g.n2 + i2_0;
+  const int cnt = (L / 2) * tr;
+  cplx<R> X[MAXU];
+#pragma unroll
+  for (int u = 0; u < MAXU; ++u) {
+    const int e = tile_elem(u, cnt);
+    const int k3 = e >> trl, r = e & (tr - 1), p = r >> 1;
+    const cplx<R> z = res[Lay<L>::at(p, k3)];
+    const cplx<R> zc = cconj(res[Lay<L>::at(p, (L - k3) % L)]);
+    if ((r & 1) == 0) {
+      X[u] = {R(0.5) * (z.x + zc.x), R(0.5) * (z.y + zc.y)};
+    } else {
+      X[u] = {R(0.5) * (z.y - zc.y), R(-0.5) * (z.x - zc.x)};
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < MAXU; ++u) {
+    const int e = threadIdx.x + u * NT;
+    if (e < cnt) ob[(e >> trl) * plane + (e & (tr - 1))] = X[u];
+  }
+}
+
+// Load a transposed half-spectrum tile S[k3][i1][i2_0 + r], k3 < L/2
+// (staging in LDS), and build z_p[k] = X_{2p}[k] + i X_{2p+1}[k] over the
+// full k range using Hermitian symmetry, with the Nyquist term k = L/2 zero.
+// stage must hold (L/2)*tr elements; z holds tr/2 rows in the padded row
+// layout.  Also stores the twiddles twv (see twiddle_load).
 template <typename R, int L>
 __device__ __forceinline__ void load_pack_half_spectra(const cplx<R>* in, cplx<R>* stage, cplx<R>* z,
-                                                       const GridDesc& g, int i1, int i2_0, int tr) {
-  constexpr int LH = L / 2 + 1;
-  for (int e = threadIdx.x; e < LH * tr; e += NT) {
-    const int k3 = e / tr, r = e - k3 * tr;
-    stage[e] = in[((size_t)k3 * g.n1 + i1) * g.n2 + i2_0 + r];
+                                                       const GridDesc& g, int i1, int i2_0, int tr,
+                                                       cplx<R>* tw, cplx<R> twv) {
+  const int trl = ilog2(tr);
+  const int plane = g.n1 * g.n2;
+  const int cnt = (L / 2) * tr;
+  const cplx<R>* ib = in + (size_t)i1 * g.n2 + i2_0;
+  cplx<R> v[MAXU];
+#pragma unroll
+  for (int u = 0; u < MAXU; ++u) {
+    const int e = tile_elem(u, cnt);
+    v[u] = ib[(e >> trl) * plane + (e & (tr - 1))];
+  }
+  twiddle_store<R, L>(tw, twv);
+#pragma unroll
+  for (int u = 0; u < MAXU; ++u) {
+    const int e = threadIdx.x + u * NT;
+    if (e < cnt) stage[e] = v[u];
   }
   __syncthreads();
-  const int hp = tr >> 1;
+  const int hp = tr >> 1, hpl = trl - 1;
   for (int e = threadIdx.x; e < hp * L; e += NT) {
-    const int k = e / hp, p = e - k * hp;
-    cplx<R> xa, xb;
-    if (2 * k <= L) {
+    const int k = e >> hpl, p = e & (hp - 1);
+    cplx<R> xa = {R(0), R(0)}, xb = {R(0), R(0)};
+    if (2 * k < L) {
       xa = stage[k * tr + 2 * p];
       xb = stage[k * tr + 2 * p + 1];
-    } else {
+    } else if (2 * k > L) {
       xa = cconj(stage[(L - k) * tr + 2 * p]);
       xb = cconj(stage[(L - k) * tr + 2 * p + 1]);
     }
@@ -168,17 +235,25 @@ __global__ void __launch_bounds__(NT) k_rpass_fwd_density(const double* __restri
   cplx<R>* tw = sm.take<cplx<R>>(L);
   double* red = sm.take<double>(NT / 64);
   const int i1 = blockIdx.y, i2_0 = blockIdx.x * tr;
-  const size_t base = ((size_t)i1 * g.n2 + i2_0) * L;
+  const double* src = phi + ((size_t)i1 * g.n2 + i2_0) * L;
+  const int cnt = tr * L;
+  const cplx<R> twv = twiddle_load<R, L>(tw_g);
+  double pv[MAXU];
+#pragma unroll
+  for (int u = 0; u < MAXU; ++u) pv[u] = src[tile_elem(u, cnt)];
+  twiddle_store<R, L>(tw, twv);
   R* zr = reinterpret_cast<R*>(za);
   double acc = 0.0;
-  for (int e = threadIdx.x; e < tr * L; e += NT) {
-    const int r = e / L, i3 = e - r * L;
-    const double p = phi[base + e];
-    const double n = p * p;
-    acc += n;
-    zr[2 * Lay<L>::at(r >> 1, i3) + (r & 1)] = R(n);
+#pragma unroll
+  for (int u = 0; u < MAXU; ++u) {
+    const int e = threadIdx.x + u * NT;
+    if (e < cnt) {
+      const int r = e / L, i3 = e - r * L;
+      const double n = pv[u] * pv[u];
+      acc += n;
+      zr[2 * Lay<L>::at(r >> 1, i3) + (r & 1)] = R(n);
+    }
   }
-  for (int m = threadIdx.x; m < L; m += NT) tw[m] = tw_g[m];
   __syncthreads();
   const cplx<R>* res = lds_fft<R, -1, L, NT>(za, zb, tw, tr / 2, threadIdx.x);
   store_half_spectra<R, L>(res, out, g, i1, i2_0, tr);
@@ -192,71 +267,76 @@ struct Arr3 {
   void* p[3];
 };
 
-// Persistent blocks: each processes tiles blockIdx.x, blockIdx.x + gridDim.x, ...
-// and issues the global loads of its next tile into registers before it
-// transforms the current one, so the loads overlap the LDS work.
-constexpr int X2_PER_THREAD_MAX = 16;   // rb * L / NT elements held in registers
-
-template <typename R, int L, int SIGN>
-__global__ void __launch_bounds__(NT) k_cpass_x2(Arr3 arrs, const cplx<R>* __restrict__ tw_g, long long nrows,
-                                                 int rb) {
+// One tile of rb rows per block; U staged elements per thread (U * NT >= rb * L).
+template <typename R, int L, int SIGN, int U>
+__global__ void __launch_bounds__(NT) k_cpass_x2(Arr3 arrs, const cplx<R>* __restrict__ tw_g, int nrows, int rb) {
   extern __shared__ __align__(16) char smem_raw[];
   Smem sm(smem_raw);
   cplx<R>* a = sm.take<cplx<R>>(rb * Lay<L>::RS);
   cplx<R>* b = sm.take<cplx<R>>(rb * Lay<L>::RS);
   cplx<R>* tw = sm.take<cplx<R>>(L);
-  cplx<R>* x = reinterpret_cast<cplx<R>*>(arrs.p[blockIdx.y]);
-  const long long ntiles = (nrows + rb - 1) / rb;
-  const int per = (rb * L + NT - 1) / NT;   // <= X2_PER_THREAD_MAX (checked on the host)
-  for (int m = threadIdx.x; m < L; m += NT) tw[m] = tw_g[m];
-  cplx<R> reg[X2_PER_THREAD_MAX];
-  auto load_tile = [&](long long tile) {
-    const long long row0 = tile * rb;
-    const int nr = (int)min<long long>(rb, nrows - row0);
-    const cplx<R>* base = x + row0 * L;
+  const int row0 = blockIdx.x * rb;
+  const int nr = min(rb, nrows - row0);
+  const int cnt = nr * L;
+  cplx<R>* x = reinterpret_cast<cplx<R>*>(arrs.p[blockIdx.y]) + (size_t)row0 * L;
+  const cplx<R> twv = twiddle_load<R, L>(tw_g);
+  cplx<R> v[U];
 #pragma unroll
-    for (int u = 0; u < X2_PER_THREAD_MAX; ++u) {
-      const int e = threadIdx.x + u * NT;
-      if (u < per) reg[u] = (e < nr * L) ? base[e] : cplx<R>{R(0), R(0)};
-    }
-  };
-  long long tile = blockIdx.x;
-  if (tile < ntiles) load_tile(tile);
-  for (; tile < ntiles; tile += gridDim.x) {
+  for (int u = 0; u < U; ++u) v[u] = x[tile_elem(u, cnt)];
+  twiddle_store<R, L>(tw, twv);
 #pragma unroll
-    for (int u = 0; u < X2_PER_THREAD_MAX; ++u) {
-      const int e = threadIdx.x + u * NT;
-      if (u < per && e < rb * L) {
-        const int row = e / L, col = e - row * L;
-        a[Lay<L>::at(row, col)] = reg[u];
-      }
-    }
-    const long long next = tile + gridDim.x;
-    if (next < ntiles) load_tile(next);   // in flight during the transform below
-    __syncthreads();
-    const cplx<R>* res = lds_fft<R, SIGN, L, NT>(a, b, tw, rb, threadIdx.x);
-    const long long row0 = tile * rb;
-    const int nr = (int)min<long long>(rb, nrows - row0);
-    cplx<R>* base = x + row0 * L;
-    for (int e = threadIdx.x; e < nr * L; e += NT) {
+  for (int u = 0; u < U; ++u) {
+    const int e = threadIdx.x + u * NT;
+    if (e < rb * L) {
       const int row = e / L, col = e - row * L;
-      base[e] = res[Lay<L>::at(row, col)];
+      a[Lay<L>::at(row, col)] = (e < cnt) ? v[u] : cplx<R>{R(0), R(0)};
     }
-    __syncthreads();
+  }
+  __syncthreads();
+  const cplx<R>* res = lds_fft<R, SIGN, L, NT>(a, b, tw, rb, threadIdx.x);
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int e = tile_elem(u, cnt);
+    const int row = e / L, col = e - row * L;
+    v[u] = res[Lay<L>::at(row, col)];
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int e = threadIdx.x + u * NT;
+    if (e < cnt) x[e] = v[u];
   }
 }
 
 // ---------------------------------------------------------------- K3: x1 pass + density ops
+// Store an x1 tile from LDS (row k1 = e >> tcl, column c = e & (tc - 1)): all
+// LDS reads first, then the global stores.
+template <typename R, int L, int U>
+__device__ __forceinline__ void store_x1_tile(const cplx<R>* o, cplx<R>* dst, const unsigned* off, int tc,
+                                              int tcl, int cnt) {
+  cplx<R> t[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int e = tile_elem(u, cnt);
+    t[u] = o[Lay<L>::at(e & (tc - 1), e >> tcl)];
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int e = threadIdx.x + u * NT;
+    if (e < cnt) dst[off[u]] = t[u];
+  }
+}
+
 enum { X1_TF = 0, X1_GGA = 1, X1_NHAT = 2 };
 
-template <typename R, int L, int MODE>
+// U: staged elements per thread, U * NT >= L * tc.
+template <typename R, int L, int MODE, int U>
 __global__ void __launch_bounds__(NT) k_x1_density(const cplx<R>* __restrict__ A, const cplx<R>* __restrict__ vext,
                                                    cplx<R>* __restrict__ out0, cplx<R>* __restrict__ out1,
                                                    cplx<R>* __restrict__ out2, cplx<R>* __restrict__ s0,
                                                    const cplx<R>* __restrict__ tw_g, GridDesc g,
                                                    double* __restrict__ partials, int maxb) {
   extern __shared__ __align__(16) char smem_raw[];
-  const int tc = g.tc;
+  const int tc = g.tc, tcl = ilog2(tc);
   Smem sm(smem_raw);
   cplx<R>* b0 = sm.take<cplx<R>>(tc * Lay<L>::RS);
   cplx<R>* b1 = sm.take<cplx<R>>(tc * Lay<L>::RS);
@@ -264,12 +344,28 @@ __global__ void __launch_bounds__(NT) k_x1_density(const cplx<R>* __restrict__ A
   cplx<R>* tw = sm.take<cplx<R>>(L);
   double* red = sm.take<double>(2 * NT / 64);
   const int k3 = blockIdx.y, i2_0 = blockIdx.x * tc;
-  const size_t plane = (size_t)k3 * g.n1 * g.n2;
-  for (int e = threadIdx.x; e < L * tc; e += NT) {
-    const int i1 = e / tc, c = e - i1 * tc;
-    b0[Lay<L>::at(c, i1)] = A[plane + (size_t)i1 * g.n2 + i2_0 + c];
+  // element e of the tile: row k1 = e >> tcl (x1 index), column c = e & (tc - 1)
+  const size_t tile0 = (size_t)k3 * g.n1 * g.n2 + i2_0;
+  const int cnt = L * tc;
+  const cplx<R> twv = twiddle_load<R, L>(tw_g);
+  unsigned off[U];
+  x1_offsets<U>(off, cnt, g.n2, tc, tcl);
+  cplx<R> av[U], ve[U];
+  const cplx<R>* At = A + tile0;
+#pragma unroll
+  for (int u = 0; u < U; ++u) av[u] = At[off[u]];
+  if constexpr (MODE != X1_NHAT) {
+    // v_ext(G) of the tile: needed after the forward FFT, in flight meanwhile
+    const cplx<R>* Vt = vext + tile0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) ve[u] = Vt[off[u]];
   }
-  for (int m = threadIdx.x; m < L; m += NT) tw[m] = tw_g[m];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int e = threadIdx.x + u * NT;
+    if (e < cnt) b0[Lay<L>::at(e & (tc - 1), e >> tcl)] = av[u];
+  }
+  twiddle_store<R, L>(tw, twv);
   __syncthreads();
   cplx<R>* res = lds_fft<R, -1, L, NT>(b0, b1, tw, tc, threadIdx.x);
   cplx<R>* fa = (res == b0) ? b1 : b0;   // free buffers
@@ -277,34 +373,37 @@ __global__ void __launch_bounds__(NT) k_x1_density(const cplx<R>* __restrict__ A
   const R inv_n = R(g.inv_n);
   const double wk = (k3 == 0) ? 1.0 : 2.0;
   double eh = 0.0, ee = 0.0;
-  for (int e = threadIdx.x; e < L * tc; e += NT) {
-    const int k1 = e / tc, c = e - k1 * tc;
-    const int k2 = i2_0 + c;
-    const int idx = Lay<L>::at(c, k1);
-    const size_t gi = plane + (size_t)k1 * g.n2 + k2;
-    double gx, gy, gz;
-    const bool keep = gvec(g, k1, k2, k3, gx, gy, gz);
-    const double G2 = gx * gx + gy * gy + gz * gz;
-    cplx<R> nh = cscale(res[idx], inv_n);
-    cplx<R> S = {R(0), R(0)};
-    if (keep && G2 > 0.0) {
-      const double nx = nh.x, ny = nh.y;
-      const double kern = kFourPi / G2;
-      if constexpr (MODE != X1_NHAT) {
-        const cplx<R> ve = vext[gi];
-        eh += wk * kern * (nx * nx + ny * ny);
-        ee += wk * (nx * double(ve.x) + ny * double(ve.y));
-        S = {R(kern * nx + double(ve.x)), R(kern * ny + double(ve.y))};
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int e = threadIdx.x + u * NT;
+    if (e < cnt) {
+      const int k1 = e >> tcl, c = e & (tc - 1);
+      const int idx = Lay<L>::at(c, k1);
+      const size_t gi = tile0 + off[u];
+      double gx, gy, gz;
+      const bool keep = gvec(g, k1, i2_0 + c, k3, gx, gy, gz);
+      const double G2 = gx * gx + gy * gy + gz * gz;
+      cplx<R> nh = cscale(res[idx], inv_n);
+      cplx<R> S = {R(0), R(0)};
+      if (keep && G2 > 0.0) {
+        const double nx = nh.x, ny = nh.y;
+        const double kern = kFourPi / G2;
+        if constexpr (MODE != X1_NHAT) {
+          const cplx<R> v = ve[u];
+          eh += wk * kern * (nx * nx + ny * ny);
+          ee += wk * (nx * double(v.x) + ny * double(v.y));
+          S = {R(kern * nx + double(v.x)), R(kern * ny + double(v.y))};
+        }
       }
-    }
-    if (!keep) nh = {R(0), R(0)};
-    if constexpr (MODE == X1_TF) {
-      res[idx] = S;
-    } else if constexpr (MODE == X1_GGA) {
-      s0[gi] = S;
-      res[idx] = nh;
-    } else {
-      out0[gi] = nh;
+      if (!keep) nh = {R(0), R(0)};
+      if constexpr (MODE == X1_TF) {
+        res[idx] = S;
+      } else if constexpr (MODE == X1_GGA) {
+        s0[gi] = S;
+        res[idx] = nh;
+      } else {
+        out0[gi] = nh;
+      }
     }
   }
   if constexpr (MODE != X1_NHAT) {
@@ -320,30 +419,23 @@ __global__ void __launch_bounds__(NT) k_x1_density(const cplx<R>* __restrict__ A
   }
   if constexpr (MODE == X1_TF) {
     const cplx<R>* o = lds_fft<R, +1, L, NT>(res, fa, tw, tc, threadIdx.x);
-    for (int e = threadIdx.x; e < L * tc; e += NT) {
-      const int i1 = e / tc, c = e - i1 * tc;
-      out0[plane + (size_t)i1 * g.n2 + i2_0 + c] = o[Lay<L>::at(c, i1)];
-    }
+    store_x1_tile<R, L, U>(o, out0 + tile0, off, tc, tcl, cnt);
   } else if constexpr (MODE == X1_GGA) {
     cplx<R>* outs[3] = {out0, out1, out2};
 #pragma unroll 1
     for (int a = 0; a < 3; ++a) {
-      for (int e = threadIdx.x; e < L * tc; e += NT) {
+      // i G_a n(G) in the transposed order (column c, row k1)
+      for (int e = threadIdx.x; e < cnt; e += NT) {
         const int c = e / L, k1 = e - c * L;
-        double gv[3];
-        gvec(g, k1, i2_0 + c, k3, gv[0], gv[1], gv[2]);
-        const R ga = R(gv[a]);
+        const int m1 = signed_freq(k1, g.n1), m2 = signed_freq(i2_0 + c, g.n2);
+        const R ga = R(m1 * g.b[a] + m2 * g.b[3 + a] + double(k3) * g.b[6 + a]);
         const int idx = Lay<L>::at(c, k1);
         const cplx<R> z = res[idx];
         fa[idx] = {-ga * z.y, ga * z.x};
       }
       __syncthreads();
       const cplx<R>* o = lds_fft<R, +1, L, NT>(fa, fb, tw, tc, threadIdx.x);
-      cplx<R>* dst = outs[a];
-      for (int e = threadIdx.x; e < L * tc; e += NT) {
-        const int i1 = e / tc, c = e - i1 * tc;
-        dst[plane + (size_t)i1 * g.n2 + i2_0 + c] = o[Lay<L>::at(c, i1)];
-      }
+      store_x1_tile<R, L, U>(o, outs[a] + tile0, off, tc, tcl, cnt);
       __syncthreads();
     }
   }
@@ -366,16 +458,23 @@ __global__ void __launch_bounds__(NT) k_rpass_inv_real(Arr3 in, RealArr3 out, co
   cplx<R>* zb = sm.take<cplx<R>>(zb_elems<L>(tr));
   cplx<R>* tw = sm.take<cplx<R>>(L);
   const int i1 = blockIdx.y, i2_0 = blockIdx.x * tr;
-  const size_t base = ((size_t)i1 * g.n2 + i2_0) * L;
   const cplx<R>* src = reinterpret_cast<const cplx<R>*>(in.p[blockIdx.z]);
-  R* dst = reinterpret_cast<R*>(out.p[blockIdx.z]);
-  for (int m = threadIdx.x; m < L; m += NT) tw[m] = tw_g[m];
-  load_pack_half_spectra<R, L>(src, zb, za, g, i1, i2_0, tr);
+  R* dst = reinterpret_cast<R*>(out.p[blockIdx.z]) + ((size_t)i1 * g.n2 + i2_0) * L;
+  load_pack_half_spectra<R, L>(src, zb, za, g, i1, i2_0, tr, tw, twiddle_load<R, L>(tw_g));
   const cplx<R>* res = lds_fft<R, +1, L, NT>(za, zb, tw, tr / 2, threadIdx.x);
-  for (int e = threadIdx.x; e < tr * L; e += NT) {
+  const int cnt = tr * L;
+  R t[MAXU];
+#pragma unroll
+  for (int u = 0; u < MAXU; ++u) {
+    const int e = tile_elem(u, cnt);
     const int r = e / L, i3 = e - r * L;
     const cplx<R> z = res[Lay<L>::at(r >> 1, i3)];
-    dst[base + e] = (r & 1) ? z.y : z.x;
+    t[u] = (r & 1) ? z.y : z.x;
+  }
+#pragma unroll
+  for (int u = 0; u < MAXU; ++u) {
+    const int e = threadIdx.x + u * NT;
+    if (e < cnt) dst[e] = t[u];
   }
 }
 
@@ -434,56 +533,87 @@ __global__ void __launch_bounds__(NT) k_rpass_fwd_real(RealArr3 in, Arr3 out, co
   cplx<R>* zb = sm.take<cplx<R>>((tr / 2) * Lay<L>::RS);
   cplx<R>* tw = sm.take<cplx<R>>(L);
   const int i1 = blockIdx.y, i2_0 = blockIdx.x * tr;
-  const size_t base = ((size_t)i1 * g.n2 + i2_0) * L;
-  const R* src = reinterpret_cast<const R*>(in.p[blockIdx.z]);
+  const R* src = reinterpret_cast<const R*>(in.p[blockIdx.z]) + ((size_t)i1 * g.n2 + i2_0) * L;
   cplx<R>* dst = reinterpret_cast<cplx<R>*>(out.p[blockIdx.z]);
+  const int cnt = tr * L;
+  const cplx<R> twv = twiddle_load<R, L>(tw_g);
+  R xv[MAXU];
+#pragma unroll
+  for (int u = 0; u < MAXU; ++u) xv[u] = src[tile_elem(u, cnt)];
+  twiddle_store<R, L>(tw, twv);
   R* zr = reinterpret_cast<R*>(za);
-  for (int e = threadIdx.x; e < tr * L; e += NT) {
-    const int r = e / L, i3 = e - r * L;
-    zr[2 * Lay<L>::at(r >> 1, i3) + (r & 1)] = src[base + e];
+#pragma unroll
+  for (int u = 0; u < MAXU; ++u) {
+    const int e = threadIdx.x + u * NT;
+    if (e < cnt) {
+      const int r = e / L, i3 = e - r * L;
+      zr[2 * Lay<L>::at(r >> 1, i3) + (r & 1)] = xv[u];
+    }
   }
-  for (int m = threadIdx.x; m < L; m += NT) tw[m] = tw_g[m];
   __syncthreads();
   const cplx<R>* res = lds_fft<R, -1, L, NT>(za, zb, tw, tr / 2, threadIdx.x);
   store_half_spectra<R, L>(res, dst, g, i1, i2_0, tr);
 }
 
 // ---------------------------------------------------------------- K5: x1 pass + divergence term
-template <typename R, int L>
+template <typename R, int L, int U>
 __global__ void __launch_bounds__(NT) k_x1_divergence(const cplx<R>* __restrict__ C0, const cplx<R>* __restrict__ C1,
                                                       const cplx<R>* __restrict__ C2, const cplx<R>* __restrict__ s0,
                                                       cplx<R>* __restrict__ out, const cplx<R>* __restrict__ tw_g,
                                                       GridDesc g) {
   extern __shared__ __align__(16) char smem_raw[];
-  const int tc = g.tc;
+  const int tc = g.tc, tcl = ilog2(tc);
   Smem sm(smem_raw);
   cplx<R>* acc = sm.take<cplx<R>>(tc * Lay<L>::RS);
   cplx<R>* b0 = sm.take<cplx<R>>(tc * Lay<L>::RS);
   cplx<R>* b1 = sm.take<cplx<R>>(tc * Lay<L>::RS);
   cplx<R>* tw = sm.take<cplx<R>>(L);
   const int k3 = blockIdx.y, i2_0 = blockIdx.x * tc;
-  const size_t plane = (size_t)k3 * g.n1 * g.n2;
-  for (int e = threadIdx.x; e < L * tc; e += NT) {
-    const int i1 = e / tc, c = e - i1 * tc;
-    acc[Lay<L>::at(c, i1)] = s0[plane + (size_t)i1 * g.n2 + i2_0 + c];
-  }
-  for (int m = threadIdx.x; m < L; m += NT) tw[m] = tw_g[m];
+  const size_t tile0 = (size_t)k3 * g.n1 * g.n2 + i2_0;
+  const int cnt = L * tc;
   const cplx<R>* Cs[3] = {C0, C1, C2};
+  const cplx<R> twv = twiddle_load<R, L>(tw_g);
+  // S0 and the first component are loaded together; each later component is
+  // loaded into registers while the previous one is transformed
+  unsigned off[U];
+  x1_offsets<U>(off, cnt, g.n2, tc, tcl);
+  cplx<R> sv[U], cv[U];
+  {
+    const cplx<R>* St = s0 + tile0;
+    const cplx<R>* Ct = C0 + tile0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      sv[u] = St[off[u]];
+      cv[u] = Ct[off[u]];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int e = threadIdx.x + u * NT;
+    if (e < cnt) acc[Lay<L>::at(e & (tc - 1), e >> tcl)] = sv[u];
+  }
+  twiddle_store<R, L>(tw, twv);
   const R inv_n = R(g.inv_n);
 #pragma unroll 1
   for (int a = 0; a < 3; ++a) {
-    for (int e = threadIdx.x; e < L * tc; e += NT) {
-      const int i1 = e / tc, c = e - i1 * tc;
-      b0[Lay<L>::at(c, i1)] = Cs[a][plane + (size_t)i1 * g.n2 + i2_0 + c];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = threadIdx.x + u * NT;
+      if (e < cnt) b0[Lay<L>::at(e & (tc - 1), e >> tcl)] = cv[u];
+    }
+    if (a < 2) {
+      const cplx<R>* nxt = Cs[a + 1] + tile0;
+#pragma unroll
+      for (int u = 0; u < U; ++u) cv[u] = nxt[off[u]];
     }
     __syncthreads();
     const cplx<R>* res = lds_fft<R, -1, L, NT>(b0, b1, tw, tc, threadIdx.x);
-    for (int e = threadIdx.x; e < L * tc; e += NT) {
+    for (int e = threadIdx.x; e < cnt; e += NT) {
       const int c = e / L, k1 = e - c * L;
-      double gv[3];
-      const bool keep = gvec(g, k1, i2_0 + c, k3, gv[0], gv[1], gv[2]);
-      if (keep) {
-        const R ga = R(gv[a]) * inv_n;
+      const int k2 = i2_0 + c;
+      if ((2 * k1 != g.n1) && (2 * k2 != g.n2) && (2 * k3 != g.n3)) {
+        const int m1 = signed_freq(k1, g.n1), m2 = signed_freq(k2, g.n2);
+        const R ga = R(m1 * g.b[a] + m2 * g.b[3 + a] + double(k3) * g.b[6 + a]) * inv_n;
         const int idx = Lay<L>::at(c, k1);
         const cplx<R> z = res[idx];
         // acc -= i G_a W_a(G)
@@ -494,10 +624,7 @@ __global__ void __launch_bounds__(NT) k_x1_divergence(const cplx<R>* __restrict_
     __syncthreads();
   }
   const cplx<R>* o = lds_fft<R, +1, L, NT>(acc, b0, tw, tc, threadIdx.x);
-  for (int e = threadIdx.x; e < L * tc; e += NT) {
-    const int i1 = e / tc, c = e - i1 * tc;
-    out[plane + (size_t)i1 * g.n2 + i2_0 + c] = o[Lay<L>::at(c, i1)];
-  }
+  store_x1_tile<R, L, U>(o, out + tile0, off, tc, tcl, cnt);
 }
 
 // ---------------------------------------------------------------- K6: final potential
@@ -515,15 +642,27 @@ __global__ void __launch_bounds__(NT) k_rpass_final(const cplx<R>* __restrict__ 
   double* red = sm.take<double>(4 * NT / 64);
   const int i1 = blockIdx.y, i2_0 = blockIdx.x * tr;
   const size_t base = ((size_t)i1 * g.n2 + i2_0) * L;
-  for (int m = threadIdx.x; m < L; m += NT) tw[m] = tw_g[m];
-  load_pack_half_spectra<R, L>(D, zb, za, g, i1, i2_0, tr);
+  const int cnt = tr * L;
+  load_pack_half_spectra<R, L>(D, zb, za, g, i1, i2_0, tr, tw, twiddle_load<R, L>(tw_g));
+  // phi and v_loc of the tile, in flight during the inverse FFT
+  double pv[MAXU];
+  R lv[MAXU];
+#pragma unroll
+  for (int u = 0; u < MAXU; ++u) {
+    const int e = tile_elem(u, cnt);
+    pv[u] = phi[base + e];
+    if constexpr (!TF) lv[u] = vloc[base + e];
+  }
   const cplx<R>* res = lds_fft<R, +1, L, NT>(za, zb, tw, tr / 2, threadIdx.x);
   double fs = 0.0, ts = 0.0, exc = 0.0, nv = 0.0;
-  for (int e = threadIdx.x; e < tr * L; e += NT) {
+#pragma unroll
+  for (int u = 0; u < MAXU; ++u) {
+    const int e = threadIdx.x + u * NT;
+    if (e >= cnt) continue;
     const int r = e / L, i3 = e - r * L;
     const cplx<R> z = res[Lay<L>::at(r >> 1, i3)];
     const double S = (r & 1) ? double(z.y) : double(z.x);
-    const double p = phi[base + e];
+    const double p = pv[u];
     const double n = p * p;
     double vl;
     if constexpr (TF) {
@@ -540,7 +679,7 @@ __global__ void __launch_bounds__(NT) k_rpass_final(const cplx<R>* __restrict__ 
         exc += n * double(eps);
       }
     } else {
-      vl = double(vloc[base + e]);
+      vl = double(lv[u]);
     }
     const R vv = R(vl + S + ep.alpha_sum);
     vout[base + e] = vv;
@@ -910,26 +1049,59 @@ static void launch_rpass_fwd(ofdft_ctx* c, const double* phi, void* out) {
                      (cplx<R>*)out, (const cplx<R>*)c->tw[2], g, c->partials, c->max_blocks);
 }
 
+template <typename R, int L, int SIGN, int U>
+static void launch_x2_u(ofdft_ctx* c, void* a0, void* a1, void* a2, int narr) {
+  const GridDesc& g = c->g;
+  const int nrows = g.n3k * g.n1;   // the k3 = n3/2 plane is not used
+  dim3 grid((unsigned)((nrows + g.rb - 1) / g.rb), narr);
+  Arr3 arr{{a0, a1, a2}};
+  hipLaunchKernelGGL((k_cpass_x2<R, L, SIGN, U>), grid, dim3(NT), (lds_x2<R, L>(g.rb)), c->stream, arr,
+                     (const cplx<R>*)c->tw[1], nrows, g.rb);
+}
+
+// Staged elements per thread of an x1 tile of L * tc elements: 1, 2, 4 or 8.
+static inline int x1_stage_u(int L, int tc) {
+  const int need = (L * tc + NT - 1) / NT;
+  return need <= 1 ? 1 : need <= 2 ? 2 : need <= 4 ? 4 : 8;
+}
+
+#define OFDFT_DISPATCH_U(UVAL, CALL)               \
+  switch (UVAL) {                                  \
+    case 1: { constexpr int U_ = 1; CALL; } break; \
+    case 2: { constexpr int U_ = 2; CALL; } break; \
+    case 4: { constexpr int U_ = 4; CALL; } break; \
+    default: { constexpr int U_ = 8; CALL; } break; \
+  }
+
+// Staged elements per thread of an x2 tile of rb rows of L: 1, 2, 4, 8 or 16.
+static inline int x2_stage_u(int L, int rb) {
+  const int need = (L * rb + NT - 1) / NT;
+  return need <= 1 ? 1 : need <= 2 ? 2 : need <= 4 ? 4 : need <= 8 ? 8 : 16;
+}
+
 template <typename R, int L, int SIGN>
 static void launch_x2(ofdft_ctx* c, void* a0, void* a1, void* a2, int narr) {
+  switch (x2_stage_u(L, c->g.rb)) {
+    case 1: launch_x2_u<R, L, SIGN, 1>(c, a0, a1, a2, narr); break;
+    case 2: launch_x2_u<R, L, SIGN, 2>(c, a0, a1, a2, narr); break;
+    case 4: launch_x2_u<R, L, SIGN, 4>(c, a0, a1, a2, narr); break;
+    case 8: launch_x2_u<R, L, SIGN, 8>(c, a0, a1, a2, narr); break;
+    default: launch_x2_u<R, L, SIGN, 16>(c, a0, a1, a2, narr); break;
+  }
+}
+
+template <typename R, int L, int MODE, int U>
+static void launch_x1_density_u(ofdft_ctx* c, void* out0, void* out1, void* out2) {
   const GridDesc& g = c->g;
-  const long long nrows = (long long)g.n3h * g.n1;
-  const long long ntiles = (nrows + g.rb - 1) / g.rb;
-  // persistent blocks: a few per CU, each looping over tiles with prefetch
-  const long long cap = 2048 / narr;
-  dim3 grid((unsigned)(ntiles < cap ? ntiles : cap), narr);
-  Arr3 arr{{a0, a1, a2}};
-  hipLaunchKernelGGL((k_cpass_x2<R, L, SIGN>), grid, dim3(NT), (lds_x2<R, L>(g.rb)), c->stream, arr,
-                     (const cplx<R>*)c->tw[1], nrows, g.rb);
+  dim3 grid(g.n2 / g.tc, g.n3k);
+  hipLaunchKernelGGL((k_x1_density<R, L, MODE, U>), grid, dim3(NT), (lds_x1<R, L>(g.tc, 2)), c->stream,
+                     (const cplx<R>*)c->A, (const cplx<R>*)c->Vext, (cplx<R>*)out0, (cplx<R>*)out1,
+                     (cplx<R>*)out2, (cplx<R>*)c->S0, (const cplx<R>*)c->tw[0], g, c->partials, c->max_blocks);
 }
 
 template <typename R, int L, int MODE>
 static void launch_x1_density(ofdft_ctx* c, void* out0, void* out1, void* out2) {
-  const GridDesc& g = c->g;
-  dim3 grid(g.n2 / g.tc, g.n3h);
-  hipLaunchKernelGGL((k_x1_density<R, L, MODE>), grid, dim3(NT), (lds_x1<R, L>(g.tc, 2)), c->stream,
-                     (const cplx<R>*)c->A, (const cplx<R>*)c->Vext, (cplx<R>*)out0, (cplx<R>*)out1,
-                     (cplx<R>*)out2, (cplx<R>*)c->S0, (const cplx<R>*)c->tw[0], g, c->partials, c->max_blocks);
+  OFDFT_DISPATCH_U(x1_stage_u(L, c->g.tc), (launch_x1_density_u<R, L, MODE, U_>(c, out0, out1, out2)));
 }
 
 template <typename R, int L>
@@ -958,13 +1130,18 @@ static void launch_rpass_fwd_real3(ofdft_ctx* c) {
                      (const cplx<R>*)c->tw[2], g);
 }
 
-template <typename R, int L>
-static void launch_x1_div(ofdft_ctx* c) {
+template <typename R, int L, int U>
+static void launch_x1_div_u(ofdft_ctx* c) {
   const GridDesc& g = c->g;
-  dim3 grid(g.n2 / g.tc, g.n3h);
-  hipLaunchKernelGGL((k_x1_divergence<R, L>), grid, dim3(NT), (lds_x1<R, L>(g.tc, 0)), c->stream,
+  dim3 grid(g.n2 / g.tc, g.n3k);
+  hipLaunchKernelGGL((k_x1_divergence<R, L, U>), grid, dim3(NT), (lds_x1<R, L>(g.tc, 0)), c->stream,
                      (const cplx<R>*)c->B[0], (const cplx<R>*)c->B[1], (const cplx<R>*)c->B[2],
                      (const cplx<R>*)c->S0, (cplx<R>*)c->D, (const cplx<R>*)c->tw[0], g);
+}
+
+template <typename R, int L>
+static void launch_x1_div(ofdft_ctx* c) {
+  OFDFT_DISPATCH_U(x1_stage_u(L, c->g.tc), (launch_x1_div_u<R, L, U_>(c)));
 }
 
 template <typename R, int L, bool TF>
@@ -1050,7 +1227,7 @@ static int eval_impl(ofdft_ctx* c, const double* phi, void* v_out, double* sc) {
     OFDFT_DISPATCH(g.n3, (launch_rpass_final<R, L_, false>(c, phi, v_out, ep)));
   }
   const int nb_r = (g.n2 / g.tr) * g.n1;
-  ReduceParams rp{nb_r, (g.n2 / g.tc) * g.n3h, tf ? nb_r : PW_BLOCKS, g.dv, g.volume, c->alpha_sum, c->E_ion};
+  ReduceParams rp{nb_r, (g.n2 / g.tc) * g.n3k, tf ? nb_r : PW_BLOCKS, g.dv, g.volume, c->alpha_sum, c->E_ion};
   tmark(c, "reduce_scalars");
   hipLaunchKernelGGL(k_reduce_scalars, dim3(1), dim3(RED_NT), 0, c->stream, c->partials, c->max_blocks, rp, sc);
   tmark(c, "end");
@@ -1122,18 +1299,43 @@ static bool upload_twiddles(ofdft_ctx* c) {
   return true;
 }
 
+static void allow_large_lds(const void* f) {
+  (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+}
+
+template <typename R, int L, int U>
+static void allow_x1() {
+  allow_large_lds((const void*)k_x1_density<R, L, X1_TF, U>);
+  allow_large_lds((const void*)k_x1_density<R, L, X1_GGA, U>);
+  allow_large_lds((const void*)k_x1_density<R, L, X1_NHAT, U>);
+  allow_large_lds((const void*)k_x1_divergence<R, L, U>);
+}
+
+template <typename R, int L>
+static void allow_x2() {
+  allow_large_lds((const void*)k_cpass_x2<R, L, -1, 1>);
+  allow_large_lds((const void*)k_cpass_x2<R, L, -1, 2>);
+  allow_large_lds((const void*)k_cpass_x2<R, L, -1, 4>);
+  allow_large_lds((const void*)k_cpass_x2<R, L, -1, 8>);
+  allow_large_lds((const void*)k_cpass_x2<R, L, -1, 16>);
+  allow_large_lds((const void*)k_cpass_x2<R, L, +1, 1>);
+  allow_large_lds((const void*)k_cpass_x2<R, L, +1, 2>);
+  allow_large_lds((const void*)k_cpass_x2<R, L, +1, 4>);
+  allow_large_lds((const void*)k_cpass_x2<R, L, +1, 8>);
+  allow_large_lds((const void*)k_cpass_x2<R, L, +1, 16>);
+}
+
 template <typename R>
 static void configure_lds() {
   // Opt every kernel into the large CDNA4 LDS.
-  auto allow = [](const void* f) { (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024); };
+  auto allow = [](const void* f) { allow_large_lds(f); };
 #define OFDFT_ALLOW(LEN)                                                             \
   allow((const void*)k_rpass_fwd_density<R, LEN>);                                   \
-  allow((const void*)k_cpass_x2<R, LEN, -1>);                                        \
-  allow((const void*)k_cpass_x2<R, LEN, +1>);                                        \
-  allow((const void*)k_x1_density<R, LEN, X1_TF>);                                   \
-  allow((const void*)k_x1_density<R, LEN, X1_GGA>);                                  \
-  allow((const void*)k_x1_density<R, LEN, X1_NHAT>);                                 \
-  allow((const void*)k_x1_divergence<R, LEN>);                                       \
+  allow_x2<R, LEN>();                                                                \
+  allow_x1<R, LEN, 1>();                                                             \
+  allow_x1<R, LEN, 2>();                                                             \
+  allow_x1<R, LEN, 4>();                                                             \
+  allow_x1<R, LEN, 8>();                                                             \
   allow((const void*)k_rpass_final<R, LEN, true>);                                   \
   allow((const void*)k_rpass_final<R, LEN, false>);                                  \
   allow((const void*)k_rpass_inv_real<R, LEN>);                                      \

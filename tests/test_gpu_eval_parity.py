@@ -84,3 +84,27 @@ def test_eval_is_deterministic():
     r2, v2 = ctx.eval(potential=True)
     assert r1.F_total == r2.F_total
     assert np.array_equal(v1, v2)
+
+
+@pytest.mark.parametrize("precision,functional", [("fp64", "VT84F"), ("mixed", "VT84F"), ("fp64", "TF")])
+def test_fft_tiles_do_not_change_results(precision, functional):
+    """Every tile choice (rows/columns per workgroup of the three FFT passes, including
+    tiles with 1, 2, 4 and 8 staged elements per thread) gives the same evaluation; the
+    oracle pins the default tiles."""
+    cell = wl.h_cell(6, 2.0, (32, 32, 32), 5e4, seed=605)
+    ctx, sysm = make_pair(cell, functional, precision=precision)
+    phi = normalized_phi(sysm, seed=11)
+    ctx.set_density(phi)
+    tol_e, tol_v = (1e-10, 1e-10) if precision == "fp64" else (1e-6, 1e-5)
+    ev = oracle.evaluate(phi, sysm)
+    rep0, v0 = ctx.eval(potential=True)
+    assert rel(rep0.F_total, ev.F_tot) <= tol_e
+    for tiles in [(2, 1, 1), (4, 2, 2), (8, 8, 8), (16, 16, 32), (32, 32, 64)]:
+        ctx.set_tiles(tiles)
+        rep, v = ctx.eval(potential=True)
+        assert rel(rep.F_total, rep0.F_total) <= (1e-13 if precision == "fp64" else 1e-6), tiles
+        assert np.max(np.abs(v - v0)) <= (1e-12 if precision == "fp64" else 1e-5) * np.max(np.abs(v0)), tiles
+    tiles = ctx.autotune(2)
+    rep, v = ctx.eval(potential=True)
+    assert rel(rep.F_total, ev.F_tot) <= tol_e, tiles
+    assert np.sqrt(np.mean((v - ev.v) ** 2)) / np.sqrt(np.mean(ev.v ** 2)) <= tol_v, tiles
