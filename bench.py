@@ -137,6 +137,19 @@ def eval_rate(ctx, steps, warmup):
     return steps / (t1 - t0), 1e3 * (t1 - t0) / steps, dev_ms / steps
 
 
+def host_api_rate(ctx, steps):
+    """Evaluations per second through the C ABI's ofdft_eval, which returns its report (and
+    optionally the FP64 potential, N doubles over PCIe) in host memory."""
+    out = {}
+    for name, pot in (("report_only", False), ("with_potential", True)):
+        ctx.eval(potential=pot)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.eval(potential=pot)
+        out[name] = steps / (time.perf_counter() - t0)
+    return out
+
+
 def md_run(P, wl, precision, n_steps):
     from paper_1406_0835_amd import md
     cell = wl.md_cell()
@@ -159,6 +172,7 @@ def md_run(P, wl, precision, n_steps):
 
 def batch_run(P, wl, n_cells, precision):
     """Heterogeneous batch: all cells minimised concurrently vs one after another."""
+    import numpy as np
     cells = wl.batch_cells(n_cells)
     def build():
         out = []
@@ -191,6 +205,7 @@ def batch_run(P, wl, n_cells, precision):
 
 def md_long(P, wl, n_steps):
     """NVE drift (Ha/atom/ps) of the mixed and FP64 paths, and mixed-vs-FP64 forces."""
+    import numpy as np
     from paper_1406_0835_amd import md
     out = {}
     cell = wl.md_cell()
@@ -212,7 +227,7 @@ def md_long(P, wl, n_steps):
         if precision == "mixed":
             ctx.set_ions(cell.positions, cell.charges)
             ctx.minimize_density()
-            _, f0, _ = ctx.free_energy_and_forces()
+            _, _, f0 = ctx.free_energy_and_forces(forces=True)
             _, f64, _ = md.step_forces(check, cell.positions, cell.charges)
             ferr[0] = float(np.max(np.abs(f0 - f64)))
         e = np.array([r.F_total + r.kinetic for r in recs])
@@ -303,6 +318,7 @@ def main():
     value, ms_per_step, dev_ms = eval_rate(ctx, args.steps, args.warmup)
     log(f"{value:.1f} evals/s; per-kernel events over {args.kernel_steps} evaluations")
     _, kern = ctx.time_evals(args.kernel_steps, 16)
+    host_api = host_api_rate(ctx, max(10, args.steps // 10))
     ctx.close()
 
     per_kernel = []
@@ -375,6 +391,7 @@ def main():
         "grid_points_per_s": value * n1 * n2 * n3,
         "device_ms_per_eval": dev_ms,
         "eval_alg_GB_s": eval_gbs,
+        "host_api_evals_per_s": host_api,
         "roofline": roofline,
         "kernels": per_kernel,
         "fp64": fp64,

@@ -40,6 +40,18 @@ __device__ __forceinline__ void cheb_series(const double* __restrict__ c, double
   }
 }
 
+// Smallest cell among the lanes in `pending` (a ballot mask): start from the
+// first pending lane and step to any pending lane with a smaller cell.  Only
+// lanes reported by __ballot are read, so a partly populated wavefront cannot
+// contribute stale values; the steps are bounded by the wavefront size.
+__device__ __forceinline__ int min_pending_cell(int cell, bool pending_lane, unsigned long long pending) {
+  int pm = __builtin_amdgcn_readlane(cell, __ffsll((long long)pending) - 1);
+  unsigned long long lower;
+  for (int step = 0; step < 64 && (lower = __ballot(pending_lane && cell < pm)) != 0ull; ++step)
+    pm = __builtin_amdgcn_readlane(cell, __ffsll((long long)lower) - 1);
+  return pm;
+}
+
 // The t-dependent factors at l = ln t (clamped to the tabulated range).
 // Piece j spans [LLO + j H, LLO + j H + W] with W = 2 H.  Each pass takes the
 // smallest cell among the lanes still pending and evaluates that piece for the
@@ -52,25 +64,22 @@ __device__ __forceinline__ void t_table(const double* __restrict__ table, double
   l = fmin(fmax(l, OFDFT_T_LLO), OFDFT_T_LHI);
   int cell = (int)((l - OFDFT_T_LLO) * (1.0 / OFDFT_T_H));
   cell = cell < 0 ? 0 : (cell >= OFDFT_T_NP ? OFDFT_T_NP - 1 : cell);
-  bool done = false;
-  // Only lanes reported by __ballot (active and pending) are ever read, so a
-  // partly populated wavefront cannot contribute stale values.
-  // Both loops are bounded by the wavefront size: each inner step moves to a
-  // distinct pending lane, each outer pass completes at least one lane.
+  // First pass: the piece of the smallest cell, written straight into s.  Every
+  // lane of that cell has l - a < H, i.e. x < 0, so each pass completes at least
+  // one lane; the loop below (bounded by the wavefront size) serves the rest.
   unsigned long long pending = __ballot(true);
-  for (int pass = 0; pending != 0ull && pass < 64; ++pass) {
-    // smallest cell among the pending lanes: start from the first pending lane
-    // and step to any pending lane with a smaller cell (strictly decreasing)
-    int pm = __builtin_amdgcn_readlane(cell, __ffsll((long long)pending) - 1);
-    unsigned long long lower;
-    for (int step = 0; step < 64 && (lower = __ballot(!done && cell < pm)) != 0ull; ++step)
-      pm = __builtin_amdgcn_readlane(cell, __ffsll((long long)lower) - 1);
-    const double a = OFDFT_T_LLO + pm * OFDFT_T_H;
-    const double x = (l - a) * (2.0 / OFDFT_T_W) - 1.0;
+  int pm = min_pending_cell(cell, true, pending);
+  double a = OFDFT_T_LLO + pm * OFDFT_T_H;
+  double x = (l - a) * (2.0 / OFDFT_T_W) - 1.0;
+  cheb_series<NF>(table + pm * NF * OFDFT_T_NC, x, s);
+  bool done = x <= 1.0;
+  pending = __ballot(!done);
+  for (int pass = 1; pending != 0ull && pass < 64; ++pass) {
+    pm = min_pending_cell(cell, !done, pending);
+    a = OFDFT_T_LLO + pm * OFDFT_T_H;
+    x = (l - a) * (2.0 / OFDFT_T_W) - 1.0;
     double r[NF];
     cheb_series<NF>(table + pm * NF * OFDFT_T_NC, x, r);
-    // every pending lane of cell pm has l - a < H, i.e. x < 0, so each pass
-    // completes at least one lane
     if (!done && x <= 1.0) {
 #pragma unroll
       for (int f = 0; f < NF; ++f) s[f] = r[f];
