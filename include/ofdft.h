@@ -90,6 +90,10 @@ typedef struct {
   int max_iter;        /* outer iterations */
   int device;          /* HIP device ordinal */
   void* stream;        /* hipStream_t to launch on; NULL = a stream owned by the context */
+  double cg_precond;   /* CG with a gradient functional: > 0 filters the gradient with
+                          1/(1 + G^2/(cg_precond k_F^2)) in reciprocal space (k_F^2 = (3 pi^2 N_e/V)^(2/3))
+                          before the direction update (preconditioned Polak-Ribiere); 0 = plain CG.
+                          ftTF always uses plain CG.  Changes the iteration path, not the minimum. */
 } ofdft_options;
 
 typedef struct {
@@ -107,7 +111,8 @@ typedef struct {
 } ofdft_report;
 
 /* Fills defaults: TF, mu_sga = 5/27, PZ81, Gaussian LPP rc = 0.5, FP64, CG,
-   tol_energy = 1e-8, tol_residual = 0, max_iter = 1000, device 0, own stream. */
+   tol_energy = 1e-8, tol_residual = 0, max_iter = 1000, device 0, own stream,
+   cg_precond = 8. */
 void ofdft_default_options(ofdft_options* opt);
 
 /* Creates a context.  opt may be NULL (defaults).  *out is set on success. */

@@ -126,7 +126,9 @@ __device__ __forceinline__ void enhancement(const EnhParams& p, R x, R& F, R& dF
     const R ex = exp(-al * x);
     const R rden = rcp<R>(R(1) + mu * x);
     const R t1 = -mu * x * ex * rden;
-    const R dt1 = -mu * ex * (R(1) - al * x - al * mu * x * x) * (rden * rden);
+    // d/dx of -mu x e^{-al x}/(1 + mu x) = -mu e^{-al x} rden (rden - al x): no x^2, so
+    // the FP32 path stays finite at the huge x of near-empty grid points
+    const R dt1 = -mu * ex * rden * (rden - al * x);
     // q = 1 - exp(-al x^2) and the term q (1/x - 1), with its small-x series
     R q, qx, qx2;
     if (x < R(1e-4)) {
@@ -213,13 +215,17 @@ __device__ __forceinline__ void gga_point(double n, R sigma, double lt0, const E
   const R dFs = -dG;
   const R xi = R(a[0]), zeta = R(a[1]);
   const R fr = A * (xi * Ft - zeta * Fs);
-  // t-derivatives enter through dt/dn = -(2/3) t/n: (t X') (-(2/3)/n)
-  const R c23 = R(-2.0 / 3.0) * rn;
-  const R ds2dn = R(-8.0 / 3.0) * s2 * rn;
-  dfdn = R(5.0 / 3.0) * fr * rn +
-         A * ((R(a[2]) * Ft - R(a[3]) * Fs) * c23 + xi * dFt * (ds2dn * p_tau + s2 * R(a[6]) * c23) -
-              zeta * dFs * (ds2dn * p_sig + s2 * R(a[7]) * c23));
-  dfds = A * (xi * dFt * p_tau - zeta * dFs * p_sig) * invden;
+  // df/dn at fixed sigma, with dt/dn = -(2/3) t/n and ds^2/dn = -(8/3) s^2/n, grouped
+  // around A/n = c_TF n^(2/3) so that no FP32 intermediate overflows where n is tiny
+  // and s^2 huge:
+  //   df/dn = (A/n) [ (5/3)(xi F_t - zeta F_s) - (2/3)(t xi' F_t - t zeta' F_s)
+  //                   - s^2 xi F_t' ((8/3) P_t + (2/3) t P_t') + s^2 zeta F_s' ((8/3) P_s + (2/3) t P_s') ]
+  const R An = R(kCTF) * n23;
+  dfdn = An * (R(5.0 / 3.0) * (xi * Ft - zeta * Fs) - R(2.0 / 3.0) * (R(a[2]) * Ft - R(a[3]) * Fs) -
+               s2 * (xi * dFt * (R(8.0 / 3.0) * p_tau + R(2.0 / 3.0) * R(a[6])) -
+                     zeta * dFs * (R(8.0 / 3.0) * p_sig + R(2.0 / 3.0) * R(a[7]))));
+  // df/dsigma = A (ds^2/dsigma) (xi F_t' P_t - zeta F_s' P_s), A ds^2/dsigma = (c_TF / S) / n
+  dfds = R(kCTF / kS2Den) * rn * (xi * dFt * p_tau - zeta * dFs * p_sig);
   f_out = double(fr);
   ts_out = double(A * zeta * Fs);
 }

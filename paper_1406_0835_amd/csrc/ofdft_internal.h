@@ -32,6 +32,7 @@ struct GridDesc {
   long long NS;   // n3h n1 n2 half-spectrum points (layout [k3][k1][k2])
   double b[9];    // reciprocal lattice rows b1, b2, b3 (a_i . b_j = 2 pi delta_ij)
   double volume, dv, inv_n;
+  double prec_k2; // reciprocal-space filter 1/(1 + G^2/prec_k2) of the preconditioned minimiser
   int tr;         // rows per block in the contiguous-axis pass (power of two >= 2, divides n2)
   int tc;         // columns per block in the strided pass (power of two, divides n2)
   int rb;         // rows per block in the x2 pass (power of two)
@@ -131,6 +132,13 @@ int dev_forces(ofdft_ctx* c, double* forces_host);
 int dev_grad_dots(ofdft_ctx* c, const double* phi, const void* v, const double* sc, const double* gprev,
                   const double* d, double* out);
 int dev_cg_direction(ofdft_ctx* c, double beta, double cproj);
+// Preconditioned variant: z = P g (P the reciprocal-space filter with g.prec_k2), formed as
+// g + w with w = (P - 1) g in c->gr[0];
+// out[0..4] = z.g, z.gprev, z.phi, sum n (v-mu)^2, phi.gprev
+int dev_precond_dots(ofdft_ctx* c, const double* phi, const void* v, const double* sc, const double* gprev,
+                     double* out);
+// d = -(z - cz phi) + beta (d - cproj phi); gprev = g; out: d.d, d.g
+int dev_pcg_direction(ofdft_ctx* c, double beta, double cproj, double cz);
 int dev_rotate(ofdft_ctx* c, double* dst, const double* phi, double ca, const double* dir, double sb);
 // dF/dtheta at the trial point, written to out[0]
 int dev_dtheta(ofdft_ctx* c, const double* phi_t, const void* v_t, const double* sc_t, const double* phi,

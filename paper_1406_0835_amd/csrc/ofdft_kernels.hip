@@ -326,7 +326,10 @@ __device__ __forceinline__ void store_x1_tile(const cplx<R>* o, cplx<R>* dst, co
   }
 }
 
-enum { X1_TF = 0, X1_GGA = 1, X1_NHAT = 2 };
+// X1_TF: 4 pi n/G^2 + v_ext and energies, inverse x1 (ftTF); X1_GGA: also i G_a n(G) x 3;
+// X1_NHAT: n(G) only (forces); X1_PREC: (P(G) - 1) g(G) with the minimiser's filter
+// P = 1/(1 + G^2/k0^2), inverse x1 (modes the passes do not carry keep P = 1).
+enum { X1_TF = 0, X1_GGA = 1, X1_NHAT = 2, X1_PREC = 3 };
 
 // U: staged elements per thread, U * NT >= L * tc.
 template <typename R, int L, int MODE, int U>
@@ -354,7 +357,7 @@ __global__ void __launch_bounds__(NT) k_x1_density(const cplx<R>* __restrict__ A
   const cplx<R>* At = A + tile0;
 #pragma unroll
   for (int u = 0; u < U; ++u) av[u] = At[off[u]];
-  if constexpr (MODE != X1_NHAT) {
+  if constexpr (MODE == X1_TF || MODE == X1_GGA) {
     // v_ext(G) of the tile: needed after the forward FFT, in flight meanwhile
     const cplx<R>* Vt = vext + tile0;
 #pragma unroll
@@ -388,7 +391,7 @@ __global__ void __launch_bounds__(NT) k_x1_density(const cplx<R>* __restrict__ A
       if (keep && G2 > 0.0) {
         const double nx = nh.x, ny = nh.y;
         const double kern = kFourPi / G2;
-        if constexpr (MODE != X1_NHAT) {
+        if constexpr (MODE == X1_TF || MODE == X1_GGA) {
           const cplx<R> v = ve[u];
           eh += wk * kern * (nx * nx + ny * ny);
           ee += wk * (nx * double(v.x) + ny * double(v.y));
@@ -396,7 +399,9 @@ __global__ void __launch_bounds__(NT) k_x1_density(const cplx<R>* __restrict__ A
         }
       }
       if (!keep) nh = {R(0), R(0)};
-      if constexpr (MODE == X1_TF) {
+      if constexpr (MODE == X1_PREC) {
+        res[idx] = cscale(nh, R(-G2 / (G2 + g.prec_k2)));   // P(G) - 1
+      } else if constexpr (MODE == X1_TF) {
         res[idx] = S;
       } else if constexpr (MODE == X1_GGA) {
         s0[gi] = S;
@@ -406,7 +411,7 @@ __global__ void __launch_bounds__(NT) k_x1_density(const cplx<R>* __restrict__ A
       }
     }
   }
-  if constexpr (MODE != X1_NHAT) {
+  if constexpr (MODE == X1_TF || MODE == X1_GGA) {
     double v[2] = {eh, ee};
     block_sum<2>(v, red);
     if (threadIdx.x == 0) {
@@ -417,7 +422,7 @@ __global__ void __launch_bounds__(NT) k_x1_density(const cplx<R>* __restrict__ A
   } else {
     __syncthreads();
   }
-  if constexpr (MODE == X1_TF) {
+  if constexpr (MODE == X1_TF || MODE == X1_PREC) {
     const cplx<R>* o = lds_fft<R, +1, L, NT>(res, fa, tw, tc, threadIdx.x);
     store_x1_tile<R, L, U>(o, out0 + tile0, off, tc, tcl, cnt);
   } else if constexpr (MODE == X1_GGA) {
@@ -553,6 +558,47 @@ __global__ void __launch_bounds__(NT) k_rpass_fwd_real(RealArr3 in, Arr3 out, co
   __syncthreads();
   const cplx<R>* res = lds_fft<R, -1, L, NT>(za, zb, tw, tr / 2, threadIdx.x);
   store_half_spectra<R, L>(res, dst, g, i1, i2_0, tr);
+}
+
+// Forward x3 FFT of the minimiser's projected gradient g = 2 dv phi (v - mu),
+// formed on the fly (the first pass of the preconditioner P g).
+template <typename R, int L>
+__global__ void __launch_bounds__(NT) k_rpass_fwd_grad(const double* __restrict__ phi, const R* __restrict__ v,
+                                                       const double* __restrict__ sc, double two_dv,
+                                                       cplx<R>* __restrict__ out, const cplx<R>* __restrict__ tw_g,
+                                                       GridDesc g) {
+  extern __shared__ __align__(16) char smem_raw[];
+  const int tr = g.tr;
+  Smem sm(smem_raw);
+  cplx<R>* za = sm.take<cplx<R>>((tr / 2) * Lay<L>::RS);
+  cplx<R>* zb = sm.take<cplx<R>>((tr / 2) * Lay<L>::RS);
+  cplx<R>* tw = sm.take<cplx<R>>(L);
+  const int i1 = blockIdx.y, i2_0 = blockIdx.x * tr;
+  const size_t base = ((size_t)i1 * g.n2 + i2_0) * L;
+  const int cnt = tr * L;
+  const cplx<R> twv = twiddle_load<R, L>(tw_g);
+  double pv[MAXU];
+  R vv[MAXU];
+#pragma unroll
+  for (int u = 0; u < MAXU; ++u) {
+    const int e = tile_elem(u, cnt);
+    pv[u] = phi[base + e];
+    vv[u] = v[base + e];
+  }
+  twiddle_store<R, L>(tw, twv);
+  const double mu = sc[SC_MU];
+  R* zr = reinterpret_cast<R*>(za);
+#pragma unroll
+  for (int u = 0; u < MAXU; ++u) {
+    const int e = threadIdx.x + u * NT;
+    if (e < cnt) {
+      const int r = e / L, i3 = e - r * L;
+      zr[2 * Lay<L>::at(r >> 1, i3) + (r & 1)] = R(two_dv * pv[u] * (double(vv[u]) - mu));
+    }
+  }
+  __syncthreads();
+  const cplx<R>* res = lds_fft<R, -1, L, NT>(za, zb, tw, tr / 2, threadIdx.x);
+  store_half_spectra<R, L>(res, out, g, i1, i2_0, tr);
 }
 
 // ---------------------------------------------------------------- K5: x1 pass + divergence term
@@ -791,6 +837,41 @@ struct OpGradDots {
     acc[1] += gprev ? gi * gprev[i] : 0.0;
     acc[2] += d ? gi * d[i] : 0.0;
     acc[3] += p * p * dvm * dvm;
+  }
+};
+
+// Preconditioned dots: z = P g = g + w with w = ((P - 1) g) from the FFT passes
+// (held in R); g.g is not needed, z.g takes its place.
+template <typename R>
+struct OpPrecDots {
+  const double* phi; const R* v; const R* w; const double* sc; const double* gprev; double two_dv;
+  __device__ void operator()(long long i, double* acc) const {
+    const double mu = sc[SC_MU];
+    const double p = phi[i];
+    const double dvm = double(v[i]) - mu;
+    const double gi = two_dv * p * dvm;
+    const double zi = gi + double(w[i]);
+    acc[0] += zi * gi;
+    acc[1] += gprev ? zi * gprev[i] : 0.0;
+    acc[2] += zi * p;
+    acc[3] += p * p * dvm * dvm;
+    acc[4] += gprev ? p * gprev[i] : 0.0;
+  }
+};
+
+// d = -(z - cz phi) + beta (d - cproj phi), z = g + w; gprev = g; dots d.d and d.g
+template <typename R>
+struct OpPrecDirection {
+  const double* phi; const R* v; const R* w; const double* sc; double* gprev; double* d;
+  double two_dv, beta, cproj, cz;
+  __device__ void operator()(long long i, double* acc) const {
+    const double p = phi[i];
+    const double gi = two_dv * p * (double(v[i]) - sc[SC_MU]);
+    const double di = -(gi + double(w[i]) - cz * p) + beta * (d[i] - cproj * p);
+    d[i] = di;
+    gprev[i] = gi;
+    acc[0] += di * di;
+    acc[1] += di * gi;
   }
 };
 
@@ -1091,17 +1172,18 @@ static void launch_x2(ofdft_ctx* c, void* a0, void* a1, void* a2, int narr) {
 }
 
 template <typename R, int L, int MODE, int U>
-static void launch_x1_density_u(ofdft_ctx* c, void* out0, void* out1, void* out2) {
+static void launch_x1_density_u(ofdft_ctx* c, const void* in, void* out0, void* out1, void* out2) {
   const GridDesc& g = c->g;
   dim3 grid(g.n2 / g.tc, g.n3k);
   hipLaunchKernelGGL((k_x1_density<R, L, MODE, U>), grid, dim3(NT), (lds_x1<R, L>(g.tc, 2)), c->stream,
-                     (const cplx<R>*)c->A, (const cplx<R>*)c->Vext, (cplx<R>*)out0, (cplx<R>*)out1,
+                     (const cplx<R>*)in, (const cplx<R>*)c->Vext, (cplx<R>*)out0, (cplx<R>*)out1,
                      (cplx<R>*)out2, (cplx<R>*)c->S0, (const cplx<R>*)c->tw[0], g, c->partials, c->max_blocks);
 }
 
+// x1 pass over the spectrum `in` (n(G) in A, or the minimiser's gradient spectrum).
 template <typename R, int L, int MODE>
-static void launch_x1_density(ofdft_ctx* c, void* out0, void* out1, void* out2) {
-  OFDFT_DISPATCH_U(x1_stage_u(L, c->g.tc), (launch_x1_density_u<R, L, MODE, U_>(c, out0, out1, out2)));
+static void launch_x1_density(ofdft_ctx* c, const void* in, void* out0, void* out1, void* out2) {
+  OFDFT_DISPATCH_U(x1_stage_u(L, c->g.tc), (launch_x1_density_u<R, L, MODE, U_>(c, in, out0, out1, out2)));
 }
 
 template <typename R, int L>
@@ -1110,6 +1192,16 @@ static void launch_rpass_inv_real3(ofdft_ctx* c) {
   dim3 grid(g.n2 / g.tr, g.n1, 3);
   Arr3 in{{c->B[0], c->B[1], c->B[2]}};
   RealArr3 out{{c->gr[0], c->gr[1], c->gr[2]}};
+  hipLaunchKernelGGL((k_rpass_inv_real<R, L>), grid, dim3(NT), (lds_rpass_inv<R, L>(g.tr, 0, 0)), c->stream, in,
+                     out, (const cplx<R>*)c->tw[2], g);
+}
+
+template <typename R, int L>
+static void launch_rpass_inv_real1(ofdft_ctx* c, void* in_spec, void* out_real) {
+  const GridDesc& g = c->g;
+  dim3 grid(g.n2 / g.tr, g.n1, 1);
+  Arr3 in{{in_spec, nullptr, nullptr}};
+  RealArr3 out{{out_real, nullptr, nullptr}};
   hipLaunchKernelGGL((k_rpass_inv_real<R, L>), grid, dim3(NT), (lds_rpass_inv<R, L>(g.tr, 0, 0)), c->stream, in,
                      out, (const cplx<R>*)c->tw[2], g);
 }
@@ -1200,10 +1292,10 @@ static int eval_impl(ofdft_ctx* c, const double* phi, void* v_out, double* sc) {
   OFDFT_DISPATCH(g.n2, (launch_x2<R, L_, -1>(c, c->A, nullptr, nullptr, 1)));
   if (tf) {
     tmark(c, "x1_density_hartree");
-    OFDFT_DISPATCH(g.n1, (launch_x1_density<R, L_, X1_TF>(c, c->D, nullptr, nullptr)));
+    OFDFT_DISPATCH(g.n1, (launch_x1_density<R, L_, X1_TF>(c, c->A, c->D, nullptr, nullptr)));
   } else {
     tmark(c, "x1_density_gradient");
-    OFDFT_DISPATCH(g.n1, (launch_x1_density<R, L_, X1_GGA>(c, c->B[0], c->B[1], c->B[2])));
+    OFDFT_DISPATCH(g.n1, (launch_x1_density<R, L_, X1_GGA>(c, c->A, c->B[0], c->B[1], c->B[2])));
     tmark(c, "cpass_x2_inv3");
     OFDFT_DISPATCH(g.n2, (launch_x2<R, L_, +1>(c, c->B[0], c->B[1], c->B[2], 3)));
     tmark(c, "rpass_inv_grad3");
@@ -1308,6 +1400,7 @@ static void allow_x1() {
   allow_large_lds((const void*)k_x1_density<R, L, X1_TF, U>);
   allow_large_lds((const void*)k_x1_density<R, L, X1_GGA, U>);
   allow_large_lds((const void*)k_x1_density<R, L, X1_NHAT, U>);
+  allow_large_lds((const void*)k_x1_density<R, L, X1_PREC, U>);
   allow_large_lds((const void*)k_x1_divergence<R, L, U>);
 }
 
@@ -1339,7 +1432,8 @@ static void configure_lds() {
   allow((const void*)k_rpass_final<R, LEN, true>);                                   \
   allow((const void*)k_rpass_final<R, LEN, false>);                                  \
   allow((const void*)k_rpass_inv_real<R, LEN>);                                      \
-  allow((const void*)k_rpass_fwd_real<R, LEN>);
+  allow((const void*)k_rpass_fwd_real<R, LEN>);                                      \
+  allow((const void*)k_rpass_fwd_grad<R, LEN>);
   OFDFT_LENGTHS(OFDFT_ALLOW)
 #undef OFDFT_ALLOW
 }
@@ -1456,7 +1550,7 @@ static int forces_impl(ofdft_ctx* c, double* out_host) {
   // n(G) of the current density into A (forward transform, kept modes, 1/N)
   OFDFT_DISPATCH(g.n3, (launch_rpass_fwd<R, L_>(c, c->phi, c->A)));
   OFDFT_DISPATCH(g.n2, (launch_x2<R, L_, -1>(c, c->A, nullptr, nullptr, 1)));
-  OFDFT_DISPATCH(g.n1, (launch_x1_density<R, L_, X1_NHAT>(c, c->D, nullptr, nullptr)));
+  OFDFT_DISPATCH(g.n1, (launch_x1_density<R, L_, X1_NHAT>(c, c->A, c->D, nullptr, nullptr)));
   const int nbx = 1024;
   const int nby = (c->nat + FORCE_IONS - 1) / FORCE_IONS;
   hipLaunchKernelGGL(k_forces<R>, dim3(nbx, nby), dim3(NT), 0, c->stream, c->nat, c->dZ, (const double2*)c->phase,
@@ -1497,6 +1591,44 @@ int dev_cg_direction(ofdft_ctx* c, double beta, double cproj) {
   if (c->rsize == 4)
     return run_vec<2>(c, OpDirection<float>{c->phi, (const float*)c->v, c->scalars, c->gprev, c->d, two_dv, beta, cproj});
   return run_vec<2>(c, OpDirection<double>{c->phi, (const double*)c->v, c->scalars, c->gprev, c->d, two_dv, beta, cproj});
+}
+
+template <typename R, int L>
+static void launch_rpass_fwd_grad(ofdft_ctx* c, const double* phi, const void* v, const double* sc, double two_dv,
+                                  void* out) {
+  const GridDesc& g = c->g;
+  hipLaunchKernelGGL((k_rpass_fwd_grad<R, L>), dim3(g.n2 / g.tr, g.n1), dim3(NT), (lds_rpass_fwd<R, L>(g.tr)),
+                     c->stream, phi, (const R*)v, sc, two_dv, (cplx<R>*)out, (const cplx<R>*)c->tw[2], g);
+}
+
+template <typename R>
+static int precond_impl(ofdft_ctx* c, const double* phi, const void* v, const double* sc, const double* gprev,
+                        double* out) {
+  const GridDesc& g = c->g;
+  const double two_dv = 2.0 * g.dv;
+  // w = (P - 1) g: forward 3D FFT of g, filter in the x1 pass, inverse 3D FFT into gr[0];
+  // z = g + w, so the modes the passes drop (Nyquist) keep P = 1
+  OFDFT_DISPATCH(g.n3, (launch_rpass_fwd_grad<R, L_>(c, phi, v, sc, two_dv, c->B[0])));
+  OFDFT_DISPATCH(g.n2, (launch_x2<R, L_, -1>(c, c->B[0], nullptr, nullptr, 1)));
+  OFDFT_DISPATCH(g.n1, (launch_x1_density<R, L_, X1_PREC>(c, c->B[0], c->B[0], nullptr, nullptr)));
+  OFDFT_DISPATCH(g.n2, (launch_x2<R, L_, +1>(c, c->B[0], nullptr, nullptr, 1)));
+  OFDFT_DISPATCH(g.n3, (launch_rpass_inv_real1<R, L_>(c, c->B[0], c->gr[0])));
+  return run_vec<5>(c, OpPrecDots<R>{phi, (const R*)v, (const R*)c->gr[0], sc, gprev, two_dv}, out);
+}
+
+int dev_precond_dots(ofdft_ctx* c, const double* phi, const void* v, const double* sc, const double* gprev,
+                     double* out) {
+  return c->rsize == 4 ? precond_impl<float>(c, phi, v, sc, gprev, out)
+                       : precond_impl<double>(c, phi, v, sc, gprev, out);
+}
+
+int dev_pcg_direction(ofdft_ctx* c, double beta, double cproj, double cz) {
+  const double two_dv = 2.0 * c->g.dv;
+  if (c->rsize == 4)
+    return run_vec<2>(c, OpPrecDirection<float>{c->phi, (const float*)c->v, (const float*)c->gr[0], c->scalars,
+                                                c->gprev, c->d, two_dv, beta, cproj, cz});
+  return run_vec<2>(c, OpPrecDirection<double>{c->phi, (const double*)c->v, (const double*)c->gr[0], c->scalars,
+                                               c->gprev, c->d, two_dv, beta, cproj, cz});
 }
 
 int dev_rotate(ofdft_ctx* c, double* dst, const double* phi, double ca, const double* dir, double sb) {

@@ -7,10 +7,11 @@ from paper_1406_0835_amd import binding as B
 
 
 def make_pair(cell, functional="TF", precision="fp64", minimizer="cg", xc="PZ81", lpp=None, tol_energy=1e-10,
-              tol_residual=0.0, max_iter=2000, mu_sga=5.0 / 27.0):
+              tol_residual=0.0, max_iter=2000, mu_sga=5.0 / 27.0, cg_precond=0.0):
     lpp = lpp or {"kind": "gauss", "rc": 0.5}
     kw = dict(functional=functional, precision=precision, minimizer=minimizer, xc=xc.lower(),
               lpp_rc=lpp["rc"], tol_energy=tol_energy, tol_residual=tol_residual, max_iter=max_iter,
+              cg_precond=cg_precond,
               mu_sga=mu_sga)
     if lpp["kind"] == "ha":
         kw.update(lpp="ha", lpp_A=lpp["A"], lpp_qc=lpp["qc"])

@@ -20,6 +20,7 @@ from _gpu_common import make_pair, rel
 
 pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+PRECOND = 8.0   # cg_precond used by the preconditioned-CG tests (the library default)
 
 
 def _golden(name):
@@ -105,6 +106,48 @@ def test_c2_truncated_newton_matches_golden(T, precision):
     else:
         assert rel(F, gold["F_tot"]) < 1e-6
         assert np.max(np.abs(forces - gf)) < 1e-4
+
+
+@pytest.mark.parametrize("functional", ["TF", "VT84F"])
+def test_preconditioned_cg_fp64_small_cell_matches_oracle(functional):
+    """The reciprocal-space preconditioner changes the path, not the minimum."""
+    cell = wl.h_cell(4, 1.5, (16, 16, 16), 3e4, seed=704)
+    ctx, sysm = make_pair(cell, functional, tol_energy=1e-12, tol_residual=1e-9, cg_precond=PRECOND)
+    rep = ctx.minimize_density()
+    F, _, forces = ctx.free_energy_and_forces()
+    r = mn.minimize_cg(sysm, tol_energy=1e-12, tol_residual=1e-9, max_iter=3000)
+    assert rep.converged and r.converged
+    assert rel(F, r.result.F_tot) < 1e-10
+    assert np.max(np.abs(forces - frc.total_forces(sysm, r.result.nhat))) < 1e-7
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_c2_preconditioned_cg_matches_golden(precision):
+    gold = _golden("c2_50000")
+    cell = wl.gga_64_cell(5e4)
+    tol = dict(tol_energy=1e-12, tol_residual=1e-8) if precision == "fp64" else dict(tol_energy=1e-8)
+    ctx, _ = make_pair(cell, "VT84F", precision=precision, cg_precond=PRECOND, **tol)
+    rep = ctx.minimize_density(check=(precision == "fp64"))
+    F, _, forces = ctx.free_energy_and_forces()
+    gf = np.array(gold["forces"])
+    if precision == "fp64":
+        assert rel(F, gold["F_tot"]) < 1e-10
+        assert np.max(np.abs(forces - gf)) < 1e-6
+    else:
+        assert rel(F, gold["F_tot"]) < 1e-6
+        assert np.max(np.abs(forces - gf)) < 1e-4
+
+
+def test_mixed_cg_from_uniform_density_at_2kK():
+    """Regression: the first trial step from the uniform density empties some grid points
+    (n at the 1e-12 floor with an O(1) spectral gradient, s^2 ~ 1e32); the FP32 GGA
+    derivatives must stay finite there (they once overflowed to NaN)."""
+    gold = _golden("c2_2000")
+    ctx, _ = make_pair(wl.gga_64_cell(2000.0), "VT84F", precision="mixed", tol_energy=1e-8)
+    rep = ctx.minimize_density(check=False)
+    assert ctx.last_rc in (B.OK,), ctx.last_rc
+    assert rep.converged
+    assert rel(rep.F_total, gold["F_tot"]) < 1e-6
 
 
 def test_batch_matches_individual_minimisations():
