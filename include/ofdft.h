@@ -186,6 +186,15 @@ int ofdft_set_tiles(ofdft_ctx* ctx, const int tiles[3]);
 int ofdft_batch_minimize(ofdft_ctx* const* ctxs, int n, ofdft_report* reps);
 
 /* Message for the last error on ctx (or a global message if ctx is NULL). */
+/* Ewald energy and forces of point ions Z_I in a neutralising background (the
+   ion-ion term E_ion of the total free energy, Sec. II; the same sum that
+   set_ions evaluates).  lattice = rows a1, a2, a3 (bohr), nat >= 1 Cartesian
+   positions tau[3*nat] (bohr) and charges Z[nat] > 0.  *E receives the energy
+   (hartree), forces[3*nat] (may be NULL) the forces (hartree/bohr).  Host code:
+   needs no context and no device.  E_ARG on NULL or non-finite input or a
+   singular lattice. */
+int ofdft_ewald(const double lattice[9], int nat, const double* tau, const double* Z, double* E, double* forces);
+
 const char* ofdft_last_error(const ofdft_ctx* ctx);
 
 #ifdef __cplusplus

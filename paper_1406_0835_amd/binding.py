@@ -85,6 +85,7 @@ def load_library() -> ctypes.CDLL:
         "ofdft_batch_minimize": [ctypes.POINTER(P), I, ctypes.POINTER(Report)],
         "ofdft_autotune": [P, I, ip],
         "ofdft_set_tiles": [P, ip],
+        "ofdft_ewald": [dp, I, dp, dp, dp, dp],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -104,6 +105,21 @@ def _check(lib, rc: int, ctx=None):
     if rc != OK:
         msg = lib.ofdft_last_error(ctx)
         raise OFDFTError(rc, (msg or b"").decode())
+
+
+def ewald(lattice, positions, charges, forces: bool = True):
+    """Ion-ion Ewald energy (hartree) and forces (hartree/bohr); host code, no device."""
+    lib = load_library()
+    lat = np.ascontiguousarray(np.asarray(lattice, dtype=np.float64).reshape(9))
+    pos = np.ascontiguousarray(np.asarray(positions, dtype=np.float64).reshape(-1))
+    z = np.ascontiguousarray(np.asarray(charges, dtype=np.float64).reshape(-1))
+    if pos.size != 3 * z.size:
+        raise OFDFTError(E_ARG, "positions must be (nat, 3) and charges (nat,)")
+    E = ctypes.c_double()
+    f = np.zeros(3 * z.size) if forces else None
+    _check(lib, lib.ofdft_ewald(_dptr(lat), int(z.size), _dptr(pos), _dptr(z), ctypes.byref(E),
+                                _dptr(f) if forces else None))
+    return E.value, (f.reshape(-1, 3) if forces else None)
 
 
 def default_options(**kw) -> Options:

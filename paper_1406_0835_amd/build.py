@@ -18,7 +18,7 @@ HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result"]
 DEVICE = ["-x", "hip", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-ffp-contract=fast", "-munsafe-fp-atomics"]
-SOURCES = [("ofdft_kernels.hip", True), ("ofdft_api.cpp", False)]
+SOURCES = [("ofdft_kernels.hip", True), ("ofdft_api.cpp", False), ("ofdft_ewald.cpp", False)]
 
 
 def _compile(src, device):

@@ -46,126 +46,6 @@ int largest_pow2_divisor_upto(int n, int cap) {
   return t;
 }
 
-// ---------------------------------------------------------------- Ewald (host FP64)
-void ewald_sum(const double lat[9], int nat, const double* pos, const double* Z, double& E,
-               std::vector<double>& F) {
-  const double* a1 = lat;
-  const double* a2 = lat + 3;
-  const double* a3 = lat + 6;
-  const double V = std::fabs(a1[0] * (a2[1] * a3[2] - a2[2] * a3[1]) - a1[1] * (a2[0] * a3[2] - a2[2] * a3[0]) +
-                             a1[2] * (a2[0] * a3[1] - a2[1] * a3[0]));
-  // reciprocal rows b_i = 2 pi (a_j x a_k) / V
-  double b[9];
-  auto cross = [](const double* u, const double* v, double* w) {
-    w[0] = u[1] * v[2] - u[2] * v[1];
-    w[1] = u[2] * v[0] - u[0] * v[2];
-    w[2] = u[0] * v[1] - u[1] * v[0];
-  };
-  cross(a2, a3, b);
-  cross(a3, a1, b + 3);
-  cross(a1, a2, b + 6);
-  const double det = a1[0] * b[0] + a1[1] * b[1] + a1[2] * b[2];
-  for (int k = 0; k < 9; ++k) b[k] *= 2.0 * kPiD / det;
-  const double split = std::sqrt(kPiD) * std::pow(nat / (V * V), 1.0 / 6.0);
-  const double cfac = std::sqrt(-std::log(1e-16));
-  const double rcut = cfac / split, gcut = 2.0 * split * cfac;
-  F.assign(3 * (size_t)nat, 0.0);
-  double Q = 0.0, Q2 = 0.0;
-  for (int i = 0; i < nat; ++i) {
-    Q += Z[i];
-    Q2 += Z[i] * Z[i];
-  }
-  // real space: images n with |n . lat| possibly < rcut + cell diagonal
-  const double diag = std::sqrt(a1[0] * a1[0] + a1[1] * a1[1] + a1[2] * a1[2]) +
-                      std::sqrt(a2[0] * a2[0] + a2[1] * a2[1] + a2[2] * a2[2]) +
-                      std::sqrt(a3[0] * a3[0] + a3[1] * a3[1] + a3[2] * a3[2]);
-  int nmax[3];
-  for (int k = 0; k < 3; ++k) {
-    const double bn = std::sqrt(b[3 * k] * b[3 * k] + b[3 * k + 1] * b[3 * k + 1] + b[3 * k + 2] * b[3 * k + 2]);
-    nmax[k] = (int)std::ceil((rcut + diag) * bn / (2.0 * kPiD)) + 1;
-  }
-  std::vector<double> imgs;
-  for (int i = -nmax[0]; i <= nmax[0]; ++i)
-    for (int j = -nmax[1]; j <= nmax[1]; ++j)
-      for (int k = -nmax[2]; k <= nmax[2]; ++k) {
-        const double L[3] = {i * a1[0] + j * a2[0] + k * a3[0], i * a1[1] + j * a2[1] + k * a3[1],
-                             i * a1[2] + j * a2[2] + k * a3[2]};
-        if (std::sqrt(L[0] * L[0] + L[1] * L[1] + L[2] * L[2]) < rcut + diag) {
-          imgs.push_back(L[0]);
-          imgs.push_back(L[1]);
-          imgs.push_back(L[2]);
-        }
-      }
-  const size_t nimg = imgs.size() / 3;
-  double Er = 0.0;
-  const double c2 = 2.0 * split / std::sqrt(kPiD);
-  for (int i = 0; i < nat; ++i) {
-    for (int j = i; j < nat; ++j) {
-      const double w = (i == j) ? 0.5 : 1.0;
-      double fx = 0, fy = 0, fz = 0, e = 0;
-      for (size_t m = 0; m < nimg; ++m) {
-        const double dx = pos[3 * i] - pos[3 * j] + imgs[3 * m];
-        const double dy = pos[3 * i + 1] - pos[3 * j + 1] + imgs[3 * m + 1];
-        const double dz = pos[3 * i + 2] - pos[3 * j + 2] + imgs[3 * m + 2];
-        const double r2 = dx * dx + dy * dy + dz * dz;
-        if (r2 < 1e-20 || r2 >= rcut * rcut) continue;
-        const double r = std::sqrt(r2);
-        const double ec = std::erfc(split * r) / r;
-        e += ec;
-        const double fm = (ec + c2 * std::exp(-split * split * r2)) / r2;
-        fx += fm * dx;
-        fy += fm * dy;
-        fz += fm * dz;
-      }
-      Er += w * Z[i] * Z[j] * e;
-      if (i != j) {
-        const double zz = Z[i] * Z[j];
-        F[3 * i] += zz * fx; F[3 * i + 1] += zz * fy; F[3 * i + 2] += zz * fz;
-        F[3 * j] -= zz * fx; F[3 * j + 1] -= zz * fy; F[3 * j + 2] -= zz * fz;
-      }
-    }
-  }
-  // reciprocal space
-  int gmax[3];
-  for (int k = 0; k < 3; ++k) {
-    const double an = std::sqrt(lat[3 * k] * lat[3 * k] + lat[3 * k + 1] * lat[3 * k + 1] + lat[3 * k + 2] * lat[3 * k + 2]);
-    gmax[k] = (int)std::ceil(gcut * an / (2.0 * kPiD)) + 1;
-  }
-  double Eg = 0.0;
-  std::vector<double> cs(nat), sn(nat);
-  for (int h = -gmax[0]; h <= gmax[0]; ++h)
-    for (int k = -gmax[1]; k <= gmax[1]; ++k)
-      for (int l = -gmax[2]; l <= gmax[2]; ++l) {
-        if (!h && !k && !l) continue;
-        const double G[3] = {h * b[0] + k * b[3] + l * b[6], h * b[1] + k * b[4] + l * b[7],
-                             h * b[2] + k * b[5] + l * b[8]};
-        const double G2 = G[0] * G[0] + G[1] * G[1] + G[2] * G[2];
-        if (G2 > gcut * gcut) continue;
-        const double wgt = std::exp(-G2 / (4.0 * split * split)) / G2;
-        double Sr = 0.0, Si = 0.0;
-        for (int i = 0; i < nat; ++i) {
-          const double ph = G[0] * pos[3 * i] + G[1] * pos[3 * i + 1] + G[2] * pos[3 * i + 2];
-          cs[i] = std::cos(ph);
-          sn[i] = std::sin(ph);
-          Sr += Z[i] * cs[i];
-          Si += Z[i] * sn[i];
-        }
-        Eg += wgt * (Sr * Sr + Si * Si);
-        for (int i = 0; i < nat; ++i) {
-          // Im[e^{iG.R_i} conj(S)]
-          const double im = sn[i] * Sr - cs[i] * Si;
-          const double f = 4.0 * kPiD / V * Z[i] * wgt * im;
-          F[3 * i] += f * G[0];
-          F[3 * i + 1] += f * G[1];
-          F[3 * i + 2] += f * G[2];
-        }
-      }
-  Eg *= 2.0 * kPiD / V;
-  const double Es = -split / std::sqrt(kPiD) * Q2;
-  const double Eb = -kPiD * Q * Q / (2.0 * V * split * split);
-  E = Er + Eg + Es + Eb;
-}
-
 double alpha_of(const ofdft_options& o, double Z, double V) {
   if (o.lpp == OFDFT_LPP_HA) return 2.0 * kPiD / V * (Z * o.lpp_rc * o.lpp_rc - 2.0 / 3.0 * o.lpp_A * std::pow(o.lpp_rc, 3));
   return kPiD * Z * o.lpp_rc * o.lpp_rc / V;
@@ -235,12 +115,9 @@ int line_search(ofdft_ctx* c, double F0, double dF0, double r, double phinorm, d
   bool best_armijo = false;
   for (int trial = 0; trial < max_trials; ++trial) {
     const double ct = std::cos(theta), st = std::sin(theta);
-    int rc = dev_rotate(c, c->phi_t, c->phi, ct * ratio, c->d, st * r / dn);
-    if (rc) return rc;
-    rc = dev_eval(c, c->phi_t, c->v_t, c->scalars_t);
-    if (rc) return rc;
-    rc = dev_dtheta(c, c->phi_t, c->v_t, c->scalars_t, c->phi, c->d, -st * ratio, ct * r / dn,
-                    c->scalars_t + SC_DOT0);
+    // phi_t = rotation of phi toward d, its evaluation and dF/dtheta in one pass sequence
+    int rc = dev_eval_trial(c, c->phi, c->d, ct * ratio, st * r / dn, c->phi_t, c->v_t, c->scalars_t,
+                            -st * ratio, ct * r / dn);
     if (rc) return rc;
     ++nevals;
     double h[SC_COUNT];
@@ -286,9 +163,8 @@ int line_search(ofdft_ctx* c, double F0, double dF0, double r, double phinorm, d
   }
   if (best_theta != last_theta) {
     const double ct = std::cos(best_theta), st = std::sin(best_theta);
-    int rc = dev_rotate(c, c->phi_t, c->phi, ct * ratio, c->d, st * r / dn);
-    if (rc) return rc;
-    rc = dev_eval(c, c->phi_t, c->v_t, c->scalars_t);
+    int rc = dev_eval_trial(c, c->phi, c->d, ct * ratio, st * r / dn, c->phi_t, c->v_t, c->scalars_t,
+                            -st * ratio, ct * r / dn);
     if (rc) return rc;
     ++nevals;
   }
@@ -950,6 +826,30 @@ int ofdft_batch_minimize(ofdft_ctx* const* ctxs, int n, ofdft_report* reps) {
       g_last_error = "batch member " + std::to_string(i) + ": " + ctxs[i]->err;
       return rcs[i];
     }
+  return OFDFT_OK;
+}
+
+int ofdft_ewald(const double lattice[9], int nat, const double* tau, const double* Z, double* E, double* forces) {
+  if (!lattice || !tau || !Z || !E) return fail(nullptr, OFDFT_E_ARG, "NULL argument");
+  if (nat < 1) return fail(nullptr, OFDFT_E_ARG, "nat must be >= 1");
+  for (int k = 0; k < 9; ++k)
+    if (!is_fin(lattice[k])) return fail(nullptr, OFDFT_E_ARG, "non-finite lattice");
+  const double* a1 = lattice;
+  const double* a2 = lattice + 3;
+  const double* a3 = lattice + 6;
+  const double det = a1[0] * (a2[1] * a3[2] - a2[2] * a3[1]) - a1[1] * (a2[0] * a3[2] - a2[2] * a3[0]) +
+                     a1[2] * (a2[0] * a3[1] - a2[1] * a3[0]);
+  if (!(std::fabs(det) > 1e-12)) return fail(nullptr, OFDFT_E_ARG, "singular lattice");
+  for (int i = 0; i < nat; ++i) {
+    if (!is_fin(tau[3 * i]) || !is_fin(tau[3 * i + 1]) || !is_fin(tau[3 * i + 2]))
+      return fail(nullptr, OFDFT_E_ARG, "non-finite position");
+    if (!(Z[i] > 0.0) || !is_fin(Z[i])) return fail(nullptr, OFDFT_E_ARG, "charges must be finite and > 0");
+  }
+  std::vector<double> F;
+  double e = 0.0;
+  ewald_sum(lattice, nat, tau, Z, e, F);
+  *E = e;
+  if (forces) std::copy(F.begin(), F.end(), forces);
   return OFDFT_OK;
 }
 

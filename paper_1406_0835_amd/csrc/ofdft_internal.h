@@ -10,7 +10,9 @@
 namespace ofdft {
 
 // Slots of the per-block partial sums written by the evaluation kernels.
-enum Slot { SL_PHI2 = 0, SL_FS, SL_TS, SL_EXC, SL_EH, SL_EEXT, SL_NV, SL_COUNT };
+// SL_DT1, SL_DT2: sums phi_t v_t q and phi_t q of a line-search trial (q = ms phi + mc d),
+// from which the reduction forms dF/dtheta once mu is known.
+enum Slot { SL_PHI2 = 0, SL_FS, SL_TS, SL_EXC, SL_EH, SL_EEXT, SL_NV, SL_DT1, SL_DT2, SL_COUNT };
 // Reduced scalars of one evaluation (double[16] on the device).
 enum Scal {
   SC_NE = 0, SC_FS, SC_TS, SC_EXC, SC_EH, SC_EEXT, SC_NV, SC_MU, SC_EAZ, SC_EION, SC_FTOT,
@@ -119,6 +121,10 @@ struct ofdft_ctx {
 
 namespace ofdft {
 
+// Ewald energy and forces of the ions (ofdft_ewald.cpp, host FP64): lat rows a1..a3 (bohr),
+// Cartesian pos[3 nat], charges Z[nat]; F receives 3 nat forces (hartree/bohr).
+void ewald_sum(const double lat[9], int nat, const double* pos, const double* Z, double& E, std::vector<double>& F);
+
 // kernels (ofdft_kernels.hip)
 int dev_upload_tables(int device);
 int dev_alloc_grid(ofdft_ctx* c);
@@ -126,6 +132,10 @@ void dev_free_grid(ofdft_ctx* c);
 int dev_alloc_ions(ofdft_ctx* c);
 int dev_structure_factor(ofdft_ctx* c);
 int dev_eval(ofdft_ctx* c, const double* phi, void* v_out, double* scalars_out);
+// One line-search trial as a single evaluation: phi_out = ca phi + sb dir is formed inside
+// the density pass, and dF/dtheta = g_t . (ms phi + mc dir) lands in scalars_out[SC_DOT0].
+int dev_eval_trial(ofdft_ctx* c, const double* phi, const double* dir, double ca, double sb, double* phi_out,
+                   void* v_out, double* scalars_out, double ms, double mc);
 int dev_forces(ofdft_ctx* c, double* forces_host);
 // vector operations for the minimisers; results land in c->vout (device)
 // g = 2 dv phi (v - mu): writes g.g, g.gprev, g.d, sum n (v-mu)^2 into out[0..3]

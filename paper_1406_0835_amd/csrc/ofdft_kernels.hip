@@ -223,10 +223,18 @@ __host__ __device__ constexpr int zb_elems(int tr) {
 }
 
 // ---------------------------------------------------------------- K1: density, x3 forward
-template <typename R, int L>
+// A line-search trial on the sphere (ROT) forms its amplitude here:
+// phi_t = ca phi + sb dir, stored to phi_out, and n = phi_t^2.
+struct Rotation {
+  const double* dir;
+  double ca, sb;
+  double* phi_out;
+};
+
+template <typename R, int L, bool ROT>
 __global__ void __launch_bounds__(NT) k_rpass_fwd_density(const double* __restrict__ phi, cplx<R>* __restrict__ out,
                                                           const cplx<R>* __restrict__ tw_g, GridDesc g,
-                                                          double* __restrict__ partials, int maxb) {
+                                                          double* __restrict__ partials, int maxb, Rotation rot) {
   extern __shared__ __align__(16) char smem_raw[];
   const int tr = g.tr;
   Smem sm(smem_raw);
@@ -241,6 +249,18 @@ __global__ void __launch_bounds__(NT) k_rpass_fwd_density(const double* __restri
   double pv[MAXU];
 #pragma unroll
   for (int u = 0; u < MAXU; ++u) pv[u] = src[tile_elem(u, cnt)];
+  if constexpr (ROT) {
+    const size_t off = ((size_t)i1 * g.n2 + i2_0) * L;
+    double dv_[MAXU];
+#pragma unroll
+    for (int u = 0; u < MAXU; ++u) dv_[u] = rot.dir[off + tile_elem(u, cnt)];
+#pragma unroll
+    for (int u = 0; u < MAXU; ++u) {
+      pv[u] = rot.ca * pv[u] + rot.sb * dv_[u];
+      const int e = threadIdx.x + u * NT;
+      if (e < cnt) rot.phi_out[off + e] = pv[u];
+    }
+  }
   twiddle_store<R, L>(tw, twv);
   R* zr = reinterpret_cast<R*>(za);
   double acc = 0.0;
@@ -674,24 +694,33 @@ __global__ void __launch_bounds__(NT) k_x1_divergence(const cplx<R>* __restrict_
 }
 
 // ---------------------------------------------------------------- K6: final potential
-template <typename R, int L, bool TF>
+// DT: a line-search trial also accumulates sum phi_t v_t q and sum phi_t q with
+// q = ms phi0 + mc dir (phi0 the point the trial rotates from), the two pieces of
+// dF/dtheta = 2 dv (sum phi_t v_t q - mu sum phi_t q).
+struct Slope {
+  const double* phi0;
+  const double* dir;
+  double ms, mc;
+};
+
+template <typename R, int L, bool TF, bool DT>
 __global__ void __launch_bounds__(NT) k_rpass_final(const cplx<R>* __restrict__ D, const double* __restrict__ phi,
                                                     const R* __restrict__ vloc, R* __restrict__ vout,
                                                     const cplx<R>* __restrict__ tw_g, GridDesc g, EvalParams ep,
-                                                    double* __restrict__ partials, int maxb) {
+                                                    double* __restrict__ partials, int maxb, Slope sl) {
   extern __shared__ __align__(16) char smem_raw[];
   const int tr = g.tr;
   Smem sm(smem_raw);
   cplx<R>* za = sm.take<cplx<R>>((tr / 2) * Lay<L>::RS);
   cplx<R>* zb = sm.take<cplx<R>>(zb_elems<L>(tr));
   cplx<R>* tw = sm.take<cplx<R>>(L);
-  double* red = sm.take<double>(4 * NT / 64);
+  double* red = sm.take<double>(6 * NT / 64);
   const int i1 = blockIdx.y, i2_0 = blockIdx.x * tr;
   const size_t base = ((size_t)i1 * g.n2 + i2_0) * L;
   const int cnt = tr * L;
   load_pack_half_spectra<R, L>(D, zb, za, g, i1, i2_0, tr, tw, twiddle_load<R, L>(tw_g));
   // phi and v_loc of the tile, in flight during the inverse FFT
-  double pv[MAXU];
+  double pv[MAXU], q[MAXU];
   R lv[MAXU];
 #pragma unroll
   for (int u = 0; u < MAXU; ++u) {
@@ -699,8 +728,19 @@ __global__ void __launch_bounds__(NT) k_rpass_final(const cplx<R>* __restrict__ 
     pv[u] = phi[base + e];
     if constexpr (!TF) lv[u] = vloc[base + e];
   }
+  if constexpr (DT) {
+    double p0[MAXU], dd[MAXU];
+#pragma unroll
+    for (int u = 0; u < MAXU; ++u) {
+      const int e = tile_elem(u, cnt);
+      p0[u] = sl.phi0[base + e];
+      dd[u] = sl.dir[base + e];
+    }
+#pragma unroll
+    for (int u = 0; u < MAXU; ++u) q[u] = sl.ms * p0[u] + sl.mc * dd[u];
+  }
   const cplx<R>* res = lds_fft<R, +1, L, NT>(za, zb, tw, tr / 2, threadIdx.x);
-  double fs = 0.0, ts = 0.0, exc = 0.0, nv = 0.0;
+  double fs = 0.0, ts = 0.0, exc = 0.0, nv = 0.0, dt1 = 0.0, dt2 = 0.0;
 #pragma unroll
   for (int u = 0; u < MAXU; ++u) {
     const int e = threadIdx.x + u * NT;
@@ -730,21 +770,30 @@ __global__ void __launch_bounds__(NT) k_rpass_final(const cplx<R>* __restrict__ 
     const R vv = R(vl + S + ep.alpha_sum);
     vout[base + e] = vv;
     nv += n * double(vv);
-  }
-  if constexpr (TF) {
-    double v[4] = {fs, ts, exc, nv};
-    block_sum<4>(v, red);
-    if (threadIdx.x == 0) {
-      const int blk = blockIdx.y * gridDim.x + blockIdx.x;
-      partials[SL_FS * maxb + blk] = v[0];
-      partials[SL_TS * maxb + blk] = v[1];
-      partials[SL_EXC * maxb + blk] = v[2];
-      partials[SL_NV * maxb + blk] = v[3];
+    if constexpr (DT) {
+      dt1 += p * double(vv) * q[u];
+      dt2 += p * q[u];
     }
-  } else {
-    double v[1] = {nv};
-    block_sum<1>(v, red);
-    if (threadIdx.x == 0) partials[SL_NV * maxb + blockIdx.y * gridDim.x + blockIdx.x] = v[0];
+  }
+  constexpr int K = (TF ? 4 : 1) + (DT ? 2 : 0);
+  double v[K];
+  int slot[K];
+  int k = 0;
+  if constexpr (TF) {
+    v[k] = fs; slot[k++] = SL_FS;
+    v[k] = ts; slot[k++] = SL_TS;
+    v[k] = exc; slot[k++] = SL_EXC;
+  }
+  v[k] = nv; slot[k++] = SL_NV;
+  if constexpr (DT) {
+    v[k] = dt1; slot[k++] = SL_DT1;
+    v[k] = dt2; slot[k++] = SL_DT2;
+  }
+  block_sum<K>(v, red);
+  if (threadIdx.x == 0) {
+    const int blk = blockIdx.y * gridDim.x + blockIdx.x;
+#pragma unroll
+    for (int m = 0; m < K; ++m) partials[slot[m] * maxb + blk] = v[m];
   }
 }
 
@@ -752,6 +801,7 @@ __global__ void __launch_bounds__(NT) k_rpass_final(const cplx<R>* __restrict__ 
 struct ReduceParams {
   int nb_r, nb_x1;   // partial counts of the row-pass and x1-pass kernels
   int nb_fs;         // partial count of the free-energy slots (pointwise kernel or row pass)
+  int trial;         // 1: also dF/dtheta of a line-search trial into SC_DOT0
   double dv, volume, alpha_sum, E_ion;
 };
 
@@ -762,7 +812,8 @@ __global__ void __launch_bounds__(RED_NT) k_reduce_scalars(const double* __restr
   __shared__ double raw[SL_COUNT];
   const int s = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int cnt = (s == SL_EH || s == SL_EEXT) ? rp.nb_x1
-                  : (s == SL_FS || s == SL_TS || s == SL_EXC) ? rp.nb_fs : rp.nb_r;
+                  : (s == SL_FS || s == SL_TS || s == SL_EXC) ? rp.nb_fs
+                  : (s == SL_DT1 || s == SL_DT2) ? (rp.trial ? rp.nb_r : 0) : rp.nb_r;
   // eight independent accumulators keep eight loads in flight per lane
   const double* ps = partials + (size_t)s * maxb;
   double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -790,6 +841,7 @@ __global__ void __launch_bounds__(RED_NT) k_reduce_scalars(const double* __restr
     sc[SC_EION] = rp.E_ion;
     sc[SC_FTOT] = sc[SC_FS] + sc[SC_EXC] + sc[SC_EH] + sc[SC_EEXT] + sc[SC_EAZ] + rp.E_ion;
     for (int k = SC_FTOT + 1; k < SC_COUNT; ++k) sc[k] = 0.0;   // dot slots cleared
+    if (rp.trial) sc[SC_DOT0] = 2.0 * rp.dv * (raw[SL_DT1] - sc[SC_MU] * raw[SL_DT2]);
   }
 }
 
@@ -1123,11 +1175,15 @@ static void set_lds_limits() {
 }
 
 template <typename R, int L>
-static void launch_rpass_fwd(ofdft_ctx* c, const double* phi, void* out) {
+static void launch_rpass_fwd(ofdft_ctx* c, const double* phi, void* out, const Rotation* rot = nullptr) {
   const GridDesc& g = c->g;
   dim3 grid(g.n2 / g.tr, g.n1);
-  hipLaunchKernelGGL((k_rpass_fwd_density<R, L>), grid, dim3(NT), (lds_rpass_fwd<R, L>(g.tr)), c->stream, phi,
-                     (cplx<R>*)out, (const cplx<R>*)c->tw[2], g, c->partials, c->max_blocks);
+  if (rot)
+    hipLaunchKernelGGL((k_rpass_fwd_density<R, L, true>), grid, dim3(NT), (lds_rpass_fwd<R, L>(g.tr)), c->stream,
+                       phi, (cplx<R>*)out, (const cplx<R>*)c->tw[2], g, c->partials, c->max_blocks, *rot);
+  else
+    hipLaunchKernelGGL((k_rpass_fwd_density<R, L, false>), grid, dim3(NT), (lds_rpass_fwd<R, L>(g.tr)), c->stream,
+                       phi, (cplx<R>*)out, (const cplx<R>*)c->tw[2], g, c->partials, c->max_blocks, Rotation{});
 }
 
 template <typename R, int L, int SIGN, int U>
@@ -1237,12 +1293,18 @@ static void launch_x1_div(ofdft_ctx* c) {
 }
 
 template <typename R, int L, bool TF>
-static void launch_rpass_final(ofdft_ctx* c, const double* phi, void* v_out, const EvalParams& ep) {
+static void launch_rpass_final(ofdft_ctx* c, const double* phi, void* v_out, const EvalParams& ep,
+                               const Slope* sl = nullptr) {
   const GridDesc& g = c->g;
   dim3 grid(g.n2 / g.tr, g.n1);
-  hipLaunchKernelGGL((k_rpass_final<R, L, TF>), grid, dim3(NT), (lds_rpass_inv<R, L>(g.tr, 0, 4)), c->stream,
-                     (const cplx<R>*)c->D, phi, (const R*)c->vloc, (R*)v_out, (const cplx<R>*)c->tw[2], g, ep,
-                     c->partials, c->max_blocks);
+  if (sl)
+    hipLaunchKernelGGL((k_rpass_final<R, L, TF, true>), grid, dim3(NT), (lds_rpass_inv<R, L>(g.tr, 0, 6)),
+                       c->stream, (const cplx<R>*)c->D, phi, (const R*)c->vloc, (R*)v_out, (const cplx<R>*)c->tw[2],
+                       g, ep, c->partials, c->max_blocks, *sl);
+  else
+    hipLaunchKernelGGL((k_rpass_final<R, L, TF, false>), grid, dim3(NT), (lds_rpass_inv<R, L>(g.tr, 0, 6)),
+                       c->stream, (const cplx<R>*)c->D, phi, (const R*)c->vloc, (R*)v_out, (const cplx<R>*)c->tw[2],
+                       g, ep, c->partials, c->max_blocks, Slope{});
 }
 
 // Dispatch on a runtime length.
@@ -1281,13 +1343,18 @@ static EvalParams make_params(ofdft_ctx* c) {
   return ep;
 }
 
+// One evaluation at phi, or (rot, sl non-null) a line-search trial: the density pass
+// forms phi_t = rot.ca phi + rot.sb rot.dir into rot.phi_out and the evaluation runs at
+// phi_t, with dF/dtheta accumulated by the final pass.
 template <typename R>
-static int eval_impl(ofdft_ctx* c, const double* phi, void* v_out, double* sc) {
+static int eval_impl(ofdft_ctx* c, const double* phi, void* v_out, double* sc, const Rotation* rot = nullptr,
+                     const Slope* sl = nullptr) {
   const GridDesc& g = c->g;
   const EvalParams ep = make_params(c);
   const bool tf = c->opt.functional == OFDFT_TF;
+  const double* phi_e = rot ? rot->phi_out : phi;   // the amplitude being evaluated
   tmark(c, "rpass_fwd_density");
-  OFDFT_DISPATCH(g.n3, (launch_rpass_fwd<R, L_>(c, phi, c->A)));
+  OFDFT_DISPATCH(g.n3, (launch_rpass_fwd<R, L_>(c, phi, c->A, rot)));
   tmark(c, "cpass_x2_fwd");
   OFDFT_DISPATCH(g.n2, (launch_x2<R, L_, -1>(c, c->A, nullptr, nullptr, 1)));
   if (tf) {
@@ -1301,7 +1368,7 @@ static int eval_impl(ofdft_ctx* c, const double* phi, void* v_out, double* sc) {
     tmark(c, "rpass_inv_grad3");
     OFDFT_DISPATCH(g.n3, (launch_rpass_inv_real3<R, L_>(c)));
     tmark(c, "pointwise_gga");
-    launch_pointwise_gga<R>(c, phi, ep);
+    launch_pointwise_gga<R>(c, phi_e, ep);
     tmark(c, "rpass_fwd_w3");
     OFDFT_DISPATCH(g.n3, (launch_rpass_fwd_real3<R, L_>(c)));
     tmark(c, "cpass_x2_fwd3");
@@ -1313,13 +1380,14 @@ static int eval_impl(ofdft_ctx* c, const double* phi, void* v_out, double* sc) {
   OFDFT_DISPATCH(g.n2, (launch_x2<R, L_, +1>(c, c->D, nullptr, nullptr, 1)));
   if (tf) {
     tmark(c, "rpass_tf_final");
-    OFDFT_DISPATCH(g.n3, (launch_rpass_final<R, L_, true>(c, phi, v_out, ep)));
+    OFDFT_DISPATCH(g.n3, (launch_rpass_final<R, L_, true>(c, phi_e, v_out, ep, sl)));
   } else {
     tmark(c, "rpass_final");
-    OFDFT_DISPATCH(g.n3, (launch_rpass_final<R, L_, false>(c, phi, v_out, ep)));
+    OFDFT_DISPATCH(g.n3, (launch_rpass_final<R, L_, false>(c, phi_e, v_out, ep, sl)));
   }
   const int nb_r = (g.n2 / g.tr) * g.n1;
-  ReduceParams rp{nb_r, (g.n2 / g.tc) * g.n3k, tf ? nb_r : PW_BLOCKS, g.dv, g.volume, c->alpha_sum, c->E_ion};
+  ReduceParams rp{nb_r, (g.n2 / g.tc) * g.n3k, tf ? nb_r : PW_BLOCKS, sl ? 1 : 0, g.dv, g.volume, c->alpha_sum,
+                  c->E_ion};
   tmark(c, "reduce_scalars");
   hipLaunchKernelGGL(k_reduce_scalars, dim3(1), dim3(RED_NT), 0, c->stream, c->partials, c->max_blocks, rp, sc);
   tmark(c, "end");
@@ -1335,7 +1403,7 @@ static size_t max_lds_impl(const ofdft_ctx* c) {
   switch (g.n3) {
 #define OFDFT_LDS3(LEN) \
     case LEN: upd(lds_rpass_fwd<R, LEN>(g.tr)); upd(lds_rpass_inv<R, LEN>(g.tr, 0, 0)); \
-              upd(lds_rpass_inv<R, LEN>(g.tr, 0, 4)); break;
+              upd(lds_rpass_inv<R, LEN>(g.tr, 0, 6)); break;
     OFDFT_LENGTHS(OFDFT_LDS3)
 #undef OFDFT_LDS3
     default: break;
@@ -1361,6 +1429,14 @@ size_t dev_max_lds(const ofdft_ctx* c) {
 
 int dev_eval(ofdft_ctx* c, const double* phi, void* v_out, double* sc) {
   return c->rsize == 4 ? eval_impl<float>(c, phi, v_out, sc) : eval_impl<double>(c, phi, v_out, sc);
+}
+
+int dev_eval_trial(ofdft_ctx* c, const double* phi, const double* dir, double ca, double sb, double* phi_out,
+                   void* v_out, double* sc, double ms, double mc) {
+  const Rotation rot{dir, ca, sb, phi_out};
+  const Slope sl{phi, dir, ms, mc};
+  return c->rsize == 4 ? eval_impl<float>(c, phi, v_out, sc, &rot, &sl)
+                       : eval_impl<double>(c, phi, v_out, sc, &rot, &sl);
 }
 
 // ---------------------------------------------------------------- allocation
@@ -1423,14 +1499,17 @@ static void configure_lds() {
   // Opt every kernel into the large CDNA4 LDS.
   auto allow = [](const void* f) { allow_large_lds(f); };
 #define OFDFT_ALLOW(LEN)                                                             \
-  allow((const void*)k_rpass_fwd_density<R, LEN>);                                   \
+  allow((const void*)k_rpass_fwd_density<R, LEN, false>);                            \
+  allow((const void*)k_rpass_fwd_density<R, LEN, true>);                             \
   allow_x2<R, LEN>();                                                                \
   allow_x1<R, LEN, 1>();                                                             \
   allow_x1<R, LEN, 2>();                                                             \
   allow_x1<R, LEN, 4>();                                                             \
   allow_x1<R, LEN, 8>();                                                             \
-  allow((const void*)k_rpass_final<R, LEN, true>);                                   \
-  allow((const void*)k_rpass_final<R, LEN, false>);                                  \
+  allow((const void*)k_rpass_final<R, LEN, true, false>);                            \
+  allow((const void*)k_rpass_final<R, LEN, false, false>);                           \
+  allow((const void*)k_rpass_final<R, LEN, true, true>);                             \
+  allow((const void*)k_rpass_final<R, LEN, false, true>);                            \
   allow((const void*)k_rpass_inv_real<R, LEN>);                                      \
   allow((const void*)k_rpass_fwd_real<R, LEN>);                                      \
   allow((const void*)k_rpass_fwd_grad<R, LEN>);
