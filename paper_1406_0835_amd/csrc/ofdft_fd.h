@@ -22,16 +22,59 @@ constexpr double kThreePi2 = 29.6088132032680758565;  // 3 pi^2
 constexpr double kThreePi2_23 = 9.57078000062730605; // (3 pi^2)^(2/3)
 constexpr double kLn3Pi2 = 3.38807206036691003968;     // ln(3 pi^2)
 constexpr double kDensityFloor = 1.0e-12;
+constexpr double kLn3Over4Pi = -1.43241195830118110158;  // ln(3/(4 pi))
 
-// NF Chebyshev series (coefficients c[f * NC + k]) at one x, sharing the T_k recurrence.
-template <int NF>
+// Chebyshev terms used in the FP32 path.  Its t-factors are rounded to FP32,
+// and the coefficients beyond the 14th sum to less than 5e-9 of the factor
+// they belong to (of xi, zeta, P_tau or P_sigma for the t-derivatives) on
+// every piece, below FP32 rounding.
+constexpr int kTermsFp32 = 14;
+
+// ln x for a positive normal double.  Reduction x = 2^e (1 + f) with 1 + f in
+// [sqrt(1/2), sqrt(2)) and s = f/(2 + f), so ln(1 + f) = 2 atanh(s) =
+// f - (f^2/2 - s (f^2/2 + R)) with R = sum_k 2 s^(2k)/(2k + 1); the exact f
+// leads and the series only corrects it (the arrangement of fdlibm's log).
+// |s| <= 0.1716, so nine terms of R leave a truncation below 3e-17 relative;
+// ln 2 is split so that e ln2_hi is exact.  Under 1 ulp against a long-double
+// logarithm, at a third of the instructions of the general double log.
+__device__ __forceinline__ double ln_pos(double x) {
+  int e;
+  double m = frexp(x, &e);
+  if (m < 0.70710678118654752440) {
+    m += m;
+    --e;
+  }
+  const double f = m - 1.0;
+  const double d = 2.0 + f;
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(fma(-d, r, 1.0), r, r);
+  r = fma(fma(-d, r, 1.0), r, r);
+  const double s = f * r, z = s * s;
+  double R = 2.0 / 19.0;
+  R = fma(R, z, 2.0 / 17.0);
+  R = fma(R, z, 2.0 / 15.0);
+  R = fma(R, z, 2.0 / 13.0);
+  R = fma(R, z, 2.0 / 11.0);
+  R = fma(R, z, 2.0 / 9.0);
+  R = fma(R, z, 2.0 / 7.0);
+  R = fma(R, z, 2.0 / 5.0);
+  R = fma(R, z, 2.0 / 3.0);
+  R *= z;
+  const double hfsq = 0.5 * f * f, ed = double(e);
+  constexpr double kLn2Hi = 6.93147180369123816490e-01, kLn2Lo = 1.90821492927058770002e-10;
+  return fma(ed, kLn2Hi, f - (hfsq - fma(s, hfsq + R, ed * kLn2Lo)));
+}
+
+// NF Chebyshev series (coefficients c[f * OFDFT_T_NC + k], first K terms used)
+// at one x, sharing the T_k recurrence.
+template <int NF, int K>
 __device__ __forceinline__ void cheb_series(const double* __restrict__ c, double x, double* s) {
 #pragma unroll
   for (int f = 0; f < NF; ++f) s[f] = fma(c[f * OFDFT_T_NC + 1], x, c[f * OFDFT_T_NC]);
   double t0 = 1.0, t1 = x;
   const double x2 = 2.0 * x;
 #pragma unroll 2
-  for (int k = 2; k < OFDFT_T_NC; ++k) {
+  for (int k = 2; k < K; ++k) {
     const double t2 = fma(x2, t1, -t0);
 #pragma unroll
     for (int f = 0; f < NF; ++f) s[f] = fma(c[f * OFDFT_T_NC + k], t2, s[f]);
@@ -59,8 +102,9 @@ __device__ __forceinline__ int min_pending_cell(int cell, bool pending_lane, uns
 // lane inside the piece takes the result.  Neighbouring points have similar
 // densities, so one pass usually serves the whole wavefront (always, when the
 // spread of l across the wavefront is at most H).
-template <int NF>
+template <int NF, int K = OFDFT_T_NC>
 __device__ __forceinline__ void t_table(const double* __restrict__ table, double l, double* s) {
+  static_assert(K >= 2 && K <= OFDFT_T_NC, "series length");
   l = fmin(fmax(l, OFDFT_T_LLO), OFDFT_T_LHI);
   int cell = (int)((l - OFDFT_T_LLO) * (1.0 / OFDFT_T_H));
   cell = cell < 0 ? 0 : (cell >= OFDFT_T_NP ? OFDFT_T_NP - 1 : cell);
@@ -71,7 +115,7 @@ __device__ __forceinline__ void t_table(const double* __restrict__ table, double
   int pm = min_pending_cell(cell, true, pending);
   double a = OFDFT_T_LLO + pm * OFDFT_T_H;
   double x = (l - a) * (2.0 / OFDFT_T_W) - 1.0;
-  cheb_series<NF>(table + pm * NF * OFDFT_T_NC, x, s);
+  cheb_series<NF, K>(table + pm * NF * OFDFT_T_NC, x, s);
   bool done = x <= 1.0;
   pending = __ballot(!done);
   for (int pass = 1; pending != 0ull && pass < 64; ++pass) {
@@ -79,7 +123,7 @@ __device__ __forceinline__ void t_table(const double* __restrict__ table, double
     a = OFDFT_T_LLO + pm * OFDFT_T_H;
     x = (l - a) * (2.0 / OFDFT_T_W) - 1.0;
     double r[NF];
-    cheb_series<NF>(table + pm * NF * OFDFT_T_NC, x, r);
+    cheb_series<NF, K>(table + pm * NF * OFDFT_T_NC, x, r);
     if (!done && x <= 1.0) {
 #pragma unroll
       for (int f = 0; f < NF; ++f) s[f] = r[f];
@@ -155,9 +199,12 @@ constexpr double kPzDen1 = 1.0 + kPzB1 + kPzB2;
 constexpr double kPzD = kPzGamma / kPzDen1 - kPzB;
 constexpr double kPzC = -kPzGamma * (0.5 * kPzB1 + kPzB2) / (kPzDen1 * kPzDen1) - kPzA - kPzD;
 
+// rs = (3/(4 pi n))^(1/3) and ln rs are formed from ln n, so neither a cube
+// root nor a logarithm is taken here.
 template <typename R>
-__device__ __forceinline__ void pz81(R n, R& eps, R& v) {
-  const R rs = cbrt(R(0.75 / kPi) * rcp<R>(n));
+__device__ __forceinline__ void pz81(double ln_n, R& eps, R& v) {
+  const R lr = R((kLn3Over4Pi - ln_n) * (1.0 / 3.0));
+  const R rs = exp(lr);
   const R rrs = rcp<R>(rs);
   const R ex = R(-0.45816529328314287) * rrs;
   R ec, dec;
@@ -167,7 +214,6 @@ __device__ __forceinline__ void pz81(R n, R& eps, R& v) {
     ec = R(kPzGamma) * rden;
     dec = -R(kPzGamma) * (R(0.5 * kPzB1) * sq * rrs + R(kPzB2)) * (rden * rden);
   } else {
-    const R lr = log(rs);
     ec = R(kPzA) * lr + R(kPzB) + R(kPzC) * rs * lr + R(kPzD) * rs;
     dec = R(kPzA) * rrs + R(kPzC) * (lr + R(1)) + R(kPzD);
   }
@@ -179,8 +225,7 @@ __device__ __forceinline__ void pz81(R n, R& eps, R& v) {
 // ftTF at density n (already floored): f = tau0 kappa, v = T eta (the uniform
 // gas chemical potential, equal to Eq. vTF), T s = tau0 zeta.  T eta is formed
 // as (t eta) T/t with T/t = (3 pi^2 n)^(2/3)/2.
-__device__ __forceinline__ void tf_point(double n, double lt0, double& f, double& v, double& ts) {
-  const double ln_n = log(n);
+__device__ __forceinline__ void tf_point(double n, double ln_n, double lt0, double& f, double& v, double& ts) {
   double s[3];
   t_table<3>(c_t_tf, lt0 - (2.0 / 3.0) * ln_n, s);   // kappa, zeta, t eta
   const double n23 = exp((2.0 / 3.0) * ln_n);
@@ -194,11 +239,10 @@ __device__ __forceinline__ void tf_point(double n, double lt0, double& f, double
 // Outputs f, df/dn at fixed sigma, df/dsigma and T s.  The t-factors are FP64
 // table values; the enhancement-factor assembly runs in R.
 template <typename R>
-__device__ __forceinline__ void gga_point(double n, R sigma, double lt0, const EnhParams& ep, double& f_out,
-                                          R& dfdn, R& dfds, double& ts_out) {
-  const double ln_n = log(n);
+__device__ __forceinline__ void gga_point(double n, double ln_n, R sigma, double lt0, const EnhParams& ep,
+                                          double& f_out, R& dfdn, R& dfds, double& ts_out) {
   double a[8];   // xi, zeta, t xi', t zeta', P_tau, P_sigma, t P_tau', t P_sigma'
-  t_table<8>(c_t_gga, lt0 - (2.0 / 3.0) * ln_n, a);
+  t_table<8, sizeof(R) == 4 ? kTermsFp32 : OFDFT_T_NC>(c_t_gga, lt0 - (2.0 / 3.0) * ln_n, a);
   const R nr = R(n);
   const R n23 = exp(R((2.0 / 3.0) * ln_n));
   const R A = R(kCTF) * nr * n23;

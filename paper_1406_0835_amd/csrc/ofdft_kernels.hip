@@ -523,11 +523,12 @@ __global__ void __launch_bounds__(NT) k_pointwise_gga(const double* __restrict__
     const R sigma = gx * gx + gy * gy + gz * gz;
     double f, tsl;
     R dfdn, dfds;
-    gga_point<R>(nf, sigma, ep.lt0, enh, f, dfdn, dfds, tsl);
+    const double ln_n = ln_pos(nf);
+    gga_point<R>(nf, ln_n, sigma, ep.lt0, enh, f, dfdn, dfds, tsl);
     R vl = dfdn;
     if (ep.xc) {
       R eps, vxc;
-      pz81<R>(R(nf), eps, vxc);
+      pz81<R>(ln_n, eps, vxc);
       vl += vxc;
       exc += n * double(eps);
     }
@@ -754,13 +755,14 @@ __global__ void __launch_bounds__(NT) k_rpass_final(const cplx<R>* __restrict__ 
     if constexpr (TF) {
       const double nf = n > kDensityFloor ? n : kDensityFloor;
       double f, vt, tsl;
-      tf_point(nf, ep.lt0, f, vt, tsl);
+      const double ln_n = ln_pos(nf);
+      tf_point(nf, ln_n, ep.lt0, f, vt, tsl);
       vl = vt;
       fs += f;
       ts += tsl;
       if (ep.xc) {
         R eps, vxc;
-        pz81<R>(R(nf), eps, vxc);
+        pz81<R>(ln_n, eps, vxc);
         vl += double(vxc);
         exc += n * double(eps);
       }

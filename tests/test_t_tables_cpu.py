@@ -1,0 +1,127 @@
+"""The device t-factor tables (Chebyshev pieces in l = ln t, Sec. III A/B)
+against the oracle's Fermi-Dirac factors at sampled temperatures.
+
+The tables are data of the HIP path, generated once by
+paper_1406_0835_amd/csrc/gen_t_tables.py; here they are read from the
+generated header and summed with numpy, both with every coefficient (the FP64
+path) and with the shorter series the FP32 path uses.  Errors are taken
+relative to the factor each entry belongs to: xi for t xi', zeta for t zeta',
+P_tau for t P_tau', P_sigma for t P_sigma'."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import fermi_dirac as fdm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_1406_0835_amd", "csrc")
+
+
+def _header():
+    text = open(os.path.join(CSRC, "t_tables.h")).read()
+    d = {k: float(v) for k, v in re.findall(r"#define OFDFT_T_(\w+) \(?(-?[\d.]+)\)?", text)}
+
+    def arr(name):
+        body = text[text.index("{", text.index(name)) + 1:text.index("};", text.index(name))]
+        return np.array([float(x) for x in body.replace("\n", " ").split(",") if x.strip()])
+
+    nc, npc = int(d["NC"]), int(d["NP"])
+    return d, arr("kTGga").reshape(npc, 8, nc), arr("kTTf").reshape(npc, 3, nc)
+
+
+def _terms_fp32():
+    text = open(os.path.join(CSRC, "ofdft_fd.h")).read()
+    return int(re.search(r"constexpr int kTermsFp32 = (\d+);", text).group(1))
+
+
+def _cheb(c, x, k):
+    """Sum of the first k Chebyshev terms of each row of c at x."""
+    t0, t1 = np.ones_like(x), x
+    s = c[:, 0:1] * t0 + c[:, 1:2] * t1
+    for j in range(2, k):
+        t0, t1 = t1, 2.0 * x * t1 - t0
+        s = s + c[:, j:j + 1] * t1
+    return s
+
+
+def _oracle_factors(l):
+    t = np.exp(l)
+    f = fdm.t_factors(t)
+    xi, dxi, zeta, dzeta = f["xi"], f["dxi"], f["zeta"], f["dzeta"]
+    h, dh, d2h = f["h"], f["dh"], f["d2h"]
+    p_tau = (h - t * dh) / xi
+    p_sig = t * dh / zeta
+    dp_tau = (-t * d2h * xi - (h - t * dh) * dxi) / (xi * xi)
+    dp_sig = ((dh + t * d2h) * zeta - t * dh * dzeta) / (zeta * zeta)
+    gga = np.array([xi, zeta, t * dxi, t * dzeta, p_tau, p_sig, t * dp_tau, t * dp_sig])
+    tf = np.array([f["kappa"], zeta, t * f["eta"]])
+    return gga, tf
+
+
+@pytest.fixture(scope="module")
+def tables():
+    return _header()
+
+
+def _pieces(d, l):
+    """Lowest and highest piece whose span [LLO + j H, LLO + j H + W] holds l."""
+    lo = np.clip(np.ceil((l - d["LLO"] - d["W"]) / d["H"]).astype(int), 0, int(d["NP"]) - 1)
+    hi = np.clip(np.floor((l - d["LLO"]) / d["H"]).astype(int), 0, int(d["NP"]) - 1)
+    return lo, hi
+
+
+def _eval(d, table, l, piece, k):
+    a = d["LLO"] + piece * d["H"]
+    x = (l - a) * (2.0 / d["W"]) - 1.0
+    assert np.all(np.abs(x) <= 1.0 + 1e-12)
+    out = np.empty((table.shape[1], l.size))
+    for i in range(l.size):
+        out[:, i] = _cheb(table[piece[i]], np.array([x[i]]), k)[:, 0]
+    return out
+
+
+# l = ln t over the warm-dense-matter range, t from 0.05 to 400.  Outside it the
+# oracle's FP64 formulas cancel (zeta = xi - kappa ~ t^2 as t -> 0, t h~' -> 0 in
+# both limits) and lose digits the tables keep, so the comparison stops there;
+# the FP32 truncation is checked against the full series over the whole table.
+L_SAMPLES = np.sort(np.random.default_rng(1406).uniform(-3.0, 6.0, 120))
+L_WIDE = np.sort(np.random.default_rng(1407).uniform(-16.0, 24.0, 400))
+PARENT = [0, 1, 0, 1, 4, 5, 4, 5]
+
+
+def test_full_series_matches_oracle(tables):
+    d, gga, tf = tables
+    ref_g, ref_t = _oracle_factors(L_SAMPLES)
+    for piece in _pieces(d, L_SAMPLES):
+        got = _eval(d, gga, L_SAMPLES, piece, gga.shape[2])
+        err = np.abs(got - ref_g) / np.abs(ref_g[PARENT])
+        assert err.max() < 1e-10, err.max(axis=1)
+        got = _eval(d, tf, L_SAMPLES, piece, tf.shape[2])
+        err = np.abs(got - ref_t) / np.abs(ref_t)
+        assert err.max() < 1e-10, err.max(axis=1)
+
+
+def test_fp32_series_below_fp32_rounding(tables):
+    """The shorter series of the FP32 path stays well below FP32 rounding (6e-8)."""
+    d, gga, _ = tables
+    k = _terms_fp32()
+    assert 2 <= k <= gga.shape[2]
+    for piece in _pieces(d, L_WIDE):
+        full = _eval(d, gga, L_WIDE, piece, gga.shape[2])
+        got = _eval(d, gga, L_WIDE, piece, k)
+        err = np.abs(got - full) / np.abs(full[PARENT])
+        assert err.max() < 1e-8, err.max(axis=1)
+    # the dropped tail on every piece, which bounds the truncation anywhere in the piece
+    tail = np.abs(gga[:, :, k:]).sum(axis=2)
+    scale = np.abs(gga[:, PARENT, 0])
+    assert (tail / scale).max() < 1e-8
+
+
+def test_tables_cover_the_documented_range(tables):
+    d, gga, tf = tables
+    assert d["W"] == 2 * d["H"]
+    last = d["LLO"] + (d["NP"] - 1) * d["H"]      # the clamped l = LHI lands in the last piece
+    assert last <= d["LHI"] <= last + d["W"]
+    assert np.all(np.isfinite(gga)) and np.all(np.isfinite(tf))
