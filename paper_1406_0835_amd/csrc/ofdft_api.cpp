@@ -60,10 +60,8 @@ struct Point {
 };
 
 int eval_at(ofdft_ctx* c, const double* phi, void* v, double* sc, Point& p) {
-  int rc = dev_eval(c, phi, v, sc);
-  if (rc) return rc;
   double h[SC_COUNT];
-  rc = dev_read(c, sc, SC_COUNT, h);
+  int rc = dev_eval(c, phi, v, sc, h);
   if (rc) return rc;
   p.F = h[SC_FTOT];
   p.Ne = h[SC_NE];
@@ -71,25 +69,29 @@ int eval_at(ofdft_ctx* c, const double* phi, void* v, double* sc, Point& p) {
   return OFDFT_OK;
 }
 
-void fill_report(ofdft_ctx* c, const double* h, double resid, ofdft_report* rep, int iters, int evals, int conv) {
+// The report of the state in h (device scalars): E_ion, which the device sums
+// leave out, is added here once the host Ewald thread has finished.
+int fill_report(ofdft_ctx* c, const double* h, double resid, ofdft_report* rep, int iters, int evals, int conv) {
+  if (!join_ewald(c)) return fail(c, OFDFT_E_ARG, "Ewald sum failed");
   ofdft_report r{};
   r.iterations = iters;
   r.evaluations = evals;
   r.converged = conv;
-  r.F_total = h[SC_FTOT];
+  r.F_total = h[SC_FTOT] + c->E_ion;
   r.F_s = h[SC_FS];
   r.TS_s = h[SC_TS];
-  r.E_internal = h[SC_FTOT] + h[SC_TS];
+  r.E_internal = r.F_total + h[SC_TS];
   r.E_xc = h[SC_EXC];
   r.E_H = h[SC_EH];
   r.E_ext = h[SC_EEXT];
   r.E_alphaZ = h[SC_EAZ];
-  r.E_ion = h[SC_EION];
+  r.E_ion = c->E_ion;
   r.N_e = h[SC_NE];
   r.mu = h[SC_MU];
   r.residual = resid;
   c->last = r;
   if (rep) *rep = r;
+  return OFDFT_OK;
 }
 
 // Line search along the rotation phi(theta) = ca phi + sb d (ca, sb from theta).
@@ -116,12 +118,11 @@ int line_search(ofdft_ctx* c, double F0, double dF0, double r, double phinorm, d
   for (int trial = 0; trial < max_trials; ++trial) {
     const double ct = std::cos(theta), st = std::sin(theta);
     // phi_t = rotation of phi toward d, its evaluation and dF/dtheta in one pass sequence
+    double h[SC_COUNT];
     int rc = dev_eval_trial(c, c->phi, c->d, ct * ratio, st * r / dn, c->phi_t, c->v_t, c->scalars_t,
-                            -st * ratio, ct * r / dn);
+                            -st * ratio, ct * r / dn, h);
     if (rc) return rc;
     ++nevals;
-    double h[SC_COUNT];
-    if ((rc = dev_read(c, c->scalars_t, SC_COUNT, h))) return rc;
     const double dth = h[SC_DOT0];
     const double Ft = h[SC_FTOT];
     if (!is_fin(Ft) || !is_fin(dth)) return fail(c, OFDFT_E_NONFINITE, "non-finite energy in line search");
@@ -205,8 +206,9 @@ bool stop_rule(const ofdft_ctx* c, int small, double resid) {
 // last steps were already below the energy tolerance; in the mixed path (FP32
 // terms summed in FP64) also once the last decrease is below 1e-6 |F| (its
 // stated accuracy).
-bool stalled_converged(const ofdft_ctx* c, int small, double last_dF, double F, double resid) {
-  const bool noise_floor = c->rsize == 4 && std::fabs(last_dF) < 1e-6 * std::fabs(F);
+bool stalled_converged(ofdft_ctx* c, int small, double last_dF, double F, double resid) {
+  // F is the electronic part; the stated accuracy refers to the total, E_ion included
+  const bool noise_floor = c->rsize == 4 && join_ewald(c) && std::fabs(last_dF) < 1e-6 * std::fabs(F + c->E_ion);
   if (c->opt.tol_residual > 0.0) return resid < c->opt.tol_residual || noise_floor;
   return small >= 1 || noise_floor;
 }
@@ -239,11 +241,10 @@ int minimize_cg(ofdft_ctx* c, ofdft_report* rep) {
   bool converged = false;
   double resid = 0.0;
   for (it = 1; it <= c->opt.max_iter; ++it) {
+    // gradient dots, beta and the new direction on the device, then one readback
+    const double cproj = have_prev ? std::sin(theta_prev) * dn_prev / r : 0.0;
+    if ((rc = dev_cg_step(c, pcg, have_prev, gg_prev, cproj))) return rc;
     double hs[SC_COUNT];
-    if (pcg) rc = dev_precond_dots(c, c->phi, c->v, c->scalars, have_prev ? c->gprev : nullptr, c->scalars + SC_DOT0);
-    else rc = dev_grad_dots(c, c->phi, c->v, c->scalars, have_prev ? c->gprev : nullptr, have_prev ? c->d : nullptr,
-                            c->scalars + SC_DOT0);
-    if (rc) return rc;
     if ((rc = dev_read(c, c->scalars, SC_COUNT, hs))) return rc;
     const double* dots = hs + SC_DOT0;
     p.F = hs[SC_FTOT];
@@ -252,20 +253,10 @@ int minimize_cg(ofdft_ctx* c, ofdft_report* rep) {
     resid = std::sqrt(dots[3] / phinorm2);
     const double gg = dots[0];   // g.g, or z.g when preconditioned
     if (gg <= 0.0 || stop_rule(c, small, resid)) { converged = true; break; }
-    double beta = 0.0, cproj = 0.0, cz = 0.0;
-    if (pcg) cz = dots[2] / phinorm2;
-    if (have_prev) {
-      const double cross = pcg ? dots[1] - cz * dots[4] : dots[1];
-      beta = std::max(0.0, (gg - cross) / gg_prev);
-      // d_old . phi_new = sin(theta) |phi| |d_old| (d_old is tangent at phi_old)
-      cproj = std::sin(theta_prev) * dn_prev / r;
-    }
-    if ((rc = pcg ? dev_pcg_direction(c, beta, cproj, cz) : dev_cg_direction(c, beta, cproj))) return rc;
-    double dd_dg[2];
-    if ((rc = dev_read(c, c->vout, 2, dd_dg))) return rc;
+    double dd_dg[2] = {hs[SC_DD], hs[SC_DG]};
     if (dd_dg[1] >= 0.0) {   // not a descent direction: restart along -g (or -z)
-      if ((rc = pcg ? dev_pcg_direction(c, 0.0, 0.0, cz) : dev_cg_direction(c, 0.0, 0.0))) return rc;
-      if ((rc = dev_read(c, c->vout, 2, dd_dg))) return rc;
+      if ((rc = dev_cg_restart(c, pcg))) return rc;
+      if ((rc = dev_read(c, c->scalars + SC_DD, 2, dd_dg))) return rc;
     }
     const double dn = std::sqrt(dd_dg[0]);
     const double dF0 = r * dd_dg[1] / dn;
@@ -291,7 +282,7 @@ int minimize_cg(ofdft_ctx* c, ofdft_report* rep) {
   }
   double h[SC_COUNT];
   if ((rc = dev_read(c, c->scalars, SC_COUNT, h))) return rc;
-  fill_report(c, h, resid, rep, std::min(it, c->opt.max_iter), nevals, converged ? 1 : 0);
+  if ((rc = fill_report(c, h, resid, rep, std::min(it, c->opt.max_iter), nevals, converged ? 1 : 0))) return rc;
   c->converged = converged;
   return converged ? OFDFT_OK : fail(c, OFDFT_E_NOT_CONVERGED, "minimisation did not converge");
 }
@@ -410,7 +401,7 @@ int minimize_tn(ofdft_ctx* c, ofdft_report* rep) {
   }
   double h[SC_COUNT];
   if ((rc = dev_read(c, c->scalars, SC_COUNT, h))) return rc;
-  fill_report(c, h, resid, rep, std::min(it, c->opt.max_iter), nevals, converged ? 1 : 0);
+  if ((rc = fill_report(c, h, resid, rep, std::min(it, c->opt.max_iter), nevals, converged ? 1 : 0))) return rc;
   c->converged = converged;
   return converged ? OFDFT_OK : fail(c, OFDFT_E_NOT_CONVERGED, "minimisation did not converge");
 }
@@ -481,6 +472,7 @@ int ofdft_create(const ofdft_options* opt, ofdft_ctx** out) {
 
 int ofdft_destroy(ofdft_ctx* c) {
   if (!c) return fail(nullptr, OFDFT_E_ARG, "null context");
+  join_ewald(c);
   (void)hipSetDevice(c->opt.device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   dev_free_grid(c);
@@ -488,7 +480,7 @@ int ofdft_destroy(ofdft_ctx* c) {
   if (c->dZ) (void)hipFree(c->dZ);
   if (c->fpart) (void)hipFree(c->fpart);
   if (c->dforces) (void)hipFree(c->dforces);
-  if (c->hbuf) (void)hipHostFree(c->hbuf);
+  if (c->hmap) (void)hipHostFree(c->hmap);
   for (hipEvent_t e : c->timing.events) (void)hipEventDestroy(e);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
@@ -539,6 +531,7 @@ int ofdft_set_cell(ofdft_ctx* c, const double lattice[9], double cell_scale, con
   g.tc = largest_pow2_divisor_upto(g.n2, tc_cap);
   g.rb = 1;
   while (2 * g.rb * g.n2 <= 1024) g.rb *= 2;   // largest power of two with rb * n2 <= 1024
+  join_ewald(c);
   std::memcpy(c->lat, lat, sizeof(lat));
   c->cell_scale = cell_scale;
   c->g = g;
@@ -562,6 +555,7 @@ int ofdft_set_ions(ofdft_ctx* c, int nat, const double* tau, const double* Z) {
       if (!is_fin(tau[3 * i + a])) return fail(c, OFDFT_E_ARG, "non-finite ion position");
   }
   if (hipSetDevice(c->opt.device) != hipSuccess) return fail(c, OFDFT_E_DEVICE, "hipSetDevice");
+  join_ewald(c);
   // positions are given in the frame of the unscaled lattice (cellScale, Sec. V B)
   const double Ne_old = c->Ne;
   c->nat = nat;
@@ -575,7 +569,7 @@ int ofdft_set_ions(ofdft_ctx* c, int nat, const double* tau, const double* Z) {
   }
   c->Ne = Ne;
   c->alpha_sum = asum;
-  ewald_sum(c->lat, nat, c->tau.data(), c->Z.data(), c->E_ion, c->F_ion);
+  start_ewald(c);
   int rc = dev_structure_factor(c);
   if (rc) return fail(c, rc, c->err.empty() ? "structure factor failed" : c->err);
   if (c->have_phi && Ne_old > 0.0 && Ne_old != Ne) {
@@ -614,6 +608,7 @@ int ofdft_free_energy_and_forces(ofdft_ctx* c, double* F_total, double* E_intern
   if (forces) {
     int rc = dev_forces(c, forces);
     if (rc) return fail(c, rc, c->err);
+    if (!join_ewald(c)) return fail(c, OFDFT_E_ARG, "Ewald sum failed");
     for (int k = 0; k < 3 * c->nat; ++k) {
       forces[k] += c->F_ion[k];
       if (!is_fin(forces[k])) return fail(c, OFDFT_E_NONFINITE, "non-finite force");
@@ -664,7 +659,7 @@ int ofdft_eval(ofdft_ctx* c, ofdft_report* rep, double* potential_out) {
   double h[SC_COUNT];
   if ((rc = dev_grad_dots(c, c->phi, c->v, c->scalars, nullptr, nullptr, c->scalars + SC_DOT0))) return rc;
   if ((rc = dev_read(c, c->scalars, SC_COUNT, h))) return rc;
-  fill_report(c, h, std::sqrt(h[SC_DOT0 + 3] / (p.Ne / c->g.dv)), rep, 0, 1, 0);
+  if ((rc = fill_report(c, h, std::sqrt(h[SC_DOT0 + 3] / (p.Ne / c->g.dv)), rep, 0, 1, 0))) return rc;
   if (potential_out) {
     if (c->rsize == 8) {
       if (hipMemcpy(potential_out, c->v, c->g.N * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)

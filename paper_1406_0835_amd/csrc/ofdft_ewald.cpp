@@ -28,11 +28,12 @@ struct Partial {
   std::vector<double> F;
 };
 
-// Threads for `items` independent work items, at least `per_thread` items each.
+// Threads for `items` independent work items, at least `per_thread` items each;
+// one hardware thread is left to the caller that keeps the device busy meanwhile.
 int thread_count(size_t items, size_t per_thread) {
-  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+  const unsigned hw = std::max(2u, std::thread::hardware_concurrency());
   const size_t by_work = std::max<size_t>(1, items / per_thread);
-  return (int)std::min<size_t>({(size_t)std::min(hw, 16u), by_work});
+  return (int)std::min<size_t>({(size_t)std::min(hw - 1, 16u), by_work});
 }
 
 template <class Fn>
@@ -230,6 +231,27 @@ void ewald_sum(const double lat[9], int nat, const double* pos, const double* Z,
   const double Es = -split / std::sqrt(kPi) * Q2;
   const double Eb = -kPi * Q * Q / (2.0 * V * split * split);
   E = Er + Eg + Es + Eb;
+}
+
+void start_ewald(ofdft_ctx* c) {
+  join_ewald(c);
+  c->ewald_failed = false;
+  c->ewald_pending = true;
+  c->ewald_thread = std::thread([c] {
+    try {
+      ewald_sum(c->lat, c->nat, c->tau.data(), c->Z.data(), c->E_ion, c->F_ion);
+    } catch (...) {
+      c->ewald_failed = true;
+    }
+  });
+}
+
+bool join_ewald(ofdft_ctx* c) {
+  if (c->ewald_pending) {
+    c->ewald_thread.join();
+    c->ewald_pending = false;
+  }
+  return !c->ewald_failed;
 }
 
 }  // namespace ofdft

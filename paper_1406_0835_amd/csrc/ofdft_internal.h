@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/ofdft.h"
@@ -13,11 +14,18 @@ namespace ofdft {
 // SL_DT1, SL_DT2: sums phi_t v_t q and phi_t q of a line-search trial (q = ms phi + mc d),
 // from which the reduction forms dF/dtheta once mu is known.
 enum Slot { SL_PHI2 = 0, SL_FS, SL_TS, SL_EXC, SL_EH, SL_EEXT, SL_NV, SL_DT1, SL_DT2, SL_COUNT };
-// Reduced scalars of one evaluation (double[16] on the device).
+// Reduced scalars of one evaluation (double[SC_COUNT] on the device).  On the device
+// SC_FTOT is the electronic part of F (E_ion, a constant of the minimisation, is
+// added on the host) and SC_EION is 0.
+constexpr int kMapDoubles = 32;
 enum Scal {
   SC_NE = 0, SC_FS, SC_TS, SC_EXC, SC_EH, SC_EEXT, SC_NV, SC_MU, SC_EAZ, SC_EION, SC_FTOT,
   SC_DOT0 = 11,   // slots 11..15: minimiser dot products written after an evaluation
-  SC_COUNT = 16
+  SC_BETA = 16,   // CG coefficients formed on the device from those dots: beta, c_z
+  SC_CZ = 17,
+  SC_DD = 18,     // d.d and d.g of the new CG direction
+  SC_DG = 19,
+  SC_COUNT = 20
 };
 
 // Largest tiles the kernels stage through registers: a contiguous-axis tile
@@ -51,7 +59,6 @@ struct EvalParams {
   double T;           // hartree
   double lt0;         // ln t = lt0 - (2/3) ln n
   double alpha_sum;   // sum_I alpha_I (G = 0 remainder of the pseudopotential)
-  double E_ion;
   double enh_kind, enh_c1, enh_a1;   // enhancement-factor parameters (kind as double)
 };
 
@@ -82,6 +89,10 @@ struct ofdft_ctx {
   std::vector<double> tau, Z;
   double Ne = 0.0, alpha_sum = 0.0, E_ion = 0.0;
   std::vector<double> F_ion;
+  // E_ion and F_ion come from a host thread started by set_ions; every reader
+  // (and every writer of lat, nat, tau, Z) joins it first (ofdft::join_ewald)
+  std::thread ewald_thread;
+  bool ewald_pending = false, ewald_failed = false;
 
   // device buffers (R = float or double by precision)
   size_t rsize = 8;
@@ -107,7 +118,11 @@ struct ofdft_ctx {
   double* tn[4] = {nullptr, nullptr, nullptr, nullptr};
   double* vpart = nullptr;     // vector-reduction partials
   double* vout = nullptr;      // vector-reduction results
-  double* hbuf = nullptr;      // pinned host mirror for small readbacks
+  // Fine-grained pinned host memory the device writes small results into:
+  // doubles [0, kMapDoubles) of data, then a 64-bit sequence word the host waits on.
+  double* hmap = nullptr;
+  double* dmap = nullptr;      // the same memory as seen by kernels
+  unsigned long long read_seq = 0;
   // ions on the device
   double* phase = nullptr;     // [nat][n1 + n2 + n3h] complex doubles
   double* dZ = nullptr;
@@ -124,6 +139,10 @@ namespace ofdft {
 // Ewald energy and forces of the ions (ofdft_ewald.cpp, host FP64): lat rows a1..a3 (bohr),
 // Cartesian pos[3 nat], charges Z[nat]; F receives 3 nat forces (hartree/bohr).
 void ewald_sum(const double lat[9], int nat, const double* pos, const double* Z, double& E, std::vector<double>& F);
+// Start ewald_sum for the context's current ions on a host thread / wait for it
+// (false if it failed).
+void start_ewald(ofdft_ctx* c);
+bool join_ewald(ofdft_ctx* c);
 
 // kernels (ofdft_kernels.hip)
 int dev_upload_tables(int device);
@@ -131,24 +150,30 @@ int dev_alloc_grid(ofdft_ctx* c);
 void dev_free_grid(ofdft_ctx* c);
 int dev_alloc_ions(ofdft_ctx* c);
 int dev_structure_factor(ofdft_ctx* c);
-int dev_eval(ofdft_ctx* c, const double* phi, void* v_out, double* scalars_out);
+// With host != NULL the reduced scalars are also delivered to host[SC_COUNT] (through
+// c->hmap, written by the reduction kernel) before the call returns.
+int dev_eval(ofdft_ctx* c, const double* phi, void* v_out, double* scalars_out, double* host = nullptr);
 // One line-search trial as a single evaluation: phi_out = ca phi + sb dir is formed inside
 // the density pass, and dF/dtheta = g_t . (ms phi + mc dir) lands in scalars_out[SC_DOT0].
 int dev_eval_trial(ofdft_ctx* c, const double* phi, const double* dir, double ca, double sb, double* phi_out,
-                   void* v_out, double* scalars_out, double ms, double mc);
+                   void* v_out, double* scalars_out, double ms, double mc, double* host = nullptr);
 int dev_forces(ofdft_ctx* c, double* forces_host);
 // vector operations for the minimisers; results land in c->vout (device)
 // g = 2 dv phi (v - mu): writes g.g, g.gprev, g.d, sum n (v-mu)^2 into out[0..3]
 int dev_grad_dots(ofdft_ctx* c, const double* phi, const void* v, const double* sc, const double* gprev,
                   const double* d, double* out);
 int dev_cg_direction(ofdft_ctx* c, double beta, double cproj);
-// Preconditioned variant: z = P g (P the reciprocal-space filter with g.prec_k2), formed as
-// g + w with w = (P - 1) g in c->gr[0];
-// out[0..4] = z.g, z.gprev, z.phi, sum n (v-mu)^2, phi.gprev
-int dev_precond_dots(ofdft_ctx* c, const double* phi, const void* v, const double* sc, const double* gprev,
-                     double* out);
-// d = -(z - cz phi) + beta (d - cproj phi); gprev = g; out: d.d, d.g
-int dev_pcg_direction(ofdft_ctx* c, double beta, double cproj, double cz);
+// One CG step's device part, leaving everything the host needs in c->scalars.
+// Dots into SC_DOT0..: plain, g.g, g.gprev, g.d, sum n (v-mu)^2; preconditioned
+// (pcg), z.g, z.gprev, z.phi, sum n (v-mu)^2, phi.gprev with z = P g, P the
+// reciprocal-space filter with g.prec_k2, formed as g + w, w = (P - 1) g in
+// c->gr[0].  Then c_z = z.phi / phi.phi and beta = max(0, (z.g - (z.gprev -
+// c_z phi.gprev)) / gg_prev) (0 without have_prev; plain: c_z = 0) into
+// SC_CZ/SC_BETA, and the new direction d = -(z - c_z phi) + beta (d - cproj phi)
+// (gprev = g) with d.d, d.g into SC_DD/SC_DG.
+int dev_cg_step(ofdft_ctx* c, bool pcg, bool have_prev, double gg_prev, double cproj);
+// The same direction with beta = 0 (after a step that was not a descent direction).
+int dev_cg_restart(ofdft_ctx* c, bool pcg);
 int dev_rotate(ofdft_ctx* c, double* dst, const double* phi, double ca, const double* dir, double sb);
 // dF/dtheta at the trial point, written to out[0]
 int dev_dtheta(ofdft_ctx* c, const double* phi_t, const void* v_t, const double* sc_t, const double* phi,
@@ -158,6 +183,8 @@ int dev_dot(ofdft_ctx* c, const double* a, const double* b);
 int dev_axpby(ofdft_ctx* c, double* y, double a, const double* x, double b);
 int dev_tn_hess_finish(ofdft_ctx* c, double* hs, const double* phi, const double* s, double inv2e,
                        double mu_term);
+// n <= kMapDoubles doubles from device memory to the host (a one-wavefront kernel
+// writes them into c->hmap and raises its sequence word; no stream synchronisation).
 int dev_read(ofdft_ctx* c, const double* dptr, int n, double* host);
 int dev_sync(ofdft_ctx* c);
 // largest dynamic LDS (bytes) any evaluation kernel needs with the tiles in c->g

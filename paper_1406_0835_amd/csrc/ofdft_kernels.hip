@@ -804,14 +804,32 @@ struct ReduceParams {
   int nb_r, nb_x1;   // partial counts of the row-pass and x1-pass kernels
   int nb_fs;         // partial count of the free-energy slots (pointwise kernel or row pass)
   int trial;         // 1: also dF/dtheta of a line-search trial into SC_DOT0
-  double dv, volume, alpha_sum, E_ion;
+  double dv, volume, alpha_sum;
 };
 
 constexpr int RED_NT = 64 * SL_COUNT;   // one wavefront per slot
 
+// Destination of a device-written readback: dst[0..n) and then the sequence
+// word flag = seq, both in fine-grained host memory (dst == nullptr: none).
+struct Publish {
+  double* dst;
+  unsigned long long* flag;
+  unsigned long long seq;
+};
+
+// Store vals[0..n) into the host buffer and raise its sequence word.  Called by
+// lanes of one wavefront only; the system-scope release on the flag orders it
+// after the wavefront's data stores.
+__device__ __forceinline__ void publish(const Publish& pub, const double* vals, int n, int lane) {
+  for (int k = lane; k < n; k += 64) pub.dst[k] = vals[k];
+  __threadfence_system();
+  if (lane == 0) __hip_atomic_store(pub.flag, pub.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 __global__ void __launch_bounds__(RED_NT) k_reduce_scalars(const double* __restrict__ partials, int maxb,
-                                                           ReduceParams rp, double* __restrict__ sc) {
+                                                           ReduceParams rp, double* __restrict__ sc, Publish pub) {
   __shared__ double raw[SL_COUNT];
+  __shared__ double out[SC_COUNT];
   const int s = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int cnt = (s == SL_EH || s == SL_EEXT) ? rp.nb_x1
                   : (s == SL_FS || s == SL_TS || s == SL_EXC) ? rp.nb_fs
@@ -831,20 +849,31 @@ __global__ void __launch_bounds__(RED_NT) k_reduce_scalars(const double* __restr
   __syncthreads();
   if (threadIdx.x == 0) {
     const double Ne = rp.dv * raw[SL_PHI2];
-    sc[SC_NE] = Ne;
-    sc[SC_FS] = rp.dv * raw[SL_FS];
-    sc[SC_TS] = rp.dv * raw[SL_TS];
-    sc[SC_EXC] = rp.dv * raw[SL_EXC];
-    sc[SC_EH] = 0.5 * rp.volume * raw[SL_EH];
-    sc[SC_EEXT] = rp.volume * raw[SL_EEXT];
-    sc[SC_NV] = rp.dv * raw[SL_NV];
-    sc[SC_MU] = raw[SL_NV] / raw[SL_PHI2];
-    sc[SC_EAZ] = Ne * rp.alpha_sum;
-    sc[SC_EION] = rp.E_ion;
-    sc[SC_FTOT] = sc[SC_FS] + sc[SC_EXC] + sc[SC_EH] + sc[SC_EEXT] + sc[SC_EAZ] + rp.E_ion;
-    for (int k = SC_FTOT + 1; k < SC_COUNT; ++k) sc[k] = 0.0;   // dot slots cleared
-    if (rp.trial) sc[SC_DOT0] = 2.0 * rp.dv * (raw[SL_DT1] - sc[SC_MU] * raw[SL_DT2]);
+    out[SC_NE] = Ne;
+    out[SC_FS] = rp.dv * raw[SL_FS];
+    out[SC_TS] = rp.dv * raw[SL_TS];
+    out[SC_EXC] = rp.dv * raw[SL_EXC];
+    out[SC_EH] = 0.5 * rp.volume * raw[SL_EH];
+    out[SC_EEXT] = rp.volume * raw[SL_EEXT];
+    out[SC_NV] = rp.dv * raw[SL_NV];
+    out[SC_MU] = raw[SL_NV] / raw[SL_PHI2];
+    out[SC_EAZ] = Ne * rp.alpha_sum;
+    out[SC_EION] = 0.0;
+    out[SC_FTOT] = out[SC_FS] + out[SC_EXC] + out[SC_EH] + out[SC_EEXT] + out[SC_EAZ];
+    for (int k = SC_FTOT + 1; k < SC_COUNT; ++k) out[k] = 0.0;   // dot slots cleared
+    if (rp.trial) out[SC_DOT0] = 2.0 * rp.dv * (raw[SL_DT1] - out[SC_MU] * raw[SL_DT2]);
   }
+  __syncthreads();
+  if (threadIdx.x < SC_COUNT) sc[threadIdx.x] = out[threadIdx.x];
+  if (pub.dst && threadIdx.x < 64) publish(pub, out, SC_COUNT, threadIdx.x);
+}
+
+// Generic small readback (dev_read): one wavefront.
+__global__ void __launch_bounds__(64) k_publish(const double* __restrict__ src, int n, Publish pub) {
+  __shared__ double v[kMapDoubles];
+  if ((int)threadIdx.x < n) v[threadIdx.x] = src[threadIdx.x];
+  __syncthreads();
+  publish(pub, v, n, threadIdx.x);
 }
 
 // ---------------------------------------------------------------- vector reductions
@@ -875,6 +904,39 @@ __global__ void __launch_bounds__(NT) k_vec_final(const double* __restrict__ par
     double v[1] = {a};
     block_sum<1>(v, red);
     if (threadIdx.x == 0) out[k] = v[0];
+  }
+}
+
+// The gradient dots of a CG step reduced into sc[SC_DOT0..], then the step's
+// coefficients: c_z = z.phi / phi.phi (preconditioned) and
+// beta = max(0, (z.g - (z.g_old - c_z phi.g_old)) / gg_prev) (Polak-Ribiere+).
+struct CgCoef {
+  int pcg, have_prev;
+  double gg_prev, dv;
+};
+
+template <int K>
+__global__ void __launch_bounds__(NT) k_cg_dots_final(const double* __restrict__ part, int nb,
+                                                      double* __restrict__ sc, CgCoef cf) {
+  __shared__ double red[NT / 64];
+  double dots[K];
+  for (int k = 0; k < K; ++k) {
+    double a = 0.0;
+    for (int i = threadIdx.x; i < nb; i += NT) a += part[k * nb + i];
+    double v[1] = {a};
+    block_sum<1>(v, red);
+    dots[k] = v[0];
+  }
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < K; ++k) sc[SC_DOT0 + k] = dots[k];
+    const double cz = (cf.pcg && K >= 5) ? dots[2] / (sc[SC_NE] / cf.dv) : 0.0;
+    double beta = 0.0;
+    if (cf.have_prev) {
+      const double cross = (cf.pcg && K >= 5) ? dots[1] - cz * dots[K >= 5 ? 4 : 0] : dots[1];
+      beta = fmax(0.0, (dots[0] - cross) / cf.gg_prev);
+    }
+    sc[SC_BETA] = beta;
+    sc[SC_CZ] = cz;
   }
 }
 
@@ -913,12 +975,14 @@ struct OpPrecDots {
   }
 };
 
-// d = -(z - cz phi) + beta (d - cproj phi), z = g + w; gprev = g; dots d.d and d.g
+// d = -(z - cz phi) + beta (d - cproj phi), z = g + w; gprev = g; dots d.d and d.g.
+// beta and cz are the device values sc[SC_BETA], sc[SC_CZ] (beta = 0 on a restart).
 template <typename R>
 struct OpPrecDirection {
   const double* phi; const R* v; const R* w; const double* sc; double* gprev; double* d;
-  double two_dv, beta, cproj, cz;
+  double two_dv, cproj; int restart;
   __device__ void operator()(long long i, double* acc) const {
+    const double beta = restart ? 0.0 : sc[SC_BETA], cz = sc[SC_CZ];
     const double p = phi[i];
     const double gi = two_dv * p * (double(v[i]) - sc[SC_MU]);
     const double di = -(gi + double(w[i]) - cz * p) + beta * (d[i] - cproj * p);
@@ -929,11 +993,14 @@ struct OpPrecDirection {
   }
 };
 
-// d = -g + beta (d - c phi); gprev = g; dots d.d and d.g
+// d = -g + beta (d - c phi); gprev = g; dots d.d and d.g.  beta from the host, or
+// the device value sc[SC_BETA] when dev_beta is set.
 template <typename R>
 struct OpDirection {
-  const double* phi; const R* v; const double* sc; double* gprev; double* d; double two_dv, beta, cproj;
+  const double* phi; const R* v; const double* sc; double* gprev; double* d; double two_dv, beta_host, cproj;
+  int dev_beta;
   __device__ void operator()(long long i, double* acc) const {
+    const double beta = dev_beta ? sc[SC_BETA] : beta_host;
     const double p = phi[i];
     const double gi = two_dv * p * (double(v[i]) - sc[SC_MU]);
     const double di = -gi + beta * (d[i] - cproj * p);
@@ -1126,6 +1193,11 @@ static inline bool hip_ok(ofdft_ctx* c, hipError_t e, const char* what) {
   if (e == hipSuccess) return true;
   c->err = std::string(what) + ": " + hipGetErrorString(e);
   return false;
+}
+
+static inline int dev_fail(ofdft_ctx* c, int code, const char* what) {
+  c->err = what;
+  return code;
 }
 
 // The t-factor tables live in __constant__ memory, one copy per device: upload
@@ -1332,7 +1404,6 @@ static EvalParams make_params(ofdft_ctx* c) {
   ep.T = c->T_ha;
   ep.lt0 = lt_offset(c->T_ha);
   ep.alpha_sum = c->alpha_sum;
-  ep.E_ion = c->E_ion;
   switch (c->opt.functional) {
     case OFDFT_SGA: ep.enh_kind = 0; ep.enh_c1 = c->opt.mu_sga; break;
     case OFDFT_VWTF: ep.enh_kind = 0; ep.enh_c1 = 5.0 / 3.0; break;
@@ -1349,8 +1420,8 @@ static EvalParams make_params(ofdft_ctx* c) {
 // forms phi_t = rot.ca phi + rot.sb rot.dir into rot.phi_out and the evaluation runs at
 // phi_t, with dF/dtheta accumulated by the final pass.
 template <typename R>
-static int eval_impl(ofdft_ctx* c, const double* phi, void* v_out, double* sc, const Rotation* rot = nullptr,
-                     const Slope* sl = nullptr) {
+static int eval_impl(ofdft_ctx* c, const double* phi, void* v_out, double* sc, const Rotation* rot,
+                     const Slope* sl, const Publish& pub) {
   const GridDesc& g = c->g;
   const EvalParams ep = make_params(c);
   const bool tf = c->opt.functional == OFDFT_TF;
@@ -1388,10 +1459,10 @@ static int eval_impl(ofdft_ctx* c, const double* phi, void* v_out, double* sc, c
     OFDFT_DISPATCH(g.n3, (launch_rpass_final<R, L_, false>(c, phi_e, v_out, ep, sl)));
   }
   const int nb_r = (g.n2 / g.tr) * g.n1;
-  ReduceParams rp{nb_r, (g.n2 / g.tc) * g.n3k, tf ? nb_r : PW_BLOCKS, sl ? 1 : 0, g.dv, g.volume, c->alpha_sum,
-                  c->E_ion};
+  ReduceParams rp{nb_r, (g.n2 / g.tc) * g.n3k, tf ? nb_r : PW_BLOCKS, sl ? 1 : 0, g.dv, g.volume, c->alpha_sum};
   tmark(c, "reduce_scalars");
-  hipLaunchKernelGGL(k_reduce_scalars, dim3(1), dim3(RED_NT), 0, c->stream, c->partials, c->max_blocks, rp, sc);
+  hipLaunchKernelGGL(k_reduce_scalars, dim3(1), dim3(RED_NT), 0, c->stream, c->partials, c->max_blocks, rp, sc,
+                     pub);
   tmark(c, "end");
   hipError_t e = hipGetLastError();
   return hip_ok(c, e, "eval launch") ? OFDFT_OK : OFDFT_E_DEVICE;
@@ -1429,16 +1500,52 @@ size_t dev_max_lds(const ofdft_ctx* c) {
   return c->rsize == 4 ? max_lds_impl<float>(c) : max_lds_impl<double>(c);
 }
 
-int dev_eval(ofdft_ctx* c, const double* phi, void* v_out, double* sc) {
-  return c->rsize == 4 ? eval_impl<float>(c, phi, v_out, sc) : eval_impl<double>(c, phi, v_out, sc);
+// Next readback slot of c->hmap.
+static Publish next_publish(ofdft_ctx* c) {
+  return Publish{c->dmap, reinterpret_cast<unsigned long long*>(c->dmap + kMapDoubles), ++c->read_seq};
+}
+
+// Wait until the device has raised the sequence word to seq, then copy n doubles
+// out.  While waiting, the stream is polled now and then so that a failed launch
+// or a drained stream without the word ends the wait with an error.
+static int wait_published(ofdft_ctx* c, unsigned long long seq, int n, double* host) {
+  const volatile unsigned long long* flag = reinterpret_cast<unsigned long long*>(c->hmap + kMapDoubles);
+  for (unsigned spin = 1;; ++spin) {
+    if (__atomic_load_n(flag, __ATOMIC_ACQUIRE) == seq) break;
+    if ((spin & 255u) == 0) {
+      const hipError_t e = hipStreamQuery(c->stream);
+      if (e == hipSuccess) {
+        if (__atomic_load_n(flag, __ATOMIC_ACQUIRE) == seq) break;
+        return dev_fail(c, OFDFT_E_DEVICE, "readback: the stream drained without raising the sequence word");
+      }
+      if (e != hipErrorNotReady) {
+        hip_ok(c, e, "readback");
+        return OFDFT_E_DEVICE;
+      }
+    }
+    __builtin_ia32_pause();
+  }
+  for (int k = 0; k < n; ++k) host[k] = c->hmap[k];
+  return OFDFT_OK;
+}
+
+int dev_eval(ofdft_ctx* c, const double* phi, void* v_out, double* sc, double* host) {
+  const Publish pub = host ? next_publish(c) : Publish{nullptr, nullptr, 0};
+  int rc = c->rsize == 4 ? eval_impl<float>(c, phi, v_out, sc, nullptr, nullptr, pub)
+                         : eval_impl<double>(c, phi, v_out, sc, nullptr, nullptr, pub);
+  if (rc || !host) return rc;
+  return wait_published(c, pub.seq, SC_COUNT, host);
 }
 
 int dev_eval_trial(ofdft_ctx* c, const double* phi, const double* dir, double ca, double sb, double* phi_out,
-                   void* v_out, double* sc, double ms, double mc) {
+                   void* v_out, double* sc, double ms, double mc, double* host) {
   const Rotation rot{dir, ca, sb, phi_out};
   const Slope sl{phi, dir, ms, mc};
-  return c->rsize == 4 ? eval_impl<float>(c, phi, v_out, sc, &rot, &sl)
-                       : eval_impl<double>(c, phi, v_out, sc, &rot, &sl);
+  const Publish pub = host ? next_publish(c) : Publish{nullptr, nullptr, 0};
+  int rc = c->rsize == 4 ? eval_impl<float>(c, phi, v_out, sc, &rot, &sl, pub)
+                         : eval_impl<double>(c, phi, v_out, sc, &rot, &sl, pub);
+  if (rc || !host) return rc;
+  return wait_published(c, pub.seq, SC_COUNT, host);
 }
 
 // ---------------------------------------------------------------- allocation
@@ -1536,7 +1643,16 @@ int dev_alloc_grid(ofdft_ctx* c) {
   for (int k = 0; k < 3 && ok; ++k) ok = dalloc_bytes(c, &c->gr[k], N * rs);
   ok = ok && dalloc(c, &c->partials, (size_t)SL_COUNT * c->max_blocks) && dalloc(c, &c->scalars, SC_COUNT) &&
        dalloc(c, &c->scalars_t, SC_COUNT) && dalloc(c, &c->vpart, 8 * VEC_BLOCKS) && dalloc(c, &c->vout, 16);
-  if (ok && !c->hbuf) ok = hip_ok(c, hipHostMalloc((void**)&c->hbuf, 64 * sizeof(double)), "hipHostMalloc");
+  if (ok && !c->hmap) {
+    ok = hip_ok(c, hipHostMalloc((void**)&c->hmap, (kMapDoubles + 1) * sizeof(double),
+                                 hipHostMallocMapped | hipHostMallocCoherent), "hipHostMalloc (mapped)");
+    if (ok) ok = hip_ok(c, hipHostGetDevicePointer((void**)&c->dmap, c->hmap, 0), "hipHostGetDevicePointer");
+    if (ok) {
+      for (int k = 0; k < kMapDoubles; ++k) c->hmap[k] = 0.0;
+      *reinterpret_cast<unsigned long long*>(c->hmap + kMapDoubles) = 0ull;
+      c->read_seq = 0;
+    }
+  }
   ok = ok && (rs == 4 ? upload_twiddles<float>(c) : upload_twiddles<double>(c));
   if (ok) {
     static bool lds_f = false, lds_d = false;
@@ -1670,8 +1786,10 @@ int dev_grad_dots(ofdft_ctx* c, const double* phi, const void* v, const double* 
 int dev_cg_direction(ofdft_ctx* c, double beta, double cproj) {
   const double two_dv = 2.0 * c->g.dv;
   if (c->rsize == 4)
-    return run_vec<2>(c, OpDirection<float>{c->phi, (const float*)c->v, c->scalars, c->gprev, c->d, two_dv, beta, cproj});
-  return run_vec<2>(c, OpDirection<double>{c->phi, (const double*)c->v, c->scalars, c->gprev, c->d, two_dv, beta, cproj});
+    return run_vec<2>(c, OpDirection<float>{c->phi, (const float*)c->v, c->scalars, c->gprev, c->d, two_dv, beta,
+                                            cproj, 0});
+  return run_vec<2>(c, OpDirection<double>{c->phi, (const double*)c->v, c->scalars, c->gprev, c->d, two_dv, beta,
+                                           cproj, 0});
 }
 
 template <typename R, int L>
@@ -1682,34 +1800,60 @@ static void launch_rpass_fwd_grad(ofdft_ctx* c, const double* phi, const void* v
                      c->stream, phi, (const R*)v, sc, two_dv, (cplx<R>*)out, (const cplx<R>*)c->tw[2], g);
 }
 
+// Reduce the K dots the op accumulates and form the CG coefficients (k_cg_dots_final).
+template <int K, class Op>
+static int run_cg_dots(ofdft_ctx* c, const Op& op, const CgCoef& cf) {
+  hipLaunchKernelGGL((k_vec<K, Op>), dim3(VEC_BLOCKS), dim3(NT), 0, c->stream, c->g.N, op, c->vpart);
+  hipLaunchKernelGGL((k_cg_dots_final<K>), dim3(1), dim3(NT), 0, c->stream, c->vpart, VEC_BLOCKS, c->scalars, cf);
+  return hip_ok(c, hipGetLastError(), "CG dots") ? OFDFT_OK : OFDFT_E_DEVICE;
+}
+
 template <typename R>
-static int precond_impl(ofdft_ctx* c, const double* phi, const void* v, const double* sc, const double* gprev,
-                        double* out) {
+static int cg_step_impl(ofdft_ctx* c, bool pcg, bool have_prev, double gg_prev, double cproj) {
   const GridDesc& g = c->g;
   const double two_dv = 2.0 * g.dv;
-  // w = (P - 1) g: forward 3D FFT of g, filter in the x1 pass, inverse 3D FFT into gr[0];
-  // z = g + w, so the modes the passes drop (Nyquist) keep P = 1
-  OFDFT_DISPATCH(g.n3, (launch_rpass_fwd_grad<R, L_>(c, phi, v, sc, two_dv, c->B[0])));
-  OFDFT_DISPATCH(g.n2, (launch_x2<R, L_, -1>(c, c->B[0], nullptr, nullptr, 1)));
-  OFDFT_DISPATCH(g.n1, (launch_x1_density<R, L_, X1_PREC>(c, c->B[0], c->B[0], nullptr, nullptr)));
-  OFDFT_DISPATCH(g.n2, (launch_x2<R, L_, +1>(c, c->B[0], nullptr, nullptr, 1)));
-  OFDFT_DISPATCH(g.n3, (launch_rpass_inv_real1<R, L_>(c, c->B[0], c->gr[0])));
-  return run_vec<5>(c, OpPrecDots<R>{phi, (const R*)v, (const R*)c->gr[0], sc, gprev, two_dv}, out);
+  const double* phi = c->phi;
+  const R* v = (const R*)c->v;
+  const double* gprev = have_prev ? c->gprev : nullptr;
+  const CgCoef cf{pcg ? 1 : 0, have_prev ? 1 : 0, gg_prev, g.dv};
+  int rc;
+  if (pcg) {
+    // w = (P - 1) g: forward 3D FFT of g, filter in the x1 pass, inverse 3D FFT into gr[0];
+    // z = g + w, so the modes the passes drop (Nyquist) keep P = 1
+    OFDFT_DISPATCH(g.n3, (launch_rpass_fwd_grad<R, L_>(c, phi, v, c->scalars, two_dv, c->B[0])));
+    OFDFT_DISPATCH(g.n2, (launch_x2<R, L_, -1>(c, c->B[0], nullptr, nullptr, 1)));
+    OFDFT_DISPATCH(g.n1, (launch_x1_density<R, L_, X1_PREC>(c, c->B[0], c->B[0], nullptr, nullptr)));
+    OFDFT_DISPATCH(g.n2, (launch_x2<R, L_, +1>(c, c->B[0], nullptr, nullptr, 1)));
+    OFDFT_DISPATCH(g.n3, (launch_rpass_inv_real1<R, L_>(c, c->B[0], c->gr[0])));
+    rc = run_cg_dots<5>(c, OpPrecDots<R>{phi, v, (const R*)c->gr[0], c->scalars, gprev, two_dv}, cf);
+    if (rc) return rc;
+    return run_vec<2>(c, OpPrecDirection<R>{phi, v, (const R*)c->gr[0], c->scalars, c->gprev, c->d, two_dv, cproj, 0},
+                      c->scalars + SC_DD);
+  }
+  rc = run_cg_dots<4>(c, OpGradDots<R>{phi, v, c->scalars, gprev, have_prev ? c->d : nullptr, two_dv}, cf);
+  if (rc) return rc;
+  return run_vec<2>(c, OpDirection<R>{phi, v, c->scalars, c->gprev, c->d, two_dv, 0.0, cproj, 1},
+                    c->scalars + SC_DD);
 }
 
-int dev_precond_dots(ofdft_ctx* c, const double* phi, const void* v, const double* sc, const double* gprev,
-                     double* out) {
-  return c->rsize == 4 ? precond_impl<float>(c, phi, v, sc, gprev, out)
-                       : precond_impl<double>(c, phi, v, sc, gprev, out);
+int dev_cg_step(ofdft_ctx* c, bool pcg, bool have_prev, double gg_prev, double cproj) {
+  return c->rsize == 4 ? cg_step_impl<float>(c, pcg, have_prev, gg_prev, cproj)
+                       : cg_step_impl<double>(c, pcg, have_prev, gg_prev, cproj);
 }
 
-int dev_pcg_direction(ofdft_ctx* c, double beta, double cproj, double cz) {
+template <typename R>
+static int cg_restart_impl(ofdft_ctx* c, bool pcg) {
   const double two_dv = 2.0 * c->g.dv;
-  if (c->rsize == 4)
-    return run_vec<2>(c, OpPrecDirection<float>{c->phi, (const float*)c->v, (const float*)c->gr[0], c->scalars,
-                                                c->gprev, c->d, two_dv, beta, cproj, cz});
-  return run_vec<2>(c, OpPrecDirection<double>{c->phi, (const double*)c->v, (const double*)c->gr[0], c->scalars,
-                                               c->gprev, c->d, two_dv, beta, cproj, cz});
+  const R* v = (const R*)c->v;
+  if (pcg)
+    return run_vec<2>(c, OpPrecDirection<R>{c->phi, v, (const R*)c->gr[0], c->scalars, c->gprev, c->d, two_dv, 0.0, 1},
+                      c->scalars + SC_DD);
+  return run_vec<2>(c, OpDirection<R>{c->phi, v, c->scalars, c->gprev, c->d, two_dv, 0.0, 0.0, 0},
+                    c->scalars + SC_DD);
+}
+
+int dev_cg_restart(ofdft_ctx* c, bool pcg) {
+  return c->rsize == 4 ? cg_restart_impl<float>(c, pcg) : cg_restart_impl<double>(c, pcg);
 }
 
 int dev_rotate(ofdft_ctx* c, double* dst, const double* phi, double ca, const double* dir, double sb) {
@@ -1744,11 +1888,11 @@ int dev_tn_hess_finish(ofdft_ctx* c, double* hs, const double* phi, const double
 }
 
 int dev_read(ofdft_ctx* c, const double* dptr, int n, double* host) {
-  if (!hip_ok(c, hipMemcpyAsync(c->hbuf, dptr, n * sizeof(double), hipMemcpyDeviceToHost, c->stream), "readback"))
-    return OFDFT_E_DEVICE;
-  if (!hip_ok(c, hipStreamSynchronize(c->stream), "sync")) return OFDFT_E_DEVICE;
-  std::memcpy(host, c->hbuf, n * sizeof(double));
-  return OFDFT_OK;
+  if (n < 1 || n > kMapDoubles) return dev_fail(c, OFDFT_E_ARG, "readback size out of range");
+  const Publish pub = next_publish(c);
+  hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, c->stream, dptr, n, pub);
+  if (!hip_ok(c, hipGetLastError(), "readback launch")) return OFDFT_E_DEVICE;
+  return wait_published(c, pub.seq, n, host);
 }
 
 int dev_sync(ofdft_ctx* c) {
