@@ -72,6 +72,11 @@ def kernel_bytes(name: str, n1: int, n2: int, n3: int, rsize: int) -> float:
         "cpass_x2_inv": 2 * CS,
         "rpass_final": CS + P + 2 * RR,
         "rpass_tf_final": CS + P + RR,
+        "plane_fwd_density": P + CS,
+        "plane_inv_grad3": 3 * CS + 3 * RR,
+        "plane_fwd_w3": 3 * CS + 3 * RR,
+        "plane_final": CS + P + 2 * RR,
+        "plane_tf_final": CS + P + RR,
         "reduce_scalars": 0,
     }
     return float(table.get(name, 0))

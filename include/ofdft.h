@@ -94,6 +94,13 @@ typedef struct {
                           1/(1 + G^2/(cg_precond k_F^2)) in reciprocal space (k_F^2 = (3 pi^2 N_e/V)^(2/3))
                           before the direction update (preconditioned Polak-Ribiere); 0 = plain CG.
                           ftTF always uses plain CG.  Changes the iteration path, not the minimum. */
+  int extrapolate;     /* starting amplitude of the next ofdft_minimize_density after ofdft_set_ions
+                          moves the ions (an ionic step): 0 = the last density as it is; 1 = linear
+                          extrapolation 2 phi_k - phi_{k-1} of the last two converged amplitudes;
+                          2 = quadratic, 3 phi_k - 3 phi_{k-1} + phi_{k-2}.  The result is renormalised
+                          to N_e.  Converged amplitudes are remembered per context; ofdft_set_cell,
+                          ofdft_set_density and a change of N_e clear the history, and the order drops
+                          to what the history holds.  Changes the starting point, not the minimum. */
 } ofdft_options;
 
 typedef struct {
@@ -112,7 +119,7 @@ typedef struct {
 
 /* Fills defaults: TF, mu_sga = 5/27, PZ81, Gaussian LPP rc = 0.5, FP64, CG,
    tol_energy = 1e-8, tol_residual = 0, max_iter = 1000, device 0, own stream,
-   cg_precond = 8. */
+   cg_precond = 8, extrapolate = 0. */
 void ofdft_default_options(ofdft_options* opt);
 
 /* Creates a context.  opt may be NULL (defaults).  *out is set on success. */

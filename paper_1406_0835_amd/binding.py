@@ -30,7 +30,8 @@ class Options(ctypes.Structure):
                 ("lpp", ctypes.c_int), ("lpp_rc", ctypes.c_double), ("lpp_A", ctypes.c_double),
                 ("lpp_qc", ctypes.c_double), ("precision", ctypes.c_int), ("minimizer", ctypes.c_int),
                 ("tol_energy", ctypes.c_double), ("tol_residual", ctypes.c_double), ("max_iter", ctypes.c_int),
-                ("device", ctypes.c_int), ("stream", ctypes.c_void_p), ("cg_precond", ctypes.c_double)]
+                ("device", ctypes.c_int), ("stream", ctypes.c_void_p), ("cg_precond", ctypes.c_double),
+                ("extrapolate", ctypes.c_int)]
 
 
 class Report(ctypes.Structure):

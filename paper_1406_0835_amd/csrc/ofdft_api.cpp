@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <thread>
 #include <vector>
@@ -177,6 +178,36 @@ void accept_trial(ofdft_ctx* c) {
   std::swap(c->phi, c->phi_t);
   std::swap(c->v, c->v_t);
   std::swap(c->scalars, c->scalars_t);
+}
+
+// Ionic-step history (options.extrapolate): remember the converged amplitude.
+int save_history(ofdft_ctx* c) {
+  const size_t bytes = (size_t)c->g.N * sizeof(double);
+  const int slot = c->n_hist == 0 ? 0 : (c->hist_head + 1) % 3;
+  if (!c->phi_hist[slot] && hipMalloc((void**)&c->phi_hist[slot], bytes) != hipSuccess)
+    return fail(c, OFDFT_E_DEVICE, "history allocation");
+  if (hipMemcpyAsync(c->phi_hist[slot], c->phi, bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+    return fail(c, OFDFT_E_DEVICE, "history copy");
+  c->hist_head = slot;
+  c->n_hist = std::min(c->n_hist + 1, 3);
+  return OFDFT_OK;
+}
+
+// Starting amplitude after the ions moved: polynomial extrapolation in the step
+// index through the last converged amplitudes, renormalised to N_e.
+int extrapolate_phi(ofdft_ctx* c) {
+  const int order = std::min(c->opt.extrapolate, c->n_hist - 1);
+  if (order < 1) return OFDFT_OK;
+  const double* h0 = c->phi_hist[c->hist_head];
+  const double* h1 = c->phi_hist[(c->hist_head + 2) % 3];
+  const double* h2 = c->phi_hist[(c->hist_head + 1) % 3];
+  int rc = order == 1 ? dev_combine3(c, c->phi, 2.0, h0, -1.0, h1, 0.0, nullptr)
+                      : dev_combine3(c, c->phi, 3.0, h0, -3.0, h1, 1.0, h2);
+  if (rc) return rc;
+  double s2 = 0.0;
+  if ((rc = dev_read(c, c->vout, 1, &s2))) return rc;
+  if (!(s2 > 0.0) || !is_fin(s2)) return fail(c, OFDFT_E_NONFINITE, "extrapolated amplitude is zero or non-finite");
+  return dev_axpby(c, c->phi, std::sqrt(c->Ne / (c->g.dv * s2)), c->phi, 0.0);
 }
 
 int ensure_phi(ofdft_ctx* c) {
@@ -429,6 +460,7 @@ void ofdft_default_options(ofdft_options* o) {
   o->device = 0;
   o->stream = nullptr;
   o->cg_precond = 8.0;
+  o->extrapolate = 0;
 }
 
 int ofdft_create(const ofdft_options* opt, ofdft_ctx** out) {
@@ -449,6 +481,7 @@ int ofdft_create(const ofdft_options* opt, ofdft_ctx** out) {
   if (o.functional == OFDFT_SGA && !(o.mu_sga >= 0.0)) return fail(nullptr, OFDFT_E_ARG, "mu_sga must be >= 0");
   if (!(o.cg_precond >= 0.0) || !std::isfinite(o.cg_precond))
     return fail(nullptr, OFDFT_E_ARG, "cg_precond must be finite and >= 0");
+  if (o.extrapolate < 0 || o.extrapolate > 2) return fail(nullptr, OFDFT_E_ARG, "extrapolate must be 0, 1 or 2");
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(nullptr, OFDFT_E_DEVICE, "no HIP device");
   if (o.device < 0 || o.device >= ndev) return fail(nullptr, OFDFT_E_ARG, "device ordinal out of range");
@@ -457,6 +490,7 @@ int ofdft_create(const ofdft_options* opt, ofdft_ctx** out) {
   ofdft_ctx* c = new ofdft_ctx();
   c->opt = o;
   c->rsize = (o.precision == OFDFT_MIXED) ? 4 : 8;
+  if (const char* pp = std::getenv("OFDFT_PLANE_PASSES")) c->plane_passes = std::atoi(pp) != 0;
   if (o.stream) {
     c->stream = (hipStream_t)o.stream;
   } else {
@@ -575,6 +609,9 @@ int ofdft_set_ions(ofdft_ctx* c, int nat, const double* tau, const double* Z) {
   if (c->have_phi && Ne_old > 0.0 && Ne_old != Ne) {
     // keep the shape of the warm start, rescale to the new electron count
     if ((rc = dev_axpby(c, c->phi, std::sqrt(Ne / Ne_old), c->phi, 0.0))) return fail(c, rc, c->err);
+    c->n_hist = 0;
+  } else if (c->have_phi && c->opt.extrapolate > 0) {
+    if ((rc = extrapolate_phi(c))) return fail(c, rc, c->err);
   }
   c->have_ions = true;
   c->converged = false;
@@ -594,7 +631,9 @@ int ofdft_minimize_density(ofdft_ctx* c, ofdft_report* rep) {
   int rc = check_ready(c);
   if (rc) return rc;
   c->converged = false;
-  return c->opt.minimizer == OFDFT_TN ? minimize_tn(c, rep) : minimize_cg(c, rep);
+  rc = c->opt.minimizer == OFDFT_TN ? minimize_tn(c, rep) : minimize_cg(c, rep);
+  if (rc == OFDFT_OK && c->opt.extrapolate > 0 && (rc = save_history(c))) return rc;
+  return rc;
 }
 
 int ofdft_free_energy_and_forces(ofdft_ctx* c, double* F_total, double* E_internal, double* forces,
@@ -646,6 +685,7 @@ int ofdft_set_density(ofdft_ctx* c, const double* phi) {
   (void)hipSetDevice(c->opt.device);
   if (hipMemcpy(c->phi, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
     return fail(c, OFDFT_E_DEVICE, "upload phi");
+  c->n_hist = 0;
   c->have_phi = true;
   c->converged = false;
   return OFDFT_OK;

@@ -192,4 +192,71 @@ __device__ __forceinline__ cplx<R>* lds_fft(cplx<R>* a, cplx<R>* b, const cplx<R
   return Stages<R, SIGN, L, NT, 0, 1>::run(a, b, tw, nrows, tid);
 }
 
+// ---------------------------------------------------------------- in-place stages
+// The same Stockham stages on one buffer: every thread first reads all the
+// butterflies it owns into registers, the block synchronises, and then the
+// outputs are written.  Half the LDS of the ping-pong form for two barriers
+// per stage.  MAXE bounds the elements per thread (nrows * L <= MAXE * NTP,
+// checked by the caller), so a thread owns at most ceil(MAXE / RAD) butterflies.
+template <typename R, int SIGN, int L, int NTP, int MAXE, int S, int NS>
+struct StagesInPlace {
+  __device__ __forceinline__ static void run(cplx<R>* buf, const cplx<R>* tw, int nrows, int tid) {
+    if constexpr (NS < L) {
+      constexpr int RAD = radix_at(L, S);
+      constexpr int LR = L / RAD;
+      constexpr int TWSTEP = L / (NS * RAD);
+      constexpr int MAXB = (MAXE + RAD - 1) / RAD;
+      const int total = nrows * LR;
+      cplx<R> v[MAXB][RAD];
+#pragma unroll
+      for (int m = 0; m < MAXB; ++m) {
+        const int b = tid + m * NTP;
+        if (b < total) {
+          const int row = b / LR, j = b - row * LR;
+          const cplx<R>* in = buf + row * Lay<L>::RS;
+#pragma unroll
+          for (int q = 0; q < RAD; ++q) {
+            const int i = j + q * LR;
+            v[m][q] = in[i + (i >> 3)];
+          }
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int m = 0; m < MAXB; ++m) {
+        const int b = tid + m * NTP;
+        if (b < total) {
+          const int row = b / LR, j = b - row * LR;
+          const int k = j % NS;
+          if constexpr (NS > 1) {
+#pragma unroll
+            for (int q = 1; q < RAD; ++q) {
+              cplx<R> w = tw[q * k * TWSTEP];
+              if constexpr (SIGN > 0) w.y = -w.y;
+              v[m][q] = cmul(v[m][q], w);
+            }
+          }
+          Bfly<R, SIGN, RAD>::run(v[m]);
+          cplx<R>* out = buf + row * Lay<L>::RS;
+          const int base = (j / NS) * NS * RAD + k;
+#pragma unroll
+          for (int q = 0; q < RAD; ++q) {
+            const int i = base + q * NS;
+            out[i + (i >> 3)] = v[m][q];
+          }
+        }
+      }
+      __syncthreads();
+      StagesInPlace<R, SIGN, L, NTP, MAXE, S + 1, NS * RAD>::run(buf, tw, nrows, tid);
+    }
+  }
+};
+
+// In-place LDS FFT of nrows rows of length L (padded layout).  Callers
+// __syncthreads() before; the routine ends with a barrier.
+template <typename R, int SIGN, int L, int NTP, int MAXE>
+__device__ __forceinline__ void lds_fft_inplace(cplx<R>* buf, const cplx<R>* tw, int nrows, int tid) {
+  StagesInPlace<R, SIGN, L, NTP, MAXE, 0, 1>::run(buf, tw, nrows, tid);
+}
+
 }  // namespace ofdft

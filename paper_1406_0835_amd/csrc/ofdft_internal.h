@@ -115,11 +115,18 @@ struct ofdft_ctx {
   // minimiser vectors
   double* d = nullptr;
   double* gprev = nullptr;
+  // converged amplitudes of the last ionic steps (extrapolate > 0): slot
+  // (hist_head - j) mod 3 holds phi_{k-j}, j < n_hist
+  double* phi_hist[3] = {nullptr, nullptr, nullptr};
+  int n_hist = 0, hist_head = 0;
   double* tn[4] = {nullptr, nullptr, nullptr, nullptr};
   double* vpart = nullptr;     // vector-reduction partials
   double* vout = nullptr;      // vector-reduction results
   // Fine-grained pinned host memory the device writes small results into:
   // doubles [0, kMapDoubles) of data, then a 64-bit sequence word the host waits on.
+  // x3 and x2 transforms as one plane pass where the grid allows (on unless
+  // OFDFT_PLANE_PASSES=0 in the environment at ofdft_create)
+  bool plane_passes = true;
   double* hmap = nullptr;
   double* dmap = nullptr;      // the same memory as seen by kernels
   unsigned long long read_seq = 0;
@@ -181,6 +188,9 @@ int dev_dtheta(ofdft_ctx* c, const double* phi_t, const void* v_t, const double*
 int dev_full_grad_acc(ofdft_ctx* c, double* out, const double* phi_t, const void* v_t, double sign);
 int dev_dot(ofdft_ctx* c, const double* a, const double* b);
 int dev_axpby(ofdft_ctx* c, double* y, double a, const double* x, double b);
+// dst = c0 x0 + c1 x1 + c2 x2 (x2 may be NULL when c2 = 0); dst.dst into c->vout[0]
+int dev_combine3(ofdft_ctx* c, double* dst, double c0, const double* x0, double c1, const double* x1, double c2,
+                 const double* x2);
 int dev_tn_hess_finish(ofdft_ctx* c, double* hs, const double* phi, const double* s, double inv2e,
                        double mu_term);
 // n <= kMapDoubles doubles from device memory to the host (a one-wavefront kernel

@@ -64,21 +64,22 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Block sum of K values; the result is valid in thread 0. red: LDS of K*NT/64 doubles.
-template <int K>
+// Block sum of K values over NTH threads; the result is valid in thread 0.
+// red: LDS of K*NTH/64 doubles.
+template <int K, int NTH = NT>
 __device__ __forceinline__ void block_sum(double* v, double* red) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const double s = wave_sum(v[k]);
-    if (lane == 0) red[k * (NT / 64) + w] = s;
+    if (lane == 0) red[k * (NTH / 64) + w] = s;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       double s = 0.0;
-      for (int i = 0; i < NT / 64; ++i) s += red[k * (NT / 64) + i];
+      for (int i = 0; i < NTH / 64; ++i) s += red[k * (NTH / 64) + i];
       v[k] = s;
     }
   }
@@ -799,6 +800,381 @@ __global__ void __launch_bounds__(NT) k_rpass_final(const cplx<R>* __restrict__ 
   }
 }
 
+// ---------------------------------------------------------------- plane passes
+// Grids with n2 == n3 = L <= 128: the x3 and x2 transforms of one i1 plane run
+// in one block of NTP threads, and the plane's half spectrum stays in LDS
+// between the two axes, so the x2 transform costs no HBM round trip (the
+// separate x2 pass and the row passes above serve the other grids).  One LDS
+// buffer of L/2 padded rows holds both layouts: packed rows P[p][i3] with
+// z_p = x_{2p} + i x_{2p+1} for the x3 transform, and T[k3][k2], k3 < L/2, for
+// the x2 transform.  Changes of layout go through registers, every read
+// before a barrier and every write after it.
+constexpr int NTP = 1024;
+constexpr int PLANE_MAXE = 8;    // (L/2) L <= PLANE_MAXE NTP for L <= 128
+
+template <typename R, int L>
+__host__ __device__ constexpr size_t lds_plane(int nred) {
+  return pad16<cplx<R>>((size_t)(L / 2) * Lay<L>::RS) + pad16<cplx<R>>(L) + pad16<double>((size_t)nred * NTP / 64);
+}
+
+// x3 forward transform of the packed rows, then the half spectra of rows 2p
+// and 2p+1 (k3 < L/2) written transposed into T[k3][2p], T[k3][2p+1].
+template <typename R, int L>
+__device__ __forceinline__ void plane_x3_fwd_to_T(cplx<R>* buf, const cplx<R>* tw) {
+  lds_fft_inplace<R, -1, L, NTP, PLANE_MAXE>(buf, tw, L / 2, threadIdx.x);
+  constexpr int H = L / 2, ITEMS = H * H, MI = (ITEMS + NTP - 1) / NTP;
+  cplx<R> xa[MI], xb[MI];
+#pragma unroll
+  for (int m = 0; m < MI; ++m) {
+    const int it = threadIdx.x + m * NTP;
+    if (it < ITEMS) {
+      const int p = it / H, k3 = it - p * H;
+      const cplx<R> z = buf[Lay<L>::at(p, k3)];
+      const cplx<R> zc = cconj(buf[Lay<L>::at(p, (L - k3) % L)]);
+      xa[m] = {R(0.5) * (z.x + zc.x), R(0.5) * (z.y + zc.y)};
+      xb[m] = {R(0.5) * (z.y - zc.y), R(-0.5) * (z.x - zc.x)};
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < MI; ++m) {
+    const int it = threadIdx.x + m * NTP;
+    if (it < ITEMS) {
+      const int p = it / H, k3 = it - p * H;
+      buf[Lay<L>::at(k3, 2 * p)] = xa[m];
+      buf[Lay<L>::at(k3, 2 * p + 1)] = xb[m];
+    }
+  }
+  __syncthreads();
+}
+
+// x2 forward transform of the T rows, stored as S[k3][i1][k2].
+template <typename R, int L>
+__device__ __forceinline__ void plane_x2_fwd_store(cplx<R>* buf, const cplx<R>* tw, cplx<R>* out,
+                                                   const GridDesc& g, int i1) {
+  lds_fft_inplace<R, -1, L, NTP, PLANE_MAXE>(buf, tw, L / 2, threadIdx.x);
+  const size_t plane = (size_t)g.n1 * L;
+  constexpr int CNT = (L / 2) * L;
+  for (int e = threadIdx.x; e < CNT; e += NTP) {
+    const int k3 = e / L, k2 = e - k3 * L;
+    out[k3 * plane + (size_t)i1 * L + k2] = buf[Lay<L>::at(k3, k2)];
+  }
+}
+
+// T[k3][k2] = S[k3][i1][k2] (k3 < L/2) and the twiddles; ends with a barrier.
+template <typename R, int L>
+__device__ __forceinline__ void plane_load_T(cplx<R>* buf, cplx<R>* tw, const cplx<R>* in,
+                                             const cplx<R>* tw_g, const GridDesc& g, int i1) {
+  const size_t plane = (size_t)g.n1 * L;
+  constexpr int CNT = (L / 2) * L, MU = (CNT + NTP - 1) / NTP;
+  const cplx<R> twv = twiddle_load<R, L>(tw_g);
+  cplx<R> v[MU];
+#pragma unroll
+  for (int m = 0; m < MU; ++m) {
+    const int e = min((int)threadIdx.x + m * NTP, CNT - 1);
+    const int k3 = e / L, k2 = e - k3 * L;
+    v[m] = in[k3 * plane + (size_t)i1 * L + k2];
+  }
+  twiddle_store<R, L>(tw, twv);
+#pragma unroll
+  for (int m = 0; m < MU; ++m) {
+    const int e = threadIdx.x + m * NTP;
+    if (e < CNT) {
+      const int k3 = e / L, k2 = e - k3 * L;
+      buf[Lay<L>::at(k3, k2)] = v[m];
+    }
+  }
+  __syncthreads();
+}
+
+// x2 inverse transform of the T rows, the packed rows z_p[k] = X_{2p}[k] +
+// i X_{2p+1}[k] over all k (Hermitian symmetry, Nyquist term zero), and the x3
+// inverse transform: real element (i2, i3) is then Re or Im of P[i2/2][i3].
+template <typename R, int L>
+__device__ __forceinline__ void plane_inv(cplx<R>* buf, const cplx<R>* tw) {
+  lds_fft_inplace<R, +1, L, NTP, PLANE_MAXE>(buf, tw, L / 2, threadIdx.x);
+  constexpr int H = L / 2, ITEMS = H * L, MI = (ITEMS + NTP - 1) / NTP;
+  cplx<R> z[MI];
+#pragma unroll
+  for (int m = 0; m < MI; ++m) {
+    const int it = threadIdx.x + m * NTP;
+    if (it < ITEMS) {
+      const int p = it / L, k = it - p * L;
+      cplx<R> xa = {R(0), R(0)}, xb = {R(0), R(0)};
+      if (2 * k < L) {
+        xa = buf[Lay<L>::at(k, 2 * p)];
+        xb = buf[Lay<L>::at(k, 2 * p + 1)];
+      } else if (2 * k > L) {
+        xa = cconj(buf[Lay<L>::at(L - k, 2 * p)]);
+        xb = cconj(buf[Lay<L>::at(L - k, 2 * p + 1)]);
+      }
+      z[m] = {xa.x - xb.y, xa.y + xb.x};
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < MI; ++m) {
+    const int it = threadIdx.x + m * NTP;
+    if (it < ITEMS) {
+      const int p = it / L, k = it - p * L;
+      buf[Lay<L>::at(p, k)] = z[m];
+    }
+  }
+  __syncthreads();
+  lds_fft_inplace<R, +1, L, NTP, PLANE_MAXE>(buf, tw, L / 2, threadIdx.x);
+}
+
+template <typename R, int L>
+__device__ __forceinline__ R plane_real(const cplx<R>* buf, int e) {
+  const int i2 = e / L, i3 = e - i2 * L;
+  const cplx<R> z = buf[Lay<L>::at(i2 >> 1, i3)];
+  return (i2 & 1) ? z.y : z.x;
+}
+
+// Chunk of the plane's real elements per thread in the load and store loops.
+constexpr int PCH = 8;
+
+// F1: n = phi^2 (phi_t = ca phi + sb dir for a line-search trial), x3 and x2
+// forward; sum phi^2 per plane.
+template <typename R, int L, bool ROT>
+__global__ void __launch_bounds__(NTP) k_plane_fwd_density(const double* __restrict__ phi, cplx<R>* __restrict__ out,
+                                                           const cplx<R>* __restrict__ tw_g, GridDesc g,
+                                                           double* __restrict__ partials, int maxb, Rotation rot) {
+  static_assert((L / 2) * L <= PLANE_MAXE * NTP, "plane larger than the in-place FFT bound");
+  extern __shared__ __align__(16) char smem_raw[];
+  Smem sm(smem_raw);
+  cplx<R>* buf = sm.take<cplx<R>>((L / 2) * Lay<L>::RS);
+  cplx<R>* tw = sm.take<cplx<R>>(L);
+  double* red = sm.take<double>(NTP / 64);
+  const int i1 = blockIdx.x;
+  const size_t base = (size_t)i1 * L * L;
+  constexpr int CNT = L * L;
+  const cplx<R> twv = twiddle_load<R, L>(tw_g);
+  R* zr = reinterpret_cast<R*>(buf);
+  double acc = 0.0;
+  for (int c0 = 0; c0 < CNT; c0 += PCH * NTP) {
+    double pv[PCH];
+#pragma unroll
+    for (int u = 0; u < PCH; ++u) pv[u] = phi[base + min(c0 + (int)threadIdx.x + u * NTP, CNT - 1)];
+    if constexpr (ROT) {
+      double dv_[PCH];
+#pragma unroll
+      for (int u = 0; u < PCH; ++u) dv_[u] = rot.dir[base + min(c0 + (int)threadIdx.x + u * NTP, CNT - 1)];
+#pragma unroll
+      for (int u = 0; u < PCH; ++u) {
+        pv[u] = rot.ca * pv[u] + rot.sb * dv_[u];
+        const int e = c0 + threadIdx.x + u * NTP;
+        if (e < CNT) rot.phi_out[base + e] = pv[u];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < PCH; ++u) {
+      const int e = c0 + threadIdx.x + u * NTP;
+      if (e < CNT) {
+        const int i2 = e / L, i3 = e - i2 * L;
+        const double n = pv[u] * pv[u];
+        acc += n;
+        zr[2 * Lay<L>::at(i2 >> 1, i3) + (i2 & 1)] = R(n);
+      }
+    }
+  }
+  twiddle_store<R, L>(tw, twv);
+  __syncthreads();
+  plane_x3_fwd_to_T<R, L>(buf, tw);
+  plane_x2_fwd_store<R, L>(buf, tw, out, g, i1);
+  double v[1] = {acc};
+  block_sum<1, NTP>(v, red);
+  if (threadIdx.x == 0) partials[SL_PHI2 * maxb + i1] = v[0];
+}
+
+// F3: forward x3 and x2 transforms of real arrays (component blockIdx.y).
+template <typename R, int L>
+__global__ void __launch_bounds__(NTP) k_plane_fwd_real(RealArr3 in, Arr3 out, const cplx<R>* __restrict__ tw_g,
+                                                        GridDesc g) {
+  static_assert((L / 2) * L <= PLANE_MAXE * NTP, "plane larger than the in-place FFT bound");
+  extern __shared__ __align__(16) char smem_raw[];
+  Smem sm(smem_raw);
+  cplx<R>* buf = sm.take<cplx<R>>((L / 2) * Lay<L>::RS);
+  cplx<R>* tw = sm.take<cplx<R>>(L);
+  const int i1 = blockIdx.x;
+  constexpr int CNT = L * L;
+  const R* src = reinterpret_cast<const R*>(in.p[blockIdx.y]) + (size_t)i1 * CNT;
+  const cplx<R> twv = twiddle_load<R, L>(tw_g);
+  R* zr = reinterpret_cast<R*>(buf);
+  for (int c0 = 0; c0 < CNT; c0 += PCH * NTP) {
+    R xv[PCH];
+#pragma unroll
+    for (int u = 0; u < PCH; ++u) xv[u] = src[min(c0 + (int)threadIdx.x + u * NTP, CNT - 1)];
+#pragma unroll
+    for (int u = 0; u < PCH; ++u) {
+      const int e = c0 + threadIdx.x + u * NTP;
+      if (e < CNT) {
+        const int i2 = e / L, i3 = e - i2 * L;
+        zr[2 * Lay<L>::at(i2 >> 1, i3) + (i2 & 1)] = xv[u];
+      }
+    }
+  }
+  twiddle_store<R, L>(tw, twv);
+  __syncthreads();
+  plane_x3_fwd_to_T<R, L>(buf, tw);
+  plane_x2_fwd_store<R, L>(buf, tw, reinterpret_cast<cplx<R>*>(out.p[blockIdx.y]), g, i1);
+}
+
+// The minimiser's projected gradient g = 2 dv phi (v - mu), formed on the fly,
+// forward x3 and x2 (the first half of the preconditioner P g).
+template <typename R, int L>
+__global__ void __launch_bounds__(NTP) k_plane_fwd_grad(const double* __restrict__ phi, const R* __restrict__ v,
+                                                        const double* __restrict__ sc, double two_dv,
+                                                        cplx<R>* __restrict__ out, const cplx<R>* __restrict__ tw_g,
+                                                        GridDesc g) {
+  static_assert((L / 2) * L <= PLANE_MAXE * NTP, "plane larger than the in-place FFT bound");
+  extern __shared__ __align__(16) char smem_raw[];
+  Smem sm(smem_raw);
+  cplx<R>* buf = sm.take<cplx<R>>((L / 2) * Lay<L>::RS);
+  cplx<R>* tw = sm.take<cplx<R>>(L);
+  const int i1 = blockIdx.x;
+  const size_t base = (size_t)i1 * L * L;
+  constexpr int CNT = L * L;
+  const cplx<R> twv = twiddle_load<R, L>(tw_g);
+  const double mu = sc[SC_MU];
+  R* zr = reinterpret_cast<R*>(buf);
+  for (int c0 = 0; c0 < CNT; c0 += PCH * NTP) {
+    double pv[PCH];
+    R vv[PCH];
+#pragma unroll
+    for (int u = 0; u < PCH; ++u) {
+      const int e = min(c0 + (int)threadIdx.x + u * NTP, CNT - 1);
+      pv[u] = phi[base + e];
+      vv[u] = v[base + e];
+    }
+#pragma unroll
+    for (int u = 0; u < PCH; ++u) {
+      const int e = c0 + threadIdx.x + u * NTP;
+      if (e < CNT) {
+        const int i2 = e / L, i3 = e - i2 * L;
+        zr[2 * Lay<L>::at(i2 >> 1, i3) + (i2 & 1)] = R(two_dv * pv[u] * (double(vv[u]) - mu));
+      }
+    }
+  }
+  twiddle_store<R, L>(tw, twv);
+  __syncthreads();
+  plane_x3_fwd_to_T<R, L>(buf, tw);
+  plane_x2_fwd_store<R, L>(buf, tw, out, g, i1);
+}
+
+// I3: inverse x2 and x3 transforms into real arrays (component blockIdx.y).
+template <typename R, int L>
+__global__ void __launch_bounds__(NTP) k_plane_inv_real(Arr3 in, RealArr3 out, const cplx<R>* __restrict__ tw_g,
+                                                        GridDesc g) {
+  static_assert((L / 2) * L <= PLANE_MAXE * NTP, "plane larger than the in-place FFT bound");
+  extern __shared__ __align__(16) char smem_raw[];
+  Smem sm(smem_raw);
+  cplx<R>* buf = sm.take<cplx<R>>((L / 2) * Lay<L>::RS);
+  cplx<R>* tw = sm.take<cplx<R>>(L);
+  const int i1 = blockIdx.x;
+  constexpr int CNT = L * L;
+  plane_load_T<R, L>(buf, tw, reinterpret_cast<const cplx<R>*>(in.p[blockIdx.y]), tw_g, g, i1);
+  plane_inv<R, L>(buf, tw);
+  R* dst = reinterpret_cast<R*>(out.p[blockIdx.y]) + (size_t)i1 * CNT;
+  for (int e = threadIdx.x; e < CNT; e += NTP) dst[e] = plane_real<R, L>(buf, e);
+}
+
+// FI: inverse x2 and x3 transforms of the reciprocal-space potential, then
+// v = v_loc + S + alpha (ftTF: the pointwise ftTF and XC here), sum n v and the
+// per-plane partials (as k_rpass_final).
+template <typename R, int L, bool TF, bool DT>
+__global__ void __launch_bounds__(NTP) k_plane_final(const cplx<R>* __restrict__ D, const double* __restrict__ phi,
+                                                     const R* __restrict__ vloc, R* __restrict__ vout,
+                                                     const cplx<R>* __restrict__ tw_g, GridDesc g, EvalParams ep,
+                                                     double* __restrict__ partials, int maxb, Slope sl) {
+  static_assert((L / 2) * L <= PLANE_MAXE * NTP, "plane larger than the in-place FFT bound");
+  extern __shared__ __align__(16) char smem_raw[];
+  Smem sm(smem_raw);
+  cplx<R>* buf = sm.take<cplx<R>>((L / 2) * Lay<L>::RS);
+  cplx<R>* tw = sm.take<cplx<R>>(L);
+  double* red = sm.take<double>(6 * NTP / 64);
+  const int i1 = blockIdx.x;
+  const size_t base = (size_t)i1 * L * L;
+  constexpr int CNT = L * L;
+  plane_load_T<R, L>(buf, tw, D, tw_g, g, i1);
+  plane_inv<R, L>(buf, tw);
+  double fs = 0.0, ts = 0.0, exc = 0.0, nv = 0.0, dt1 = 0.0, dt2 = 0.0;
+  constexpr int CH = TF ? 2 : PCH;   // the inlined ftTF point is register-heavy
+  for (int c0 = 0; c0 < CNT; c0 += CH * NTP) {
+    double pv[CH], q[CH];
+    R lv[CH];
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int e = min(c0 + (int)threadIdx.x + u * NTP, CNT - 1);
+      pv[u] = phi[base + e];
+      if constexpr (!TF) lv[u] = vloc[base + e];
+    }
+    if constexpr (DT) {
+      double p0[CH], dd[CH];
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        const int e = min(c0 + (int)threadIdx.x + u * NTP, CNT - 1);
+        p0[u] = sl.phi0[base + e];
+        dd[u] = sl.dir[base + e];
+      }
+#pragma unroll
+      for (int u = 0; u < CH; ++u) q[u] = sl.ms * p0[u] + sl.mc * dd[u];
+    }
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int e = c0 + threadIdx.x + u * NTP;
+      if (e >= CNT) continue;
+      const double S = double(plane_real<R, L>(buf, e));
+      const double p = pv[u];
+      const double n = p * p;
+      double vl;
+      if constexpr (TF) {
+        const double nf = n > kDensityFloor ? n : kDensityFloor;
+        double f, vt, tsl;
+        const double ln_n = ln_pos(nf);
+        tf_point(nf, ln_n, ep.lt0, f, vt, tsl);
+        vl = vt;
+        fs += f;
+        ts += tsl;
+        if (ep.xc) {
+          R eps, vxc;
+          pz81<R>(ln_n, eps, vxc);
+          vl += double(vxc);
+          exc += n * double(eps);
+        }
+      } else {
+        vl = double(lv[u]);
+      }
+      const R vv = R(vl + S + ep.alpha_sum);
+      vout[base + e] = vv;
+      nv += n * double(vv);
+      if constexpr (DT) {
+        dt1 += p * double(vv) * q[u];
+        dt2 += p * q[u];
+      }
+    }
+  }
+  constexpr int K = (TF ? 4 : 1) + (DT ? 2 : 0);
+  double v[K];
+  int slot[K];
+  int k = 0;
+  if constexpr (TF) {
+    v[k] = fs; slot[k++] = SL_FS;
+    v[k] = ts; slot[k++] = SL_TS;
+    v[k] = exc; slot[k++] = SL_EXC;
+  }
+  v[k] = nv; slot[k++] = SL_NV;
+  if constexpr (DT) {
+    v[k] = dt1; slot[k++] = SL_DT1;
+    v[k] = dt2; slot[k++] = SL_DT2;
+  }
+  block_sum<K, NTP>(v, red);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int m = 0; m < K; ++m) partials[slot[m] * maxb + i1] = v[m];
+  }
+}
+
 // ---------------------------------------------------------------- K7: scalar reduction
 struct ReduceParams {
   int nb_r, nb_x1;   // partial counts of the row-pass and x1-pass kernels
@@ -1047,6 +1423,17 @@ struct OpAxpby {
   __device__ void operator()(long long i, double*) const { y[i] = (a == 0.0 ? 0.0 : a * y[i]) + b * x[i]; }
 };
 
+// dst = c0 x0 + c1 x1 + c2 x2; dot dst.dst
+struct OpCombine3 {
+  double* dst; const double* x0; const double* x1; const double* x2; double c0, c1, c2;
+  __device__ void operator()(long long i, double* acc) const {
+    double y = c0 * x0[i] + c1 * x1[i];
+    if (x2) y += c2 * x2[i];
+    dst[i] = y;
+    acc[0] += y * y;
+  }
+};
+
 // hs = hs * inv2e - c phi - mu_term s, with c chosen later; first pass: hs *= inv2e; dot hs.phi
 struct OpHessScale {
   double* hs; const double* phi; double inv2e;
@@ -1188,6 +1575,7 @@ __global__ void __launch_bounds__(NT) k_forces_final(int nat, const double* __re
 
 // ---------------------------------------------------------------- host side
 #define OFDFT_LENGTHS(X) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(256)
+#define OFDFT_PLANE_LENGTHS(X) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128)
 
 static inline bool hip_ok(ofdft_ctx* c, hipError_t e, const char* what) {
   if (e == hipSuccess) return true;
@@ -1336,6 +1724,58 @@ static void launch_rpass_inv_real1(ofdft_ctx* c, void* in_spec, void* out_real) 
                      out, (const cplx<R>*)c->tw[2], g);
 }
 
+// ---- plane-pass launchers (n2 == n3 = L <= 128; see plane_mode)
+template <typename R, int L>
+static void launch_plane_fwd_density(ofdft_ctx* c, const double* phi, void* out, const Rotation* rot) {
+  const GridDesc& g = c->g;
+  if (rot)
+    hipLaunchKernelGGL((k_plane_fwd_density<R, L, true>), dim3(g.n1), dim3(NTP), (lds_plane<R, L>(1)), c->stream,
+                       phi, (cplx<R>*)out, (const cplx<R>*)c->tw[2], g, c->partials, c->max_blocks, *rot);
+  else
+    hipLaunchKernelGGL((k_plane_fwd_density<R, L, false>), dim3(g.n1), dim3(NTP), (lds_plane<R, L>(1)), c->stream,
+                       phi, (cplx<R>*)out, (const cplx<R>*)c->tw[2], g, c->partials, c->max_blocks, Rotation{});
+}
+
+template <typename R, int L>
+static void launch_plane_inv_real(ofdft_ctx* c, void* in0, void* in1, void* in2, void* out0, void* out1, void* out2,
+                                  int narr) {
+  const GridDesc& g = c->g;
+  Arr3 in{{in0, in1, in2}};
+  RealArr3 out{{out0, out1, out2}};
+  hipLaunchKernelGGL((k_plane_inv_real<R, L>), dim3(g.n1, narr), dim3(NTP), (lds_plane<R, L>(0)), c->stream, in, out,
+                     (const cplx<R>*)c->tw[2], g);
+}
+
+template <typename R, int L>
+static void launch_plane_fwd_real3(ofdft_ctx* c) {
+  const GridDesc& g = c->g;
+  RealArr3 in{{c->gr[0], c->gr[1], c->gr[2]}};
+  Arr3 out{{c->B[0], c->B[1], c->B[2]}};
+  hipLaunchKernelGGL((k_plane_fwd_real<R, L>), dim3(g.n1, 3), dim3(NTP), (lds_plane<R, L>(0)), c->stream, in, out,
+                     (const cplx<R>*)c->tw[2], g);
+}
+
+template <typename R, int L>
+static void launch_plane_fwd_grad(ofdft_ctx* c, const double* phi, const void* v, const double* sc, double two_dv,
+                                  void* out) {
+  const GridDesc& g = c->g;
+  hipLaunchKernelGGL((k_plane_fwd_grad<R, L>), dim3(g.n1), dim3(NTP), (lds_plane<R, L>(0)), c->stream, phi,
+                     (const R*)v, sc, two_dv, (cplx<R>*)out, (const cplx<R>*)c->tw[2], g);
+}
+
+template <typename R, int L, bool TF>
+static void launch_plane_final(ofdft_ctx* c, const double* phi, void* v_out, const EvalParams& ep, const Slope* sl) {
+  const GridDesc& g = c->g;
+  if (sl)
+    hipLaunchKernelGGL((k_plane_final<R, L, TF, true>), dim3(g.n1), dim3(NTP), (lds_plane<R, L>(6)), c->stream,
+                       (const cplx<R>*)c->D, phi, (const R*)c->vloc, (R*)v_out, (const cplx<R>*)c->tw[2], g, ep,
+                       c->partials, c->max_blocks, *sl);
+  else
+    hipLaunchKernelGGL((k_plane_final<R, L, TF, false>), dim3(g.n1), dim3(NTP), (lds_plane<R, L>(6)), c->stream,
+                       (const cplx<R>*)c->D, phi, (const R*)c->vloc, (R*)v_out, (const cplx<R>*)c->tw[2], g, ep,
+                       c->partials, c->max_blocks, Slope{});
+}
+
 template <typename R>
 static void launch_pointwise_gga(ofdft_ctx* c, const double* phi, const EvalParams& ep) {
   hipLaunchKernelGGL((k_pointwise_gga<R>), dim3(PW_BLOCKS), dim3(NT), 0, c->stream, phi, (R*)c->gr[0],
@@ -1397,6 +1837,28 @@ static void launch_rpass_final(ofdft_ctx* c, const double* phi, void* v_out, con
     default: return OFDFT_E_GRID;                        \
   }
 
+// Dispatch of the plane passes (lengths up to 128).
+#define OFDFT_DISPATCH_PLANE(LEN, CALL)                  \
+  switch (LEN) {                                         \
+    case 8: { constexpr int L_ = 8; CALL; } break;       \
+    case 12: { constexpr int L_ = 12; CALL; } break;     \
+    case 16: { constexpr int L_ = 16; CALL; } break;     \
+    case 24: { constexpr int L_ = 24; CALL; } break;     \
+    case 32: { constexpr int L_ = 32; CALL; } break;     \
+    case 48: { constexpr int L_ = 48; CALL; } break;     \
+    case 64: { constexpr int L_ = 64; CALL; } break;     \
+    case 96: { constexpr int L_ = 96; CALL; } break;     \
+    case 128: { constexpr int L_ = 128; CALL; } break;   \
+    default: return OFDFT_E_GRID;                        \
+  }
+
+// The x3 and x2 transforms run as plane passes when the (i2, i3) planes are
+// square with L <= 128 (the plane's half spectrum then fits the LDS of one
+// block) and the context has not switched them off.
+static bool plane_mode(const ofdft_ctx* c) {
+  return c->plane_passes && c->g.n2 == c->g.n3 && c->g.n3 <= 128;
+}
+
 static EvalParams make_params(ofdft_ctx* c) {
   EvalParams ep{};
   ep.functional = c->opt.functional;
@@ -1426,39 +1888,67 @@ static int eval_impl(ofdft_ctx* c, const double* phi, void* v_out, double* sc, c
   const EvalParams ep = make_params(c);
   const bool tf = c->opt.functional == OFDFT_TF;
   const double* phi_e = rot ? rot->phi_out : phi;   // the amplitude being evaluated
-  tmark(c, "rpass_fwd_density");
-  OFDFT_DISPATCH(g.n3, (launch_rpass_fwd<R, L_>(c, phi, c->A, rot)));
-  tmark(c, "cpass_x2_fwd");
-  OFDFT_DISPATCH(g.n2, (launch_x2<R, L_, -1>(c, c->A, nullptr, nullptr, 1)));
+  const bool plane = plane_mode(c);
+  if (plane) {
+    tmark(c, "plane_fwd_density");
+    OFDFT_DISPATCH_PLANE(g.n3, (launch_plane_fwd_density<R, L_>(c, phi, c->A, rot)));
+  } else {
+    tmark(c, "rpass_fwd_density");
+    OFDFT_DISPATCH(g.n3, (launch_rpass_fwd<R, L_>(c, phi, c->A, rot)));
+    tmark(c, "cpass_x2_fwd");
+    OFDFT_DISPATCH(g.n2, (launch_x2<R, L_, -1>(c, c->A, nullptr, nullptr, 1)));
+  }
   if (tf) {
     tmark(c, "x1_density_hartree");
     OFDFT_DISPATCH(g.n1, (launch_x1_density<R, L_, X1_TF>(c, c->A, c->D, nullptr, nullptr)));
   } else {
     tmark(c, "x1_density_gradient");
     OFDFT_DISPATCH(g.n1, (launch_x1_density<R, L_, X1_GGA>(c, c->A, c->B[0], c->B[1], c->B[2])));
-    tmark(c, "cpass_x2_inv3");
-    OFDFT_DISPATCH(g.n2, (launch_x2<R, L_, +1>(c, c->B[0], c->B[1], c->B[2], 3)));
-    tmark(c, "rpass_inv_grad3");
-    OFDFT_DISPATCH(g.n3, (launch_rpass_inv_real3<R, L_>(c)));
+    if (plane) {
+      tmark(c, "plane_inv_grad3");
+      OFDFT_DISPATCH_PLANE(g.n3, (launch_plane_inv_real<R, L_>(c, c->B[0], c->B[1], c->B[2], c->gr[0], c->gr[1],
+                                                               c->gr[2], 3)));
+    } else {
+      tmark(c, "cpass_x2_inv3");
+      OFDFT_DISPATCH(g.n2, (launch_x2<R, L_, +1>(c, c->B[0], c->B[1], c->B[2], 3)));
+      tmark(c, "rpass_inv_grad3");
+      OFDFT_DISPATCH(g.n3, (launch_rpass_inv_real3<R, L_>(c)));
+    }
     tmark(c, "pointwise_gga");
     launch_pointwise_gga<R>(c, phi_e, ep);
-    tmark(c, "rpass_fwd_w3");
-    OFDFT_DISPATCH(g.n3, (launch_rpass_fwd_real3<R, L_>(c)));
-    tmark(c, "cpass_x2_fwd3");
-    OFDFT_DISPATCH(g.n2, (launch_x2<R, L_, -1>(c, c->B[0], c->B[1], c->B[2], 3)));
+    if (plane) {
+      tmark(c, "plane_fwd_w3");
+      OFDFT_DISPATCH_PLANE(g.n3, (launch_plane_fwd_real3<R, L_>(c)));
+    } else {
+      tmark(c, "rpass_fwd_w3");
+      OFDFT_DISPATCH(g.n3, (launch_rpass_fwd_real3<R, L_>(c)));
+      tmark(c, "cpass_x2_fwd3");
+      OFDFT_DISPATCH(g.n2, (launch_x2<R, L_, -1>(c, c->B[0], c->B[1], c->B[2], 3)));
+    }
     tmark(c, "x1_divergence");
     OFDFT_DISPATCH(g.n1, (launch_x1_div<R, L_>(c)));
   }
-  tmark(c, "cpass_x2_inv");
-  OFDFT_DISPATCH(g.n2, (launch_x2<R, L_, +1>(c, c->D, nullptr, nullptr, 1)));
-  if (tf) {
-    tmark(c, "rpass_tf_final");
-    OFDFT_DISPATCH(g.n3, (launch_rpass_final<R, L_, true>(c, phi_e, v_out, ep, sl)));
+  if (plane) {
+    if (tf) {
+      tmark(c, "plane_tf_final");
+      OFDFT_DISPATCH_PLANE(g.n3, (launch_plane_final<R, L_, true>(c, phi_e, v_out, ep, sl)));
+    } else {
+      tmark(c, "plane_final");
+      OFDFT_DISPATCH_PLANE(g.n3, (launch_plane_final<R, L_, false>(c, phi_e, v_out, ep, sl)));
+    }
   } else {
-    tmark(c, "rpass_final");
-    OFDFT_DISPATCH(g.n3, (launch_rpass_final<R, L_, false>(c, phi_e, v_out, ep, sl)));
+    tmark(c, "cpass_x2_inv");
+    OFDFT_DISPATCH(g.n2, (launch_x2<R, L_, +1>(c, c->D, nullptr, nullptr, 1)));
+    if (tf) {
+      tmark(c, "rpass_tf_final");
+      OFDFT_DISPATCH(g.n3, (launch_rpass_final<R, L_, true>(c, phi_e, v_out, ep, sl)));
+    } else {
+      tmark(c, "rpass_final");
+      OFDFT_DISPATCH(g.n3, (launch_rpass_final<R, L_, false>(c, phi_e, v_out, ep, sl)));
+    }
   }
-  const int nb_r = (g.n2 / g.tr) * g.n1;
+  // partial sums of the density and final passes: one per block
+  const int nb_r = plane ? g.n1 : (g.n2 / g.tr) * g.n1;
   ReduceParams rp{nb_r, (g.n2 / g.tc) * g.n3k, tf ? nb_r : PW_BLOCKS, sl ? 1 : 0, g.dv, g.volume, c->alpha_sum};
   tmark(c, "reduce_scalars");
   hipLaunchKernelGGL(k_reduce_scalars, dim3(1), dim3(RED_NT), 0, c->stream, c->partials, c->max_blocks, rp, sc,
@@ -1492,6 +1982,14 @@ static size_t max_lds_impl(const ofdft_ctx* c) {
     OFDFT_LENGTHS(OFDFT_LDS1)
 #undef OFDFT_LDS1
     default: break;
+  }
+  if (plane_mode(c)) {
+    switch (g.n3) {
+#define OFDFT_LDSP(LEN) case LEN: upd(lds_plane<R, LEN>(6)); break;
+      OFDFT_PLANE_LENGTHS(OFDFT_LDSP)
+#undef OFDFT_LDSP
+      default: break;
+    }
   }
   return m;
 }
@@ -1624,7 +2122,20 @@ static void configure_lds() {
   allow((const void*)k_rpass_fwd_grad<R, LEN>);
   OFDFT_LENGTHS(OFDFT_ALLOW)
 #undef OFDFT_ALLOW
+#define OFDFT_ALLOW_PLANE(LEN)                                                       \
+  allow((const void*)k_plane_fwd_density<R, LEN, false>);                            \
+  allow((const void*)k_plane_fwd_density<R, LEN, true>);                             \
+  allow((const void*)k_plane_fwd_real<R, LEN>);                                      \
+  allow((const void*)k_plane_fwd_grad<R, LEN>);                                      \
+  allow((const void*)k_plane_inv_real<R, LEN>);                                      \
+  allow((const void*)k_plane_final<R, LEN, true, false>);                            \
+  allow((const void*)k_plane_final<R, LEN, false, false>);                           \
+  allow((const void*)k_plane_final<R, LEN, true, true>);                             \
+  allow((const void*)k_plane_final<R, LEN, false, true>);
+  OFDFT_PLANE_LENGTHS(OFDFT_ALLOW_PLANE)
+#undef OFDFT_ALLOW_PLANE
 }
+
 
 int dev_alloc_grid(ofdft_ctx* c) {
   dev_free_grid(c);
@@ -1672,11 +2183,13 @@ void dev_free_grid(ofdft_ctx* c) {
                  (void**)&c->tn[1], (void**)&c->tn[2], (void**)&c->tn[3], &c->v, &c->v_t, &c->vloc, &c->A,
                  &c->S0, &c->D, &c->Vext, &c->B[0], &c->B[1], &c->B[2], &c->tw[0], &c->tw[1], &c->tw[2],
                  (void**)&c->partials, (void**)&c->scalars, (void**)&c->scalars_t, (void**)&c->vpart,
-                 (void**)&c->vout, &c->gr[0], &c->gr[1], &c->gr[2]};
+                 (void**)&c->vout, &c->gr[0], &c->gr[1], &c->gr[2], (void**)&c->phi_hist[0],
+                 (void**)&c->phi_hist[1], (void**)&c->phi_hist[2]};
   for (void** p : ps) {
     if (*p) (void)hipFree(*p);
     *p = nullptr;
   }
+  c->n_hist = 0;
 }
 
 int dev_alloc_ions(ofdft_ctx* c) {
@@ -1745,8 +2258,12 @@ template <typename R>
 static int forces_impl(ofdft_ctx* c, double* out_host) {
   const GridDesc& g = c->g;
   // n(G) of the current density into A (forward transform, kept modes, 1/N)
-  OFDFT_DISPATCH(g.n3, (launch_rpass_fwd<R, L_>(c, c->phi, c->A)));
-  OFDFT_DISPATCH(g.n2, (launch_x2<R, L_, -1>(c, c->A, nullptr, nullptr, 1)));
+  if (plane_mode(c)) {
+    OFDFT_DISPATCH_PLANE(g.n3, (launch_plane_fwd_density<R, L_>(c, c->phi, c->A, nullptr)));
+  } else {
+    OFDFT_DISPATCH(g.n3, (launch_rpass_fwd<R, L_>(c, c->phi, c->A)));
+    OFDFT_DISPATCH(g.n2, (launch_x2<R, L_, -1>(c, c->A, nullptr, nullptr, 1)));
+  }
   OFDFT_DISPATCH(g.n1, (launch_x1_density<R, L_, X1_NHAT>(c, c->A, c->D, nullptr, nullptr)));
   const int nbx = 1024;
   const int nby = (c->nat + FORCE_IONS - 1) / FORCE_IONS;
@@ -1820,11 +2337,19 @@ static int cg_step_impl(ofdft_ctx* c, bool pcg, bool have_prev, double gg_prev, 
   if (pcg) {
     // w = (P - 1) g: forward 3D FFT of g, filter in the x1 pass, inverse 3D FFT into gr[0];
     // z = g + w, so the modes the passes drop (Nyquist) keep P = 1
-    OFDFT_DISPATCH(g.n3, (launch_rpass_fwd_grad<R, L_>(c, phi, v, c->scalars, two_dv, c->B[0])));
-    OFDFT_DISPATCH(g.n2, (launch_x2<R, L_, -1>(c, c->B[0], nullptr, nullptr, 1)));
-    OFDFT_DISPATCH(g.n1, (launch_x1_density<R, L_, X1_PREC>(c, c->B[0], c->B[0], nullptr, nullptr)));
-    OFDFT_DISPATCH(g.n2, (launch_x2<R, L_, +1>(c, c->B[0], nullptr, nullptr, 1)));
-    OFDFT_DISPATCH(g.n3, (launch_rpass_inv_real1<R, L_>(c, c->B[0], c->gr[0])));
+    if (plane_mode(c)) {
+      OFDFT_DISPATCH_PLANE(g.n3, (launch_plane_fwd_grad<R, L_>(c, phi, v, c->scalars, two_dv, c->B[0])));
+      OFDFT_DISPATCH(g.n1, (launch_x1_density<R, L_, X1_PREC>(c, c->B[0], c->B[0], nullptr, nullptr)));
+      OFDFT_DISPATCH_PLANE(g.n3, (launch_plane_inv_real<R, L_>(c, c->B[0], nullptr, nullptr, c->gr[0], nullptr,
+                                                               nullptr, 1)));
+    } else {
+      OFDFT_DISPATCH(g.n3, (launch_rpass_fwd_grad<R, L_>(c, phi, v, c->scalars, two_dv, c->B[0])));
+      OFDFT_DISPATCH(g.n2, (launch_x2<R, L_, -1>(c, c->B[0], nullptr, nullptr, 1)));
+      OFDFT_DISPATCH(g.n1, (launch_x1_density<R, L_, X1_PREC>(c, c->B[0], c->B[0], nullptr, nullptr)));
+      OFDFT_DISPATCH(g.n2, (launch_x2<R, L_, +1>(c, c->B[0], nullptr, nullptr, 1)));
+      OFDFT_DISPATCH(g.n3, (launch_rpass_inv_real1<R, L_>(c, c->B[0], c->gr[0])));
+    }
+
     rc = run_cg_dots<5>(c, OpPrecDots<R>{phi, v, (const R*)c->gr[0], c->scalars, gprev, two_dv}, cf);
     if (rc) return rc;
     return run_vec<2>(c, OpPrecDirection<R>{phi, v, (const R*)c->gr[0], c->scalars, c->gprev, c->d, two_dv, cproj, 0},
@@ -1879,6 +2404,11 @@ int dev_dot(ofdft_ctx* c, const double* a, const double* b) { return run_vec<1>(
 
 int dev_axpby(ofdft_ctx* c, double* y, double a, const double* x, double b) {
   return run_vec<0>(c, OpAxpby{y, x, a, b});
+}
+
+int dev_combine3(ofdft_ctx* c, double* dst, double c0, const double* x0, double c1, const double* x1, double c2,
+                 const double* x2) {
+  return run_vec<1>(c, OpCombine3{dst, x0, x1, c2 != 0.0 ? x2 : nullptr, c0, c1, c2});
 }
 
 int dev_tn_hess_finish(ofdft_ctx* c, double* hs, const double* phi, const double* s, double inv2e, double mu_term) {

@@ -108,3 +108,39 @@ def test_fft_tiles_do_not_change_results(precision, functional):
     rep, v = ctx.eval(potential=True)
     assert rel(rep.F_total, ev.F_tot) <= tol_e, tiles
     assert np.sqrt(np.mean((v - ev.v) ** 2)) / np.sqrt(np.mean(ev.v ** 2)) <= tol_v, tiles
+
+
+@pytest.mark.parametrize("precision,functional,shape", [
+    ("fp64", "VT84F", (16, 24, 24)), ("mixed", "VT84F", (12, 48, 48)), ("fp64", "TF", (8, 32, 32)),
+    ("mixed", "SGA", (8, 96, 96)), ("mixed", "VT84F", (8, 128, 128)), ("fp64", "VT84F", (8, 128, 128)),
+])
+def test_plane_passes_match_row_passes(precision, functional, shape, monkeypatch):
+    """Square (i2, i3) planes up to 128 run the x3 and x2 transforms as one plane pass
+    per i1; with it switched off (row passes and a separate x2 pass) the evaluation, a
+    line-search trial and the forces agree, and the oracle pins the plane path."""
+    cell = wl.h_cell(4, 1.0, shape, 5e4, seed=606)
+    ctx, sysm = make_pair(cell, functional, precision=precision)
+    monkeypatch.setenv("OFDFT_PLANE_PASSES", "0")
+    ctx_row, _ = make_pair(cell, functional, precision=precision)
+    monkeypatch.delenv("OFDFT_PLANE_PASSES")
+    phi = normalized_phi(sysm, seed=12, contrast=0.6)
+    tol_f, tol_v = (1e-12, 1e-11) if precision == "fp64" else (1e-6, 1e-5)
+    ctx.set_density(phi)
+    ctx_row.set_density(phi)
+    rep, v = ctx.eval(potential=True)
+    rep_r, v_r = ctx_row.eval(potential=True)
+    for a, _ in COMPONENTS:
+        got, ref = getattr(rep, a), getattr(rep_r, a)
+        assert abs(got - ref) <= tol_f * max(abs(ref), 1e-3 * abs(rep_r.F_total)), (a, got, ref)
+    assert np.max(np.abs(v - v_r)) <= tol_v * np.max(np.abs(v_r))
+    if shape[1] <= 48:
+        ev = oracle.evaluate(phi, sysm)
+        assert rel(rep.F_total, ev.F_tot) <= (1e-10 if precision == "fp64" else 1e-6)
+        assert np.sqrt(np.mean((v - ev.v) ** 2)) / np.sqrt(np.mean(ev.v ** 2)) <= tol_v * 10
+    # a minimisation (line-search trials, preconditioned directions) and the forces
+    r1 = ctx.minimize_density()
+    r2 = ctx_row.minimize_density()
+    assert abs(r1.F_total - r2.F_total) <= (1e-9 if precision == "fp64" else 1e-5) * abs(r2.F_total)
+    _, _, f1 = ctx.free_energy_and_forces()
+    _, _, f2 = ctx_row.free_energy_and_forces()
+    assert np.max(np.abs(f1 - f2)) <= (1e-6 if precision == "fp64" else 1e-4)
