@@ -96,7 +96,11 @@ int fill_report(ofdft_ctx* c, const double* h, double resid, ofdft_report* rep, 
 }
 
 // Line search along the rotation phi(theta) = ca phi + sb d (ca, sb from theta).
-// On success the accepted state is in phi_t / v_t / scalars_t.
+// On success the accepted state is in phi_t / v_t / scalars_t.  Trials alternate
+// between two buffers so that the best one so far is kept while the next is
+// evaluated (no re-evaluation when an earlier trial wins).  pre, when given, holds
+// the scalars of a first trial at theta1 already evaluated into phi_t / v_t /
+// scalars_t.
 struct LS {
   double theta;
   double F;
@@ -104,12 +108,23 @@ struct LS {
 };
 
 int line_search(ofdft_ctx* c, double F0, double dF0, double r, double phinorm, double dn, double theta1,
-                int& nevals, LS& out) {
+                int& nevals, LS& out, const double* pre = nullptr) {
   const double ratio = r / phinorm;   // renormalises phi to the exact sphere
   double lo = 0.0, dlo = dF0, hi = -1.0, dhi = 0.0;
   double theta = theta1;
   double best_theta = -1.0, best_F = F0;
-  double last_theta = -1.0;
+  int cur = 0, best_buf = -1;
+  double* tphi[2] = {c->phi_t, c->phi_t2};
+  void* tv[2] = {c->v_t, c->v_t2};
+  double* tsc[2] = {c->scalars_t, c->scalars_t2};
+  // leave the chosen trial in phi_t / v_t / scalars_t
+  auto select = [&](int b) {
+    if (b == 1) {
+      std::swap(c->phi_t, c->phi_t2);
+      std::swap(c->v_t, c->v_t2);
+      std::swap(c->scalars_t, c->scalars_t2);
+    }
+  };
   // In the mixed path F and dF/dtheta carry FP32 noise, so near convergence the
   // slope test can fail at random: after three trials a point with sufficient
   // decrease is taken, and the search gives up after eight.
@@ -117,28 +132,34 @@ int line_search(ofdft_ctx* c, double F0, double dF0, double r, double phinorm, d
   const int max_trials = mixed ? 8 : 14;
   bool best_armijo = false;
   for (int trial = 0; trial < max_trials; ++trial) {
-    const double ct = std::cos(theta), st = std::sin(theta);
-    // phi_t = rotation of phi toward d, its evaluation and dF/dtheta in one pass sequence
     double h[SC_COUNT];
-    int rc = dev_eval_trial(c, c->phi, c->d, ct * ratio, st * r / dn, c->phi_t, c->v_t, c->scalars_t,
-                            -st * ratio, ct * r / dn, h);
-    if (rc) return rc;
-    ++nevals;
+    if (trial == 0 && pre) {
+      std::copy(pre, pre + SC_COUNT, h);
+    } else {
+      const double ct = std::cos(theta), st = std::sin(theta);
+      // phi_t = rotation of phi toward d, its evaluation and dF/dtheta in one pass sequence
+      int rc = dev_eval_trial(c, c->phi, c->d, ct * ratio, st * r / dn, tphi[cur], tv[cur], tsc[cur],
+                              -st * ratio, ct * r / dn, h);
+      if (rc) return rc;
+      ++nevals;
+    }
     const double dth = h[SC_DOT0];
     const double Ft = h[SC_FTOT];
     if (!is_fin(Ft) || !is_fin(dth)) return fail(c, OFDFT_E_NONFINITE, "non-finite energy in line search");
-    last_theta = theta;
     const bool armijo = Ft <= F0 + 1e-4 * theta * dF0;
+    // once F changes at its rounding level only the slope test can decide
+    const bool flat = Ft <= F0 + 1e-14 * std::fabs(F0);
+    if ((armijo || flat) && std::fabs(dth) <= 0.1 * std::fabs(dF0)) {
+      select(cur);
+      out = {theta, Ft, true};
+      return OFDFT_OK;
+    }
     if (Ft <= F0 && (best_theta < 0 || Ft < best_F)) {
       best_theta = theta;
       best_F = Ft;
       best_armijo = armijo;
-    }
-    // once F changes at its rounding level only the slope test can decide
-    const bool flat = Ft <= F0 + 1e-14 * std::fabs(F0);
-    if ((armijo || flat) && std::fabs(dth) <= 0.1 * std::fabs(dF0)) {
-      out = {theta, Ft, true};
-      return OFDFT_OK;
+      best_buf = cur;
+      cur ^= 1;   // keep this trial; the next one goes to the other buffer
     }
     if (mixed && trial >= 2 && best_armijo) break;
     if (dth > 0.0 || !armijo) {
@@ -163,13 +184,7 @@ int line_search(ofdft_ctx* c, double F0, double dF0, double r, double phinorm, d
     out = {0.0, F0, false};
     return OFDFT_OK;
   }
-  if (best_theta != last_theta) {
-    const double ct = std::cos(best_theta), st = std::sin(best_theta);
-    int rc = dev_eval_trial(c, c->phi, c->d, ct * ratio, st * r / dn, c->phi_t, c->v_t, c->scalars_t,
-                            -st * ratio, ct * r / dn);
-    if (rc) return rc;
-    ++nevals;
-  }
+  select(best_buf);
   out = {best_theta, best_F, true};
   return OFDFT_OK;
 }
@@ -272,11 +287,17 @@ int minimize_cg(ofdft_ctx* c, ofdft_report* rep) {
   bool converged = false;
   double resid = 0.0;
   for (it = 1; it <= c->opt.max_iter; ++it) {
-    // gradient dots, beta and the new direction on the device, then one readback
+    // gradient dots, beta, the new direction and the first trial angle on the device;
+    // that trial is evaluated before anything is read back, so one readback serves both
     const double cproj = have_prev ? std::sin(theta_prev) * dn_prev / r : 0.0;
-    if ((rc = dev_cg_step(c, pcg, have_prev, gg_prev, cproj))) return rc;
-    double hs[SC_COUNT];
-    if ((rc = dev_read(c, c->scalars, SC_COUNT, hs))) return rc;
+    if ((rc = dev_cg_step(c, pcg, have_prev, gg_prev, cproj, Fprev, r))) return rc;
+    double both[2 * SC_COUNT];
+    if ((rc = dev_eval_trial_dev(c, c->phi, c->d, c->scalars + SC_CA, c->phi_t, c->v_t, c->scalars_t, c->scalars,
+                                 both)))
+      return rc;
+    ++nevals;
+    const double* trial0 = both;
+    const double* hs = both + SC_COUNT;
     const double* dots = hs + SC_DOT0;
     p.F = hs[SC_FTOT];
     p.Ne = hs[SC_NE];
@@ -285,14 +306,17 @@ int minimize_cg(ofdft_ctx* c, ofdft_report* rep) {
     const double gg = dots[0];   // g.g, or z.g when preconditioned
     if (gg <= 0.0 || stop_rule(c, small, resid)) { converged = true; break; }
     double dd_dg[2] = {hs[SC_DD], hs[SC_DG]};
-    if (dd_dg[1] >= 0.0) {   // not a descent direction: restart along -g (or -z)
+    bool have_trial0 = true;
+    if (dd_dg[1] >= 0.0) {   // not a descent direction: restart along -g (or -z); the trial is void
       if ((rc = dev_cg_restart(c, pcg))) return rc;
       if ((rc = dev_read(c, c->scalars + SC_DD, 2, dd_dg))) return rc;
+      have_trial0 = false;
     }
     const double dn = std::sqrt(dd_dg[0]);
     const double dF0 = r * dd_dg[1] / dn;
     LS ls;
-    if ((rc = line_search(c, F, dF0, r, std::sqrt(phinorm2), dn, first_step(F, Fprev, have_prev, dF0), nevals, ls)))
+    const double theta1 = have_trial0 ? hs[SC_TH1] : first_step(F, Fprev, have_prev, dF0);
+    if ((rc = line_search(c, F, dF0, r, std::sqrt(phinorm2), dn, theta1, nevals, ls, have_trial0 ? trial0 : nullptr)))
       return rc;
     if (!ls.ok) {
       converged = stalled_converged(c, small, last_dF, F, resid);

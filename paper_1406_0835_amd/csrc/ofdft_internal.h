@@ -17,7 +17,7 @@ enum Slot { SL_PHI2 = 0, SL_FS, SL_TS, SL_EXC, SL_EH, SL_EEXT, SL_NV, SL_DT1, SL
 // Reduced scalars of one evaluation (double[SC_COUNT] on the device).  On the device
 // SC_FTOT is the electronic part of F (E_ion, a constant of the minimisation, is
 // added on the host) and SC_EION is 0.
-constexpr int kMapDoubles = 32;
+constexpr int kMapDoubles = 64;
 enum Scal {
   SC_NE = 0, SC_FS, SC_TS, SC_EXC, SC_EH, SC_EEXT, SC_NV, SC_MU, SC_EAZ, SC_EION, SC_FTOT,
   SC_DOT0 = 11,   // slots 11..15: minimiser dot products written after an evaluation
@@ -25,7 +25,12 @@ enum Scal {
   SC_CZ = 17,
   SC_DD = 18,     // d.d and d.g of the new CG direction
   SC_DG = 19,
-  SC_COUNT = 20
+  SC_TH1 = 20,    // first line-search angle along it and the rotation/slope
+  SC_CA = 21,     // coefficients of that trial: ca, sb, ms, mc (contiguous)
+  SC_SB = 22,
+  SC_MS = 23,
+  SC_MC = 24,
+  SC_COUNT = 25
 };
 
 // Largest tiles the kernels stage through registers: a contiguous-axis tile
@@ -112,6 +117,10 @@ struct ofdft_ctx {
   int max_blocks = 0;
   double* scalars = nullptr;   // current point, double[SC_COUNT]
   double* scalars_t = nullptr; // trial point
+  // a second trial buffer: the line search keeps its best trial while it evaluates the next
+  double* phi_t2 = nullptr;
+  void* v_t2 = nullptr;
+  double* scalars_t2 = nullptr;
   // minimiser vectors
   double* d = nullptr;
   double* gprev = nullptr;
@@ -164,6 +173,10 @@ int dev_eval(ofdft_ctx* c, const double* phi, void* v_out, double* scalars_out, 
 // the density pass, and dF/dtheta = g_t . (ms phi + mc dir) lands in scalars_out[SC_DOT0].
 int dev_eval_trial(ofdft_ctx* c, const double* phi, const double* dir, double ca, double sb, double* phi_out,
                    void* v_out, double* scalars_out, double ms, double mc, double* host = nullptr);
+// The same trial with ca, sb, ms, mc read on the device from coef[0..3]; host receives
+// the trial's scalars followed by extra[0..SC_COUNT) (2 SC_COUNT doubles).
+int dev_eval_trial_dev(ofdft_ctx* c, const double* phi, const double* dir, const double* coef, double* phi_out,
+                       void* v_out, double* scalars_out, const double* extra, double* host);
 int dev_forces(ofdft_ctx* c, double* forces_host);
 // vector operations for the minimisers; results land in c->vout (device)
 // g = 2 dv phi (v - mu): writes g.g, g.gprev, g.d, sum n (v-mu)^2 into out[0..3]
@@ -178,7 +191,10 @@ int dev_cg_direction(ofdft_ctx* c, double beta, double cproj);
 // c_z phi.gprev)) / gg_prev) (0 without have_prev; plain: c_z = 0) into
 // SC_CZ/SC_BETA, and the new direction d = -(z - c_z phi) + beta (d - cproj phi)
 // (gprev = g) with d.d, d.g into SC_DD/SC_DG.
-int dev_cg_step(ofdft_ctx* c, bool pcg, bool have_prev, double gg_prev, double cproj);
+// Also the first line-search angle along d (the rule of first_step with the
+// previous free energy F_prev and the sphere radius r) and that trial's rotation
+// and slope coefficients into SC_TH1, SC_CA..SC_MC.
+int dev_cg_step(ofdft_ctx* c, bool pcg, bool have_prev, double gg_prev, double cproj, double F_prev, double r);
 // The same direction with beta = 0 (after a step that was not a descent direction).
 int dev_cg_restart(ofdft_ctx* c, bool pcg);
 int dev_rotate(ofdft_ctx* c, double* dst, const double* phi, double ca, const double* dir, double sb);

@@ -230,6 +230,9 @@ struct Rotation {
   const double* dir;
   double ca, sb;
   double* phi_out;
+  const double* coef;   // if set, ca and sb are coef[0], coef[1] (device values)
+  __device__ double cos_part() const { return coef ? coef[0] : ca; }
+  __device__ double sin_part() const { return coef ? coef[1] : sb; }
 };
 
 template <typename R, int L, bool ROT>
@@ -253,11 +256,12 @@ __global__ void __launch_bounds__(NT) k_rpass_fwd_density(const double* __restri
   if constexpr (ROT) {
     const size_t off = ((size_t)i1 * g.n2 + i2_0) * L;
     double dv_[MAXU];
+    const double ca = rot.cos_part(), sb = rot.sin_part();
 #pragma unroll
     for (int u = 0; u < MAXU; ++u) dv_[u] = rot.dir[off + tile_elem(u, cnt)];
 #pragma unroll
     for (int u = 0; u < MAXU; ++u) {
-      pv[u] = rot.ca * pv[u] + rot.sb * dv_[u];
+      pv[u] = ca * pv[u] + sb * dv_[u];
       const int e = threadIdx.x + u * NT;
       if (e < cnt) rot.phi_out[off + e] = pv[u];
     }
@@ -703,6 +707,9 @@ struct Slope {
   const double* phi0;
   const double* dir;
   double ms, mc;
+  const double* coef;   // if set, ms and mc are coef[2], coef[3] (device values)
+  __device__ double ms_part() const { return coef ? coef[2] : ms; }
+  __device__ double mc_part() const { return coef ? coef[3] : mc; }
 };
 
 template <typename R, int L, bool TF, bool DT>
@@ -738,8 +745,9 @@ __global__ void __launch_bounds__(NT) k_rpass_final(const cplx<R>* __restrict__ 
       p0[u] = sl.phi0[base + e];
       dd[u] = sl.dir[base + e];
     }
+    const double ms = sl.ms_part(), mc = sl.mc_part();
 #pragma unroll
-    for (int u = 0; u < MAXU; ++u) q[u] = sl.ms * p0[u] + sl.mc * dd[u];
+    for (int u = 0; u < MAXU; ++u) q[u] = ms * p0[u] + mc * dd[u];
   }
   const cplx<R>* res = lds_fft<R, +1, L, NT>(za, zb, tw, tr / 2, threadIdx.x);
   double fs = 0.0, ts = 0.0, exc = 0.0, nv = 0.0, dt1 = 0.0, dt2 = 0.0;
@@ -958,11 +966,12 @@ __global__ void __launch_bounds__(NTP) k_plane_fwd_density(const double* __restr
     for (int u = 0; u < PCH; ++u) pv[u] = phi[base + min(c0 + (int)threadIdx.x + u * NTP, CNT - 1)];
     if constexpr (ROT) {
       double dv_[PCH];
+      const double ca = rot.cos_part(), sb = rot.sin_part();
 #pragma unroll
       for (int u = 0; u < PCH; ++u) dv_[u] = rot.dir[base + min(c0 + (int)threadIdx.x + u * NTP, CNT - 1)];
 #pragma unroll
       for (int u = 0; u < PCH; ++u) {
-        pv[u] = rot.ca * pv[u] + rot.sb * dv_[u];
+        pv[u] = ca * pv[u] + sb * dv_[u];
         const int e = c0 + threadIdx.x + u * NTP;
         if (e < CNT) rot.phi_out[base + e] = pv[u];
       }
@@ -1117,8 +1126,9 @@ __global__ void __launch_bounds__(NTP) k_plane_final(const cplx<R>* __restrict__
         p0[u] = sl.phi0[base + e];
         dd[u] = sl.dir[base + e];
       }
+      const double ms = sl.ms_part(), mc = sl.mc_part();
 #pragma unroll
-      for (int u = 0; u < CH; ++u) q[u] = sl.ms * p0[u] + sl.mc * dd[u];
+      for (int u = 0; u < CH; ++u) q[u] = ms * p0[u] + mc * dd[u];
     }
 #pragma unroll
     for (int u = 0; u < CH; ++u) {
@@ -1191,6 +1201,8 @@ struct Publish {
   double* dst;
   unsigned long long* flag;
   unsigned long long seq;
+  const double* extra;   // also extra[0..n_extra) after the kernel's own values
+  int n_extra;
 };
 
 // Store vals[0..n) into the host buffer and raise its sequence word.  Called by
@@ -1198,6 +1210,7 @@ struct Publish {
 // after the wavefront's data stores.
 __device__ __forceinline__ void publish(const Publish& pub, const double* vals, int n, int lane) {
   for (int k = lane; k < n; k += 64) pub.dst[k] = vals[k];
+  for (int k = lane; k < pub.n_extra; k += 64) pub.dst[n + k] = pub.extra[k];
   __threadfence_system();
   if (lane == 0) __hip_atomic_store(pub.flag, pub.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
@@ -1313,6 +1326,44 @@ __global__ void __launch_bounds__(NT) k_cg_dots_final(const double* __restrict__
     }
     sc[SC_BETA] = beta;
     sc[SC_CZ] = cz;
+  }
+}
+
+// Direction dots d.d, d.g of a CG step, then the first line-search angle along d
+// and its rotation/slope coefficients: theta = 2 (F_prev - F) / (-dF0) clamped to
+// [1e-6, 0.3] when a previous step decreased F, else 0.05 (dF0 = r d.g / |d|).
+struct TrialCoef {
+  double F_prev;
+  int have_prev;
+  double r, dv;
+};
+
+__global__ void __launch_bounds__(NT) k_dir_final(const double* __restrict__ part, int nb, double* __restrict__ sc,
+                                                  TrialCoef tc) {
+  __shared__ double red[NT / 64];
+  double dots[2];
+  for (int k = 0; k < 2; ++k) {
+    double a = 0.0;
+    for (int i = threadIdx.x; i < nb; i += NT) a += part[k * nb + i];
+    double v[1] = {a};
+    block_sum<1>(v, red);
+    dots[k] = v[0];
+  }
+  if (threadIdx.x == 0) {
+    sc[SC_DD] = dots[0];
+    sc[SC_DG] = dots[1];
+    const double dn = sqrt(dots[0]);
+    const double dF0 = tc.r * dots[1] / dn;
+    const double F = sc[SC_FTOT];
+    double th = 0.05;
+    if (tc.have_prev && dF0 < 0.0 && tc.F_prev > F) th = fmin(fmax(2.0 * (tc.F_prev - F) / (-dF0), 1e-6), 0.3);
+    const double ratio = tc.r / sqrt(sc[SC_NE] / tc.dv);
+    const double ct = cos(th), st = sin(th);
+    sc[SC_TH1] = th;
+    sc[SC_CA] = ct * ratio;
+    sc[SC_SB] = st * tc.r / dn;
+    sc[SC_MS] = -st * ratio;
+    sc[SC_MC] = ct * tc.r / dn;
   }
 }
 
@@ -1564,13 +1615,16 @@ __global__ void __launch_bounds__(NT) k_forces(int nat, const double* __restrict
   }
 }
 
+// One wavefront per force component: lanes stride over its block partials, then
+// a fixed-order wave sum (k is uniform across a wavefront, so whole waves exit).
 __global__ void __launch_bounds__(NT) k_forces_final(int nat, const double* __restrict__ part, int nb, double scale,
                                                      double* __restrict__ out) {
-  const int k = blockIdx.x * NT + threadIdx.x;
+  const int k = blockIdx.x * (NT / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (k >= 3 * nat) return;
   double s = 0.0;
-  for (int i = 0; i < nb; ++i) s += part[(size_t)k * nb + i];
-  out[k] = scale * s;
+  for (int i = lane; i < nb; i += 64) s += part[(size_t)k * nb + i];
+  s = wave_sum(s);
+  if (lane == 0) out[k] = scale * s;
 }
 
 // ---------------------------------------------------------------- host side
@@ -2035,6 +2089,19 @@ int dev_eval(ofdft_ctx* c, const double* phi, void* v_out, double* sc, double* h
   return wait_published(c, pub.seq, SC_COUNT, host);
 }
 
+int dev_eval_trial_dev(ofdft_ctx* c, const double* phi, const double* dir, const double* coef, double* phi_out,
+                       void* v_out, double* sc, const double* extra, double* host) {
+  const Rotation rot{dir, 0.0, 0.0, phi_out, coef};
+  const Slope sl{phi, dir, 0.0, 0.0, coef};
+  Publish pub = next_publish(c);
+  pub.extra = extra;
+  pub.n_extra = SC_COUNT;
+  int rc = c->rsize == 4 ? eval_impl<float>(c, phi, v_out, sc, &rot, &sl, pub)
+                         : eval_impl<double>(c, phi, v_out, sc, &rot, &sl, pub);
+  if (rc) return rc;
+  return wait_published(c, pub.seq, 2 * SC_COUNT, host);
+}
+
 int dev_eval_trial(ofdft_ctx* c, const double* phi, const double* dir, double ca, double sb, double* phi_out,
                    void* v_out, double* sc, double ms, double mc, double* host) {
   const Rotation rot{dir, ca, sb, phi_out};
@@ -2145,6 +2212,7 @@ int dev_alloc_grid(ofdft_ctx* c) {
   bool ok = dalloc(c, &c->phi, N) && dalloc(c, &c->phi_t, N) && dalloc(c, &c->d, N) && dalloc(c, &c->gprev, N);
   for (int k = 0; k < 4 && ok; ++k) ok = dalloc(c, &c->tn[k], N);
   ok = ok && dalloc_bytes(c, &c->v, N * rs) && dalloc_bytes(c, &c->v_t, N * rs) && dalloc_bytes(c, &c->vloc, N * rs);
+  ok = ok && dalloc(c, &c->phi_t2, N) && dalloc_bytes(c, &c->v_t2, N * rs);
   ok = ok && dalloc_bytes(c, &c->A, NS * 2 * rs) && dalloc_bytes(c, &c->S0, NS * 2 * rs) &&
        dalloc_bytes(c, &c->D, NS * 2 * rs) && dalloc_bytes(c, &c->Vext, NS * 2 * rs);
   for (int k = 0; k < 3 && ok; ++k) ok = dalloc_bytes(c, &c->B[k], NS * 2 * rs);
@@ -2153,7 +2221,7 @@ int dev_alloc_grid(ofdft_ctx* c) {
   c->max_blocks = std::max(std::max(nb_r, nb_x1), PW_BLOCKS);
   for (int k = 0; k < 3 && ok; ++k) ok = dalloc_bytes(c, &c->gr[k], N * rs);
   ok = ok && dalloc(c, &c->partials, (size_t)SL_COUNT * c->max_blocks) && dalloc(c, &c->scalars, SC_COUNT) &&
-       dalloc(c, &c->scalars_t, SC_COUNT) && dalloc(c, &c->vpart, 8 * VEC_BLOCKS) && dalloc(c, &c->vout, 16);
+       dalloc(c, &c->scalars_t, SC_COUNT) && dalloc(c, &c->scalars_t2, SC_COUNT) && dalloc(c, &c->vpart, 8 * VEC_BLOCKS) && dalloc(c, &c->vout, 16);
   if (ok && !c->hmap) {
     ok = hip_ok(c, hipHostMalloc((void**)&c->hmap, (kMapDoubles + 1) * sizeof(double),
                                  hipHostMallocMapped | hipHostMallocCoherent), "hipHostMalloc (mapped)");
@@ -2184,7 +2252,8 @@ void dev_free_grid(ofdft_ctx* c) {
                  &c->S0, &c->D, &c->Vext, &c->B[0], &c->B[1], &c->B[2], &c->tw[0], &c->tw[1], &c->tw[2],
                  (void**)&c->partials, (void**)&c->scalars, (void**)&c->scalars_t, (void**)&c->vpart,
                  (void**)&c->vout, &c->gr[0], &c->gr[1], &c->gr[2], (void**)&c->phi_hist[0],
-                 (void**)&c->phi_hist[1], (void**)&c->phi_hist[2]};
+                 (void**)&c->phi_hist[1], (void**)&c->phi_hist[2], (void**)&c->phi_t2, &c->v_t2,
+                 (void**)&c->scalars_t2};
   for (void** p : ps) {
     if (*p) (void)hipFree(*p);
     *p = nullptr;
@@ -2265,12 +2334,13 @@ static int forces_impl(ofdft_ctx* c, double* out_host) {
     OFDFT_DISPATCH(g.n2, (launch_x2<R, L_, -1>(c, c->A, nullptr, nullptr, 1)));
   }
   OFDFT_DISPATCH(g.n1, (launch_x1_density<R, L_, X1_NHAT>(c, c->A, c->D, nullptr, nullptr)));
-  const int nbx = 1024;
+  // about sixteen G vectors per thread, so the per-block reduction stays a small share
+  const int nbx = (int)std::min<long long>(1024, std::max<long long>(1, g.NS / (16LL * NT)));
   const int nby = (c->nat + FORCE_IONS - 1) / FORCE_IONS;
   hipLaunchKernelGGL(k_forces<R>, dim3(nbx, nby), dim3(NT), 0, c->stream, c->nat, c->dZ, (const double2*)c->phase,
                      (const cplx<R>*)c->D, g, lpp_of(c), c->fpart);
-  hipLaunchKernelGGL(k_forces_final, dim3((3 * c->nat + NT - 1) / NT), dim3(NT), 0, c->stream, c->nat, c->fpart,
-                     nbx, -g.volume, c->dforces);
+  hipLaunchKernelGGL(k_forces_final, dim3((3 * c->nat + NT / 64 - 1) / (NT / 64)), dim3(NT), 0, c->stream, c->nat,
+                     c->fpart, nbx, -g.volume, c->dforces);
   if (!hip_ok(c, hipMemcpyAsync(out_host, c->dforces, 3 * (size_t)c->nat * sizeof(double), hipMemcpyDeviceToHost,
                                 c->stream),
               "forces copy"))
@@ -2325,8 +2395,18 @@ static int run_cg_dots(ofdft_ctx* c, const Op& op, const CgCoef& cf) {
   return hip_ok(c, hipGetLastError(), "CG dots") ? OFDFT_OK : OFDFT_E_DEVICE;
 }
 
+// The direction pass of a CG step: d, gprev and its dots reduced by k_dir_final.
+template <class Op>
+static int run_direction(ofdft_ctx* c, const Op& op, const TrialCoef& tc) {
+  hipLaunchKernelGGL((k_vec<2, Op>), dim3(VEC_BLOCKS), dim3(NT), 0, c->stream, c->g.N, op, c->vpart);
+  hipLaunchKernelGGL(k_dir_final, dim3(1), dim3(NT), 0, c->stream, c->vpart, VEC_BLOCKS, c->scalars, tc);
+  return hip_ok(c, hipGetLastError(), "CG direction") ? OFDFT_OK : OFDFT_E_DEVICE;
+}
+
 template <typename R>
-static int cg_step_impl(ofdft_ctx* c, bool pcg, bool have_prev, double gg_prev, double cproj) {
+static int cg_step_impl(ofdft_ctx* c, bool pcg, bool have_prev, double gg_prev, double cproj, double F_prev,
+                        double r) {
+  const TrialCoef tc{F_prev, have_prev ? 1 : 0, r, c->g.dv};
   const GridDesc& g = c->g;
   const double two_dv = 2.0 * g.dv;
   const double* phi = c->phi;
@@ -2352,18 +2432,17 @@ static int cg_step_impl(ofdft_ctx* c, bool pcg, bool have_prev, double gg_prev, 
 
     rc = run_cg_dots<5>(c, OpPrecDots<R>{phi, v, (const R*)c->gr[0], c->scalars, gprev, two_dv}, cf);
     if (rc) return rc;
-    return run_vec<2>(c, OpPrecDirection<R>{phi, v, (const R*)c->gr[0], c->scalars, c->gprev, c->d, two_dv, cproj, 0},
-                      c->scalars + SC_DD);
+    return run_direction(c, OpPrecDirection<R>{phi, v, (const R*)c->gr[0], c->scalars, c->gprev, c->d, two_dv, cproj, 0},
+                         tc);
   }
   rc = run_cg_dots<4>(c, OpGradDots<R>{phi, v, c->scalars, gprev, have_prev ? c->d : nullptr, two_dv}, cf);
   if (rc) return rc;
-  return run_vec<2>(c, OpDirection<R>{phi, v, c->scalars, c->gprev, c->d, two_dv, 0.0, cproj, 1},
-                    c->scalars + SC_DD);
+  return run_direction(c, OpDirection<R>{phi, v, c->scalars, c->gprev, c->d, two_dv, 0.0, cproj, 1}, tc);
 }
 
-int dev_cg_step(ofdft_ctx* c, bool pcg, bool have_prev, double gg_prev, double cproj) {
-  return c->rsize == 4 ? cg_step_impl<float>(c, pcg, have_prev, gg_prev, cproj)
-                       : cg_step_impl<double>(c, pcg, have_prev, gg_prev, cproj);
+int dev_cg_step(ofdft_ctx* c, bool pcg, bool have_prev, double gg_prev, double cproj, double F_prev, double r) {
+  return c->rsize == 4 ? cg_step_impl<float>(c, pcg, have_prev, gg_prev, cproj, F_prev, r)
+                       : cg_step_impl<double>(c, pcg, have_prev, gg_prev, cproj, F_prev, r);
 }
 
 template <typename R>

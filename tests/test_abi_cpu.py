@@ -119,3 +119,12 @@ def test_no_device_is_reported_not_faked(lib):
     assert lib.ofdft_create(ctypes.byref(o), ctypes.byref(h)) == B.E_DEVICE
     with pytest.raises(B.OFDFTError):
         B.Context()
+
+
+def test_extrapolate_option_is_validated(lib):
+    o = B.default_options(extrapolate=3)
+    h = ctypes.c_void_p()
+    rc = lib.ofdft_create(ctypes.byref(o), ctypes.byref(h))
+    assert rc == B.E_ARG
+    assert b"extrapolate" in lib.ofdft_last_error(None)
+    assert B.default_options().extrapolate == 0

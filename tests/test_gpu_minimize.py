@@ -180,3 +180,33 @@ def test_warm_start_and_state_machine():
     assert warm.evaluations < cold.evaluations
     F, E, f = ctx.free_energy_and_forces()
     assert np.all(np.isfinite(f))
+
+
+def test_extrapolated_warm_start_reaches_the_same_minimum():
+    """options.extrapolate changes only the starting amplitude of an ionic step: along a
+    straight ion trajectory, linear and quadratic extrapolation reach the minimum the
+    plain warm start reaches, and set_density clears the history."""
+    cell = wl.h_cell(6, 1.0, (24, 24, 24), 5e4, seed=704)
+    rng = np.random.default_rng(704)
+    step = rng.normal(0.0, 0.05, cell.positions.shape)
+    ctxs = []
+    for ext in (0, 1, 2):
+        c = B.Context(B.default_options(functional="VT84F", precision="fp64", tol_energy=1e-11, max_iter=2000,
+                                        extrapolate=ext))
+        c.set_cell(cell.lattice, cell.grid)
+        c.set_ions(cell.positions, cell.charges)
+        c.set_temperature(cell.temperature_K)
+        ctxs.append(c)
+    for k in range(5):
+        x = cell.positions + k * step
+        F = []
+        for c in ctxs:
+            c.set_ions(x, cell.charges)
+            F.append(c.minimize_density().F_total)
+        assert abs(F[1] - F[0]) <= 1e-9 * abs(F[0]), (k, F)
+        assert abs(F[2] - F[0]) <= 1e-9 * abs(F[0]), (k, F)
+    # an explicit density restarts the history: the next step is a plain warm start again
+    phi = ctxs[1].get_density()
+    ctxs[1].set_density(phi)
+    ctxs[1].set_ions(cell.positions + 5 * step, cell.charges)
+    assert np.allclose(ctxs[1].get_density(), phi, rtol=1e-13, atol=0.0)
