@@ -36,7 +36,7 @@ VALU_PEAK_TFLOPS = 78.6
 # T_2..T_21: 40; 8 series of 22 terms: 336; energy sums: 2) + FP32 151 (density powers and
 # s^2: 16; two VT84F enhancement factors: 64; f, df/dn, df/dsigma, T s: 37; PZ81: 24; W and
 # v_loc: 5; sums: 5).
-POINTWISE_GGA_FLOP_PER_POINT = 534
+POINTWISE_GGA_FLOP_PER_POINT = 390
 WORKLOAD = "1024 H, 4.0 g/cm^3, 128^3 grid, T=100 kK, VT84F+PZ81 ftGGA, Gaussian LPP rc=0.5"
 
 

@@ -192,9 +192,11 @@ int dev_cg_direction(ofdft_ctx* c, double beta, double cproj);
 // SC_CZ/SC_BETA, and the new direction d = -(z - c_z phi) + beta (d - cproj phi)
 // (gprev = g) with d.d, d.g into SC_DD/SC_DG.
 // Also the first line-search angle along d (the rule of first_step with the
-// previous free energy F_prev and the sphere radius r) and that trial's rotation
-// and slope coefficients into SC_TH1, SC_CA..SC_MC.
-int dev_cg_step(ofdft_ctx* c, bool pcg, bool have_prev, double gg_prev, double cproj, double F_prev, double r);
+// previous free energy F_prev, the previous curvature kappa (0: none) and the
+// sphere radius r) and that trial's rotation and slope coefficients into SC_TH1,
+// SC_CA..SC_MC.
+int dev_cg_step(ofdft_ctx* c, bool pcg, bool have_prev, double gg_prev, double cproj, double F_prev, double r,
+                double kappa);
 // The same direction with beta = 0 (after a step that was not a descent direction).
 int dev_cg_restart(ofdft_ctx* c, bool pcg);
 int dev_rotate(ofdft_ctx* c, double* dst, const double* phi, double ca, const double* dir, double sb);

@@ -4,24 +4,27 @@
 // is a fixed sequence of fused passes over a real grid [N1][N2][N3] and its
 // transposed half spectrum S[k3][k1][k2] (k3 = 0..N3/2 slowest):
 //
-//   rpass_fwd_density   n = phi^2, real FFT along x3 (two rows per complex
-//                       row), transposed store; sum phi^2
-//   cpass x2            FFT along x2: contiguous rows of the transposed layout
+//   plane_fwd_density   n = phi^2, real FFT along x3 (two rows per complex
+//                       row) and FFT along x2 of one i1 plane in LDS,
+//                       transposed store; sum phi^2
 //   x1_density_*        FFT along x1 on column tiles, then in reciprocal space:
 //                       Hartree (Eq. E2) and pseudopotential energies, the
 //                       potential 4 pi n/G^2 + v_ext(G), and for gradient
 //                       functionals i G_a n(G) (Eq. s_0defn), inverse x1 FFT
-//   cpass x2 (inverse)
-//   rpass_inv_grad3     inverse x3 FFT of the three components of grad n
+//   plane_inv_grad3     inverse x2 and x3 FFTs of the three components of grad n
 //   pointwise_gga       ftGGA + PZ81 at every point (Eqs. FGGA..vftGGA),
 //                       W = 2 df/dsigma grad n
-//   rpass_fwd_w3        forward x3 FFT of W
-//   cpass x2, x1_divergence   S = v_H + v_ext - i G.W(G) (last line of
-//                       Eq. vftGGA in reciprocal space), inverse x1 FFT
-//   cpass x2 (inverse)
-//   rpass_final         inverse x3 FFT, v = df/dn + v_xc + S + alpha, sum n v
-//   reduce_scalars      fixed-order sums of the per-block partials (FP64)
+//   plane_fwd_w3        forward x3 and x2 FFTs of W
+//   x1_divergence       S = v_H + v_ext - i G.W(G) (last line of Eq. vftGGA
+//                       in reciprocal space), inverse x1 FFT
+//   plane_final         inverse x2 and x3 FFTs, v = df/dn + v_xc + S + alpha,
+//                       sum n v
+//   reduce_scalars      fixed-order sums of the per-block partials (FP64),
+//                       published to host memory when asked
 //
+// Grids whose (i2, i3) planes are not square or exceed 128 use row passes
+// (x3 only: rpass_*) with a separate x2 pass (cpass_x2) instead of the plane
+// passes.
 // Reciprocal-space operators act on the G set without Nyquist components
 // (closed under G -> -G), so the potential is the exact gradient of the
 // discrete energy.  All energy and dot-product sums are FP64 wave-shuffle +
@@ -699,6 +702,81 @@ __global__ void __launch_bounds__(NT) k_x1_divergence(const cplx<R>* __restrict_
   store_x1_tile<R, L, U>(o, out + tile0, off, tc, tcl, cnt);
 }
 
+// ---------------------------------------------------------------- scalar reduction
+struct ReduceParams {
+  int nb_r, nb_x1;   // partial counts of the density/final passes and the x1 pass
+  int nb_fs;         // partial count of the free-energy slots (pointwise kernel or final pass)
+  int trial;         // 1: also dF/dtheta of a line-search trial into SC_DOT0
+  double dv, volume, alpha_sum;
+};
+
+// Destination of a device-written readback: dst[0..n) and then the sequence
+// word flag = seq, both in fine-grained host memory (dst == nullptr: none).
+struct Publish {
+  double* dst;
+  unsigned long long* flag;
+  unsigned long long seq;
+  const double* extra;   // also extra[0..n_extra) after the kernel's own values
+  int n_extra;
+};
+
+// Store vals[0..n) into the host buffer and raise its sequence word.  Called by
+// lanes of one wavefront only; the system-scope release on the flag orders it
+// after the wavefront's data stores.
+__device__ __forceinline__ void publish(const Publish& pub, const double* vals, int n, int lane) {
+  for (int k = lane; k < n; k += 64) pub.dst[k] = vals[k];
+  for (int k = lane; k < pub.n_extra; k += 64) pub.dst[n + k] = pub.extra[k];
+  __threadfence_system();
+  if (lane == 0) __hip_atomic_store(pub.flag, pub.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// The evaluation's scalars from the per-block partials: each wavefront of the
+// NTH-thread block sums whole slots in a fixed order (eight accumulators per
+// lane, then the wave sum), thread 0 forms the energies, mu and dF/dtheta.
+// raw: LDS of SL_COUNT doubles, out: LDS of SC_COUNT doubles.
+template <int NTH>
+__device__ __forceinline__ void reduce_scalars(const double* __restrict__ partials, int maxb, const ReduceParams& rp,
+                                               double* __restrict__ sc, const Publish& pub, double* raw,
+                                               double* out) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int s = w; s < SL_COUNT; s += NTH / 64) {
+    const int cnt = (s == SL_EH || s == SL_EEXT) ? rp.nb_x1
+                    : (s == SL_FS || s == SL_TS || s == SL_EXC) ? rp.nb_fs
+                    : (s == SL_DT1 || s == SL_DT2) ? (rp.trial ? rp.nb_r : 0) : rp.nb_r;
+    const double* ps = partials + (size_t)s * maxb;
+    double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int i = lane;
+    for (; i + 7 * 64 < cnt; i += 8 * 64) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u] += ps[i + u * 64];
+    }
+    for (; i < cnt; i += 64) a[0] += ps[i];
+    double acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    acc = wave_sum(acc);
+    if (lane == 0) raw[s] = acc;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double Ne = rp.dv * raw[SL_PHI2];
+    out[SC_NE] = Ne;
+    out[SC_FS] = rp.dv * raw[SL_FS];
+    out[SC_TS] = rp.dv * raw[SL_TS];
+    out[SC_EXC] = rp.dv * raw[SL_EXC];
+    out[SC_EH] = 0.5 * rp.volume * raw[SL_EH];
+    out[SC_EEXT] = rp.volume * raw[SL_EEXT];
+    out[SC_NV] = rp.dv * raw[SL_NV];
+    out[SC_MU] = raw[SL_NV] / raw[SL_PHI2];
+    out[SC_EAZ] = Ne * rp.alpha_sum;
+    out[SC_EION] = 0.0;
+    out[SC_FTOT] = out[SC_FS] + out[SC_EXC] + out[SC_EH] + out[SC_EEXT] + out[SC_EAZ];
+    for (int k = SC_FTOT + 1; k < SC_COUNT; ++k) out[k] = 0.0;   // dot slots cleared
+    if (rp.trial) out[SC_DOT0] = 2.0 * rp.dv * (raw[SL_DT1] - out[SC_MU] * raw[SL_DT2]);
+  }
+  __syncthreads();
+  if (threadIdx.x < SC_COUNT) sc[threadIdx.x] = out[threadIdx.x];
+  if (pub.dst && threadIdx.x < 64) publish(pub, out, SC_COUNT, threadIdx.x);
+}
+
 // ---------------------------------------------------------------- K6: final potential
 // DT: a line-search trial also accumulates sum phi_t v_t q and sum phi_t q with
 // q = ms phi0 + mc dir (phi0 the point the trial rotates from), the two pieces of
@@ -1186,75 +1264,13 @@ __global__ void __launch_bounds__(NTP) k_plane_final(const cplx<R>* __restrict__
 }
 
 // ---------------------------------------------------------------- K7: scalar reduction
-struct ReduceParams {
-  int nb_r, nb_x1;   // partial counts of the row-pass and x1-pass kernels
-  int nb_fs;         // partial count of the free-energy slots (pointwise kernel or row pass)
-  int trial;         // 1: also dF/dtheta of a line-search trial into SC_DOT0
-  double dv, volume, alpha_sum;
-};
-
 constexpr int RED_NT = 64 * SL_COUNT;   // one wavefront per slot
-
-// Destination of a device-written readback: dst[0..n) and then the sequence
-// word flag = seq, both in fine-grained host memory (dst == nullptr: none).
-struct Publish {
-  double* dst;
-  unsigned long long* flag;
-  unsigned long long seq;
-  const double* extra;   // also extra[0..n_extra) after the kernel's own values
-  int n_extra;
-};
-
-// Store vals[0..n) into the host buffer and raise its sequence word.  Called by
-// lanes of one wavefront only; the system-scope release on the flag orders it
-// after the wavefront's data stores.
-__device__ __forceinline__ void publish(const Publish& pub, const double* vals, int n, int lane) {
-  for (int k = lane; k < n; k += 64) pub.dst[k] = vals[k];
-  for (int k = lane; k < pub.n_extra; k += 64) pub.dst[n + k] = pub.extra[k];
-  __threadfence_system();
-  if (lane == 0) __hip_atomic_store(pub.flag, pub.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-}
 
 __global__ void __launch_bounds__(RED_NT) k_reduce_scalars(const double* __restrict__ partials, int maxb,
                                                            ReduceParams rp, double* __restrict__ sc, Publish pub) {
   __shared__ double raw[SL_COUNT];
   __shared__ double out[SC_COUNT];
-  const int s = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int cnt = (s == SL_EH || s == SL_EEXT) ? rp.nb_x1
-                  : (s == SL_FS || s == SL_TS || s == SL_EXC) ? rp.nb_fs
-                  : (s == SL_DT1 || s == SL_DT2) ? (rp.trial ? rp.nb_r : 0) : rp.nb_r;
-  // eight independent accumulators keep eight loads in flight per lane
-  const double* ps = partials + (size_t)s * maxb;
-  double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  int i = lane;
-  for (; i + 7 * 64 < cnt; i += 8 * 64) {
-#pragma unroll
-    for (int u = 0; u < 8; ++u) a[u] += ps[i + u * 64];
-  }
-  for (; i < cnt; i += 64) a[0] += ps[i];
-  double acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
-  acc = wave_sum(acc);
-  if (lane == 0) raw[s] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const double Ne = rp.dv * raw[SL_PHI2];
-    out[SC_NE] = Ne;
-    out[SC_FS] = rp.dv * raw[SL_FS];
-    out[SC_TS] = rp.dv * raw[SL_TS];
-    out[SC_EXC] = rp.dv * raw[SL_EXC];
-    out[SC_EH] = 0.5 * rp.volume * raw[SL_EH];
-    out[SC_EEXT] = rp.volume * raw[SL_EEXT];
-    out[SC_NV] = rp.dv * raw[SL_NV];
-    out[SC_MU] = raw[SL_NV] / raw[SL_PHI2];
-    out[SC_EAZ] = Ne * rp.alpha_sum;
-    out[SC_EION] = 0.0;
-    out[SC_FTOT] = out[SC_FS] + out[SC_EXC] + out[SC_EH] + out[SC_EEXT] + out[SC_EAZ];
-    for (int k = SC_FTOT + 1; k < SC_COUNT; ++k) out[k] = 0.0;   // dot slots cleared
-    if (rp.trial) out[SC_DOT0] = 2.0 * rp.dv * (raw[SL_DT1] - out[SC_MU] * raw[SL_DT2]);
-  }
-  __syncthreads();
-  if (threadIdx.x < SC_COUNT) sc[threadIdx.x] = out[threadIdx.x];
-  if (pub.dst && threadIdx.x < 64) publish(pub, out, SC_COUNT, threadIdx.x);
+  reduce_scalars<RED_NT>(partials, maxb, rp, sc, pub, raw, out);
 }
 
 // Generic small readback (dev_read): one wavefront.
@@ -1330,12 +1346,14 @@ __global__ void __launch_bounds__(NT) k_cg_dots_final(const double* __restrict__
 }
 
 // Direction dots d.d, d.g of a CG step, then the first line-search angle along d
-// and its rotation/slope coefficients: theta = 2 (F_prev - F) / (-dF0) clamped to
-// [1e-6, 0.3] when a previous step decreased F, else 0.05 (dF0 = r d.g / |d|).
+// and its rotation/slope coefficients (dF0 = r d.g / |d|): theta = -dF0 / kappa with
+// kappa the curvature d2F/dtheta2 measured by the previous line search, else
+// 2 (F_prev - F) / (-dF0) when a previous step decreased F, clamped to [1e-6, 0.3];
+// 0.05 without either.
 struct TrialCoef {
   double F_prev;
   int have_prev;
-  double r, dv;
+  double r, dv, kappa;
 };
 
 __global__ void __launch_bounds__(NT) k_dir_final(const double* __restrict__ part, int nb, double* __restrict__ sc,
@@ -1356,7 +1374,8 @@ __global__ void __launch_bounds__(NT) k_dir_final(const double* __restrict__ par
     const double dF0 = tc.r * dots[1] / dn;
     const double F = sc[SC_FTOT];
     double th = 0.05;
-    if (tc.have_prev && dF0 < 0.0 && tc.F_prev > F) th = fmin(fmax(2.0 * (tc.F_prev - F) / (-dF0), 1e-6), 0.3);
+    if (tc.kappa > 0.0 && dF0 < 0.0) th = fmin(fmax(-dF0 / tc.kappa, 1e-6), 0.3);
+    else if (tc.have_prev && dF0 < 0.0 && tc.F_prev > F) th = fmin(fmax(2.0 * (tc.F_prev - F) / (-dF0), 1e-6), 0.3);
     const double ratio = tc.r / sqrt(sc[SC_NE] / tc.dv);
     const double ct = cos(th), st = sin(th);
     sc[SC_TH1] = th;
@@ -1861,8 +1880,7 @@ static void launch_x1_div(ofdft_ctx* c) {
 }
 
 template <typename R, int L, bool TF>
-static void launch_rpass_final(ofdft_ctx* c, const double* phi, void* v_out, const EvalParams& ep,
-                               const Slope* sl = nullptr) {
+static void launch_rpass_final(ofdft_ctx* c, const double* phi, void* v_out, const EvalParams& ep, const Slope* sl) {
   const GridDesc& g = c->g;
   dim3 grid(g.n2 / g.tr, g.n1);
   if (sl)
@@ -2003,7 +2021,8 @@ static int eval_impl(ofdft_ctx* c, const double* phi, void* v_out, double* sc, c
   }
   // partial sums of the density and final passes: one per block
   const int nb_r = plane ? g.n1 : (g.n2 / g.tr) * g.n1;
-  ReduceParams rp{nb_r, (g.n2 / g.tc) * g.n3k, tf ? nb_r : PW_BLOCKS, sl ? 1 : 0, g.dv, g.volume, c->alpha_sum};
+  const ReduceParams rp{nb_r, (g.n2 / g.tc) * g.n3k, tf ? nb_r : PW_BLOCKS, sl ? 1 : 0, g.dv, g.volume,
+                        c->alpha_sum};
   tmark(c, "reduce_scalars");
   hipLaunchKernelGGL(k_reduce_scalars, dim3(1), dim3(RED_NT), 0, c->stream, c->partials, c->max_blocks, rp, sc,
                      pub);
@@ -2141,8 +2160,15 @@ static bool upload_twiddles(ofdft_ctx* c) {
   return true;
 }
 
+// Opt a kernel into the 160 KB of LDS a CDNA4 workgroup can hold: the dynamic
+// limit is what its static LDS leaves.  A failure only keeps the default limit;
+// the error is consumed here so that it cannot surface at a later launch check.
 static void allow_large_lds(const void* f) {
-  (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  hipFuncAttributes a{};
+  size_t stat = 0;
+  if (hipFuncGetAttributes(&a, f) == hipSuccess) stat = a.sharedSizeBytes;
+  (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(160 * 1024 - stat));
+  (void)hipGetLastError();
 }
 
 template <typename R, int L, int U>
@@ -2221,7 +2247,8 @@ int dev_alloc_grid(ofdft_ctx* c) {
   c->max_blocks = std::max(std::max(nb_r, nb_x1), PW_BLOCKS);
   for (int k = 0; k < 3 && ok; ++k) ok = dalloc_bytes(c, &c->gr[k], N * rs);
   ok = ok && dalloc(c, &c->partials, (size_t)SL_COUNT * c->max_blocks) && dalloc(c, &c->scalars, SC_COUNT) &&
-       dalloc(c, &c->scalars_t, SC_COUNT) && dalloc(c, &c->scalars_t2, SC_COUNT) && dalloc(c, &c->vpart, 8 * VEC_BLOCKS) && dalloc(c, &c->vout, 16);
+       dalloc(c, &c->scalars_t, SC_COUNT) && dalloc(c, &c->scalars_t2, SC_COUNT) &&
+       dalloc(c, &c->vpart, 8 * VEC_BLOCKS) && dalloc(c, &c->vout, 16);
   if (ok && !c->hmap) {
     ok = hip_ok(c, hipHostMalloc((void**)&c->hmap, (kMapDoubles + 1) * sizeof(double),
                                  hipHostMallocMapped | hipHostMallocCoherent), "hipHostMalloc (mapped)");
@@ -2405,8 +2432,8 @@ static int run_direction(ofdft_ctx* c, const Op& op, const TrialCoef& tc) {
 
 template <typename R>
 static int cg_step_impl(ofdft_ctx* c, bool pcg, bool have_prev, double gg_prev, double cproj, double F_prev,
-                        double r) {
-  const TrialCoef tc{F_prev, have_prev ? 1 : 0, r, c->g.dv};
+                        double r, double kappa) {
+  const TrialCoef tc{F_prev, have_prev ? 1 : 0, r, c->g.dv, kappa};
   const GridDesc& g = c->g;
   const double two_dv = 2.0 * g.dv;
   const double* phi = c->phi;
@@ -2440,9 +2467,10 @@ static int cg_step_impl(ofdft_ctx* c, bool pcg, bool have_prev, double gg_prev, 
   return run_direction(c, OpDirection<R>{phi, v, c->scalars, c->gprev, c->d, two_dv, 0.0, cproj, 1}, tc);
 }
 
-int dev_cg_step(ofdft_ctx* c, bool pcg, bool have_prev, double gg_prev, double cproj, double F_prev, double r) {
-  return c->rsize == 4 ? cg_step_impl<float>(c, pcg, have_prev, gg_prev, cproj, F_prev, r)
-                       : cg_step_impl<double>(c, pcg, have_prev, gg_prev, cproj, F_prev, r);
+int dev_cg_step(ofdft_ctx* c, bool pcg, bool have_prev, double gg_prev, double cproj, double F_prev, double r,
+                double kappa) {
+  return c->rsize == 4 ? cg_step_impl<float>(c, pcg, have_prev, gg_prev, cproj, F_prev, r, kappa)
+                       : cg_step_impl<double>(c, pcg, have_prev, gg_prev, cproj, F_prev, r, kappa);
 }
 
 template <typename R>
