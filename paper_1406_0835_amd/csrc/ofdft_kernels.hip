@@ -32,6 +32,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <thread>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -2078,11 +2079,14 @@ static Publish next_publish(ofdft_ctx* c) {
 
 // Wait until the device has raised the sequence word to seq, then copy n doubles
 // out.  While waiting, the stream is polled now and then so that a failed launch
-// or a drained stream without the word ends the wait with an error.
+// or a drained stream without the word ends the wait with an error.  After the
+// first few thousand polls the thread yields between polls, so that many
+// contexts waiting at once (a batch) do not starve each other's launches.
 static int wait_published(ofdft_ctx* c, unsigned long long seq, int n, double* host) {
   const volatile unsigned long long* flag = reinterpret_cast<unsigned long long*>(c->hmap + kMapDoubles);
   for (unsigned spin = 1;; ++spin) {
     if (__atomic_load_n(flag, __ATOMIC_ACQUIRE) == seq) break;
+    if (spin > 4096) std::this_thread::yield();
     if ((spin & 255u) == 0) {
       const hipError_t e = hipStreamQuery(c->stream);
       if (e == hipSuccess) {
