@@ -512,7 +512,14 @@ __global__ void __launch_bounds__(NT) k_rpass_inv_real(Arr3 in, RealArr3 out, co
   }
 }
 
-constexpr int PW_BLOCKS = 2048;
+constexpr int PW_BLOCKS = 2048;   // at most; four points per thread at 128^3
+
+// Blocks of the pointwise kernel: PW_BLOCKS, or one point per thread on grids
+// too small to give every thread of PW_BLOCKS blocks a point.
+static inline int pw_blocks(const GridDesc& g) {
+  const long long b = (g.N + NT - 1) / NT;
+  return (int)std::max(1LL, std::min<long long>(PW_BLOCKS, b));
+}
 
 // Finite-T GGA + PZ81 at every point: v_loc = df/dn + v_xc, W = 2 df/dsigma grad n
 // (written over grad n), energy partial sums per block.
@@ -896,8 +903,11 @@ __global__ void __launch_bounds__(NT) k_rpass_final(const cplx<R>* __restrict__ 
 // z_p = x_{2p} + i x_{2p+1} for the x3 transform, and T[k3][k2], k3 < L/2, for
 // the x2 transform.  Changes of layout go through registers, every read
 // before a barrier and every write after it.
-constexpr int NTP = 1024;
-constexpr int PLANE_MAXE = 8;    // (L/2) L <= PLANE_MAXE NTP for L <= 128
+constexpr int NTP = 1024;   // threads of a plane block
+
+// Elements per thread of the in-place transforms of a half plane ((L/2) L points).
+template <int L, int NTH>
+__host__ __device__ constexpr int plane_maxe() { return ((L / 2) * L + NTH - 1) / NTH; }
 
 template <typename R, int L>
 __host__ __device__ constexpr size_t lds_plane(int nred) {
@@ -906,14 +916,14 @@ __host__ __device__ constexpr size_t lds_plane(int nred) {
 
 // x3 forward transform of the packed rows, then the half spectra of rows 2p
 // and 2p+1 (k3 < L/2) written transposed into T[k3][2p], T[k3][2p+1].
-template <typename R, int L>
+template <typename R, int L, int NTH>
 __device__ __forceinline__ void plane_x3_fwd_to_T(cplx<R>* buf, const cplx<R>* tw) {
-  lds_fft_inplace<R, -1, L, NTP, PLANE_MAXE>(buf, tw, L / 2, threadIdx.x);
-  constexpr int H = L / 2, ITEMS = H * H, MI = (ITEMS + NTP - 1) / NTP;
+  lds_fft_inplace<R, -1, L, NTH, plane_maxe<L, NTH>()>(buf, tw, L / 2, threadIdx.x);
+  constexpr int H = L / 2, ITEMS = H * H, MI = (ITEMS + NTH - 1) / NTH;
   cplx<R> xa[MI], xb[MI];
 #pragma unroll
   for (int m = 0; m < MI; ++m) {
-    const int it = threadIdx.x + m * NTP;
+    const int it = threadIdx.x + m * NTH;
     if (it < ITEMS) {
       const int p = it / H, k3 = it - p * H;
       const cplx<R> z = buf[Lay<L>::at(p, k3)];
@@ -925,7 +935,7 @@ __device__ __forceinline__ void plane_x3_fwd_to_T(cplx<R>* buf, const cplx<R>* t
   __syncthreads();
 #pragma unroll
   for (int m = 0; m < MI; ++m) {
-    const int it = threadIdx.x + m * NTP;
+    const int it = threadIdx.x + m * NTH;
     if (it < ITEMS) {
       const int p = it / H, k3 = it - p * H;
       buf[Lay<L>::at(k3, 2 * p)] = xa[m];
@@ -936,36 +946,36 @@ __device__ __forceinline__ void plane_x3_fwd_to_T(cplx<R>* buf, const cplx<R>* t
 }
 
 // x2 forward transform of the T rows, stored as S[k3][i1][k2].
-template <typename R, int L>
+template <typename R, int L, int NTH>
 __device__ __forceinline__ void plane_x2_fwd_store(cplx<R>* buf, const cplx<R>* tw, cplx<R>* out,
                                                    const GridDesc& g, int i1) {
-  lds_fft_inplace<R, -1, L, NTP, PLANE_MAXE>(buf, tw, L / 2, threadIdx.x);
+  lds_fft_inplace<R, -1, L, NTH, plane_maxe<L, NTH>()>(buf, tw, L / 2, threadIdx.x);
   const size_t plane = (size_t)g.n1 * L;
   constexpr int CNT = (L / 2) * L;
-  for (int e = threadIdx.x; e < CNT; e += NTP) {
+  for (int e = threadIdx.x; e < CNT; e += NTH) {
     const int k3 = e / L, k2 = e - k3 * L;
     out[k3 * plane + (size_t)i1 * L + k2] = buf[Lay<L>::at(k3, k2)];
   }
 }
 
 // T[k3][k2] = S[k3][i1][k2] (k3 < L/2) and the twiddles; ends with a barrier.
-template <typename R, int L>
+template <typename R, int L, int NTH>
 __device__ __forceinline__ void plane_load_T(cplx<R>* buf, cplx<R>* tw, const cplx<R>* in,
                                              const cplx<R>* tw_g, const GridDesc& g, int i1) {
   const size_t plane = (size_t)g.n1 * L;
-  constexpr int CNT = (L / 2) * L, MU = (CNT + NTP - 1) / NTP;
+  constexpr int CNT = (L / 2) * L, MU = (CNT + NTH - 1) / NTH;
   const cplx<R> twv = twiddle_load<R, L>(tw_g);
   cplx<R> v[MU];
 #pragma unroll
   for (int m = 0; m < MU; ++m) {
-    const int e = min((int)threadIdx.x + m * NTP, CNT - 1);
+    const int e = min((int)threadIdx.x + m * NTH, CNT - 1);
     const int k3 = e / L, k2 = e - k3 * L;
     v[m] = in[k3 * plane + (size_t)i1 * L + k2];
   }
   twiddle_store<R, L>(tw, twv);
 #pragma unroll
   for (int m = 0; m < MU; ++m) {
-    const int e = threadIdx.x + m * NTP;
+    const int e = threadIdx.x + m * NTH;
     if (e < CNT) {
       const int k3 = e / L, k2 = e - k3 * L;
       buf[Lay<L>::at(k3, k2)] = v[m];
@@ -977,14 +987,14 @@ __device__ __forceinline__ void plane_load_T(cplx<R>* buf, cplx<R>* tw, const cp
 // x2 inverse transform of the T rows, the packed rows z_p[k] = X_{2p}[k] +
 // i X_{2p+1}[k] over all k (Hermitian symmetry, Nyquist term zero), and the x3
 // inverse transform: real element (i2, i3) is then Re or Im of P[i2/2][i3].
-template <typename R, int L>
+template <typename R, int L, int NTH>
 __device__ __forceinline__ void plane_inv(cplx<R>* buf, const cplx<R>* tw) {
-  lds_fft_inplace<R, +1, L, NTP, PLANE_MAXE>(buf, tw, L / 2, threadIdx.x);
-  constexpr int H = L / 2, ITEMS = H * L, MI = (ITEMS + NTP - 1) / NTP;
+  lds_fft_inplace<R, +1, L, NTH, plane_maxe<L, NTH>()>(buf, tw, L / 2, threadIdx.x);
+  constexpr int H = L / 2, ITEMS = H * L, MI = (ITEMS + NTH - 1) / NTH;
   cplx<R> z[MI];
 #pragma unroll
   for (int m = 0; m < MI; ++m) {
-    const int it = threadIdx.x + m * NTP;
+    const int it = threadIdx.x + m * NTH;
     if (it < ITEMS) {
       const int p = it / L, k = it - p * L;
       cplx<R> xa = {R(0), R(0)}, xb = {R(0), R(0)};
@@ -1001,14 +1011,14 @@ __device__ __forceinline__ void plane_inv(cplx<R>* buf, const cplx<R>* tw) {
   __syncthreads();
 #pragma unroll
   for (int m = 0; m < MI; ++m) {
-    const int it = threadIdx.x + m * NTP;
+    const int it = threadIdx.x + m * NTH;
     if (it < ITEMS) {
       const int p = it / L, k = it - p * L;
       buf[Lay<L>::at(p, k)] = z[m];
     }
   }
   __syncthreads();
-  lds_fft_inplace<R, +1, L, NTP, PLANE_MAXE>(buf, tw, L / 2, threadIdx.x);
+  lds_fft_inplace<R, +1, L, NTH, plane_maxe<L, NTH>()>(buf, tw, L / 2, threadIdx.x);
 }
 
 template <typename R, int L>
@@ -1027,7 +1037,7 @@ template <typename R, int L, bool ROT>
 __global__ void __launch_bounds__(NTP) k_plane_fwd_density(const double* __restrict__ phi, cplx<R>* __restrict__ out,
                                                            const cplx<R>* __restrict__ tw_g, GridDesc g,
                                                            double* __restrict__ partials, int maxb, Rotation rot) {
-  static_assert((L / 2) * L <= PLANE_MAXE * NTP, "plane larger than the in-place FFT bound");
+  static_assert(plane_maxe<L, NTP>() <= 16, "plane too large for the in-place FFT registers");
   extern __shared__ __align__(16) char smem_raw[];
   Smem sm(smem_raw);
   cplx<R>* buf = sm.take<cplx<R>>((L / 2) * Lay<L>::RS);
@@ -1068,18 +1078,18 @@ __global__ void __launch_bounds__(NTP) k_plane_fwd_density(const double* __restr
   }
   twiddle_store<R, L>(tw, twv);
   __syncthreads();
-  plane_x3_fwd_to_T<R, L>(buf, tw);
-  plane_x2_fwd_store<R, L>(buf, tw, out, g, i1);
+  plane_x3_fwd_to_T<R, L, NTP>(buf, tw);
+  plane_x2_fwd_store<R, L, NTP>(buf, tw, out, g, i1);
   double v[1] = {acc};
   block_sum<1, NTP>(v, red);
   if (threadIdx.x == 0) partials[SL_PHI2 * maxb + i1] = v[0];
 }
 
 // F3: forward x3 and x2 transforms of real arrays (component blockIdx.y).
-template <typename R, int L>
-__global__ void __launch_bounds__(NTP) k_plane_fwd_real(RealArr3 in, Arr3 out, const cplx<R>* __restrict__ tw_g,
+template <typename R, int L, int NTH>
+__global__ void __launch_bounds__(NTH, 4) k_plane_fwd_real(RealArr3 in, Arr3 out, const cplx<R>* __restrict__ tw_g,
                                                         GridDesc g) {
-  static_assert((L / 2) * L <= PLANE_MAXE * NTP, "plane larger than the in-place FFT bound");
+  static_assert(plane_maxe<L, NTH>() <= 16, "plane too large for the in-place FFT registers");
   extern __shared__ __align__(16) char smem_raw[];
   Smem sm(smem_raw);
   cplx<R>* buf = sm.take<cplx<R>>((L / 2) * Lay<L>::RS);
@@ -1089,13 +1099,13 @@ __global__ void __launch_bounds__(NTP) k_plane_fwd_real(RealArr3 in, Arr3 out, c
   const R* src = reinterpret_cast<const R*>(in.p[blockIdx.y]) + (size_t)i1 * CNT;
   const cplx<R> twv = twiddle_load<R, L>(tw_g);
   R* zr = reinterpret_cast<R*>(buf);
-  for (int c0 = 0; c0 < CNT; c0 += PCH * NTP) {
+  for (int c0 = 0; c0 < CNT; c0 += PCH * NTH) {
     R xv[PCH];
 #pragma unroll
-    for (int u = 0; u < PCH; ++u) xv[u] = src[min(c0 + (int)threadIdx.x + u * NTP, CNT - 1)];
+    for (int u = 0; u < PCH; ++u) xv[u] = src[min(c0 + (int)threadIdx.x + u * NTH, CNT - 1)];
 #pragma unroll
     for (int u = 0; u < PCH; ++u) {
-      const int e = c0 + threadIdx.x + u * NTP;
+      const int e = c0 + threadIdx.x + u * NTH;
       if (e < CNT) {
         const int i2 = e / L, i3 = e - i2 * L;
         zr[2 * Lay<L>::at(i2 >> 1, i3) + (i2 & 1)] = xv[u];
@@ -1104,8 +1114,8 @@ __global__ void __launch_bounds__(NTP) k_plane_fwd_real(RealArr3 in, Arr3 out, c
   }
   twiddle_store<R, L>(tw, twv);
   __syncthreads();
-  plane_x3_fwd_to_T<R, L>(buf, tw);
-  plane_x2_fwd_store<R, L>(buf, tw, reinterpret_cast<cplx<R>*>(out.p[blockIdx.y]), g, i1);
+  plane_x3_fwd_to_T<R, L, NTH>(buf, tw);
+  plane_x2_fwd_store<R, L, NTH>(buf, tw, reinterpret_cast<cplx<R>*>(out.p[blockIdx.y]), g, i1);
 }
 
 // The minimiser's projected gradient g = 2 dv phi (v - mu), formed on the fly,
@@ -1115,7 +1125,7 @@ __global__ void __launch_bounds__(NTP) k_plane_fwd_grad(const double* __restrict
                                                         const double* __restrict__ sc, double two_dv,
                                                         cplx<R>* __restrict__ out, const cplx<R>* __restrict__ tw_g,
                                                         GridDesc g) {
-  static_assert((L / 2) * L <= PLANE_MAXE * NTP, "plane larger than the in-place FFT bound");
+  static_assert(plane_maxe<L, NTP>() <= 16, "plane too large for the in-place FFT registers");
   extern __shared__ __align__(16) char smem_raw[];
   Smem sm(smem_raw);
   cplx<R>* buf = sm.take<cplx<R>>((L / 2) * Lay<L>::RS);
@@ -1146,25 +1156,25 @@ __global__ void __launch_bounds__(NTP) k_plane_fwd_grad(const double* __restrict
   }
   twiddle_store<R, L>(tw, twv);
   __syncthreads();
-  plane_x3_fwd_to_T<R, L>(buf, tw);
-  plane_x2_fwd_store<R, L>(buf, tw, out, g, i1);
+  plane_x3_fwd_to_T<R, L, NTP>(buf, tw);
+  plane_x2_fwd_store<R, L, NTP>(buf, tw, out, g, i1);
 }
 
 // I3: inverse x2 and x3 transforms into real arrays (component blockIdx.y).
-template <typename R, int L>
-__global__ void __launch_bounds__(NTP) k_plane_inv_real(Arr3 in, RealArr3 out, const cplx<R>* __restrict__ tw_g,
+template <typename R, int L, int NTH>
+__global__ void __launch_bounds__(NTH, 4) k_plane_inv_real(Arr3 in, RealArr3 out, const cplx<R>* __restrict__ tw_g,
                                                         GridDesc g) {
-  static_assert((L / 2) * L <= PLANE_MAXE * NTP, "plane larger than the in-place FFT bound");
+  static_assert(plane_maxe<L, NTH>() <= 16, "plane too large for the in-place FFT registers");
   extern __shared__ __align__(16) char smem_raw[];
   Smem sm(smem_raw);
   cplx<R>* buf = sm.take<cplx<R>>((L / 2) * Lay<L>::RS);
   cplx<R>* tw = sm.take<cplx<R>>(L);
   const int i1 = blockIdx.x;
   constexpr int CNT = L * L;
-  plane_load_T<R, L>(buf, tw, reinterpret_cast<const cplx<R>*>(in.p[blockIdx.y]), tw_g, g, i1);
-  plane_inv<R, L>(buf, tw);
+  plane_load_T<R, L, NTH>(buf, tw, reinterpret_cast<const cplx<R>*>(in.p[blockIdx.y]), tw_g, g, i1);
+  plane_inv<R, L, NTH>(buf, tw);
   R* dst = reinterpret_cast<R*>(out.p[blockIdx.y]) + (size_t)i1 * CNT;
-  for (int e = threadIdx.x; e < CNT; e += NTP) dst[e] = plane_real<R, L>(buf, e);
+  for (int e = threadIdx.x; e < CNT; e += NTH) dst[e] = plane_real<R, L>(buf, e);
 }
 
 // FI: inverse x2 and x3 transforms of the reciprocal-space potential, then
@@ -1175,7 +1185,7 @@ __global__ void __launch_bounds__(NTP) k_plane_final(const cplx<R>* __restrict__
                                                      const R* __restrict__ vloc, R* __restrict__ vout,
                                                      const cplx<R>* __restrict__ tw_g, GridDesc g, EvalParams ep,
                                                      double* __restrict__ partials, int maxb, Slope sl) {
-  static_assert((L / 2) * L <= PLANE_MAXE * NTP, "plane larger than the in-place FFT bound");
+  static_assert(plane_maxe<L, NTP>() <= 16, "plane too large for the in-place FFT registers");
   extern __shared__ __align__(16) char smem_raw[];
   Smem sm(smem_raw);
   cplx<R>* buf = sm.take<cplx<R>>((L / 2) * Lay<L>::RS);
@@ -1184,8 +1194,8 @@ __global__ void __launch_bounds__(NTP) k_plane_final(const cplx<R>* __restrict__
   const int i1 = blockIdx.x;
   const size_t base = (size_t)i1 * L * L;
   constexpr int CNT = L * L;
-  plane_load_T<R, L>(buf, tw, D, tw_g, g, i1);
-  plane_inv<R, L>(buf, tw);
+  plane_load_T<R, L, NTP>(buf, tw, D, tw_g, g, i1);
+  plane_inv<R, L, NTP>(buf, tw);
   double fs = 0.0, ts = 0.0, exc = 0.0, nv = 0.0, dt1 = 0.0, dt2 = 0.0;
   constexpr int CH = TF ? 2 : PCH;   // the inlined ftTF point is register-heavy
   for (int c0 = 0; c0 < CNT; c0 += CH * NTP) {
@@ -1816,8 +1826,8 @@ static void launch_plane_inv_real(ofdft_ctx* c, void* in0, void* in1, void* in2,
   const GridDesc& g = c->g;
   Arr3 in{{in0, in1, in2}};
   RealArr3 out{{out0, out1, out2}};
-  hipLaunchKernelGGL((k_plane_inv_real<R, L>), dim3(g.n1, narr), dim3(NTP), (lds_plane<R, L>(0)), c->stream, in, out,
-                     (const cplx<R>*)c->tw[2], g);
+  hipLaunchKernelGGL((k_plane_inv_real<R, L, NTP>), dim3(g.n1, narr), dim3(NTP), (lds_plane<R, L>(0)), c->stream, in,
+                     out, (const cplx<R>*)c->tw[2], g);
 }
 
 template <typename R, int L>
@@ -1825,8 +1835,8 @@ static void launch_plane_fwd_real3(ofdft_ctx* c) {
   const GridDesc& g = c->g;
   RealArr3 in{{c->gr[0], c->gr[1], c->gr[2]}};
   Arr3 out{{c->B[0], c->B[1], c->B[2]}};
-  hipLaunchKernelGGL((k_plane_fwd_real<R, L>), dim3(g.n1, 3), dim3(NTP), (lds_plane<R, L>(0)), c->stream, in, out,
-                     (const cplx<R>*)c->tw[2], g);
+  hipLaunchKernelGGL((k_plane_fwd_real<R, L, NTP>), dim3(g.n1, 3), dim3(NTP), (lds_plane<R, L>(0)), c->stream, in,
+                     out, (const cplx<R>*)c->tw[2], g);
 }
 
 template <typename R, int L>
@@ -1852,7 +1862,7 @@ static void launch_plane_final(ofdft_ctx* c, const double* phi, void* v_out, con
 
 template <typename R>
 static void launch_pointwise_gga(ofdft_ctx* c, const double* phi, const EvalParams& ep) {
-  hipLaunchKernelGGL((k_pointwise_gga<R>), dim3(PW_BLOCKS), dim3(NT), 0, c->stream, phi, (R*)c->gr[0],
+  hipLaunchKernelGGL((k_pointwise_gga<R>), dim3(pw_blocks(c->g)), dim3(NT), 0, c->stream, phi, (R*)c->gr[0],
                      (R*)c->gr[1], (R*)c->gr[2], (R*)c->vloc, c->g.N, ep, c->partials, c->max_blocks);
 }
 
@@ -2022,7 +2032,7 @@ static int eval_impl(ofdft_ctx* c, const double* phi, void* v_out, double* sc, c
   }
   // partial sums of the density and final passes: one per block
   const int nb_r = plane ? g.n1 : (g.n2 / g.tr) * g.n1;
-  const ReduceParams rp{nb_r, (g.n2 / g.tc) * g.n3k, tf ? nb_r : PW_BLOCKS, sl ? 1 : 0, g.dv, g.volume,
+  const ReduceParams rp{nb_r, (g.n2 / g.tc) * g.n3k, tf ? nb_r : pw_blocks(g), sl ? 1 : 0, g.dv, g.volume,
                         c->alpha_sum};
   tmark(c, "reduce_scalars");
   hipLaunchKernelGGL(k_reduce_scalars, dim3(1), dim3(RED_NT), 0, c->stream, c->partials, c->max_blocks, rp, sc,
@@ -2222,9 +2232,9 @@ static void configure_lds() {
 #define OFDFT_ALLOW_PLANE(LEN)                                                       \
   allow((const void*)k_plane_fwd_density<R, LEN, false>);                            \
   allow((const void*)k_plane_fwd_density<R, LEN, true>);                             \
-  allow((const void*)k_plane_fwd_real<R, LEN>);                                      \
+  allow((const void*)k_plane_fwd_real<R, LEN, NTP>);                                 \
   allow((const void*)k_plane_fwd_grad<R, LEN>);                                      \
-  allow((const void*)k_plane_inv_real<R, LEN>);                                      \
+  allow((const void*)k_plane_inv_real<R, LEN, NTP>);                                 \
   allow((const void*)k_plane_final<R, LEN, true, false>);                            \
   allow((const void*)k_plane_final<R, LEN, false, false>);                           \
   allow((const void*)k_plane_final<R, LEN, true, true>);                             \
