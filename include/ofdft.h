@@ -147,10 +147,21 @@ int ofdft_set_temperature(ofdft_ctx* ctx, double T_kelvin);
 int ofdft_minimize_density(ofdft_ctx* ctx, ofdft_report* rep);
 
 /* After a converged minimisation: F_total (etot), E_internal (einternel) and,
-   if forces != NULL, forces[3*nat] (hartree/bohr, Eq. M12 + Ewald).
-   pressure must be NULL (the stress tensor is not provided). */
+   if forces != NULL, forces[3*nat] (hartree/bohr, Eq. M12 + Ewald); if
+   pressure != NULL, P = -Tr Sigma / 3 (Eq. pressure, hartree/bohr^3) from
+   ofdft_stress. */
 int ofdft_free_energy_and_forces(ofdft_ctx* ctx, double* F_total, double* E_internal,
                                  double* forces, double* pressure);
+
+/* Stress tensor (Eq. StressTensor): sigma[9] (row-major, symmetric, hartree/bohr^3)
+   = (1/V) dOmega/d eps_ab under a homogeneous strain h -> (1 + eps) h of the cell,
+   ions at fixed fractional coordinates, the converged density carried with the
+   cell.  Sum of the non-interacting part (Eqs. stressTF_a, stressTF_b), the LDA
+   XC term, Hartree and pseudopotential reciprocal-space terms, the alpha Z term
+   and the Ewald term.  Needs a converged minimisation (OFDFT_E_STATE otherwise);
+   OFDFT_E_ARG if sigma is NULL.  Runs three FFT passes, two grid sums and an
+   N_ion x N_G phase sum on the device and the Ewald strain sum on the host. */
+int ofdft_stress(ofdft_ctx* ctx, double sigma[9]);
 
 /* Current amplitude phi (N1*N2*N3 doubles). */
 int ofdft_get_density(ofdft_ctx* ctx, double* phi_out);
@@ -197,10 +208,12 @@ int ofdft_batch_minimize(ofdft_ctx* const* ctxs, int n, ofdft_report* reps);
    ion-ion term E_ion of the total free energy, Sec. II; the same sum that
    set_ions evaluates).  lattice = rows a1, a2, a3 (bohr), nat >= 1 Cartesian
    positions tau[3*nat] (bohr) and charges Z[nat] > 0.  *E receives the energy
-   (hartree), forces[3*nat] (may be NULL) the forces (hartree/bohr).  Host code:
-   needs no context and no device.  E_ARG on NULL or non-finite input or a
-   singular lattice. */
-int ofdft_ewald(const double lattice[9], int nat, const double* tau, const double* Z, double* E, double* forces);
+   (hartree), forces[3*nat] (may be NULL) the forces (hartree/bohr), stress[9]
+   (may be NULL) its term of the stress tensor (row-major, hartree/bohr^3, the
+   strain derivative of ofdft_stress).  Host code: needs no context and no device.
+   E_ARG on NULL or non-finite input or a singular lattice. */
+int ofdft_ewald(const double lattice[9], int nat, const double* tau, const double* Z, double* E, double* forces,
+                double* stress);
 
 const char* ofdft_last_error(const ofdft_ctx* ctx);
 

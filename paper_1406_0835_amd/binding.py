@@ -86,7 +86,8 @@ def load_library() -> ctypes.CDLL:
         "ofdft_batch_minimize": [ctypes.POINTER(P), I, ctypes.POINTER(Report)],
         "ofdft_autotune": [P, I, ip],
         "ofdft_set_tiles": [P, ip],
-        "ofdft_ewald": [dp, I, dp, dp, dp, dp],
+        "ofdft_ewald": [dp, I, dp, dp, dp, dp, dp],
+        "ofdft_stress": [P, dp],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -108,8 +109,9 @@ def _check(lib, rc: int, ctx=None):
         raise OFDFTError(rc, (msg or b"").decode())
 
 
-def ewald(lattice, positions, charges, forces: bool = True):
-    """Ion-ion Ewald energy (hartree) and forces (hartree/bohr); host code, no device."""
+def ewald(lattice, positions, charges, forces: bool = True, stress: bool = False):
+    """Ion-ion Ewald energy (hartree), forces (hartree/bohr) and, with stress=True, its
+    stress-tensor term (3, 3, hartree/bohr^3) as a third result; host code, no device."""
     lib = load_library()
     lat = np.ascontiguousarray(np.asarray(lattice, dtype=np.float64).reshape(9))
     pos = np.ascontiguousarray(np.asarray(positions, dtype=np.float64).reshape(-1))
@@ -118,8 +120,11 @@ def ewald(lattice, positions, charges, forces: bool = True):
         raise OFDFTError(E_ARG, "positions must be (nat, 3) and charges (nat,)")
     E = ctypes.c_double()
     f = np.zeros(3 * z.size) if forces else None
+    sig = np.zeros(9) if stress else None
     _check(lib, lib.ofdft_ewald(_dptr(lat), int(z.size), _dptr(pos), _dptr(z), ctypes.byref(E),
-                                _dptr(f) if forces else None))
+                                _dptr(f) if forces else None, _dptr(sig) if stress else None))
+    if stress:
+        return E.value, (f.reshape(-1, 3) if forces else None), sig.reshape(3, 3)
     return E.value, (f.reshape(-1, 3) if forces else None)
 
 
@@ -205,6 +210,16 @@ class Context:
                                                     _dptr(f) if forces else None, None)
         _check(self._lib, rc, self._h)
         return F.value, E.value, (f.reshape(-1, 3) if forces else None)
+
+    def stress(self) -> np.ndarray:
+        """Stress tensor (3, 3) in hartree/bohr^3 at the converged density."""
+        sig = np.zeros(9)
+        _check(self._lib, self._lib.ofdft_stress(self._h, _dptr(sig)), self._h)
+        return sig.reshape(3, 3)
+
+    def pressure(self) -> float:
+        """P = -Tr(stress)/3 (hartree/bohr^3)."""
+        return -float(np.trace(self.stress())) / 3.0
 
     def get_density(self) -> np.ndarray:
         out = np.zeros(int(np.prod(self.shape)))

@@ -675,11 +675,46 @@ int ofdft_minimize_density(ofdft_ctx* c, ofdft_report* rep) {
   return rc;
 }
 
+int ofdft_stress(ofdft_ctx* c, double sigma[9]) {
+  if (!c) return fail(nullptr, OFDFT_E_ARG, "null context");
+  if (!sigma) return fail(c, OFDFT_E_ARG, "sigma is NULL");
+  if (!c->converged) return fail(c, OFDFT_E_STATE, "no converged density: call ofdft_minimize_density first");
+  if (hipSetDevice(c->opt.device) != hipSuccess) return fail(c, OFDFT_E_DEVICE, "hipSetDevice");
+  double s[20];
+  int rc = dev_stress(c, s);
+  if (rc) return fail(c, rc, c->err);
+  if (!join_ewald(c)) return fail(c, OFDFT_E_ARG, "Ewald sum failed");
+  double E_ew = 0.0, ew[6];
+  std::vector<double> F_ew;
+  ewald_sum(c->lat, c->nat, c->tau.data(), c->Z.data(), E_ew, F_ew, ew);
+  const double V = c->g.volume;
+  const ofdft_report& r = c->last;
+  // V Sigma per term: local delta (sum(f - n df/dn) + sum n (eps - v_xc) - tr B) - B,
+  // Hartree V H - delta E_H, pseudopotential -X - delta E_ext, alpha -delta E_alphaZ, Ewald
+  const double trB = s[2] + s[3] + s[4];
+  double t[6];
+  for (int k = 0; k < 6; ++k) t[k] = -s[2 + k] + V * s[8 + k] - s[14 + k] + ew[k];
+  for (int k = 0; k < 3; ++k) t[k] += s[0] + s[1] - trB - r.E_H - r.E_ext - r.E_alphaZ;
+  const int ia[6] = {0, 1, 2, 0, 1, 0}, ib[6] = {0, 1, 2, 1, 2, 2};
+  for (int k = 0; k < 6; ++k) {
+    sigma[3 * ia[k] + ib[k]] = t[k] / V;
+    sigma[3 * ib[k] + ia[k]] = t[k] / V;
+  }
+  for (int k = 0; k < 9; ++k)
+    if (!is_fin(sigma[k])) return fail(c, OFDFT_E_NONFINITE, "non-finite stress");
+  return OFDFT_OK;
+}
+
 int ofdft_free_energy_and_forces(ofdft_ctx* c, double* F_total, double* E_internal, double* forces,
                                  double* pressure) {
   if (!c) return fail(nullptr, OFDFT_E_ARG, "null context");
-  if (pressure) return fail(c, OFDFT_E_ARG, "pressure must be NULL: the stress tensor is not provided");
   if (!c->converged) return fail(c, OFDFT_E_STATE, "no converged density: call ofdft_minimize_density first");
+  if (pressure) {
+    double sig[9];
+    int rc = ofdft_stress(c, sig);
+    if (rc) return rc;
+    *pressure = -(sig[0] + sig[4] + sig[8]) / 3.0;
+  }
   if (hipSetDevice(c->opt.device) != hipSuccess) return fail(c, OFDFT_E_DEVICE, "hipSetDevice");
   if (F_total) *F_total = c->last.F_total;
   if (E_internal) *E_internal = c->last.E_internal;
@@ -903,7 +938,8 @@ int ofdft_batch_minimize(ofdft_ctx* const* ctxs, int n, ofdft_report* reps) {
   return OFDFT_OK;
 }
 
-int ofdft_ewald(const double lattice[9], int nat, const double* tau, const double* Z, double* E, double* forces) {
+int ofdft_ewald(const double lattice[9], int nat, const double* tau, const double* Z, double* E, double* forces,
+                double* stress) {
   if (!lattice || !tau || !Z || !E) return fail(nullptr, OFDFT_E_ARG, "NULL argument");
   if (nat < 1) return fail(nullptr, OFDFT_E_ARG, "nat must be >= 1");
   for (int k = 0; k < 9; ++k)
@@ -920,10 +956,15 @@ int ofdft_ewald(const double lattice[9], int nat, const double* tau, const doubl
     if (!(Z[i] > 0.0) || !is_fin(Z[i])) return fail(nullptr, OFDFT_E_ARG, "charges must be finite and > 0");
   }
   std::vector<double> F;
-  double e = 0.0;
-  ewald_sum(lattice, nat, tau, Z, e, F);
+  double e = 0.0, s6[6];
+  ewald_sum(lattice, nat, tau, Z, e, F, stress ? s6 : nullptr);
   *E = e;
   if (forces) std::copy(F.begin(), F.end(), forces);
+  if (stress) {
+    const double V = std::fabs(det);
+    const int ia[6] = {0, 1, 2, 0, 1, 0}, ib[6] = {0, 1, 2, 1, 2, 2};
+    for (int k = 0; k < 6; ++k) stress[3 * ia[k] + ib[k]] = stress[3 * ib[k] + ia[k]] = s6[k] / V;
+  }
   return OFDFT_OK;
 }
 

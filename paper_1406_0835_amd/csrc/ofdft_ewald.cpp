@@ -26,6 +26,7 @@ constexpr double kPi = 3.141592653589793238462643383279502884;
 struct Partial {
   double E = 0.0;
   std::vector<double> F;
+  double S[6] = {0, 0, 0, 0, 0, 0};   // strain-derivative sums (xx, yy, zz, xy, yz, xz)
 };
 
 // Threads for `items` independent work items, at least `per_thread` items each;
@@ -52,7 +53,7 @@ void run_threads(int nt, Fn&& fn) {
 }  // namespace
 
 void ewald_sum(const double lat[9], int nat, const double* pos, const double* Z, double& E,
-               std::vector<double>& F) {
+               std::vector<double>& F, double* strain6) {
   const double* a[3] = {lat, lat + 3, lat + 6};
   auto cross = [](const double* u, const double* v, double* w) {
     w[0] = u[1] * v[2] - u[2] * v[1];
@@ -135,7 +136,7 @@ void ewald_sum(const double lat[9], int nat, const double* pos, const double* Z,
                               df[0] * a[0][1] + df[1] * a[1][1] + df[2] * a[2][1],
                               df[0] * a[0][2] + df[1] * a[1][2] + df[2] * a[2][2]};
         const double tmax = rcut + std::sqrt(d0[0] * d0[0] + d0[1] * d0[1] + d0[2] * d0[2]);
-        double e = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
+        double e = 0.0, fx = 0.0, fy = 0.0, fz = 0.0, sd[6] = {0, 0, 0, 0, 0, 0};
         for (size_t m = 0; m < nT && Ts[m][3] < tmax; ++m) {
           const double dx = d0[0] + Ts[m][0], dy = d0[1] + Ts[m][1], dz = d0[2] + Ts[m][2];
           const double r2 = dx * dx + dy * dy + dz * dz;
@@ -147,9 +148,15 @@ void ewald_sum(const double lat[9], int nat, const double* pos, const double* Z,
           fx += fm * dx;
           fy += fm * dy;
           fz += fm * dz;
+          if (strain6) {
+            sd[0] += fm * dx * dx; sd[1] += fm * dy * dy; sd[2] += fm * dz * dz;
+            sd[3] += fm * dx * dy; sd[4] += fm * dy * dz; sd[5] += fm * dx * dz;
+          }
         }
         const double zz = Z[i] * Z[j];
         P.E += (i == j ? 0.5 : 1.0) * zz * e;
+        // d/d eps_ab of erfc(a r)/r summed: phi'(r) r_a r_b / r = -fm r_a r_b
+        for (int k = 0; k < 6; ++k) P.S[k] -= (i == j ? 0.5 : 1.0) * zz * sd[k];
         if (i != j) {
           P.F[3 * i] += zz * fx; P.F[3 * i + 1] += zz * fy; P.F[3 * i + 2] += zz * fz;
           P.F[3 * j] -= zz * fx; P.F[3 * j + 1] -= zz * fy; P.F[3 * j + 2] -= zz * fz;
@@ -207,6 +214,12 @@ void ewald_sum(const double lat[9], int nat, const double* pos, const double* Z,
       }
       // +G and -G together: 2 w |S|^2 and forces 2 (4 pi/V) Z_I w G Im[e^{iG.R_I} S*]
       P.E += 2.0 * w * std::norm(S);
+      if (strain6) {
+        // strain derivative of w(G): w 2 G_a G_b (1/G^2 + 1/(4 a^2)) (G scales as (1 + eps)^-T)
+        const double k2 = 2.0 * w * std::norm(S) * 2.0 * (1.0 / G2 + 1.0 / (4.0 * split * split));
+        P.S[0] += k2 * G[0] * G[0]; P.S[1] += k2 * G[1] * G[1]; P.S[2] += k2 * G[2] * G[2];
+        P.S[3] += k2 * G[0] * G[1]; P.S[4] += k2 * G[1] * G[2]; P.S[5] += k2 * G[0] * G[2];
+      }
       for (int i = 0; i < nat; ++i) {
         const double im = e[i].imag() * S.real() - e[i].real() * S.imag();
         const double f = 2.0 * 4.0 * kPi / V * Z[i] * w * im;
@@ -231,6 +244,16 @@ void ewald_sum(const double lat[9], int nat, const double* pos, const double* Z,
   const double Es = -split / std::sqrt(kPi) * Q2;
   const double Eb = -kPi * Q * Q / (2.0 * V * split * split);
   E = Er + Eg + Es + Eb;
+  if (strain6) {
+    // V Sigma: real-space pair terms, reciprocal terms minus delta E_rec, minus delta E_bg
+    // (the self term does not depend on the cell)
+    double sr[6] = {0, 0, 0, 0, 0, 0}, sg[6] = {0, 0, 0, 0, 0, 0};
+    for (const Partial& P : pr)
+      for (int k = 0; k < 6; ++k) sr[k] += P.S[k];
+    for (const Partial& P : pg)
+      for (int k = 0; k < 6; ++k) sg[k] += P.S[k];
+    for (int k = 0; k < 6; ++k) strain6[k] = sr[k] + 2.0 * kPi / V * sg[k] - (k < 3 ? Eg + Eb : 0.0);
+  }
 }
 
 void start_ewald(ofdft_ctx* c) {

@@ -154,7 +154,9 @@ namespace ofdft {
 
 // Ewald energy and forces of the ions (ofdft_ewald.cpp, host FP64): lat rows a1..a3 (bohr),
 // Cartesian pos[3 nat], charges Z[nat]; F receives 3 nat forces (hartree/bohr).
-void ewald_sum(const double lat[9], int nat, const double* pos, const double* Z, double& E, std::vector<double>& F);
+// strain6, if given, receives V Sigma of the Ewald energy (xx, yy, zz, xy, yz, xz).
+void ewald_sum(const double lat[9], int nat, const double* pos, const double* Z, double& E, std::vector<double>& F,
+               double* strain6 = nullptr);
 // Start ewald_sum for the context's current ions on a host thread / wait for it
 // (false if it failed).
 void start_ewald(ofdft_ctx* c);
@@ -178,6 +180,10 @@ int dev_eval_trial(ofdft_ctx* c, const double* phi, const double* dir, double ca
 int dev_eval_trial_dev(ofdft_ctx* c, const double* phi, const double* dir, const double* coef, double* phi_out,
                        void* v_out, double* scalars_out, const double* extra, double* host);
 int dev_forces(ofdft_ctx* c, double* forces_host);
+// Stress sums at the current density: sums[0] = dv sum (f - n df/dn), sums[1] = dv sum
+// n (eps_xc - v_xc), sums[2..7] = dv sum W_a d_b n, sums[8..13] Hartree and
+// sums[14..19] pseudopotential reciprocal sums (xx, yy, zz, xy, yz, xz).
+int dev_stress(ofdft_ctx* c, double* sums);
 // vector operations for the minimisers; results land in c->vout (device)
 // g = 2 dv phi (v - mu): writes g.g, g.gprev, g.d, sum n (v-mu)^2 into out[0..3]
 int dev_grad_dots(ofdft_ctx* c, const double* phi, const void* v, const double* sc, const double* gprev,

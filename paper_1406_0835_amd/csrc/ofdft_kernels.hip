@@ -1657,6 +1657,131 @@ __global__ void __launch_bounds__(NT) k_forces_final(int nat, const double* __re
   if (lane == 0) out[k] = scale * s;
 }
 
+// ---------------------------------------------------------------- stress (Eqs. StressTensor, stressTF_a/b)
+// d/dq of the volume-free form factor V v_I(q) = Z_I ua(q) + ub(q).
+__device__ __forceinline__ void form_ab_dq(const LppParams& lp, double q, double& dua, double& dub) {
+  const double P = -kFourPi / (q * q), dP = 2.0 * kFourPi / (q * q * q);
+  if (lp.kind == 0) {
+    const double e = exp(-0.25 * q * q * lp.rc * lp.rc);
+    dua = dP * e + P * e * (-0.5 * q * lp.rc * lp.rc);
+    dub = 0.0;
+  } else {
+    double sn, cs;
+    sincos(q * lp.rc, &sn, &cs);
+    const double x = q / lp.qc;
+    const double x2 = x * x;
+    const double f = exp(-x2 * x2 * x2);
+    const double df = -6.0 * x2 * x2 * x / lp.qc * f;
+    dua = dP * cs * f - P * lp.rc * sn * f + P * cs * df;
+    const double h = -lp.A * lp.rc * cs + lp.A / q * sn;
+    const double dh = lp.A * lp.rc * lp.rc * sn + lp.A * (lp.rc * cs / q - sn / (q * q));
+    dub = dP * h * f + P * dh * f + P * h * df;
+  }
+}
+
+// Reciprocal-space stress sums over the kept G != 0 (w = 1 on the k3 = 0 plane,
+// 2 elsewhere), in the order xx, yy, zz, xy, yz, xz:
+//   part[0..5]:  w 4 pi |n(G)|^2 G_a G_b / G^4                  (Hartree)
+//   part[6..11]: w Re[conj(n(G)) sum_I u_I'(|G|) e^{-iG.R_I}] G_a G_b / |G|   (pseudopotential)
+template <typename R>
+__global__ void __launch_bounds__(NT) k_stress_recip(int nat, const double* __restrict__ Z,
+                                                     const double2* __restrict__ tab,
+                                                     const cplx<R>* __restrict__ nhat, GridDesc g, LppParams lp,
+                                                     double* __restrict__ part) {
+  __shared__ double red[12 * NT / 64];
+  const int M = g.n1 + g.n2 + g.n3h;
+  const long long plane = (long long)g.n1 * g.n2;
+  double acc[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) acc[k] = 0.0;
+  for (long long gi = (long long)blockIdx.x * NT + threadIdx.x; gi < g.NS; gi += (long long)gridDim.x * NT) {
+    const int k3 = (int)(gi / plane);
+    const long long rem = gi - k3 * plane;
+    const int k1 = (int)(rem / g.n2), k2 = (int)(rem - (long long)k1 * g.n2);
+    double gx, gy, gz;
+    const bool keep = gvec(g, k1, k2, k3, gx, gy, gz);
+    const double G2 = gx * gx + gy * gy + gz * gz;
+    if (!keep || G2 == 0.0) continue;
+    const double q = sqrt(G2);
+    const double wk = (k3 == 0) ? 1.0 : 2.0;
+    const cplx<R> nh = nhat[gi];
+    const double nx = double(nh.x), ny = double(nh.y);
+    const double gg[6] = {gx * gx, gy * gy, gz * gz, gx * gy, gy * gz, gx * gz};
+    const double h = wk * kFourPi * (nx * nx + ny * ny) / (G2 * G2);
+    double dua, dub;
+    form_ab_dq(lp, q, dua, dub);
+    double sx = 0.0, sy = 0.0;
+    for (int I = 0; I < nat; ++I) {
+      const double2* t = tab + (size_t)I * M;
+      const double2 e = zmul(zmul(t[k1], t[g.n1 + k2]), t[g.n1 + g.n2 + k3]);
+      const double u = Z[I] * dua + dub;
+      sx += u * e.x;
+      sy += u * e.y;
+    }
+    const double x = wk * (nx * sx + ny * sy) / q;   // w Re[conj(n) S']/|G|
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      acc[k] += h * gg[k];
+      acc[6 + k] += x * gg[k];
+    }
+  }
+  block_sum<12>(acc, red);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) part[k * gridDim.x + blockIdx.x] = acc[k];
+  }
+}
+
+// Local stress sums at every point (FP64), in part[k * gridDim.x + block]:
+//   0: f - n df/dn (ftTF: f - n T eta), 1: n (eps_xc - v_xc),
+//   2..7: W_a d_b n with W = 2 df/dsigma grad n (xx, yy, zz, xy, yz, xz; zero for ftTF).
+template <typename R, bool TF>
+__global__ void __launch_bounds__(NT) k_stress_local(const double* __restrict__ phi, const R* __restrict__ g0,
+                                                     const R* __restrict__ g1, const R* __restrict__ g2,
+                                                     long long npts, EvalParams ep, double* __restrict__ part) {
+  __shared__ double red[8 * NT / 64];
+  EnhParams enh{(int)ep.enh_kind, ep.enh_c1, ep.enh_a1};
+  double acc[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) acc[k] = 0.0;
+  for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < npts; i += (long long)gridDim.x * NT) {
+    const double p = phi[i];
+    const double n = p * p;
+    const double nf = n > kDensityFloor ? n : kDensityFloor;
+    const double ln_n = ln_pos(nf);
+    if constexpr (TF) {
+      double f, vt, tsl;
+      tf_point(nf, ln_n, ep.lt0, f, vt, tsl);
+      acc[0] += f - n * vt;
+    } else {
+      const R gx = g0[i], gy = g1[i], gz = g2[i];
+      const R sigma = gx * gx + gy * gy + gz * gz;
+      double f, tsl;
+      R dfdn, dfds;
+      gga_point<R>(nf, ln_n, sigma, ep.lt0, enh, f, dfdn, dfds, tsl);
+      acc[0] += f - n * double(dfdn);
+      const double w2 = 2.0 * double(dfds);
+      const double dx = double(gx), dy = double(gy), dz = double(gz);
+      acc[2] += w2 * dx * dx;
+      acc[3] += w2 * dy * dy;
+      acc[4] += w2 * dz * dz;
+      acc[5] += w2 * dx * dy;
+      acc[6] += w2 * dy * dz;
+      acc[7] += w2 * dx * dz;
+    }
+    if (ep.xc) {
+      R eps, vxc;
+      pz81<R>(ln_n, eps, vxc);
+      acc[1] += n * (double(eps) - double(vxc));
+    }
+  }
+  block_sum<8>(acc, red);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) part[k * gridDim.x + blockIdx.x] = acc[k];
+  }
+}
+
 // ---------------------------------------------------------------- host side
 #define OFDFT_LENGTHS(X) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(256)
 #define OFDFT_PLANE_LENGTHS(X) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128)
@@ -2262,7 +2387,7 @@ int dev_alloc_grid(ofdft_ctx* c) {
   for (int k = 0; k < 3 && ok; ++k) ok = dalloc_bytes(c, &c->gr[k], N * rs);
   ok = ok && dalloc(c, &c->partials, (size_t)SL_COUNT * c->max_blocks) && dalloc(c, &c->scalars, SC_COUNT) &&
        dalloc(c, &c->scalars_t, SC_COUNT) && dalloc(c, &c->scalars_t2, SC_COUNT) &&
-       dalloc(c, &c->vpart, 8 * VEC_BLOCKS) && dalloc(c, &c->vout, 16);
+       dalloc(c, &c->vpart, 8 * VEC_BLOCKS) && dalloc(c, &c->vout, 32);
   if (ok && !c->hmap) {
     ok = hip_ok(c, hipHostMalloc((void**)&c->hmap, (kMapDoubles + 1) * sizeof(double),
                                  hipHostMallocMapped | hipHostMallocCoherent), "hipHostMalloc (mapped)");
@@ -2312,7 +2437,8 @@ int dev_alloc_ions(ofdft_ctx* c) {
     c->phase = nullptr; c->dZ = nullptr; c->fpart = nullptr; c->dforces = nullptr;
     const int cap = c->nat * M;
     bool ok = dalloc(c, &c->phase, 2 * (size_t)cap) && dalloc(c, &c->dZ, c->nat + 4 * (size_t)c->nat) &&
-              dalloc(c, &c->fpart, (size_t)3 * c->nat * 1024) && dalloc(c, &c->dforces, 3 * (size_t)c->nat);
+              dalloc(c, &c->fpart, std::max<size_t>((size_t)3 * c->nat * 1024, 8 * PW_BLOCKS + 12 * 1024)) &&
+              dalloc(c, &c->dforces, 3 * (size_t)c->nat);
     if (!ok) return OFDFT_E_DEVICE;
     c->phase_cap = cap;
   }
@@ -2392,6 +2518,57 @@ static int forces_impl(ofdft_ctx* c, double* out_host) {
 
 int dev_forces(ofdft_ctx* c, double* forces_host) {
   return c->rsize == 4 ? forces_impl<float>(c, forces_host) : forces_impl<double>(c, forces_host);
+}
+
+// Stress sums at the current density: out[0..7] the local sums of k_stress_local
+// (times dv), out[8..19] the reciprocal sums of k_stress_recip.
+template <typename R>
+static int stress_impl(ofdft_ctx* c, double* out_host) {
+  const GridDesc& g = c->g;
+  const bool tf = c->opt.functional == OFDFT_TF;
+  const EvalParams ep = make_params(c);
+  // n(G) into D (kept modes, 1/N), and for a gradient functional grad n into gr[0..2]
+  if (plane_mode(c)) {
+    OFDFT_DISPATCH_PLANE(g.n3, (launch_plane_fwd_density<R, L_>(c, c->phi, c->A, nullptr)));
+  } else {
+    OFDFT_DISPATCH(g.n3, (launch_rpass_fwd<R, L_>(c, c->phi, c->A)));
+    OFDFT_DISPATCH(g.n2, (launch_x2<R, L_, -1>(c, c->A, nullptr, nullptr, 1)));
+  }
+  OFDFT_DISPATCH(g.n1, (launch_x1_density<R, L_, X1_NHAT>(c, c->A, c->D, nullptr, nullptr)));
+  if (!tf) {
+    OFDFT_DISPATCH(g.n1, (launch_x1_density<R, L_, X1_GGA>(c, c->A, c->B[0], c->B[1], c->B[2])));
+    if (plane_mode(c)) {
+      OFDFT_DISPATCH_PLANE(g.n3, (launch_plane_inv_real<R, L_>(c, c->B[0], c->B[1], c->B[2], c->gr[0], c->gr[1],
+                                                               c->gr[2], 3)));
+    } else {
+      OFDFT_DISPATCH(g.n2, (launch_x2<R, L_, +1>(c, c->B[0], c->B[1], c->B[2], 3)));
+      OFDFT_DISPATCH(g.n3, (launch_rpass_inv_real3<R, L_>(c)));
+    }
+  }
+  const int nbl = pw_blocks(g);
+  if (tf)
+    hipLaunchKernelGGL((k_stress_local<R, true>), dim3(nbl), dim3(NT), 0, c->stream, c->phi, (const R*)nullptr,
+                       (const R*)nullptr, (const R*)nullptr, g.N, ep, c->fpart);
+  else
+    hipLaunchKernelGGL((k_stress_local<R, false>), dim3(nbl), dim3(NT), 0, c->stream, c->phi, (const R*)c->gr[0],
+                       (const R*)c->gr[1], (const R*)c->gr[2], g.N, ep, c->fpart);
+  hipLaunchKernelGGL((k_vec_final<8>), dim3(1), dim3(NT), 0, c->stream, c->fpart, nbl, c->vout);
+  const int nbr = (int)std::min<long long>(1024, std::max<long long>(1, g.NS / (16LL * NT)));
+  hipLaunchKernelGGL(k_stress_recip<R>, dim3(nbr), dim3(NT), 0, c->stream, c->nat, c->dZ, (const double2*)c->phase,
+                     (const cplx<R>*)c->D, g, lpp_of(c), c->fpart + 8 * (size_t)nbl);
+  hipLaunchKernelGGL((k_vec_final<12>), dim3(1), dim3(NT), 0, c->stream, c->fpart + 8 * (size_t)nbl, nbr,
+                     c->vout + 8);
+  if (!hip_ok(c, hipGetLastError(), "stress launch")) return OFDFT_E_DEVICE;
+  double h[20];
+  int rc = dev_read(c, c->vout, 20, h);
+  if (rc) return rc;
+  for (int k = 0; k < 8; ++k) out_host[k] = h[k] * g.dv;
+  for (int k = 8; k < 20; ++k) out_host[k] = h[k];
+  return OFDFT_OK;
+}
+
+int dev_stress(ofdft_ctx* c, double* sums) {
+  return c->rsize == 4 ? stress_impl<float>(c, sums) : stress_impl<double>(c, sums);
 }
 
 // ---------------------------------------------------------------- vector-op launchers

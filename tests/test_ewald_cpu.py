@@ -81,3 +81,22 @@ def test_invalid_arguments_are_rejected():
         B.ewald(np.eye(3) * 5, np.zeros((1, 3)), -np.ones(1))
     with pytest.raises(B.OFDFTError):
         B.ewald(np.eye(3) * 5, np.full((1, 3), np.nan), np.ones(1))
+
+
+@pytest.mark.parametrize("case", ["cubic", "triclinic"])
+def test_stress_term_matches_oracle(case):
+    """The library's Ewald stress term against the oracle's strain derivative (which the
+    oracle's own tests pin by finite differences of the energy under strain)."""
+    from oracle import stress as st
+    if case == "cubic":
+        c = wl.h_cell(16, 1.0, 16, 1e4, seed=903)
+        lat, pos, Z = c.lattice, c.positions, c.charges
+    else:
+        rng = np.random.default_rng(12)
+        lat = np.array([[6.1, 0.0, 0.0], [1.3, 5.4, 0.0], [-0.8, 0.9, 7.2]])
+        pos = rng.random((9, 3)) @ lat
+        Z = rng.uniform(0.5, 3.0, 9)
+    E, F, sig = B.ewald(lat, pos, Z, stress=True)
+    ref = st.ewald_stress(lat, pos, Z) / abs(np.linalg.det(lat))
+    assert np.allclose(sig, sig.T)
+    assert np.max(np.abs(sig - ref)) <= 1e-11 * np.max(np.abs(ref))
