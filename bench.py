@@ -165,8 +165,16 @@ def md_run(P, wl, precision, n_steps):
     recs = md.velocity_verlet(ctx, cell.positions, v0, cell.charges, masses, dt, n_steps)
     steps = recs[1:]
     e = [r.F_total + r.kinetic for r in recs]
+    # stress tensor at the last converged density (ofdft_stress), timed
+    ctx.stress()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        sig = ctx.stress()
+    stress_ms = (time.perf_counter() - t0) / 5 * 1e3
     ctx.close()
     return {
+        "stress_ms": stress_ms,
+        "pressure_Ha_per_bohr3": -float(sig[0][0] + sig[1][1] + sig[2][2]) / 3.0,
         "ms_per_step": sum(r.wall_ms for r in steps) / len(steps),
         "evals_per_step": sum(r.evaluations for r in steps) / len(steps),
         "first_minimization_ms": recs[0].wall_ms,

@@ -21,6 +21,9 @@ Modules
   energy       one evaluation of F_tot[n = phi^2] and its derivative.
   minimize     sphere-constrained nonlinear CG and truncated Newton (Sec. II).
   forces       ionic forces at the converged density (Eq. M12).
+  stress       stress tensor and pressure (Eqs. StressTensor, pressure,
+               stressTF_a, stressTF_b, and the Hartree, pseudopotential and
+               Ewald strain derivatives).
   md           velocity-Verlet Born-Oppenheimer dynamics.
 
 All quantities are in Hartree atomic units; temperatures enter in kelvin at the
@@ -30,5 +33,5 @@ Parity status: every function is pinned by a test in tests/test_oracle_*.py
 against closed forms, limits, brute-force sums or high-precision quadrature
 (see each module's header for its pins).
 """
-from . import fermi_dirac, functionals, grid, potentials, energy, minimize, forces, md  # noqa: F401
+from . import fermi_dirac, functionals, grid, potentials, energy, minimize, forces, md, stress  # noqa: F401
 from .energy import System, evaluate  # noqa: F401
