@@ -80,3 +80,22 @@ def test_stress_is_the_strain_derivative_of_the_converged_energy():
     V0 = abs(np.linalg.det(cell.lattice))
     dFdV = (F[2] - F[0]) / (V0 * ((1 + h) ** 3 - (1 - h) ** 3))
     assert P == pytest.approx(-dFdV, rel=1e-5)
+
+
+def test_nvt_md_steps_with_pressure_and_output_block(tmp_path):
+    """A few Andersen-NVT steps through the library with the pressure in each record,
+    the paper's output block and an md.xyz trajectory."""
+    from paper_1406_0835_amd import md
+    cell = _cell((16, 16, 16), False, nat=4, seed=822)
+    ctx, _ = make_pair(cell, "VT84F", tol_energy=1e-9)
+    m = np.full(cell.nat, md.H_MASS_ME)
+    v0 = md.maxwell_boltzmann(cell.nat, 5e4, md.H_MASS_ME, seed=3)
+    frames = []
+    recs = md.velocity_verlet(ctx, cell.positions, v0, cell.charges, m, 0.2 * md.FS_AU, 3,
+                              thermostat=md.Thermostat(5e4, 0.01, seed=4), pressure=True,
+                              callback=lambda r, x, v, f: frames.append((r.step, x.copy(), r.F_total)))
+    assert all(np.isfinite(r.pressure) for r in recs)
+    assert recs[-1].E_internal == pytest.approx(recs[-1].F_total + recs[-1].TS, rel=1e-12)
+    assert "EinternEl" in md.output_block(recs[-1])
+    md.write_xyz(str(tmp_path / "md.xyz"), frames, ["H"] * cell.nat)
+    assert (tmp_path / "md.xyz").read_text().count("step") == 3
