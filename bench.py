@@ -183,6 +183,30 @@ def md_run(P, wl, precision, n_steps):
     }
 
 
+def al_static(P, wl, precision):
+    """The static fcc-Al workload: 2048 ions (8^3 conventional cells), 2.70 g/cm^3, 100 K,
+    VT84F + PZ81, Heine-Abarenkov Al pseudopotential, 128^3 grid; one density optimisation
+    from the uniform density, then forces and stress."""
+    cell = wl.fcc_al_cell(8, 128)
+    lpp = wl.AL_HA_LPP
+    ctx = make_context(P, cell, "VT84F", precision, tol_energy=1e-9 * cell.nat, max_iter=2000,
+                       lpp="ha", lpp_rc=lpp["rc"], lpp_A=lpp["A"], lpp_qc=lpp["qc"])
+    sync()
+    t0 = time.perf_counter()
+    rep = ctx.minimize_density()
+    sync()
+    t_min = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _, _, f = ctx.free_energy_and_forces(forces=True)
+    P_el = ctx.pressure()
+    t_fs = time.perf_counter() - t0
+    ctx.close()
+    return {"atoms": cell.nat, "grid": list(cell.grid), "precision": precision,
+            "minimize_ms": 1e3 * t_min, "iterations": rep.iterations, "evaluations": rep.evaluations,
+            "F_per_atom_Ha": rep.F_total / cell.nat, "max_force_Ha_bohr": float(abs(f).max()),
+            "pressure_Ha_per_bohr3": P_el, "forces_and_stress_ms": 1e3 * t_fs}
+
+
 def batch_run(P, wl, n_cells, precision):
     """Heterogeneous batch: all cells minimised concurrently vs one after another."""
     import numpy as np
@@ -295,6 +319,7 @@ def main():
     ap.add_argument("--no-md", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-al", action="store_true", help="skip the static fcc-Al line (--no-md skips it too)")
     ap.add_argument("--kernel-steps", type=int, default=50)
     ap.add_argument("--no-tune", action="store_true", help="keep the default FFT tiles")
     ap.add_argument("--batch", type=int, default=0, help="also run the heterogeneous batch of this many cells")
@@ -372,6 +397,11 @@ def main():
         md_res = {"mixed": md_run(P, wl, "mixed", args.md_steps), "fp64": md_run(P, wl, "fp64", args.md_steps),
                   "workload": "128 H, 1.0 g/cm^3, 64^3 grid, T=50 kK, VT84F+PZ81, CG to 1e-8 Ha, dt=0.2 fs"}
 
+    al = None
+    if not args.no_al and not args.no_md:
+        log("static fcc-Al: 2048 ions, 128^3, mixed and FP64")
+        al = {"mixed": al_static(P, wl, "mixed"), "fp64": al_static(P, wl, "fp64")}
+
     batch = None
     if args.batch > 0:
         log(f"batch of {args.batch} cells")
@@ -409,6 +439,7 @@ def main():
         "kernels": per_kernel,
         "fp64": fp64,
         "md_step": md_res,
+        "al_static": al,
         "batch": batch,
         "md_trajectory": mdl,
         "cpu_baseline": cpu,

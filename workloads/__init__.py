@@ -122,6 +122,27 @@ def md_cell() -> HCell:
     return h_cell(128, 1.0, 64, 5.0e4, SEED_BASE + 4)
 
 
+AL_MASS_AMU = 26.9815385
+# Heine-Abarenkov local pseudopotential of Al (parameters quoted in the paper's
+# pseudopotential section, Eq. E4A): r_c (bohr), A (hartree), q_c (1/bohr)
+AL_HA_LPP = {"kind": "ha", "rc": 1.15, "A": 0.1107, "qc": 3.5}
+
+
+def fcc_al_cell(n_rep: int, grid, temperature_K: float = 100.0, rho_gcc: float = 2.70) -> HCell:
+    """fcc aluminium (Z = 3 valence electrons per ion), n_rep^3 conventional cells of four
+    ions at rho (the static scaling workload: 2.70 g/cm^3, 100 K, 2048 ions for n_rep = 8)."""
+    if isinstance(grid, int):
+        grid = (grid, grid, grid)
+    a = cubic_edge_bohr(4, rho_gcc, AL_MASS_AMU)
+    basis = np.array([[0, 0, 0], [0, 0.5, 0.5], [0.5, 0, 0.5], [0.5, 0.5, 0]])
+    cells = np.array([[i, j, k] for i in range(n_rep) for j in range(n_rep) for k in range(n_rep)], dtype=float)
+    pos = (cells[:, None, :] + basis[None, :, :]).reshape(-1, 3) * a
+    nat = pos.shape[0]
+    return HCell(lattice=np.eye(3) * a * n_rep, positions=pos, charges=np.full(nat, 3.0),
+                 grid=tuple(int(g) for g in grid), temperature_K=float(temperature_K), rho_gcc=float(rho_gcc),
+                 seed=0)
+
+
 def smooth_field(shape, n_modes: int, seed: int, max_freq: int = 3) -> np.ndarray:
     """A smooth real field on a periodic grid: a sum of random low-order cosines, max |.| = 1."""
     rng = np.random.Generator(np.random.PCG64(seed))
