@@ -12,9 +12,12 @@ launched back to back on the library's stream.
 Also reported: the same rate in FP64, per-kernel HIP-event durations with the
 roofline of the dominant kernel, milliseconds per converged MD step (128 H,
 1.0 g/cm^3, 64^3, 50 kK, VT84F, warm-started velocity Verlet) in mixed and FP64
-precision, and the FP64 CPU oracle timed on the host as a baseline.
+precision with the stress tensor timed at the last step, one density optimisation
+of the static fcc-Al workload (2048 ions, 128^3, 100 K, Heine-Abarenkov Al
+pseudopotential) in mixed and FP64 with its forces and pressure, and the FP64
+CPU oracle timed on the host as a baseline.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--md-steps M] [--no-md] [--no-cpu]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--md-steps M] [--no-md] [--no-al] [--no-cpu]
 """
 import argparse
 import json
