@@ -1087,7 +1087,7 @@ __global__ void __launch_bounds__(NTP) k_plane_fwd_density(const double* __restr
 
 // F3: forward x3 and x2 transforms of real arrays (component blockIdx.y).
 template <typename R, int L, int NTH>
-__global__ void __launch_bounds__(NTH, 4) k_plane_fwd_real(RealArr3 in, Arr3 out, const cplx<R>* __restrict__ tw_g,
+__global__ void __launch_bounds__(NTH, sizeof(R) == 4 ? 8 : 4) k_plane_fwd_real(RealArr3 in, Arr3 out, const cplx<R>* __restrict__ tw_g,
                                                         GridDesc g) {
   static_assert(plane_maxe<L, NTH>() <= 16, "plane too large for the in-place FFT registers");
   extern __shared__ __align__(16) char smem_raw[];
@@ -1162,7 +1162,7 @@ __global__ void __launch_bounds__(NTP) k_plane_fwd_grad(const double* __restrict
 
 // I3: inverse x2 and x3 transforms into real arrays (component blockIdx.y).
 template <typename R, int L, int NTH>
-__global__ void __launch_bounds__(NTH, 4) k_plane_inv_real(Arr3 in, RealArr3 out, const cplx<R>* __restrict__ tw_g,
+__global__ void __launch_bounds__(NTH, sizeof(R) == 4 ? 8 : 4) k_plane_inv_real(Arr3 in, RealArr3 out, const cplx<R>* __restrict__ tw_g,
                                                         GridDesc g) {
   static_assert(plane_maxe<L, NTH>() <= 16, "plane too large for the in-place FFT registers");
   extern __shared__ __align__(16) char smem_raw[];
