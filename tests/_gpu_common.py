@@ -6,8 +6,8 @@ import workloads as wl
 from paper_1406_0835_amd import binding as B
 
 
-def make_pair(cell, functional="TF", precision="fp64", minimizer="cg", xc="PZ81", lpp=None, tol_energy=1e-10,
-              tol_residual=0.0, max_iter=2000, mu_sga=5.0 / 27.0, cg_precond=0.0):
+def make_ctx(cell, functional="TF", precision="fp64", minimizer="cg", xc="PZ81", lpp=None, tol_energy=1e-10,
+             tol_residual=0.0, max_iter=2000, mu_sga=5.0 / 27.0, cg_precond=0.0):
     lpp = lpp or {"kind": "gauss", "rc": 0.5}
     kw = dict(functional=functional, precision=precision, minimizer=minimizer, xc=xc.lower(),
               lpp_rc=lpp["rc"], tol_energy=tol_energy, tol_residual=tol_residual, max_iter=max_iter,
@@ -19,10 +19,21 @@ def make_pair(cell, functional="TF", precision="fp64", minimizer="cg", xc="PZ81"
     ctx.set_cell(cell.lattice, cell.grid)
     ctx.set_ions(cell.positions, cell.charges)
     ctx.set_temperature(cell.temperature_K)
-    sysm = oracle.System(cell.lattice, cell.grid, cell.positions, cell.charges, cell.temperature_K,
+    return ctx
+
+
+def oracle_system(cell, functional="TF", xc="PZ81", lpp=None, mu_sga=5.0 / 27.0):
+    lpp = lpp or {"kind": "gauss", "rc": 0.5}
+    return oracle.System(cell.lattice, cell.grid, cell.positions, cell.charges, cell.temperature_K,
                          functional=functional, xc=xc.upper() if xc.upper() != "NONE" else "NONE", lpp=lpp,
                          mu_sga=mu_sga)
-    return ctx, sysm
+
+
+def make_pair(cell, functional="TF", precision="fp64", minimizer="cg", xc="PZ81", lpp=None, tol_energy=1e-10,
+              tol_residual=0.0, max_iter=2000, mu_sga=5.0 / 27.0, cg_precond=0.0):
+    ctx = make_ctx(cell, functional, precision, minimizer, xc, lpp, tol_energy, tol_residual, max_iter, mu_sga,
+                   cg_precond)
+    return ctx, oracle_system(cell, functional, xc, lpp, mu_sga)
 
 
 def normalized_phi(sysm, seed, contrast=0.5):

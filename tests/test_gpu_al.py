@@ -1,14 +1,17 @@
 """fcc aluminium with the Heine-Abarenkov Al pseudopotential (Eq. E4A, the paper's
 static scaling workload at 2.70 g/cm^3 and 100 K): one evaluation against the
 oracle, and at the converged density the symmetries of the perfect lattice (zero
-forces, an isotropic stress tensor) in FP64 and mixed precision."""
+forces, an isotropic stress tensor) in FP64 and mixed precision.  At the workload's
+full sizes (2048 ions on 128^3, 16384 ions on 256^3, 16 points per cell edge) a density
+with the period of one conventional cell makes the supercell's free energy exactly n^3
+times the single cell's, so the oracle's one-cell evaluation checks the full-size one."""
 import numpy as np
 import pytest
 
 import oracle
 import workloads as wl
 
-from _gpu_common import make_pair, normalized_phi, rel
+from _gpu_common import make_ctx, make_pair, normalized_phi, oracle_system, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -42,3 +45,60 @@ def test_al_lattice_symmetries_at_the_minimum():
         assert np.max(np.abs(d - d.mean())) <= (1e-8 if precision == "fp64" else 1e-5) * abs(d.mean())
         assert np.max(np.abs(sig - np.diag(d))) <= (1e-8 if precision == "fp64" else 1e-5) * abs(d.mean())
     assert rel(F["mixed"], F["fp64"]) <= 1e-6
+
+
+@pytest.mark.parametrize("n_rep", [8, 16])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-6)])
+def test_al_supercell_evaluation_is_the_tiled_cell(n_rep, precision, tol):
+    one = wl.fcc_al_cell(1, 16)
+    s1 = oracle_system(one, "VT84F", lpp=wl.AL_HA_LPP)
+    phi1 = normalized_phi(s1, seed=41, contrast=0.4)
+    ev = oracle.evaluate(phi1, s1)
+    cell = wl.fcc_al_cell(n_rep, 16 * n_rep)
+    ctx = make_ctx(cell, "VT84F", precision=precision, lpp=wl.AL_HA_LPP)
+    ctx.set_density(np.tile(phi1, (n_rep,) * 3))
+    rep, v = ctx.eval(potential=True)
+    k = n_rep ** 3
+    for a, b in [("F_total", "F_tot"), ("F_s", "F_s"), ("E_H", "E_H"), ("E_ext", "E_ext"), ("E_xc", "E_xc"),
+                 ("E_ion", "E_ion")]:
+        assert abs(getattr(rep, a) / k - getattr(ev, b)) <= tol * max(abs(getattr(ev, b)), 1e-3 * abs(ev.F_tot)), a
+    assert abs(rep.mu - ev.mu) <= tol * abs(ev.mu)
+    vt = np.tile(ev.v, (n_rep,) * 3)
+    assert np.sqrt(np.mean((v - vt) ** 2)) / np.sqrt(np.mean(vt ** 2)) <= 10 * tol
+    ctx.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_al_supercell_minimum_is_the_one_cell_minimum(precision):
+    """16384 ions on 256^3 reach the single cell's minimum per ion on the same grid spacing,
+    with zero forces and the single cell's isotropic stress.  From the uniform density the
+    energy-change stop leaves a convergence error of ~1e-8 per ion on this slowly converging
+    system; in FP64 a restart from the tiled one-cell minimum must then stay at it."""
+    fp64 = precision == "fp64"
+    one = wl.fcc_al_cell(1, 16)
+    c1 = make_ctx(one, "VT84F", precision=precision, lpp=wl.AL_HA_LPP, tol_energy=1e-10 * one.nat, cg_precond=8.0)
+    F1 = c1.minimize_density().F_total / one.nat
+    s1 = c1.stress()
+    phi1 = c1.get_density()
+    c1.close()
+    big = wl.fcc_al_cell(16, 256)
+    ctx = make_ctx(big, "VT84F", precision=precision, lpp=wl.AL_HA_LPP, tol_energy=1e-10 * big.nat, cg_precond=8.0)
+    rep = ctx.minimize_density()
+    print(precision, "uniform start", rep.iterations, rep.F_total / big.nat, F1, flush=True)
+    assert rel(rep.F_total / big.nat, F1) <= 1e-7
+    if fp64:
+        ctx.set_density(np.tile(phi1, (16, 16, 16)))
+        rep = ctx.minimize_density()
+        print(precision, "tiled start", rep.iterations, rep.F_total / big.nat, F1, flush=True)
+        # the single cell's own stop leaves ~1e-10 per ion, which the restart recovers
+        assert rel(rep.F_total / big.nat, F1) <= 1e-9
+    _, _, f = ctx.free_energy_and_forces()
+    sig = ctx.stress()
+    ctx.close()
+    d = np.diag(sig)
+    print(np.max(np.abs(f)), sig, s1, flush=True)
+    assert np.max(np.abs(f)) < (1e-6 if fp64 else 1e-4)
+    assert np.max(np.abs(sig - np.diag(d))) <= (1e-8 if fp64 else 1e-5) * abs(d.mean())
+    assert np.max(np.abs(d - d.mean())) <= (1e-8 if fp64 else 1e-5) * abs(d.mean())
+    # the stress is first order in the density error that either stop leaves
+    assert np.max(np.abs(sig - s1)) <= (1e-4 if fp64 else 1e-3) * abs(d.mean())
