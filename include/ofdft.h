@@ -159,8 +159,10 @@ int ofdft_free_energy_and_forces(ofdft_ctx* ctx, double* F_total, double* E_inte
    cell.  Sum of the non-interacting part (Eqs. stressTF_a, stressTF_b), the LDA
    XC term, Hartree and pseudopotential reciprocal-space terms, the alpha Z term
    and the Ewald term.  Needs a converged minimisation (OFDFT_E_STATE otherwise);
-   OFDFT_E_ARG if sigma is NULL.  Runs three FFT passes, two grid sums and an
-   N_ion x N_G phase sum on the device and the Ewald strain sum on the host. */
+   OFDFT_E_ARG if sigma is NULL.  Runs three FFT passes and two grid sums on the
+   device (the pseudopotential term reads the structure factors that
+   ofdft_set_ions stored); the Ewald strain sum comes from the host thread that
+   ofdft_set_ions started. */
 int ofdft_stress(ofdft_ctx* ctx, double sigma[9]);
 
 /* Current amplitude phi (N1*N2*N3 doubles). */

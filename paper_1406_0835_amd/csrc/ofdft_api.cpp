@@ -530,6 +530,7 @@ int ofdft_create(const ofdft_options* opt, ofdft_ctx** out) {
   c->opt = o;
   c->rsize = (o.precision == OFDFT_MIXED) ? 4 : 8;
   if (const char* pp = std::getenv("OFDFT_PLANE_PASSES")) c->plane_passes = std::atoi(pp) != 0;
+  if (const char* pf = std::getenv("OFDFT_ION_FORCES")) c->ion_forces = std::atoi(pf) != 0 ? 1 : 0;
   if (o.stream) {
     c->stream = (hipStream_t)o.stream;
   } else {
@@ -684,9 +685,7 @@ int ofdft_stress(ofdft_ctx* c, double sigma[9]) {
   int rc = dev_stress(c, s);
   if (rc) return fail(c, rc, c->err);
   if (!join_ewald(c)) return fail(c, OFDFT_E_ARG, "Ewald sum failed");
-  double E_ew = 0.0, ew[6];
-  std::vector<double> F_ew;
-  ewald_sum(c->lat, c->nat, c->tau.data(), c->Z.data(), E_ew, F_ew, ew);
+  const double* ew = c->ewald_strain;   // from the set_ions thread
   const double V = c->g.volume;
   const ofdft_report& r = c->last;
   // V Sigma per term: local delta (sum(f - n df/dn) + sum n (eps - v_xc) - tr B) - B,

@@ -262,7 +262,7 @@ void start_ewald(ofdft_ctx* c) {
   c->ewald_pending = true;
   c->ewald_thread = std::thread([c] {
     try {
-      ewald_sum(c->lat, c->nat, c->tau.data(), c->Z.data(), c->E_ion, c->F_ion);
+      ewald_sum(c->lat, c->nat, c->tau.data(), c->Z.data(), c->E_ion, c->F_ion, c->ewald_strain);
     } catch (...) {
       c->ewald_failed = true;
     }

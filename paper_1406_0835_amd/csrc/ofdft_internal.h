@@ -94,6 +94,7 @@ struct ofdft_ctx {
   std::vector<double> tau, Z;
   double Ne = 0.0, alpha_sum = 0.0, E_ion = 0.0;
   std::vector<double> F_ion;
+  double ewald_strain[6] = {0, 0, 0, 0, 0, 0};   // V Sigma of the Ewald energy (xx yy zz xy yz xz)
   // E_ion and F_ion come from a host thread started by set_ions; every reader
   // (and every writer of lat, nat, tau, Z) joins it first (ofdft::join_ewald)
   std::thread ewald_thread;
@@ -136,11 +137,17 @@ struct ofdft_ctx {
   // x3 and x2 transforms as one plane pass where the grid allows (on unless
   // OFDFT_PLANE_PASSES=0 in the environment at ofdft_create)
   bool plane_passes = true;
+  // force kernel: -1 picks by ion count, 0 the G-parallel one, 1 one thread per ion
+  // (OFDFT_ION_FORCES in the environment at ofdft_create)
+  int ion_forces = -1;
   double* hmap = nullptr;
   double* dmap = nullptr;      // the same memory as seen by kernels
   unsigned long long read_seq = 0;
   // ions on the device
   double* phase = nullptr;     // [nat][n1 + n2 + n3h] complex doubles
+  // structure factors sum_I Z_I e^{-iG.R_I} and sum_I e^{-iG.R_I} on the half spectrum
+  // ([2][NS] complex doubles), written with V_ext and read by the stress
+  double* sfac = nullptr;
   double* dZ = nullptr;
   double* fpart = nullptr;
   double* dforces = nullptr;

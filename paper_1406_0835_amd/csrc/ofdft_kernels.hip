@@ -1566,7 +1566,7 @@ __device__ __forceinline__ void form_ab(const LppParams& lp, double q, double vo
 template <typename R>
 __global__ void __launch_bounds__(NT) k_structure_factor(int nat, const double* __restrict__ Z,
                                                          const double2* __restrict__ tab, GridDesc g, LppParams lp,
-                                                         cplx<R>* __restrict__ vext) {
+                                                         cplx<R>* __restrict__ vext, double2* __restrict__ sfac) {
   const int M = g.n1 + g.n2 + g.n3h;
   const long long plane = (long long)g.n1 * g.n2;
   for (long long gi = (long long)blockIdx.x * NT + threadIdx.x; gi < g.NS; gi += (long long)gridDim.x * NT) {
@@ -1577,10 +1577,10 @@ __global__ void __launch_bounds__(NT) k_structure_factor(int nat, const double* 
     const bool keep = gvec(g, k1, k2, k3, gx, gy, gz);
     const double G2 = gx * gx + gy * gy + gz * gz;
     double2 out = make_double2(0.0, 0.0);
+    double2 sz = make_double2(0.0, 0.0), s1 = make_double2(0.0, 0.0);
     if (keep && G2 > 0.0) {
       double a, b;
       form_ab(lp, sqrt(G2), g.volume, a, b);
-      double2 sz = make_double2(0.0, 0.0), s1 = make_double2(0.0, 0.0);
       for (int I = 0; I < nat; ++I) {
         const double2* t = tab + (size_t)I * M;
         const double2 e = zmul(zmul(t[k1], t[g.n1 + k2]), t[g.n1 + g.n2 + k3]);
@@ -1592,6 +1592,8 @@ __global__ void __launch_bounds__(NT) k_structure_factor(int nat, const double* 
       out = make_double2(a * sz.x + b * s1.x, a * sz.y + b * s1.y);
     }
     vext[gi] = cplx<R>{R(out.x), R(out.y)};
+    sfac[gi] = sz;
+    sfac[g.NS + gi] = s1;
   }
 }
 
@@ -1645,6 +1647,77 @@ __global__ void __launch_bounds__(NT) k_forces(int nat, const double* __restrict
   }
 }
 
+// The same force sums with one thread per ion, for cells with many ions.  A block
+// takes a tile of NT ions and a chunk of rows (k3, k1) of the half spectrum; the
+// G-dependent factors of a row (G, and w conj(n) times the two form-factor parts)
+// are computed once into LDS and read by every ion of the tile, and each ion
+// advances its phase e^{-iG.R} along k2 by one complex multiply, re-seeded from
+// the phase tables every FRC_RESEED steps and where the signed frequency wraps
+// (k2 = n2/2 + 1).
+constexpr int FRC_RESEED = 8;
+constexpr int FRC_MAX_N2 = 256;
+
+template <typename R>
+__global__ void __launch_bounds__(NT) k_forces_ions(int nat, const double* __restrict__ Z,
+                                                    const double2* __restrict__ tab,
+                                                    const cplx<R>* __restrict__ nhat, GridDesc g, LppParams lp,
+                                                    int rows_per_chunk, double* __restrict__ part) {
+  __shared__ double4 sg[FRC_MAX_N2];   // G
+  __shared__ double4 sp[FRC_MAX_N2];   // w conj(n) a, w conj(n) b as (re, im, re, im)
+  const int M = g.n1 + g.n2 + g.n3h;
+  const int I = blockIdx.y * NT + threadIdx.x;
+  const bool have = I < nat;
+  const double2* t = tab + (size_t)(have ? I : 0) * M;
+  const double zI = have ? Z[I] : 0.0;
+  const double2 step = t[g.n1 + 1];   // m2 = +1
+  const int wrap2 = g.n2 / 2 + 1;   // m2 jumps from +n2/2 to 1 - n2/2 here
+  double ax = 0.0, ay = 0.0, az = 0.0;
+  const int nrows = g.n1 * g.n3h;
+  const int r0 = blockIdx.x * rows_per_chunk;
+  const int r1 = min(nrows, r0 + rows_per_chunk);
+  for (int r = r0; r < r1; ++r) {
+    const int k3 = r / g.n1, k1 = r - k3 * g.n1;
+    __syncthreads();   // every ion is done with the previous row
+    for (int k2 = threadIdx.x; k2 < g.n2; k2 += NT) {
+      double gx, gy, gz;
+      const bool keep = gvec(g, k1, k2, k3, gx, gy, gz);
+      const double G2 = gx * gx + gy * gy + gz * gz;
+      double4 fg = make_double4(0.0, 0.0, 0.0, 0.0), fp = make_double4(0.0, 0.0, 0.0, 0.0);
+      if (keep && G2 > 0.0) {
+        double a, b;
+        form_ab(lp, sqrt(G2), g.volume, a, b);
+        const double wk = (k3 == 0) ? 1.0 : 2.0;
+        const cplx<R> nh = nhat[(size_t)r * g.n2 + k2];
+        const double cx = wk * double(nh.x), cy = -wk * double(nh.y);
+        fg = make_double4(gx, gy, gz, 0.0);
+        fp = make_double4(cx * a, cy * a, cx * b, cy * b);
+      }
+      sg[k2] = fg;
+      sp[k2] = fp;
+    }
+    __syncthreads();
+    const double2 base = zmul(t[k1], t[g.n1 + g.n2 + k3]);
+    double2 e = base;
+    for (int k2 = 0; k2 < g.n2; ++k2) {
+      if ((k2 & (FRC_RESEED - 1)) == 0 || k2 == wrap2) e = zmul(base, t[g.n1 + k2]);
+      else e = zmul(e, step);
+      const double4 fg = sg[k2], fp = sp[k2];
+      // Im[w conj(n) e] (Z a + b)
+      const double ia = fp.x * e.y + fp.y * e.x;
+      const double ib = fp.z * e.y + fp.w * e.x;
+      const double im = zI * ia + ib;
+      ax += fg.x * im;
+      ay += fg.y * im;
+      az += fg.z * im;
+    }
+  }
+  if (have) {
+    part[((size_t)I * 3 + 0) * gridDim.x + blockIdx.x] = ax;
+    part[((size_t)I * 3 + 1) * gridDim.x + blockIdx.x] = ay;
+    part[((size_t)I * 3 + 2) * gridDim.x + blockIdx.x] = az;
+  }
+}
+
 // One wavefront per force component: lanes stride over its block partials, then
 // a fixed-order wave sum (k is uniform across a wavefront, so whole waves exit).
 __global__ void __launch_bounds__(NT) k_forces_final(int nat, const double* __restrict__ part, int nb, double scale,
@@ -1684,12 +1757,10 @@ __device__ __forceinline__ void form_ab_dq(const LppParams& lp, double q, double
 //   part[0..5]:  w 4 pi |n(G)|^2 G_a G_b / G^4                  (Hartree)
 //   part[6..11]: w Re[conj(n(G)) sum_I u_I'(|G|) e^{-iG.R_I}] G_a G_b / |G|   (pseudopotential)
 template <typename R>
-__global__ void __launch_bounds__(NT) k_stress_recip(int nat, const double* __restrict__ Z,
-                                                     const double2* __restrict__ tab,
+__global__ void __launch_bounds__(NT) k_stress_recip(const double2* __restrict__ sfac,
                                                      const cplx<R>* __restrict__ nhat, GridDesc g, LppParams lp,
                                                      double* __restrict__ part) {
   __shared__ double red[12 * NT / 64];
-  const int M = g.n1 + g.n2 + g.n3h;
   const long long plane = (long long)g.n1 * g.n2;
   double acc[12];
 #pragma unroll
@@ -1710,14 +1781,10 @@ __global__ void __launch_bounds__(NT) k_stress_recip(int nat, const double* __re
     const double h = wk * kFourPi * (nx * nx + ny * ny) / (G2 * G2);
     double dua, dub;
     form_ab_dq(lp, q, dua, dub);
-    double sx = 0.0, sy = 0.0;
-    for (int I = 0; I < nat; ++I) {
-      const double2* t = tab + (size_t)I * M;
-      const double2 e = zmul(zmul(t[k1], t[g.n1 + k2]), t[g.n1 + g.n2 + k3]);
-      const double u = Z[I] * dua + dub;
-      sx += u * e.x;
-      sy += u * e.y;
-    }
+    // sum_I (Z_I u_a' + u_b') e^{-iG.R_I} from the stored structure factors
+    const double2 sz = sfac[gi], s1 = sfac[g.NS + gi];
+    const double sx = dua * sz.x + dub * s1.x;
+    const double sy = dua * sz.y + dub * s1.y;
     const double x = wk * (nx * sx + ny * sy) / q;   // w Re[conj(n) S']/|G|
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
@@ -2381,6 +2448,7 @@ int dev_alloc_grid(ofdft_ctx* c) {
   ok = ok && dalloc_bytes(c, &c->A, NS * 2 * rs) && dalloc_bytes(c, &c->S0, NS * 2 * rs) &&
        dalloc_bytes(c, &c->D, NS * 2 * rs) && dalloc_bytes(c, &c->Vext, NS * 2 * rs);
   for (int k = 0; k < 3 && ok; ++k) ok = dalloc_bytes(c, &c->B[k], NS * 2 * rs);
+  ok = ok && dalloc(c, &c->sfac, 4 * NS);
   // sized for the smallest tiles the tuner may pick (2 rows / 2 columns per block)
   const int nb_r = (g.n2 / 2) * g.n1, nb_x1 = (g.n2 / 2) * g.n3h;
   c->max_blocks = std::max(std::max(nb_r, nb_x1), PW_BLOCKS);
@@ -2419,7 +2487,7 @@ void dev_free_grid(ofdft_ctx* c) {
                  (void**)&c->partials, (void**)&c->scalars, (void**)&c->scalars_t, (void**)&c->vpart,
                  (void**)&c->vout, &c->gr[0], &c->gr[1], &c->gr[2], (void**)&c->phi_hist[0],
                  (void**)&c->phi_hist[1], (void**)&c->phi_hist[2], (void**)&c->phi_t2, &c->v_t2,
-                 (void**)&c->scalars_t2};
+                 (void**)&c->scalars_t2, (void**)&c->sfac};
   for (void** p : ps) {
     if (*p) (void)hipFree(*p);
     *p = nullptr;
@@ -2482,10 +2550,10 @@ int dev_structure_factor(ofdft_ctx* c) {
   const int nb2 = (int)std::min<long long>(8192, (g.NS + NT - 1) / NT);
   if (c->rsize == 4)
     hipLaunchKernelGGL(k_structure_factor<float>, dim3(nb2), dim3(NT), 0, c->stream, c->nat, c->dZ,
-                       (const double2*)c->phase, g, lpp_of(c), (cplx<float>*)c->Vext);
+                       (const double2*)c->phase, g, lpp_of(c), (cplx<float>*)c->Vext, (double2*)c->sfac);
   else
     hipLaunchKernelGGL(k_structure_factor<double>, dim3(nb2), dim3(NT), 0, c->stream, c->nat, c->dZ,
-                       (const double2*)c->phase, g, lpp_of(c), (cplx<double>*)c->Vext);
+                       (const double2*)c->phase, g, lpp_of(c), (cplx<double>*)c->Vext, (double2*)c->sfac);
   hipError_t e = hipStreamSynchronize(c->stream);
   return hip_ok(c, e, "structure factor") ? OFDFT_OK : OFDFT_E_DEVICE;
 }
@@ -2501,11 +2569,25 @@ static int forces_impl(ofdft_ctx* c, double* out_host) {
     OFDFT_DISPATCH(g.n2, (launch_x2<R, L_, -1>(c, c->A, nullptr, nullptr, 1)));
   }
   OFDFT_DISPATCH(g.n1, (launch_x1_density<R, L_, X1_NHAT>(c, c->A, c->D, nullptr, nullptr)));
-  // about sixteen G vectors per thread, so the per-block reduction stays a small share
-  const int nbx = (int)std::min<long long>(1024, std::max<long long>(1, g.NS / (16LL * NT)));
-  const int nby = (c->nat + FORCE_IONS - 1) / FORCE_IONS;
-  hipLaunchKernelGGL(k_forces<R>, dim3(nbx, nby), dim3(NT), 0, c->stream, c->nat, c->dZ, (const double2*)c->phase,
-                     (const cplx<R>*)c->D, g, lpp_of(c), c->fpart);
+  int nbx;
+  const bool per_ion = c->nat > 0 && (c->ion_forces == 1 || (c->ion_forces < 0 && c->nat >= NT));
+  if (per_ion) {
+    // one tile of NT ions per block row; enough row chunks for about 4096 blocks (at most
+    // 1024, the partial-sum capacity per force component)
+    const int nby = (c->nat + NT - 1) / NT;
+    const int nrows = g.n1 * g.n3h;
+    const int want = (int)std::min<long long>(std::min(1024, nrows), std::max(1, (4096 + nby - 1) / nby));
+    const int rows_per_chunk = (nrows + want - 1) / want;
+    nbx = (nrows + rows_per_chunk - 1) / rows_per_chunk;
+    hipLaunchKernelGGL(k_forces_ions<R>, dim3(nbx, nby), dim3(NT), 0, c->stream, c->nat, c->dZ,
+                       (const double2*)c->phase, (const cplx<R>*)c->D, g, lpp_of(c), rows_per_chunk, c->fpart);
+  } else {
+    // about sixteen G vectors per thread, so the per-block reduction stays a small share
+    nbx = (int)std::min<long long>(1024, std::max<long long>(1, g.NS / (16LL * NT)));
+    const int nby = (c->nat + FORCE_IONS - 1) / FORCE_IONS;
+    hipLaunchKernelGGL(k_forces<R>, dim3(nbx, nby), dim3(NT), 0, c->stream, c->nat, c->dZ,
+                       (const double2*)c->phase, (const cplx<R>*)c->D, g, lpp_of(c), c->fpart);
+  }
   hipLaunchKernelGGL(k_forces_final, dim3((3 * c->nat + NT / 64 - 1) / (NT / 64)), dim3(NT), 0, c->stream, c->nat,
                      c->fpart, nbx, -g.volume, c->dforces);
   if (!hip_ok(c, hipMemcpyAsync(out_host, c->dforces, 3 * (size_t)c->nat * sizeof(double), hipMemcpyDeviceToHost,
@@ -2554,7 +2636,7 @@ static int stress_impl(ofdft_ctx* c, double* out_host) {
                        (const R*)c->gr[1], (const R*)c->gr[2], g.N, ep, c->fpart);
   hipLaunchKernelGGL((k_vec_final<8>), dim3(1), dim3(NT), 0, c->stream, c->fpart, nbl, c->vout);
   const int nbr = (int)std::min<long long>(1024, std::max<long long>(1, g.NS / (16LL * NT)));
-  hipLaunchKernelGGL(k_stress_recip<R>, dim3(nbr), dim3(NT), 0, c->stream, c->nat, c->dZ, (const double2*)c->phase,
+  hipLaunchKernelGGL(k_stress_recip<R>, dim3(nbr), dim3(NT), 0, c->stream, (const double2*)c->sfac,
                      (const cplx<R>*)c->D, g, lpp_of(c), c->fpart + 8 * (size_t)nbl);
   hipLaunchKernelGGL((k_vec_final<12>), dim3(1), dim3(NT), 0, c->stream, c->fpart + 8 * (size_t)nbl, nbr,
                      c->vout + 8);
