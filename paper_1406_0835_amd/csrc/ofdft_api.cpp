@@ -259,7 +259,9 @@ bool stop_rule(const ofdft_ctx* c, int small, double resid) {
 // converged if the residual target (when one is set) is met, otherwise if the
 // last steps were already below the energy tolerance; in the mixed path (FP32
 // terms summed in FP64) also once the last decrease is below 1e-6 |F| (its
-// stated accuracy).
+// stated accuracy).  Before any step is taken (a start at a converged density)
+// the first-order decrease |dF/dtheta(0)| theta_1 at the rejected first trial
+// stands in for the last decrease.
 bool stalled_converged(ofdft_ctx* c, int small, double last_dF, double F, double resid) {
   // F is the electronic part; the stated accuracy refers to the total, E_ion included
   const bool noise_floor = c->rsize == 4 && join_ewald(c) && std::fabs(last_dF) < 1e-6 * std::fabs(F + c->E_ion);
@@ -332,7 +334,7 @@ int minimize_cg(ofdft_ctx* c, ofdft_report* rep) {
     if ((rc = line_search(c, F, dF0, r, std::sqrt(phinorm2), dn, theta1, nevals, ls, have_trial0 ? trial0 : nullptr)))
       return rc;
     if (!ls.ok) {
-      converged = stalled_converged(c, small, last_dF, F, resid);
+      converged = stalled_converged(c, small, have_prev ? last_dF : std::fabs(dF0) * theta1, F, resid);
       break;
     }
     accept_trial(c);

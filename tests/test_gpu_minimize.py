@@ -210,3 +210,23 @@ def test_extrapolated_warm_start_reaches_the_same_minimum():
     ctxs[1].set_density(phi)
     ctxs[1].set_ions(cell.positions + 5 * step, cell.charges)
     assert np.allclose(ctxs[1].get_density(), phi, rtol=1e-13, atol=0.0)
+
+
+@pytest.mark.parametrize("kind", ["h", "al"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_restart_at_the_converged_density_reports_convergence(kind, precision):
+    """A second optimisation started at the converged density stays there and converges (in
+    the mixed path its first line search can find nothing below the noise floor)."""
+    if kind == "h":
+        cell, lpp, fn = wl.h_cell(32, 1.0, 32, 5e4, seed=705), None, "VT84F"
+    else:
+        cell, lpp, fn = wl.fcc_al_cell(2, 32), wl.AL_HA_LPP, "VT84F"
+    tol = 1e-10 if precision == "fp64" else 1e-8
+    ctx, _ = make_pair(cell, fn, precision=precision, lpp=lpp, tol_energy=tol * cell.nat, cg_precond=PRECOND)
+    F1 = ctx.minimize_density().F_total
+    ctx.set_density(ctx.get_density())
+    rep = ctx.minimize_density()
+    assert rep.converged
+    # FP64 may keep descending by what the first stop left (~1e-9 relative here)
+    assert rel(rep.F_total, F1) <= (1e-8 if precision == "fp64" else 1e-6)
+    assert rep.F_total <= F1 + (1e-12 if precision == "fp64" else 1e-6) * abs(F1)
