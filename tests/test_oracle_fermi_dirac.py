@@ -94,8 +94,8 @@ def test_kappa_low_temperature_limit():
     assert f["kappa"][0] == pytest.approx(1 - 5 * math.pi ** 2 / 12 * 1e-6, abs=1e-11)
     assert f["xi"][0] == pytest.approx(1 + 5 * math.pi ** 2 / 12 * 1e-6, abs=1e-11)
     assert f["zeta"][0] == pytest.approx(5 * math.pi ** 2 / 6 * 1e-6, rel=1e-5)
-    # survey value at t = 0.01
-    assert fd.t_factors(np.array([0.01]))["kappa"][0] == pytest.approx(0.9995887868, abs=2e-10)
+    # the full value at t = 0.01 from the polylogarithm (see _kappa_polylog)
+    assert fd.t_factors(np.array([0.01]))["kappa"][0] == pytest.approx(_kappa_polylog(0.01), abs=2e-10)
 
 
 def test_classical_ideal_gas_limit():
@@ -114,8 +114,23 @@ def test_classical_ideal_gas_limit():
     assert f["xi"][0] / (2.5 * t) == pytest.approx(1.0 + y / 2 ** 2.5, rel=1e-9)
 
 
-def test_survey_classical_value():
-    assert fd.t_factors(np.array([50.0]))["kappa"][0] == pytest.approx(-596.02844, abs=2e-5)
+def _kappa_polylog(t):
+    """kappa(t) = (5/3) t (eta - F_{3/2}/F_{1/2}) (Table I, note a) with F_j(eta) =
+    -Li_{j+1}(-e^eta) from mpmath's polylogarithm at 40 digits and eta from
+    F_{1/2}(eta) = 4/(3 sqrt pi) t^(-3/2) (Eq. tred): independent of the oracle's quadrature."""
+    mp = pytest.importorskip("mpmath")
+    with mp.workdps(40):
+        def F(j, eta):
+            return -mp.polylog(j + 1, -mp.e ** eta)
+        tt = mp.mpf(t)
+        target = 4 / (3 * mp.sqrt(mp.pi)) * tt ** mp.mpf(-1.5)
+        eta = mp.findroot(lambda e: F(mp.mpf(1) / 2, e) - target, 1 / tt if tt < 1 else mp.log(target))
+        return float(mp.re(5 * tt / 3 * (eta - F(mp.mpf(3) / 2, eta) / F(mp.mpf(1) / 2, eta))))
+
+
+@pytest.mark.parametrize("t", [0.3, 2.0, 50.0])
+def test_kappa_against_polylogarithm(t):
+    assert fd.t_factors(np.array([t]))["kappa"][0] == pytest.approx(_kappa_polylog(t), rel=1e-11)
 
 
 def test_t_derivatives_by_finite_difference():
