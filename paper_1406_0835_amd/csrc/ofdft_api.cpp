@@ -695,7 +695,8 @@ int ofdft_stress(ofdft_ctx* c, double sigma[9]) {
   const double trB = s[2] + s[3] + s[4];
   double t[6];
   for (int k = 0; k < 6; ++k) t[k] = -s[2 + k] + V * s[8 + k] - s[14 + k] + ew[k];
-  for (int k = 0; k < 3; ++k) t[k] += s[0] + s[1] - trB - r.E_H - r.E_ext - r.E_alphaZ;
+  // the device reciprocal sums carry the Ewald G-space strain terms; -delta E_rec here
+  for (int k = 0; k < 3; ++k) t[k] += s[0] + s[1] - trB - r.E_H - r.E_ext - r.E_alphaZ - c->E_rec;
   const int ia[6] = {0, 1, 2, 0, 1, 0}, ib[6] = {0, 1, 2, 1, 2, 2};
   for (int k = 0; k < 6; ++k) {
     sigma[3 * ia[k] + ib[k]] = t[k] / V;

@@ -53,7 +53,7 @@ void run_threads(int nt, Fn&& fn) {
 }  // namespace
 
 void ewald_sum(const double lat[9], int nat, const double* pos, const double* Z, double& E,
-               std::vector<double>& F, double* strain6) {
+               std::vector<double>& F, double* strain6, double split_in, bool reciprocal) {
   const double* a[3] = {lat, lat + 3, lat + 6};
   auto cross = [](const double* u, const double* v, double* w) {
     w[0] = u[1] * v[2] - u[2] * v[1];
@@ -76,7 +76,7 @@ void ewald_sum(const double lat[9], int nat, const double* pos, const double* Z,
 
   // splitting parameter: 1.4 x the textbook balance sqrt(pi) (N/V^2)^(1/6), which moves
   // work from the (erfc-bound) real-space sum to the cheaper reciprocal sum
-  const double split = 1.4 * std::sqrt(kPi) * std::pow(nat / (V * V), 1.0 / 6.0);
+  const double split = split_in > 0.0 ? split_in : 1.4 * std::sqrt(kPi) * std::pow(nat / (V * V), 1.0 / 6.0);
   const double cfac = std::sqrt(-std::log(1e-16));   // erfc(cfac) ~ 1e-17
   const double rcut = cfac / split, gcut = 2.0 * split * cfac;
   double Q = 0.0, Q2 = 0.0;
@@ -166,6 +166,8 @@ void ewald_sum(const double lat[9], int nat, const double* pos, const double* Z,
   });
 
   // ---- reciprocal space: G = h b1 + k b2 + l b3, half space (h, k, l) > 0 lexicographically
+  std::vector<Partial> pg;
+  if (reciprocal) {
   int gmax[3];
   for (int k = 0; k < 3; ++k) {
     const double an = std::sqrt(a[k][0] * a[k][0] + a[k][1] * a[k][1] + a[k][2] * a[k][2]);
@@ -194,7 +196,7 @@ void ewald_sum(const double lat[9], int nat, const double* pos, const double* Z,
         if (G[0] * G[0] + G[1] * G[1] + G[2] * G[2] <= gcut * gcut) gl.push_back({h, k, l});
       }
   const int ntg = thread_count(gl.size() * (size_t)nat, 16384);
-  std::vector<Partial> pg(ntg);
+  pg.resize(ntg);
   const int M0 = 2 * gmax[0] + 1, M1 = 2 * gmax[1] + 1, M2 = 2 * gmax[2] + 1;
   run_threads(ntg, [&](int t) {
     Partial& P = pg[t];
@@ -229,6 +231,7 @@ void ewald_sum(const double lat[9], int nat, const double* pos, const double* Z,
       }
     }
   });
+  }
 
   F.assign(3 * (size_t)nat, 0.0);
   double Er = 0.0, Eg = 0.0;
@@ -256,13 +259,28 @@ void ewald_sum(const double lat[9], int nat, const double* pos, const double* Z,
   }
 }
 
+double grid_ewald_split(const ofdft_ctx* c) {
+  // |m_k| = |G . a_k| / 2 pi <= |G| |a_k| / 2 pi, so the sphere |G| < G_in with
+  // G_in = min_k 2 pi (n_k/2 - 1) / |a_k| lies inside the kept modes
+  const int n[3] = {c->g.n1, c->g.n2, c->g.n3};
+  double g_in = 1e300;
+  for (int k = 0; k < 3; ++k) {
+    const double* a = c->lat + 3 * k;
+    const double an = std::sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+    g_in = std::min(g_in, 2.0 * kPi * (n[k] / 2 - 1) / an);
+  }
+  return g_in / (2.0 * std::sqrt(-std::log(1e-16)));
+}
+
 void start_ewald(ofdft_ctx* c) {
   join_ewald(c);
   c->ewald_failed = false;
   c->ewald_pending = true;
+  c->ewald_split = grid_ewald_split(c);
   c->ewald_thread = std::thread([c] {
     try {
-      ewald_sum(c->lat, c->nat, c->tau.data(), c->Z.data(), c->E_ion, c->F_ion, c->ewald_strain);
+      ewald_sum(c->lat, c->nat, c->tau.data(), c->Z.data(), c->E_ion_host, c->F_ion, c->ewald_strain,
+                c->ewald_split, false);
     } catch (...) {
       c->ewald_failed = true;
     }
@@ -273,6 +291,7 @@ bool join_ewald(ofdft_ctx* c) {
   if (c->ewald_pending) {
     c->ewald_thread.join();
     c->ewald_pending = false;
+    c->E_ion = c->E_ion_host + c->E_rec;
   }
   return !c->ewald_failed;
 }

@@ -95,6 +95,12 @@ struct ofdft_ctx {
   double Ne = 0.0, alpha_sum = 0.0, E_ion = 0.0;
   std::vector<double> F_ion;
   double ewald_strain[6] = {0, 0, 0, 0, 0, 0};   // V Sigma of the Ewald energy (xx yy zz xy yz xz)
+  // The host thread sums the real-space, self and background Ewald terms with the
+  // splitting parameter ewald_split into E_ion_host, F_ion and ewald_strain; the
+  // reciprocal-space energy E_rec comes from the device structure factor (set_ions),
+  // its forces and strain terms from the force and stress kernels.  join_ewald sets
+  // E_ion = E_ion_host + E_rec.
+  double E_ion_host = 0.0, E_rec = 0.0, ewald_split = 0.0;
   // E_ion and F_ion come from a host thread started by set_ions; every reader
   // (and every writer of lat, nat, tau, Z) joins it first (ofdft::join_ewald)
   std::thread ewald_thread;
@@ -162,8 +168,15 @@ namespace ofdft {
 // Ewald energy and forces of the ions (ofdft_ewald.cpp, host FP64): lat rows a1..a3 (bohr),
 // Cartesian pos[3 nat], charges Z[nat]; F receives 3 nat forces (hartree/bohr).
 // strain6, if given, receives V Sigma of the Ewald energy (xx, yy, zz, xy, yz, xz).
+// split > 0 fixes the splitting parameter; reciprocal = false leaves out the
+// reciprocal-space sum (energy, forces and strain), which the library's contexts
+// take on the device from the stored structure factor.
 void ewald_sum(const double lat[9], int nat, const double* pos, const double* Z, double& E, std::vector<double>& F,
-               double* strain6 = nullptr);
+               double* strain6 = nullptr, double split = 0.0, bool reciprocal = true);
+// Splitting parameter for which the reciprocal Ewald sum is complete on the FFT
+// grid of the context (exp(-G^2/4a^2) <= 1e-16 beyond the largest sphere inside
+// the grid's G set).
+double grid_ewald_split(const ofdft_ctx* c);
 // Start ewald_sum for the context's current ions on a host thread / wait for it
 // (false if it failed).
 void start_ewald(ofdft_ctx* c);

@@ -1597,13 +1597,42 @@ __global__ void __launch_bounds__(NT) k_structure_factor(int nat, const double* 
   }
 }
 
+// Reciprocal-space Ewald energy from the stored structure factor S_Z, per block:
+// sum over the half spectrum of w exp(-G^2/4a^2)/G^2 |S_Z|^2 (times 2 pi/V on the host).
+__global__ void __launch_bounds__(NT) k_ewald_recip(const double2* __restrict__ sfac, GridDesc g, double split,
+                                                    double* __restrict__ part) {
+  __shared__ double red[NT / 64];
+  const long long plane = (long long)g.n1 * g.n2;
+  const double q4 = 0.25 / (split * split);
+  double acc[1] = {0.0};
+  for (long long gi = (long long)blockIdx.x * NT + threadIdx.x; gi < g.NS; gi += (long long)gridDim.x * NT) {
+    const int k3 = (int)(gi / plane);
+    const long long rem = gi - k3 * plane;
+    const int k1 = (int)(rem / g.n2), k2 = (int)(rem - (long long)k1 * g.n2);
+    double gx, gy, gz;
+    const bool keep = gvec(g, k1, k2, k3, gx, gy, gz);
+    const double G2 = gx * gx + gy * gy + gz * gz;
+    if (!keep || G2 == 0.0) continue;
+    const double2 sz = sfac[gi];
+    acc[0] += ((k3 == 0) ? 1.0 : 2.0) * exp(-G2 * q4) / G2 * (sz.x * sz.x + sz.y * sz.y);
+  }
+  block_sum<1>(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc[0];
+}
+
+// Coefficient of conj(S_Z) that adds the reciprocal Ewald force to the
+// electron-ion force sums: w (4 pi / V^2) exp(-G^2/4a^2)/G^2.
+__device__ __forceinline__ double ewald_force_coef(double wk, double G2, double volume, double split) {
+  return wk * kFourPi / (volume * volume) * exp(-G2 * 0.25 / (split * split)) / G2;
+}
+
 constexpr int FORCE_IONS = 8;
 
 // F_I partial sums: sum_G w G Im[conj(n(G)) e^{-iG.R_I}] (Z_I a + b)
 template <typename R>
 __global__ void __launch_bounds__(NT) k_forces(int nat, const double* __restrict__ Z, const double2* __restrict__ tab,
-                                               const cplx<R>* __restrict__ nhat, GridDesc g, LppParams lp,
-                                               double* __restrict__ part) {
+                                               const cplx<R>* __restrict__ nhat, const double2* __restrict__ sfac,
+                                               double split, GridDesc g, LppParams lp, double* __restrict__ part) {
   __shared__ double red[3 * FORCE_IONS * NT / 64];
   const int M = g.n1 + g.n2 + g.n3h;
   const long long plane = (long long)g.n1 * g.n2;
@@ -1624,13 +1653,17 @@ __global__ void __launch_bounds__(NT) k_forces(int nat, const double* __restrict
     const double wk = (k3 == 0) ? 1.0 : 2.0;
     const cplx<R> nh = nhat[gi];
     const double cx = wk * double(nh.x), cy = -wk * double(nh.y);   // w conj(n)
+    // Z-proportional part: w conj(n) a plus the Ewald term; the rest: w conj(n) b
+    const double ke = ewald_force_coef(wk, G2, g.volume, split);
+    const double2 sz = sfac[gi];
+    const double pzx = cx * a + ke * sz.x, pzy = cy * a - ke * sz.y, pbx = cx * b, pby = cy * b;
 #pragma unroll
     for (int j = 0; j < FORCE_IONS; ++j) {
       const int I = I0 + j;
       if (I < nat) {
         const double2* t = tab + (size_t)I * M;
         const double2 e = zmul(zmul(t[k1], t[g.n1 + k2]), t[g.n1 + g.n2 + k3]);
-        const double im = (cx * e.y + cy * e.x) * (Z[I] * a + b);
+        const double im = Z[I] * (pzx * e.y + pzy * e.x) + (pbx * e.y + pby * e.x);
         acc[3 * j + 0] += gx * im;
         acc[3 * j + 1] += gy * im;
         acc[3 * j + 2] += gz * im;
@@ -1660,10 +1693,11 @@ constexpr int FRC_MAX_N2 = 256;
 template <typename R>
 __global__ void __launch_bounds__(NT) k_forces_ions(int nat, const double* __restrict__ Z,
                                                     const double2* __restrict__ tab,
-                                                    const cplx<R>* __restrict__ nhat, GridDesc g, LppParams lp,
-                                                    int rows_per_chunk, double* __restrict__ part) {
+                                                    const cplx<R>* __restrict__ nhat,
+                                                    const double2* __restrict__ sfac, double split, GridDesc g,
+                                                    LppParams lp, int rows_per_chunk, double* __restrict__ part) {
   __shared__ double4 sg[FRC_MAX_N2];   // G
-  __shared__ double4 sp[FRC_MAX_N2];   // w conj(n) a, w conj(n) b as (re, im, re, im)
+  __shared__ double4 sp[FRC_MAX_N2];   // w conj(n) a + Ewald term, w conj(n) b as (re, im, re, im)
   const int M = g.n1 + g.n2 + g.n3h;
   const int I = blockIdx.y * NT + threadIdx.x;
   const bool have = I < nat;
@@ -1687,10 +1721,13 @@ __global__ void __launch_bounds__(NT) k_forces_ions(int nat, const double* __res
         double a, b;
         form_ab(lp, sqrt(G2), g.volume, a, b);
         const double wk = (k3 == 0) ? 1.0 : 2.0;
-        const cplx<R> nh = nhat[(size_t)r * g.n2 + k2];
+        const size_t gi = (size_t)r * g.n2 + k2;
+        const cplx<R> nh = nhat[gi];
         const double cx = wk * double(nh.x), cy = -wk * double(nh.y);
+        const double ke = ewald_force_coef(wk, G2, g.volume, split);
+        const double2 sz = sfac[gi];
         fg = make_double4(gx, gy, gz, 0.0);
-        fp = make_double4(cx * a, cy * a, cx * b, cy * b);
+        fp = make_double4(cx * a + ke * sz.x, cy * a - ke * sz.y, cx * b, cy * b);
       }
       sg[k2] = fg;
       sp[k2] = fp;
@@ -1759,7 +1796,7 @@ __device__ __forceinline__ void form_ab_dq(const LppParams& lp, double q, double
 template <typename R>
 __global__ void __launch_bounds__(NT) k_stress_recip(const double2* __restrict__ sfac,
                                                      const cplx<R>* __restrict__ nhat, GridDesc g, LppParams lp,
-                                                     double* __restrict__ part) {
+                                                     double split, double* __restrict__ part) {
   __shared__ double red[12 * NT / 64];
   const long long plane = (long long)g.n1 * g.n2;
   double acc[12];
@@ -1778,7 +1815,13 @@ __global__ void __launch_bounds__(NT) k_stress_recip(const double2* __restrict__
     const cplx<R> nh = nhat[gi];
     const double nx = double(nh.x), ny = double(nh.y);
     const double gg[6] = {gx * gx, gy * gy, gz * gz, gx * gy, gy * gz, gx * gz};
-    const double h = wk * kFourPi * (nx * nx + ny * ny) / (G2 * G2);
+    const double2 szf = sfac[gi];
+    // Hartree, V 4 pi |n|^2 / G^4, plus the reciprocal Ewald term (1/V of it here, the
+    // sum is scaled by V): (2 pi / V^2) exp(-G^2/4a^2)/G^2 |S_Z|^2 2 (1/G^2 + 1/(4 a^2))
+    const double q4 = 0.25 / (split * split);
+    const double h = wk * (kFourPi * (nx * nx + ny * ny) / (G2 * G2) +
+                           0.5 * kFourPi / (g.volume * g.volume) * exp(-G2 * q4) / G2 * (szf.x * szf.x + szf.y * szf.y) *
+                               2.0 * (1.0 / G2 + q4));
     double dua, dub;
     form_ab_dq(lp, q, dua, dub);
     // sum_I (Z_I u_a' + u_b') e^{-iG.R_I} from the stored structure factors
@@ -2554,6 +2597,16 @@ int dev_structure_factor(ofdft_ctx* c) {
   else
     hipLaunchKernelGGL(k_structure_factor<double>, dim3(nb2), dim3(NT), 0, c->stream, c->nat, c->dZ,
                        (const double2*)c->phase, g, lpp_of(c), (cplx<double>*)c->Vext, (double2*)c->sfac);
+  // reciprocal-space Ewald energy from S_Z (the host thread sums the rest)
+  const int nbe = (int)std::min<long long>(1024, std::max<long long>(1, g.NS / (16LL * NT)));
+  hipLaunchKernelGGL(k_ewald_recip, dim3(nbe), dim3(NT), 0, c->stream, (const double2*)c->sfac, g, c->ewald_split,
+                     c->fpart);
+  hipLaunchKernelGGL((k_vec_final<1>), dim3(1), dim3(NT), 0, c->stream, c->fpart, nbe, c->vout);
+  if (!hip_ok(c, hipGetLastError(), "structure factor launch")) return OFDFT_E_DEVICE;
+  double er = 0.0;
+  rc = dev_read(c, c->vout, 1, &er);
+  if (rc) return rc;
+  c->E_rec = 0.5 * kFourPi / g.volume * er;
   hipError_t e = hipStreamSynchronize(c->stream);
   return hip_ok(c, e, "structure factor") ? OFDFT_OK : OFDFT_E_DEVICE;
 }
@@ -2580,13 +2633,15 @@ static int forces_impl(ofdft_ctx* c, double* out_host) {
     const int rows_per_chunk = (nrows + want - 1) / want;
     nbx = (nrows + rows_per_chunk - 1) / rows_per_chunk;
     hipLaunchKernelGGL(k_forces_ions<R>, dim3(nbx, nby), dim3(NT), 0, c->stream, c->nat, c->dZ,
-                       (const double2*)c->phase, (const cplx<R>*)c->D, g, lpp_of(c), rows_per_chunk, c->fpart);
+                       (const double2*)c->phase, (const cplx<R>*)c->D, (const double2*)c->sfac, c->ewald_split, g,
+                       lpp_of(c), rows_per_chunk, c->fpart);
   } else {
     // about sixteen G vectors per thread, so the per-block reduction stays a small share
     nbx = (int)std::min<long long>(1024, std::max<long long>(1, g.NS / (16LL * NT)));
     const int nby = (c->nat + FORCE_IONS - 1) / FORCE_IONS;
     hipLaunchKernelGGL(k_forces<R>, dim3(nbx, nby), dim3(NT), 0, c->stream, c->nat, c->dZ,
-                       (const double2*)c->phase, (const cplx<R>*)c->D, g, lpp_of(c), c->fpart);
+                       (const double2*)c->phase, (const cplx<R>*)c->D, (const double2*)c->sfac, c->ewald_split, g,
+                       lpp_of(c), c->fpart);
   }
   hipLaunchKernelGGL(k_forces_final, dim3((3 * c->nat + NT / 64 - 1) / (NT / 64)), dim3(NT), 0, c->stream, c->nat,
                      c->fpart, nbx, -g.volume, c->dforces);
@@ -2637,7 +2692,7 @@ static int stress_impl(ofdft_ctx* c, double* out_host) {
   hipLaunchKernelGGL((k_vec_final<8>), dim3(1), dim3(NT), 0, c->stream, c->fpart, nbl, c->vout);
   const int nbr = (int)std::min<long long>(1024, std::max<long long>(1, g.NS / (16LL * NT)));
   hipLaunchKernelGGL(k_stress_recip<R>, dim3(nbr), dim3(NT), 0, c->stream, (const double2*)c->sfac,
-                     (const cplx<R>*)c->D, g, lpp_of(c), c->fpart + 8 * (size_t)nbl);
+                     (const cplx<R>*)c->D, g, lpp_of(c), c->ewald_split, c->fpart + 8 * (size_t)nbl);
   hipLaunchKernelGGL((k_vec_final<12>), dim3(1), dim3(NT), 0, c->stream, c->fpart + 8 * (size_t)nbl, nbr,
                      c->vout + 8);
   if (!hip_ok(c, hipGetLastError(), "stress launch")) return OFDFT_E_DEVICE;
