@@ -133,7 +133,10 @@ int ofdft_set_cell(ofdft_ctx* ctx, const double lattice[9], double cell_scale, c
 
 /* Ions: nat >= 1 Cartesian positions tau[3*nat] (bohr, multiplied by the
    cell_scale of set_cell) and valence charges Z[nat] > 0.  N_e = sum Z.
-   Rebuilds v_ext(G) (structure-factor sum) and the Ewald energy/forces.
+   Rebuilds v_ext(G) (structure-factor sum, kept with the structure factors) and
+   the Ewald term: its G-space energy on the device from the structure factor,
+   with a splitting parameter chosen for the grid, and its real-space part on a
+   host thread that runs while the density is optimised.
    Keeps the density as a warm start (rescaled to the new N_e if it changed)
    but clears the converged flag. */
 int ofdft_set_ions(ofdft_ctx* ctx, int nat, const double* tau, const double* Z);
@@ -160,9 +163,9 @@ int ofdft_free_energy_and_forces(ofdft_ctx* ctx, double* F_total, double* E_inte
    XC term, Hartree and pseudopotential reciprocal-space terms, the alpha Z term
    and the Ewald term.  Needs a converged minimisation (OFDFT_E_STATE otherwise);
    OFDFT_E_ARG if sigma is NULL.  Runs three FFT passes and two grid sums on the
-   device (the pseudopotential term reads the structure factors that
-   ofdft_set_ions stored); the Ewald strain sum comes from the host thread that
-   ofdft_set_ions started. */
+   device (the pseudopotential and Ewald G-space terms read the structure
+   factors that ofdft_set_ions stored); the real-space Ewald strain sum comes
+   from the host thread that ofdft_set_ions started. */
 int ofdft_stress(ofdft_ctx* ctx, double sigma[9]);
 
 /* Current amplitude phi (N1*N2*N3 doubles). */

@@ -7,7 +7,10 @@
 // Reciprocal space: half of the G sphere (S(-G) = S(G)*), with e^{iG.R} built
 // from per-ion phase tables along the three reciprocal axes.  Each thread sums
 // a fixed slice and the slices are added in order, so a run is reproducible
-// for a given thread count.
+// for a given thread count.  The standalone entry point sums both parts with a
+// balanced splitting parameter; a context sums only the real-space, self and
+// background terms, with the splitting parameter of grid_ewald_split, and takes
+// the reciprocal part on the device from its structure factor.
 #include <algorithm>
 #include <array>
 #include <cmath>
