@@ -122,7 +122,12 @@ typedef struct {
    cg_precond = 8, extrapolate = 0. */
 void ofdft_default_options(ofdft_options* opt);
 
-/* Creates a context.  opt may be NULL (defaults).  *out is set on success. */
+/* Creates a context.  opt may be NULL (defaults).  *out is set on success.
+   Two environment variables, read here, pick between equivalent kernels (for
+   tests and diagnosis; results agree to rounding): OFDFT_PLANE_PASSES=0 uses the
+   row FFT passes where plane passes would run; OFDFT_ION_FORCES=0 or 1 forces the
+   G-parallel or the one-thread-per-ion force kernel (default: per ion from 256
+   ions up). */
 int ofdft_create(const ofdft_options* opt, ofdft_ctx** out);
 int ofdft_destroy(ofdft_ctx* ctx);
 
