@@ -1687,7 +1687,7 @@ __global__ void __launch_bounds__(NT) k_forces(int nat, const double* __restrict
 // advances its phase e^{-iG.R} along k2 by one complex multiply, re-seeded from
 // the phase tables every FRC_RESEED steps and where the signed frequency wraps
 // (k2 = n2/2 + 1).
-constexpr int FRC_RESEED = 8;
+constexpr int FRC_RESEED = 32;
 constexpr int FRC_MAX_N2 = 256;
 
 template <typename R>
