@@ -1018,7 +1018,11 @@ __device__ __forceinline__ void plane_inv(cplx<R>* buf, const cplx<R>* tw) {
     }
   }
   __syncthreads();
-  lds_fft_inplace<R, +1, L, NTH, plane_maxe<L, NTH>()>(buf, tw, L / 2, threadIdx.x);
+  // an opaque copy of the thread index, so that the second transform recomputes its LDS
+  // addresses instead of keeping the first transform's live (which spilled them)
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
+  lds_fft_inplace<R, +1, L, NTH, plane_maxe<L, NTH>()>(buf, tw, L / 2, tid);
 }
 
 template <typename R, int L>
