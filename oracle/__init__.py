@@ -31,7 +31,8 @@ System level and are converted with k_B (CODATA 2018).
 
 Parity status: every function is pinned by a test in tests/test_oracle_*.py
 against closed forms, limits, brute-force sums or high-precision quadrature
-(see each module's header for its pins).
+(see each module's header for its pins), except the PZ81 correlation constants,
+which are "parity unpinned" (functionals module header).
 """
 from . import fermi_dirac, functionals, grid, potentials, energy, minimize, forces, md, stress  # noqa: F401
 from .energy import System, evaluate  # noqa: F401

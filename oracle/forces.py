@@ -11,9 +11,12 @@ E_ext = V sum_G conj(n(G)) v_ext(G), the first term is
 a brute-force sum over the full spectrum, one ion at a time.  The second term
 is the Ewald force.
 
-Pins (tests/test_oracle_forces.py): frozen-density central differences of E_ext
-with respect to R_I; the total force against central differences of the
-re-minimised F_tot; sum of forces ~ 0 for a translation-invariant system.
+Pins: frozen-density central differences of E_ext with respect to R_I and the
+total force against central differences of the re-minimised F_tot
+(tests/test_oracle_energy.py); the force on one ion from a Gaussian electron
+density against the gradient of the periodic Gaussian-Gaussian interaction,
+computed independently by Poisson summation, which fixes the sign of the phase
+exp(-i G.R_I) (tests/test_oracle_orientation.py).
 """
 from __future__ import annotations
 

@@ -35,8 +35,15 @@ Exchange-correlation: ground-state spin-unpolarised LDA in the Perdew-Zunger
 Pins (tests/test_oracle_functionals.py): ftTF potential equals T*eta (uniform
 gas chemical potential); SGA equals f_TF + (h~/72)|grad n|^2/n; VWTF at t -> 0
 equals TF + von Weizsaecker; VT84F (F-1)/s^2 -> 5/27 and F -> 5/3 s^2 + 1/s^2;
-df/dn and df/dsigma against central finite differences; exchange closed form;
-PZ81 continuity of eps_c and its slope at rs = 1; v_xc by finite differences.
+df/dn and df/dsigma against central finite differences; the KST2-form factors'
+small-s slope C1 and large-s bound 1 + C1/a1 (1.804 for APBEF); exchange closed
+form; PZ81 continuity of eps_c and its slope at rs = 1; v_xc by finite differences.
+
+Parity unpinned: the PZ81 correlation constants themselves (gamma, beta1, beta2,
+A, B, and C, D).  They come from the cited publication, not from the paper, and
+no test here reproduces them from something independent; the continuity-fixed
+C, D differ from the published rounded values by 1.9e-5 and -3.2e-5, which moves
+eps_c by -2.3e-5 to -3.2e-5 hartree per electron for rs in [0.5, 1).
 """
 from __future__ import annotations
 

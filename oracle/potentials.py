@@ -21,7 +21,10 @@ a cubic box against its closed form with the simple-cubic Madelung constant;
 the Gaussian form factor against the radial Fourier integral of
 -Z erf(r/r_c)/r; alpha terms against the series of the form factors; Ewald
 independence of the split parameter and the one-ion simple-cubic Madelung
-energy; Ewald forces by central differences.
+energy; Ewald forces by central differences.  The sign of the phase
+exp(-i G.R_I): the potential of one ion is deepest on the ion, and the energy of
+a Gaussian density centred at R' equals the independently summed periodic
+Gaussian-Gaussian interaction at R' - R (tests/test_oracle_orientation.py).
 """
 from __future__ import annotations
 

@@ -66,6 +66,30 @@ def test_vt84f_enhancement_limits():
     assert abs(F[1] - F[0]) < 1e-12 and abs(dF[1] - dF[0]) < 1e-9
 
 
+# Eq. KST2F with the constants printed beside it: KST2 (C1 = 2.03087, a1 = 0.29424),
+# APBEF (C1 = 0.23889, a1 = C1/0.804) and TW (C1 = 0.2319, a1 = 0.2748).  The form
+# F(s) = 1 + C1 s^2/(1 + a1 s^2) fixes the gradient-expansion slope (F - 1)/s^2 -> C1
+# as s -> 0 and the bound F -> 1 + C1/a1 as s -> infinity; for APBEF that bound is
+# 1 + 0.804, the PBE enhancement bound its a1 is defined by.  A transposed constant,
+# s in place of s^2 or a1 in the numerator fails one of these.
+@pytest.mark.parametrize("name, c1, a1, f_inf", [("KST2", 2.03087, 0.29424, 1 + 2.03087 / 0.29424),
+                                                  ("APBEF", 0.23889, 0.23889 / 0.804, 1.804),
+                                                  ("TW", 0.2319, 0.2748, 1 + 0.2319 / 0.2748)])
+def test_kst2_form_enhancement_limits(name, c1, a1, f_inf):
+    enh = fn.enhancement(name)
+    x0 = np.array([1e-8, 1e-7])   # (F - 1)/x = C1 (1 - a1 x + ...); F - 1 keeps ~1e-8 relative
+    F, dF = enh(x0)
+    assert np.allclose((F - 1) / x0, c1, rtol=1e-6)
+    assert np.allclose(dF, c1, rtol=1e-6)
+    F, dF = enh(np.array([1e12]))
+    assert F[0] == pytest.approx(f_inf, rel=1e-10)
+    assert abs(dF[0]) < 1e-20
+    # monotone increase between the two limits
+    x = np.geomspace(1e-4, 1e4, 200)
+    F, dF = enh(x)
+    assert np.all(np.diff(F) > 0) and np.all(dF > 0) and np.all(F < f_inf)
+
+
 @pytest.mark.parametrize("name", ["VT84F", "KST2", "TW", "APBEF", "SGA", "VWTF"])
 def test_enhancement_derivative_fd(name):
     enh = fn.enhancement(name)
