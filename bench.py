@@ -30,16 +30,24 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# Vector ALU peak for the pointwise kernel: 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz.
-# FP64 runs at this rate; FP32 without packed math (not used here) runs at the same lane rate.
-VALU_PEAK_TFLOPS = 78.6
+# Published MI355X vector peaks: FP64 78.6 TFLOP/s (256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA)
+# x 2.4 GHz) and FP32 157.3 TFLOP/s (twice that, by packed or dual-issued FP32).  The pointwise
+# kernel's peak is the rate at which its mix of FP64 and FP32 flops would finish with each
+# dtype at its own peak (FP32 at its published rate, although this build issues FP32 unpacked).
+FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
 # Algorithmic flops per grid point of the pointwise GGA kernel (VT84F + PZ81), counting an FMA
 # as 2 and every add, multiply, reciprocal, square root, exp or log as 1, with one pass over
 # the t-factor tables: FP64 239 (ln n and l: 3; piece abscissa: 2; Chebyshev recurrence
 # T_2..T_13: 24; 8 series of 14 terms: 208; energy sums: 2) + FP32 151 (density powers and
 # s^2: 16; two VT84F enhancement factors: 64; f, df/dn, df/dsigma, T s: 37; PZ81: 24; W and
 # v_loc: 5; sums: 5).
-POINTWISE_GGA_FLOP_PER_POINT = 390
+POINTWISE_GGA_FLOP_FP64 = 239
+POINTWISE_GGA_FLOP_FP32 = 151
+POINTWISE_GGA_FLOP_PER_POINT = POINTWISE_GGA_FLOP_FP64 + POINTWISE_GGA_FLOP_FP32
+# whole-evaluation algorithmic traffic of the minimum-traffic fused schedule of an SGA/GGA
+# evaluation: 26 whole-grid FP32 array transfers (P1 2 + P2 6 + P3 8 + P4 6 + P5 4)
+EVAL_ALG_UNITS = 26
 WORKLOAD = "1024 H, 4.0 g/cm^3, 128^3 grid, T=100 kK, VT84F+PZ81 ftGGA, Gaussian LPP rc=0.5"
 
 
@@ -172,12 +180,13 @@ def md_run(P, wl, precision, n_steps):
     ctx.stress()
     t0 = time.perf_counter()
     for _ in range(5):
-        sig = ctx.stress()
+        ctx.stress()
     stress_ms = (time.perf_counter() - t0) / 5 * 1e3
+    pressure = ctx.pressure()
     ctx.close()
     return {
         "stress_ms": stress_ms,
-        "pressure_Ha_per_bohr3": -float(sig[0][0] + sig[1][1] + sig[2][2]) / 3.0,
+        "pressure_Ha_per_bohr3": pressure,
         "ms_per_step": sum(r.wall_ms for r in steps) / len(steps),
         "evals_per_step": sum(r.evaluations for r in steps) / len(steps),
         "first_minimization_ms": recs[0].wall_ms,
@@ -218,64 +227,76 @@ def al_static(P, wl, precision, n_rep=8):
             "pressure_Ha_per_bohr3": P_el, "forces_and_stress_ms": 1e3 * t_fs, "setup_ms": 1e3 * t_set}
 
 
-def batch_run(P, wl, n_cells, precision):
-    """Heterogeneous batch: all cells minimised concurrently vs one after another."""
+def batch_run(P, wl, n_cells):
+    """C4: the heterogeneous batch (16-256 H, grids {32,48,64,96}^3, 0.5-5 g/cm^3, 2 kK-4 MK,
+    VT84F + PZ81, CG to 1e-8 Ha).  Three runs over the same cells:
+      batched      mixed precision, HIP-graph CG, all cells through one ofdft_batch_minimize
+                   (one host thread, each cell's captured iteration on its own stream);
+      one_by_one   the same graph-CG contexts minimised one after another;
+      fp64_single  the plain FP64 single-cell form: host-driven CG, one cell after another.
+    Every cell starts from the uniform density; contexts are set up before the clock starts."""
     import numpy as np
     cells = wl.batch_cells(n_cells)
-    def build():
-        out = []
-        for c in cells:
-            out.append(make_context(P, c, "VT84F", precision, tol_energy=1e-8, max_iter=2000))
-        return out
-    seq = build()
-    sync()
-    t0 = time.perf_counter()
-    seq_reps = [c.minimize_density() for c in seq]
-    sync()
-    t_seq = time.perf_counter() - t0
-    bat = build()
-    sync()
-    t0 = time.perf_counter()
-    bat_reps = P.batch_minimize(bat)
-    sync()
-    t_bat = time.perf_counter() - t0
+
+    def build(precision, graph):
+        return [make_context(P, c, "VT84F", precision, tol_energy=1e-8, max_iter=2000, graph_cg=graph)
+                for c in cells]
+
+    def timed(fn):
+        sync()
+        t0 = time.perf_counter()
+        out = fn()
+        sync()
+        return out, time.perf_counter() - t0
+
+    bat = build("mixed", 1)
+    bat_reps, t_bat = timed(lambda: P.batch_minimize(bat))
+    one = build("mixed", 1)
+    one_reps, t_one = timed(lambda: [c.minimize_density() for c in one])
+    f64 = build("fp64", 0)
+    f64_reps, t_f64 = timed(lambda: [c.minimize_density() for c in f64])
     pts = sum(int(np.prod(c.grid)) for c in cells)
-    evals = sum(r.evaluations for r in bat_reps)
     pt_evals = sum(int(np.prod(c.grid)) * r.evaluations for c, r in zip(cells, bat_reps))
-    dF = max(abs(a.F_total - b.F_total) / abs(b.F_total) for a, b in zip(bat_reps, seq_reps))
-    for c in seq + bat:
+    dF = max(abs(a.F_total - b.F_total) / abs(b.F_total) for a, b in zip(bat_reps, f64_reps))
+    for c in bat + one + f64:
         c.close()
-    return {"cells": n_cells, "precision": precision, "batched_s": t_bat, "sequential_s": t_seq,
-            "speedup": t_seq / t_bat, "grid_points": pts, "evaluations": evals,
-            "grid_points_per_s": pt_evals / t_bat, "max_rel_dF_batch_vs_sequential": dF,
-            "all_converged": all(r.converged for r in bat_reps)}
+    return {"cells": n_cells, "batched_mixed_s": t_bat, "one_by_one_mixed_s": t_one, "fp64_single_s": t_f64,
+            "speedup_batched_vs_fp64_single": t_f64 / t_bat, "speedup_batched_vs_one_by_one": t_one / t_bat,
+            "grid_points": pts, "evaluations_batched": sum(r.evaluations for r in bat_reps),
+            "evaluations_fp64_single": sum(r.evaluations for r in f64_reps),
+            "grid_point_evals_per_s_batched": pt_evals / t_bat,
+            "max_rel_dF_batched_mixed_vs_fp64_single": dF,
+            "all_converged": all(r.converged for r in bat_reps + f64_reps)}
 
 
-def md_long(P, wl, n_steps):
-    """NVE drift (Ha/atom/ps) of the mixed and FP64 paths, and mixed-vs-FP64 forces."""
+def md_long(P, wl, n_steps, graph):
+    """C5: 128 H, 64^3, 1.0 g/cm^3, 50 kK, VT84F + PZ81, velocity Verlet with dt = 0.2 fs and a
+    warm start each step, in mixed and FP64 precision: ms per converged step, the NVE drift of
+    E_cons = sum M v^2/2 + F_tot (Ha/atom/ps, linear fit), and the mixed path's force error
+    against the FP64 path (converged to 1e-10 Ha) at steps 0, n/2 and n.  The E_cons span of
+    the first 0.8 fs is also taken at dt/2: a span that falls ~4x is velocity-Verlet's
+    O(dt^2) integration error, not a force/energy mismatch."""
     import numpy as np
     from paper_1406_0835_amd import md
     out = {}
     cell = wl.md_cell()
-    check = make_context(P, cell, "VT84F", "fp64", tol_energy=1e-10, max_iter=2000)
+    masses = [md.H_MASS_ME] * cell.nat
+    v0 = md.maxwell_boltzmann(cell.nat, cell.temperature_K, md.H_MASS_ME, seed=wl.SEED_BASE + 4)
+    dt = 0.2 * md.FS_AU
+    check = make_context(P, cell, "VT84F", "fp64", tol_energy=1e-10, max_iter=2000, graph_cg=graph)
     for precision in ("mixed", "fp64"):
-        ctx = make_context(P, cell, "VT84F", precision, tol_energy=1e-8, max_iter=400)
-        masses = [md.H_MASS_ME] * cell.nat
-        v0 = md.maxwell_boltzmann(cell.nat, cell.temperature_K, md.H_MASS_ME, seed=wl.SEED_BASE + 4)
-        dt = 0.2 * md.FS_AU
+        ctx = make_context(P, cell, "VT84F", precision, tol_energy=1e-8, max_iter=400, graph_cg=graph)
         ferr = {}
 
         def cb(rec, x, v, f):
             if precision == "mixed" and rec.step in (n_steps // 2, n_steps):
                 _, f64, _ = md.step_forces(check, x, cell.charges)
                 ferr[rec.step] = float(np.max(np.abs(f - f64)))
-            if rec.step % 20 == 0:
+            if rec.step % 50 == 0:
                 log(f"MD {precision} step {rec.step}")
         recs = md.velocity_verlet(ctx, cell.positions, v0, cell.charges, masses, dt, n_steps, callback=cb)
         if precision == "mixed":
-            ctx.set_ions(cell.positions, cell.charges)
-            ctx.minimize_density()
-            _, _, f0 = ctx.free_energy_and_forces(forces=True)
+            _, f0, _ = md.step_forces(ctx, cell.positions, cell.charges)
             _, f64, _ = md.step_forces(check, cell.positions, cell.charges)
             ferr[0] = float(np.max(np.abs(f0 - f64)))
         e = np.array([r.F_total + r.kinetic for r in recs])
@@ -283,15 +304,56 @@ def md_long(P, wl, n_steps):
         slope = float(np.polyfit(tps, e, 1)[0]) / cell.nat
         out[precision] = {"steps": n_steps, "ms_per_step": float(np.mean([r.wall_ms for r in recs[1:]])),
                           "drift_Ha_per_atom_per_ps": slope, "E_cons_std_Ha": float(np.std(e)),
+                          "E_cons_span_first_0.8fs_Ha": float(np.ptp(e[:5])),
                           "evals_per_step": float(np.mean([r.evaluations for r in recs[1:]]))}
+        if precision == "fp64":
+            ctx.set_density(ctx.get_density())   # a fresh run at dt/2 over the same 0.8 fs
+            half = md.velocity_verlet(ctx, cell.positions, v0, cell.charges, masses, 0.5 * dt, 8)
+            eh = np.array([r.F_total + r.kinetic for r in half])
+            out[precision]["E_cons_span_first_0.8fs_half_dt_Ha"] = float(np.ptp(eh))
         if ferr:
-            out[precision]["max_force_diff_vs_fp64_Ha_bohr"] = ferr
+            out[precision]["max_force_diff_vs_fp64_Ha_bohr"] = {str(k): v for k, v in sorted(ferr.items())}
         ctx.close()
     check.close()
+    out["workload"] = "128 H, 1.0 g/cm^3, 64^3 grid, T=50 kK, VT84F+PZ81, CG to 1e-8 Ha, dt=0.2 fs, warm start"
+    out["graph_cg"] = bool(graph)
     return out
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_eval_seconds(wl, n, threads, functional="VT84F"):
+    """One oracle evaluation of a seeded H cell at n^3 (the 128^3 cell's grid spacing and
+    density) in a child process with OFDFT_ORACLE_THREADS = threads."""
+    import subprocess
+    code = (
+        "import sys, time, numpy as np; sys.path.insert(0, %r)\n"
+        "import oracle, workloads as wl\n"
+        "nat = max(2, int(round(1024 * (%d / 128) ** 3)))\n"
+        "c = wl.h_cell(nat, 4.0, %d, 1.0e5, wl.SEED_BASE + 2)\n"
+        "s = oracle.System(c.lattice, c.grid, c.positions, c.charges, c.temperature_K, functional=%r)\n"
+        "V = abs(np.linalg.det(c.lattice))\n"
+        "phi = wl.trial_phi(c.grid, c.nat / V, seed=7, contrast=0.6)\n"
+        "t0 = time.perf_counter(); oracle.evaluate(phi, s); print(time.perf_counter() - t0)\n"
+    ) % (ROOT, n, n, functional)
+    env = dict(os.environ, OFDFT_ORACLE_THREADS=str(threads), OMP_NUM_THREADS=str(threads))
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=600)
+    return float(out.stdout.strip().splitlines()[-1])
+
+
 def cpu_baseline(wl, cell, phi):
+    """The FP64 oracle (numpy/scipy, not tuned) on the host: one 128^3 evaluation of the benchmark
+    cell on all host threads (the reported value), plus 32^3 and 64^3 evaluations on all threads
+    and a 64^3 evaluation on one core."""
     os.environ.setdefault("OFDFT_ORACLE_THREADS", str(host_threads()))
     import numpy as np
     import oracle
@@ -302,11 +364,20 @@ def cpu_baseline(wl, cell, phi):
     oracle.evaluate(phi, sysm)
     dt = time.perf_counter() - t0
     from oracle import fermi_dirac
-    return {"value": 1.0 / dt, "unit": "evals/s", "cores": fermi_dirac._THREADS, "kind": "oracle",
+    threads = fermi_dirac._THREADS
+    extra = {}
+    try:
+        extra["eval_s_32cubed"] = _oracle_eval_seconds(wl, 32, threads)
+        extra["eval_s_64cubed"] = _oracle_eval_seconds(wl, 64, threads)
+        extra["eval_s_64cubed_one_core"] = _oracle_eval_seconds(wl, 64, 1)
+    except Exception as e:  # the headline baseline stands without these
+        extra["error"] = str(e)
+    return {"value": 1.0 / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
             "sample": "one FP64 oracle F+gradient evaluation of the 128^3 VT84F+PZ81 cell at the benchmark "
                       "phi (numpy/scipy, threaded Fermi-Dirac quadrature); the ionic setup (structure factor, "
                       "Ewald) is outside the timed region",
-            "seconds": dt}
+            "seconds": dt, **extra}
 
 
 def copy_probe(mib: float):
@@ -330,11 +401,13 @@ def main():
     ap.add_argument("--no-md", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the 128^3 SGA/4 MK and 256^3 evaluation lines")
     ap.add_argument("--no-al", action="store_true", help="skip the static fcc-Al line (--no-md skips it too)")
     ap.add_argument("--kernel-steps", type=int, default=50)
     ap.add_argument("--no-tune", action="store_true", help="keep the default FFT tiles")
-    ap.add_argument("--batch", type=int, default=0, help="also run the heterogeneous batch of this many cells")
-    ap.add_argument("--md-long", type=int, default=0, help="also run an NVE trajectory of this many steps")
+    ap.add_argument("--batch", type=int, default=64, help="cells of the heterogeneous batch (0: skip)")
+    ap.add_argument("--md-long", type=int, default=200, help="steps of the NVE trajectory (0: skip)")
+    ap.add_argument("--graph-cg", type=int, default=1, help="MD lines: 1 = HIP-graph CG, 0 = host-driven CG")
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="only run a plain device copy of this many MiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -343,8 +416,8 @@ def main():
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(sharding is described in DESIGN.md); use --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(each cell or batch runs on one device); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -378,10 +451,14 @@ def main():
     dom = max(per_kernel, key=lambda k: k["avg_us"])
     traffic = measured_traffic(dom["kernel"])
     if dom["kernel"] == "pointwise_gga":
-        flops = POINTWISE_GGA_FLOP_PER_POINT * n1 * n2 * n3
+        N = n1 * n2 * n3
+        flops = POINTWISE_GGA_FLOP_PER_POINT * N
         achieved = flops / (dom["avg_us"] * 1e-6) / 1e12
-        roofline = {"bound": "alu", "kernel": dom["kernel"], "achieved": achieved, "peak": VALU_PEAK_TFLOPS,
-                    "unit": "TFLOP/s", "frac": achieved / VALU_PEAK_TFLOPS, "traffic": traffic,
+        t_min = N * (POINTWISE_GGA_FLOP_FP64 / FP64_PEAK_TFLOPS + POINTWISE_GGA_FLOP_FP32 / FP32_PEAK_TFLOPS) * 1e-12
+        peak = flops / t_min / 1e12
+        roofline = {"bound": "alu", "kernel": dom["kernel"], "achieved": achieved, "peak": peak,
+                    "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
+                    "peak_basis": "FP64 239 flop/pt at 78.6 + FP32 151 flop/pt at 157.3 TFLOP/s",
                     "alg_flop_per_launch": float(flops), "alg_bytes_per_launch": dom["alg_bytes"],
                     "hbm_GB_s": dom["GB_s"], "avg_launch_us": dom["avg_us"]}
     else:
@@ -391,6 +468,36 @@ def main():
                     "alg_bytes_per_launch": dom["alg_bytes"], "avg_launch_us": dom["avg_us"]}
     total_alg = sum(k["alg_bytes"] for k in per_kernel)
     eval_gbs = total_alg / (dev_ms * 1e-3) / 1e9
+    # the whole evaluation against HBM: the fused schedule's 26 FP32 grid arrays per evaluation
+    eval_bytes = EVAL_ALG_UNITS * 4 * n1 * n2 * n3
+    eval_roofline = {"bound": "hbm", "alg_bytes_per_eval": float(eval_bytes),
+                     "achieved_GB_s": eval_bytes * value / 1e9, "peak_GB_s": HBM_PEAK_GBS,
+                     "frac": eval_bytes * value / 1e9 / HBM_PEAK_GBS,
+                     "evals_per_s_at_50pct": 0.5 * HBM_PEAK_GBS * 1e9 / eval_bytes,
+                     "pass_bytes_per_eval": float(total_alg)}
+
+    extra_lines = {}
+    if not args.no_extra:
+        log("128^3 SGA at 4 MK (mixed)")
+        c2 = wl.gga_128_cell(4.0e6)
+        cs = make_context(P, c2, "SGA", "mixed")
+        cs.set_density(phi)
+        cs.set_tiles(tiles) if tiles else None
+        v_sga, ms_sga, _ = eval_rate(cs, max(20, args.steps // 4), max(2, args.warmup // 2))
+        cs.close()
+        extra_lines["128cubed_SGA_4MK_mixed"] = {"evals_per_s": v_sga, "ms_per_eval": ms_sga}
+        log("256^3 VT84F at 100 kK (mixed): 8192 H at 4.0 g/cm^3, the 128^3 cell's grid spacing")
+        c3 = wl.h_cell(8192, 4.0, 256, 1.0e5, wl.SEED_BASE + 5)
+        c256 = make_context(P, c3, "VT84F", "mixed")
+        V3 = abs(np.linalg.det(c3.lattice))
+        c256.set_density(wl.trial_phi(c3.grid, c3.nat / V3, seed=wl.SEED_BASE + 5, contrast=0.6))
+        v256, ms256, dev256 = eval_rate(c256, 20, 3)
+        c256.close()
+        b256 = EVAL_ALG_UNITS * 4 * 256 ** 3
+        extra_lines["256cubed_VT84F_100kK_mixed"] = {
+            "evals_per_s": v256, "ms_per_eval": ms256, "grid_points_per_s": v256 * 256 ** 3,
+            "eval_hbm_frac": b256 * v256 / 1e9 / HBM_PEAK_GBS,
+            "note": "working set ~1 GB, beyond the 256 MB MALL: the HBM-bound case"}
 
     fp64 = None
     if not args.no_fp64:
@@ -418,11 +525,12 @@ def main():
     batch = None
     if args.batch > 0:
         log(f"batch of {args.batch} cells")
-        batch = batch_run(P, wl, args.batch, "mixed")
+        batch = batch_run(P, wl, args.batch)
 
     mdl = None
     if args.md_long > 0:
-        mdl = md_long(P, wl, args.md_long)
+        log(f"MD trajectory: {args.md_long} steps mixed and FP64")
+        mdl = md_long(P, wl, args.md_long, args.graph_cg)
 
     cpu = None
     if not args.no_cpu:
@@ -449,7 +557,9 @@ def main():
         "eval_alg_GB_s": eval_gbs,
         "host_api_evals_per_s": host_api,
         "roofline": roofline,
+        "eval_roofline": eval_roofline,
         "kernels": per_kernel,
+        "extra_evals": extra_lines,
         "fp64": fp64,
         "md_step": md_res,
         "al_static": al,

@@ -12,12 +12,12 @@
  *     GGA of the form of Eq. FGGA (SGA, VWTF, VT84F, KST2, TW, APBEF;
  *     Eqs. xizeta, s_s, s_0defn, VT84F, KST2F, SGA-F, vftGGA);
  *   - F_xc: ground-state LDA in the Perdew-Zunger parametrisation (the "PZ"
- *     XC of Sec. VI) or none;
+ *     XC of Sec. VI), the finite-T LDA of Sec. IV A (KSDT, Eq. fit2) or none;
  *   - F_H in reciprocal space (Eq. E2); v_ext from a local pseudopotential
  *     structure-factor sum (Gaussian-regularised Coulomb, or the
  *     Heine-Abarenkov form of Eq. E4A);
  *   - forces at the converged density (Eq. M12) plus the Ewald ion-ion term.
- * The call pattern mirrors the interface of Sec. V C (ions and temperature in,
+ * The call pattern mirrors the interface of Sec. V D (ions and temperature in,
  * free energy, internal energy and forces out), with the geometry keywords of
  * Sec. V B (TEMP in kelvin, cellScale).
  *
@@ -37,6 +37,8 @@
  */
 #ifndef OFDFT_H
 #define OFDFT_H
+
+#include <stddef.h>
 
 #ifdef __cplusplus
 extern "C" {
@@ -61,7 +63,10 @@ extern "C" {
 #define OFDFT_APBEF 6   /* finite-T APBEK: C1 = 0.23889, a1 = C1/0.804 */
 
 #define OFDFT_XC_NONE 0
-#define OFDFT_XC_PZ81 1
+#define OFDFT_XC_PZ81 1 /* ground-state LDA, Perdew-Zunger parametrisation (temperature-independent) */
+#define OFDFT_XC_KSDT 2 /* finite-T LDA XC free energy of Sec. IV A (Eq. fit2, spin-unpolarised,
+                           parameters of the fit's publication), potential by Eq. vxc1, stress by
+                           Eq. stressLSDAxc; evaluated in FP64 in both precisions */
 
 #define OFDFT_LPP_GAUSS 0 /* v(r) = -Z erf(r/rc)/r */
 #define OFDFT_LPP_HA 1    /* Heine-Abarenkov, Eq. E4A (rc, A, qc) */
@@ -78,7 +83,7 @@ typedef struct ofdft_ctx ofdft_ctx;
 typedef struct {
   int functional;      /* OFDFT_TF ... OFDFT_APBEF */
   double mu_sga;       /* SGA coefficient (PARA MU); used by OFDFT_SGA */
-  int xc;              /* OFDFT_XC_NONE or OFDFT_XC_PZ81 */
+  int xc;              /* OFDFT_XC_NONE, OFDFT_XC_PZ81 or OFDFT_XC_KSDT */
   int lpp;             /* OFDFT_LPP_GAUSS or OFDFT_LPP_HA */
   double lpp_rc;       /* bohr */
   double lpp_A;        /* hartree (HA only) */
@@ -101,6 +106,29 @@ typedef struct {
                           to N_e.  Converged amplitudes are remembered per context; ofdft_set_cell,
                           ofdft_set_density and a change of N_e clear the history, and the order drops
                           to what the history holds.  Changes the starting point, not the minimum. */
+  /* Device memory of the context.  alloc == NULL: the library calls hipMalloc/hipFree.
+     Otherwise every device buffer of the context (grids, spectra, minimiser vectors,
+     ion tables, partial sums) comes from alloc(bytes, alloc_ctx), which returns a
+     device pointer on opt.device aligned to at least 256 bytes, or NULL (then the
+     calling entry point fails with OFDFT_E_DEVICE), and goes back through
+     free_(ptr, alloc_ctx) when the context releases it (set_cell, destroy).  Both
+     must be set together (OFDFT_E_ARG otherwise).  Buffers are used only on the
+     context's stream; a caching allocator bound to that stream (e.g. PyTorch's,
+     with stream = its current stream) may hand them out.  The callbacks may be
+     called from the thread that calls any entry point of the context, including
+     the worker threads of ofdft_batch_minimize.  The small pinned host buffer the
+     device writes its results into stays with hipHostMalloc. */
+  void* (*alloc)(size_t bytes, void* alloc_ctx);
+  void (*free_)(void* ptr, void* alloc_ctx);
+  void* alloc_ctx;
+  int graph_cg;        /* CG minimiser only.  1: each CG iteration is one replay of a HIP graph whose
+                          launches take every decision on the device (stop rule, line search with at
+                          most two trials: the first at the curvature-based angle, the second at the
+                          secant of the slopes), gated by device flags, so no host round trip sits
+                          between iterations; the host keeps one iteration queued ahead and reads a
+                          status word.  0: the host-driven CG (line search of up to 8 (mixed) / 14
+                          (FP64) trials decided on the host).  Both stop on the same rule; their
+                          iteration paths differ. */
 } ofdft_options;
 
 typedef struct {
@@ -108,13 +136,15 @@ typedef struct {
   int evaluations;     /* F + gradient evaluations */
   int converged;       /* 1 if the stopping rule was met */
   double F_total;      /* free energy F_tot (etot), hartree */
-  double E_internal;   /* F_tot + T S_s (einternel; XC is T-independent here) */
+  double E_internal;   /* F_tot + T S_s + T S_xc (einternel) */
   double F_s;          /* non-interacting free energy T_s - T S_s */
   double TS_s;         /* T times the non-interacting entropy */
   double E_xc, E_H, E_ext, E_alphaZ, E_ion;
   double N_e;          /* int n */
   double mu;           /* Euler-equation multiplier int n v / N_e (Eq. E10) */
   double residual;     /* sqrt(sum n (v-mu)^2 / sum n) */
+  double TS_xc;        /* T S_xc = -T dF_xc/dT of a temperature-dependent XC (KSDT); 0 for PZ81.
+                          E_xc is the XC free energy F_xc; the XC internal energy is E_xc + TS_xc */
 } ofdft_report;
 
 /* Fills defaults: TF, mu_sga = 5/27, PZ81, Gaussian LPP rc = 0.5, FP64, CG,
@@ -127,7 +157,10 @@ void ofdft_default_options(ofdft_options* opt);
    tests and diagnosis; results agree to rounding): OFDFT_PLANE_PASSES=0 uses the
    row FFT passes where plane passes would run; OFDFT_ION_FORCES=0 or 1 forces the
    G-parallel or the one-thread-per-ion force kernel (default: per ion from 256
-   ions up). */
+   ions up).  A third, OFDFT_TEST_NONFINITE=k, exists for tests of the recovery
+   path of ofdft_minimize_density: the host treats the k-th line-search trial of
+   the context (counted from 1; k < 0: every trial) as non-finite; the device
+   state is not touched. */
 int ofdft_create(const ofdft_options* opt, ofdft_ctx** out);
 int ofdft_destroy(ofdft_ctx* ctx);
 
@@ -151,13 +184,20 @@ int ofdft_set_temperature(ofdft_ctx* ctx, double T_kelvin);
 
 /* Minimises F_tot over phi at fixed N_e.  Starts from the current density
    (uniform if none).  rep may be NULL.  Returns OFDFT_E_NOT_CONVERGED (and
-   keeps the best state) if max_iter is reached. */
+   keeps the best state, whose energies rep receives) if max_iter is reached.
+   Recovery in the CG minimiser, each at most once per call: a line-search trial
+   with a non-finite energy or slope restarts the CG along the steepest-descent
+   direction from the last finite point (a second one ends the call with
+   OFDFT_E_NONFINITE, the last finite state kept and reported); a line search
+   that finds no lower F before the stopping rule is met restarts along -g.
+   A non-finite energy at the starting density is OFDFT_E_NONFINITE at once. */
 int ofdft_minimize_density(ofdft_ctx* ctx, ofdft_report* rep);
 
 /* After a converged minimisation: F_total (etot), E_internal (einternel) and,
    if forces != NULL, forces[3*nat] (hartree/bohr, Eq. M12 + Ewald); if
    pressure != NULL, P = -Tr Sigma / 3 (Eq. pressure, hartree/bohr^3) from
-   ofdft_stress. */
+   ofdft_stress.  These are the outputs of the interface routine of Sec. V D
+   (etot, einternel, force and pressure).  Any output pointer may be NULL. */
 int ofdft_free_energy_and_forces(ofdft_ctx* ctx, double* F_total, double* E_internal,
                                  double* forces, double* pressure);
 
@@ -208,9 +248,13 @@ int ofdft_time_evals(ofdft_ctx* ctx, int n_evals, double* total_ms, int max_kern
 int ofdft_autotune(ofdft_ctx* ctx, int n_evals, int tiles[3]);
 int ofdft_set_tiles(ofdft_ctx* ctx, const int tiles[3]);
 
-/* Minimises several independent contexts together: their evaluations are
-   interleaved on the contexts' streams so that small cells overlap on the
-   device.  reps[n] may be NULL.  Returns the first error, if any. */
+/* Minimises several independent contexts together.  Contexts with graph_cg set are
+   driven by the calling thread alone: each replays its captured CG iteration on its
+   own stream, at most two iterations queued ahead, and leaves the rotation when the
+   status its device control kernel publishes says it has stopped; the device runs
+   the cells' iterations side by side.  Other contexts run on one host thread each.
+   reps[n] may be NULL.  Returns the first error, if any (every context is still
+   taken to its end). */
 int ofdft_batch_minimize(ofdft_ctx* const* ctxs, int n, ofdft_report* reps);
 
 /* Message for the last error on ctx (or a global message if ctx is NULL). */

@@ -7,7 +7,8 @@ minimisation, Sec. II):
   F_tot = F_s[n] + E_xc[n] + E_H[n] + int n v_ext + E_alphaZ + E_ion
 (Eqs. E1, E3, E4 with the Euler-equation objective of Sec. II), where
   F_s   : ftTF or finite-T GGA (Eqs. TF, FGGA), integrated as dv * sum_r
-  E_xc  : PZ81 LDA, dv * sum n eps_xc (or none)
+  E_xc  : PZ81 LDA, dv * sum n eps_xc, or the finite-T KSDT LDA free energy
+          dv * sum n f_xc(rs, t) (Sec. IV A, Eq. fit2), or none
   E_H   : Eq. E2 in reciprocal space (background-neutralised)
   v_ext : local pseudopotential structure-factor sum (Eq. E4A or Gaussian)
   E_alphaZ = N_e sum_I alpha_I, E_ion = Ewald.
@@ -89,11 +90,12 @@ class EvalResult:
     v: np.ndarray         # total potential on the grid
     nhat: np.ndarray
     grad: np.ndarray      # projected gradient g = 2 dv phi (v - mu)
+    TS_xc: float = 0.0    # T S_xc = -T dF_xc/dT (KSDT; 0 for the T-independent PZ81)
 
     @property
     def E_internal(self) -> float:
-        """F_tot + T S_s (XC here is temperature-independent)."""
-        return self.F_tot + self.TS_s
+        """F_tot + T S_s + T S_xc: the internal energy (the XC entropy term vanishes for PZ81)."""
+        return self.F_tot + self.TS_s + self.TS_xc
 
     def residual(self, phi) -> float:
         """sqrt(sum n (v-mu)^2 / sum n), in hartree."""
@@ -126,9 +128,15 @@ def evaluate(phi, system: System) -> EvalResult:
         v -= g.divergence(W)
     F_s = g.integrate(f)
     TS_s = g.integrate(ts)
+    TS_xc = 0.0
     if system.xc == "PZ81":
         eps, vxc = fnl.pz81(np.maximum(n, fnl.DENSITY_FLOOR))
         E_xc = g.integrate(n * eps)
+        v += vxc
+    elif system.xc == "KSDT":
+        fxc, vxc, tsxc = fnl.ksdt(np.maximum(n, fnl.DENSITY_FLOOR), system.T)
+        E_xc = g.integrate(n * fxc)
+        TS_xc = g.integrate(n * tsxc)
         v += vxc
     elif system.xc == "NONE":
         E_xc = 0.0
@@ -143,7 +151,7 @@ def evaluate(phi, system: System) -> EvalResult:
     grad = 2.0 * g.dv * phi * (v - mu)
     return EvalResult(F_tot=F_tot, F_s=F_s, TS_s=TS_s, E_xc=E_xc, E_H=E_H, E_ext=E_ext,
                       E_alphaZ=E_aZ, E_ion=system.E_ion, N_e=N_e, mu=mu, v=v, nhat=nhat,
-                      grad=grad)
+                      grad=grad, TS_xc=TS_xc)
 
 
 def energy_only(phi, system: System) -> float:

@@ -200,3 +200,68 @@ def pz81(n):
     dec = np.where(hi, dec_hi, dec_lo)
     vc = ec - (rs / 3.0) * dec
     return ex + ec, vx + vc
+
+
+# ---------------------------------------------------------------- KSDT finite-T LDA XC
+# Sec. IV A, Eq. fit2, spin-unpolarised (omega_u = 1):
+#   f_xc(rs, t) = -(1/rs) (a(t) + b(t) rs^(1/2) + c(t) rs) / (1 + d(t) rs^(1/2) + e(t) rs),
+# rs = (3/(4 pi n))^(1/3), t from Eq. tred.  The functions a(t)..e(t) and their parameters
+# are those of the publication the paper cites for the fit (Karasiev, Sjostrom, Dufty,
+# Trickey, Phys. Rev. Lett. 112, 076403 (2014), unpolarised set):
+#   a(t) = 0.610887 tanh(1/t) (0.75 + 3.04363 t^2 - 0.09227 t^3 + 1.7035 t^4)
+#                              / (1 + 8.31051 t^2 + 5.1105 t^4)
+#   b(t) = tanh(1/sqrt t) (b1 + b2 t^2 + b3 t^4) / (1 + b4 t^2 + b5 t^4)
+#   c(t) = (c1 + c2 exp(-c3/t)) e(t)
+#   d(t) = tanh(1/sqrt t) (d1 + d2 t^2 + d3 t^4) / (1 + d4 t^2 + d5 t^4)
+#   e(t) = tanh(1/t) (e1 + e2 t^2 + e3 t^4) / (1 + e4 t^2 + e5 t^4)
+KSDT_A = (0.610887, 0.75, 3.04363, -0.09227, 1.7035, 8.31051, 5.1105)
+KSDT_B = (0.283997, 48.932154, 0.370919, 61.095357, 0.871837)
+KSDT_C = (0.870089, 0.193077, 2.414644)
+KSDT_D = (0.579824, 94.537454, 97.839603, 59.939999, 24.388037)
+KSDT_E = (0.212036, 16.731249, 28.485792, 34.028876, 17.235515)
+
+
+def ksdt_coefficients(t):
+    """a(t), b(t), c(t), d(t), e(t) of Eq. fit2 (t real or complex)."""
+    A0, A1, A2, A3, A4, A5, A6 = KSDT_A
+    t2 = t * t
+    t4 = t2 * t2
+    a = A0 * np.tanh(1.0 / t) * (A1 + A2 * t2 + A3 * t2 * t + A4 * t4) / (1.0 + A5 * t2 + A6 * t4)
+    rt = np.sqrt(t)
+    b = np.tanh(1.0 / rt) * (KSDT_B[0] + KSDT_B[1] * t2 + KSDT_B[2] * t4) / (1.0 + KSDT_B[3] * t2 + KSDT_B[4] * t4)
+    e = np.tanh(1.0 / t) * (KSDT_E[0] + KSDT_E[1] * t2 + KSDT_E[2] * t4) / (1.0 + KSDT_E[3] * t2 + KSDT_E[4] * t4)
+    c = (KSDT_C[0] + KSDT_C[1] * np.exp(-KSDT_C[2] / t)) * e
+    d = np.tanh(1.0 / rt) * (KSDT_D[0] + KSDT_D[1] * t2 + KSDT_D[2] * t4) / (1.0 + KSDT_D[3] * t2 + KSDT_D[4] * t4)
+    return a, b, c, d, e
+
+
+def ksdt_fxc(rs, t):
+    """XC free energy per electron f_xc(rs, t), Eq. fit2 (unpolarised)."""
+    a, b, c, d, e = ksdt_coefficients(t)
+    q = np.sqrt(rs)
+    return -(a + b * q + c * rs) / (rs * (1.0 + d * q + e * rs))
+
+
+def _complex_step(fun, x, y, wrt):
+    """d fun(x, y)/d(x or y) by the complex step fun(x + i h)/h (exact to rounding)."""
+    h = 1e-30 * np.maximum(np.abs(x if wrt == 0 else y), 1.0)
+    if wrt == 0:
+        return np.imag(fun(x + 1j * h, y)) / h
+    return np.imag(fun(x, y + 1j * h)) / h
+
+
+def ksdt(n, T_ha):
+    """(f_xc, v_xc, T s_xc) per electron for KSDT at density n and temperature T (hartree).
+
+    v_xc follows Eq. vxc1: f + n (df/drs drs/dn + df/dt dt/dn) with drs/dn = -rs/(3n) and
+    dt/dn = -2t/(3n).  T s_xc = -T df/dT at fixed n = -t df/dt (t is proportional to T), so
+    the XC internal energy per electron is f_xc + T s_xc."""
+    n = np.asarray(n, dtype=np.float64)
+    rs = (3.0 / (4.0 * pi * n)) ** (1.0 / 3.0)
+    t = fdm.reduced_temperature(n, T_ha)
+    f = ksdt_fxc(rs, t)
+    df_drs = _complex_step(ksdt_fxc, rs, t, 0)
+    df_dt = _complex_step(ksdt_fxc, rs, t, 1)
+    v = f - (rs / 3.0) * df_drs - (2.0 * t / 3.0) * df_dt
+    return f, v, -t * df_dt
+

@@ -4,8 +4,8 @@ TEST INFRASTRUCTURE (oracle).
 
 Each ionic step re-minimises the electronic free energy (warm-started from the
 previous density) and takes the forces of Eq. M12, as in the paper's MD flow
-(Sec. I figure, Sec. V C).  The conserved quantity is
-E_cons = sum_I M_I v_I^2 / 2 + F_tot (the paper prints Ekin + Etot, Sec. V C).
+(Sec. I figure, Sec. V D).  The conserved quantity is
+E_cons = sum_I M_I v_I^2 / 2 + F_tot (the paper prints Ekin + Etot, Sec. V D).
 """
 from __future__ import annotations
 

@@ -70,6 +70,10 @@ def local_stress(phi, system: System):
     if system.xc == "PZ81":
         eps, vxc = fnl.pz81(np.maximum(n, fnl.DENSITY_FLOOR))
         iso += g.integrate(n * (eps - vxc))
+    elif system.xc == "KSDT":
+        # Eq. stressLSDAxc: delta_ab int (n f_xc - n v_xc)
+        fxc, vxc, _ = fnl.ksdt(np.maximum(n, fnl.DENSITY_FLOOR), system.T)
+        iso += g.integrate(n * (fxc - vxc))
     S = np.eye(3) * iso
     if W is not None:
         B = np.array([[g.integrate(W[a] * grad_n[b]) for b in range(3)] for a in range(3)])

@@ -17,12 +17,17 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 OK = 0
 E_ARG, E_GRID, E_NOT_CONVERGED, E_NONFINITE, E_DEVICE, E_STATE = -1, -2, -3, -4, -5, -6
 TF, SGA, VWTF, VT84F, KST2, TW, APBEF = range(7)
-XC_NONE, XC_PZ81 = 0, 1
+XC_NONE, XC_PZ81, XC_KSDT = 0, 1, 2
 LPP_GAUSS, LPP_HA = 0, 1
 FP64, MIXED = 0, 1
 CG, TN = 0, 1
 
 FUNCTIONAL_NAMES = {"TF": TF, "SGA": SGA, "VWTF": VWTF, "VT84F": VT84F, "KST2": KST2, "TW": TW, "APBEF": APBEF}
+
+
+# device allocator callbacks of ofdft_options: void* alloc(size_t, void*), void free_(void*, void*)
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
 
 class Options(ctypes.Structure):
@@ -31,7 +36,8 @@ class Options(ctypes.Structure):
                 ("lpp_qc", ctypes.c_double), ("precision", ctypes.c_int), ("minimizer", ctypes.c_int),
                 ("tol_energy", ctypes.c_double), ("tol_residual", ctypes.c_double), ("max_iter", ctypes.c_int),
                 ("device", ctypes.c_int), ("stream", ctypes.c_void_p), ("cg_precond", ctypes.c_double),
-                ("extrapolate", ctypes.c_int)]
+                ("extrapolate", ctypes.c_int), ("alloc", ALLOC_FN), ("free_", FREE_FN),
+                ("alloc_ctx", ctypes.c_void_p), ("graph_cg", ctypes.c_int)]
 
 
 class Report(ctypes.Structure):
@@ -39,7 +45,8 @@ class Report(ctypes.Structure):
                 ("F_total", ctypes.c_double), ("E_internal", ctypes.c_double), ("F_s", ctypes.c_double),
                 ("TS_s", ctypes.c_double), ("E_xc", ctypes.c_double), ("E_H", ctypes.c_double),
                 ("E_ext", ctypes.c_double), ("E_alphaZ", ctypes.c_double), ("E_ion", ctypes.c_double),
-                ("N_e", ctypes.c_double), ("mu", ctypes.c_double), ("residual", ctypes.c_double)]
+                ("N_e", ctypes.c_double), ("mu", ctypes.c_double), ("residual", ctypes.c_double),
+                ("TS_xc", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -58,6 +65,18 @@ def library_path() -> str:
     return os.environ.get("OFDFT_LIBRARY", os.path.join(_HERE, "libofdft.so"))
 
 
+def _share_torch_hip_runtime() -> None:
+    """PyTorch for ROCm carries its own copy of the HIP runtime (same soname as the system's,
+    but its own libraries ask for it under another name).  Loading PyTorch first makes the
+    library bind to that copy, so the process has one HIP runtime: device pointers from
+    PyTorch's allocator and its streams are then valid in the library.  Loaded the other way
+    round, PyTorch would start a second runtime that sees no GPU."""
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+
+
 def load_library() -> ctypes.CDLL:
     global _LIB
     if _LIB is not None:
@@ -65,6 +84,7 @@ def load_library() -> ctypes.CDLL:
     path = library_path()
     if not os.path.exists(path):
         raise OFDFTError(E_DEVICE, f"{path} not found: build it with python -m paper_1406_0835_amd.build")
+    _share_torch_hip_runtime()
     lib = ctypes.CDLL(path)
     P, D, I = ctypes.c_void_p, ctypes.c_double, ctypes.c_int
     dp = ctypes.POINTER(ctypes.c_double)
@@ -140,7 +160,7 @@ def default_options(**kw) -> Options:
         if k == "minimizer" and isinstance(v, str):
             v = {"cg": CG, "tn": TN}[v.lower()]
         if k == "xc" and isinstance(v, str):
-            v = {"none": XC_NONE, "pz81": XC_PZ81}[v.lower()]
+            v = {"none": XC_NONE, "pz81": XC_PZ81, "ksdt": XC_KSDT}[v.lower()]
         if k == "lpp" and isinstance(v, str):
             v = {"gauss": LPP_GAUSS, "ha": LPP_HA}[v.lower()]
         setattr(o, k, v)
@@ -202,14 +222,19 @@ class Context:
         self.last_rc = rc
         return rep
 
-    def free_energy_and_forces(self, forces: bool = True):
+    def free_energy_and_forces(self, forces: bool = True, pressure: bool = False):
+        """(F_total, E_internal, forces (nat, 3) or None[, pressure]) from
+        ofdft_free_energy_and_forces; the pressure is appended when asked for."""
         F = ctypes.c_double()
         E = ctypes.c_double()
+        P = ctypes.c_double()
         f = np.zeros(3 * self.nat) if forces else None
         rc = self._lib.ofdft_free_energy_and_forces(self._h, ctypes.byref(F), ctypes.byref(E),
-                                                    _dptr(f) if forces else None, None)
+                                                    _dptr(f) if forces else None,
+                                                    ctypes.byref(P) if pressure else None)
         _check(self._lib, rc, self._h)
-        return F.value, E.value, (f.reshape(-1, 3) if forces else None)
+        out = (F.value, E.value, (f.reshape(-1, 3) if forces else None))
+        return out + (P.value,) if pressure else out
 
     def stress(self) -> np.ndarray:
         """Stress tensor (3, 3) in hartree/bohr^3 at the converged density."""
@@ -218,8 +243,8 @@ class Context:
         return sig.reshape(3, 3)
 
     def pressure(self) -> float:
-        """P = -Tr(stress)/3 (hartree/bohr^3)."""
-        return -float(np.trace(self.stress())) / 3.0
+        """Pressure (hartree/bohr^3), the pressure output of ofdft_free_energy_and_forces."""
+        return self.free_energy_and_forces(forces=False, pressure=True)[3]
 
     def get_density(self) -> np.ndarray:
         out = np.zeros(int(np.prod(self.shape)))

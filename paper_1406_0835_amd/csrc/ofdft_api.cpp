@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
 #include <thread>
 #include <vector>
@@ -81,7 +82,8 @@ int fill_report(ofdft_ctx* c, const double* h, double resid, ofdft_report* rep, 
   r.F_total = h[SC_FTOT] + c->E_ion;
   r.F_s = h[SC_FS];
   r.TS_s = h[SC_TS];
-  r.E_internal = r.F_total + h[SC_TS];
+  r.TS_xc = h[SC_TSXC];
+  r.E_internal = r.F_total + h[SC_TS] + h[SC_TSXC];
   r.E_xc = h[SC_EXC];
   r.E_H = h[SC_EH];
   r.E_ext = h[SC_EEXT];
@@ -105,7 +107,8 @@ struct LS {
   double theta;
   double F;
   bool ok;
-  double dth;   // dF/dtheta at the accepted angle
+  double dth;     // dF/dtheta at the accepted angle
+  double bound;   // failed search: |dF0| times the smallest angle tried, all of which raised F
 };
 
 // Strong-Wolfe slope test |dF/dtheta| <= 0.1 |dF0|.  A looser test (0.3) accepted the
@@ -119,7 +122,7 @@ int line_search(ofdft_ctx* c, double F0, double dF0, double r, double phinorm, d
   const double ratio = r / phinorm;   // renormalises phi to the exact sphere
   double lo = 0.0, dlo = dF0, hi = -1.0, dhi = 0.0;
   double theta = theta1;
-  double best_theta = -1.0, best_F = F0, best_dth = 0.0;
+  double best_theta = -1.0, best_F = F0, best_dth = 0.0, min_theta = theta1;
   int cur = 0, best_buf = -1;
   double* tphi[2] = {c->phi_t, c->phi_t2};
   void* tv[2] = {c->v_t, c->v_t2};
@@ -151,14 +154,19 @@ int line_search(ofdft_ctx* c, double F0, double dF0, double r, double phinorm, d
       ++nevals;
     }
     const double dth = h[SC_DOT0];
-    const double Ft = h[SC_FTOT];
+    double Ft = h[SC_FTOT];
+    min_theta = std::min(min_theta, theta);
+    // OFDFT_TEST_NONFINITE: the host treats this trial's energy as non-finite (tests of
+    // the recovery path; the device state is untouched)
+    ++c->trials_seen;
+    if (c->test_nonfinite != 0 && (c->test_nonfinite < 0 || c->trials_seen == c->test_nonfinite)) Ft = NAN;
     if (!is_fin(Ft) || !is_fin(dth)) return fail(c, OFDFT_E_NONFINITE, "non-finite energy in line search");
     const bool armijo = Ft <= F0 + 1e-4 * theta * dF0;
     // once F changes at its rounding level only the slope test can decide
     const bool flat = Ft <= F0 + 1e-14 * std::fabs(F0);
     if ((armijo || flat) && std::fabs(dth) <= kSlopeTest * std::fabs(dF0)) {
       select(cur);
-      out = {theta, Ft, true, dth};
+      out = {theta, Ft, true, dth, 0.0};
       return OFDFT_OK;
     }
     if (Ft <= F0 && (best_theta < 0 || Ft < best_F)) {
@@ -189,11 +197,14 @@ int line_search(ofdft_ctx* c, double F0, double dF0, double r, double phinorm, d
     theta = next;
   }
   if (best_theta < 0.0) {
-    out = {0.0, F0, false, dF0};
+    // every trial raised F: if F is convex along the line, F(theta) >= F0 + dF0 theta, and
+    // it rises beyond the smallest trial angle, so no point of the line lies lower than
+    // F0 - |dF0| min_theta
+    out = {0.0, F0, false, dF0, std::fabs(dF0) * min_theta};
     return OFDFT_OK;
   }
   select(best_buf);
-  out = {best_theta, best_F, true, best_dth};
+  out = {best_theta, best_F, true, best_dth, 0.0};
   return OFDFT_OK;
 }
 
@@ -207,7 +218,7 @@ void accept_trial(ofdft_ctx* c) {
 int save_history(ofdft_ctx* c) {
   const size_t bytes = (size_t)c->g.N * sizeof(double);
   const int slot = c->n_hist == 0 ? 0 : (c->hist_head + 1) % 3;
-  if (!c->phi_hist[slot] && hipMalloc((void**)&c->phi_hist[slot], bytes) != hipSuccess)
+  if (!c->phi_hist[slot] && ctx_malloc(c, (void**)&c->phi_hist[slot], bytes) != hipSuccess)
     return fail(c, OFDFT_E_DEVICE, "history allocation");
   if (hipMemcpyAsync(c->phi_hist[slot], c->phi, bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
     return fail(c, OFDFT_E_DEVICE, "history copy");
@@ -260,13 +271,13 @@ bool stop_rule(const ofdft_ctx* c, int small, double resid) {
 // last steps were already below the energy tolerance; in the mixed path (FP32
 // terms summed in FP64) also once the last decrease is below 1e-6 |F| (its
 // stated accuracy).  Before any step is taken (a start at a converged density)
-// the first-order decrease |dF/dtheta(0)| theta_1 at the rejected first trial
-// stands in for the last decrease.
+// the failed search's bound on the decrease along the line, |dF/dtheta(0)| times
+// the smallest angle tried, stands in for the last decrease.
 bool stalled_converged(ofdft_ctx* c, int small, double last_dF, double F, double resid) {
   // F is the electronic part; the stated accuracy refers to the total, E_ion included
   const bool noise_floor = c->rsize == 4 && join_ewald(c) && std::fabs(last_dF) < 1e-6 * std::fabs(F + c->E_ion);
   if (c->opt.tol_residual > 0.0) return resid < c->opt.tol_residual || noise_floor;
-  return small >= 1 || noise_floor;
+  return small >= 1 || std::fabs(last_dF) < c->opt.tol_energy || noise_floor;
 }
 
 // First trial angle: the minimum of the quadratic with slope dF0 and the previous
@@ -301,6 +312,11 @@ int minimize_cg(ofdft_ctx* c, ofdft_report* rep) {
   int small = 0, it = 0;
   bool converged = false;
   double resid = 0.0;
+  // recovery (each at most once per minimisation): a non-finite trial restarts the CG from
+  // the steepest-descent direction at the last finite point; a line search that finds no
+  // lower F before the stopping rule holds restarts along -g (-z when preconditioned)
+  bool nonfinite_restart_used = false, ls_restart_used = false;
+  int final_rc = OFDFT_OK;
   for (it = 1; it <= c->opt.max_iter; ++it) {
     // gradient dots, beta, the new direction and the first trial angle on the device;
     // that trial is evaluated before anything is read back, so one readback serves both
@@ -331,10 +347,28 @@ int minimize_cg(ofdft_ctx* c, ofdft_report* rep) {
     const double dF0 = r * dd_dg[1] / dn;
     LS ls;
     const double theta1 = have_trial0 ? hs[SC_TH1] : first_step(F, Fprev, have_prev, dF0, kappa);
-    if ((rc = line_search(c, F, dF0, r, std::sqrt(phinorm2), dn, theta1, nevals, ls, have_trial0 ? trial0 : nullptr)))
-      return rc;
+    rc = line_search(c, F, dF0, r, std::sqrt(phinorm2), dn, theta1, nevals, ls, have_trial0 ? trial0 : nullptr);
+    if (rc == OFDFT_E_NONFINITE && !nonfinite_restart_used) {
+      // phi, v and the scalars of the current point are untouched (trials live in their own buffers)
+      nonfinite_restart_used = true;
+      have_prev = false;
+      kappa = 0.0;
+      small = 0;
+      continue;
+    }
+    if (rc == OFDFT_E_NONFINITE) {
+      final_rc = rc;
+      break;
+    }
+    if (rc) return rc;
     if (!ls.ok) {
-      converged = stalled_converged(c, small, have_prev ? last_dF : std::fabs(dF0) * theta1, F, resid);
+      converged = stalled_converged(c, small, have_prev ? last_dF : ls.bound, F, resid);
+      if (!converged && have_prev && !ls_restart_used) {
+        ls_restart_used = true;
+        have_prev = false;
+        kappa = 0.0;
+        continue;
+      }
       break;
     }
     accept_trial(c);
@@ -356,7 +390,112 @@ int minimize_cg(ofdft_ctx* c, ofdft_report* rep) {
   if ((rc = dev_read(c, c->scalars, SC_COUNT, h))) return rc;
   if ((rc = fill_report(c, h, resid, rep, std::min(it, c->opt.max_iter), nevals, converged ? 1 : 0))) return rc;
   c->converged = converged;
+  if (final_rc == OFDFT_E_NONFINITE)
+    return fail(c, OFDFT_E_NONFINITE, "non-finite energy in line search after a steepest-descent restart "
+                                      "(the last finite state is kept)");
   return converged ? OFDFT_OK : fail(c, OFDFT_E_NOT_CONVERGED, "minimisation did not converge");
+}
+
+// ---------------------------------------------------------------- HIP-graph CG
+// The device-resident iteration of dev_cg_graph_*: the host only replays the captured
+// graph, keeping up to kGraphDepth iterations queued, and reads the status word that
+// each iteration's control kernel publishes into mapped host memory.
+constexpr int kGraphDepth = 2;
+
+struct GraphRun {
+  ofdft_ctx* c;
+  int launched = 0;        // graph replays queued
+  double seen = 0.0;       // replays whose status the host has read
+  bool done = false;
+  int rc = OFDFT_OK;
+};
+
+double status_word(const ofdft_ctx* c, int k) {
+  double v;
+  __atomic_load(&c->hmap[kMapStatus + k], &v, __ATOMIC_ACQUIRE);
+  return v;
+}
+
+// Queue the starting evaluation, the state initialisation and the first replays.
+int graph_begin(GraphRun& g) {
+  ofdft_ctx* c = g.c;
+  const double r = std::sqrt(c->Ne / c->g.dv);
+  const bool pcg = c->opt.cg_precond > 0.0 && c->opt.functional != OFDFT_TF;
+  if (pcg) c->g.prec_k2 = c->opt.cg_precond * std::pow(3.0 * kPiD * kPiD * c->Ne / c->g.volume, 2.0 / 3.0);
+  const CgConst k{r, c->g.dv, c->opt.tol_energy, c->opt.tol_residual, c->opt.max_iter, pcg ? 1 : 0,
+                  c->rsize == 4 ? 1 : 0, c->test_nonfinite};
+  int rc;
+  if ((rc = dev_cg_graph_prepare(c, pcg, k))) return rc;
+  c->hmap[kMapStatus] = 0.0;      // the device counts replays from zero again
+  if ((rc = dev_eval(c, c->phi, c->v, c->scalars))) return rc;
+  if ((rc = dev_cg_graph_start(c))) return rc;
+  for (; g.launched < kGraphDepth; ++g.launched)
+    if ((rc = dev_cg_graph_launch(c))) return rc;
+  return OFDFT_OK;
+}
+
+// Non-blocking progress: read the status word, queue replays; done once the device
+// reports the minimisation stopped.  wait = true spins until there is progress.
+int graph_step(GraphRun& g, bool wait) {
+  ofdft_ctx* c = g.c;
+  for (unsigned spin = 1;; ++spin) {
+    const double n = status_word(c, 0);
+    if (n > g.seen) {
+      g.seen = n;
+      if (status_word(c, 1) == 0.0) {
+        g.done = true;
+        return OFDFT_OK;
+      }
+      int rc;
+      for (; g.launched < (int)g.seen + kGraphDepth; ++g.launched)
+        if ((rc = dev_cg_graph_launch(c))) return rc;
+      return OFDFT_OK;
+    }
+    if (!wait) return OFDFT_OK;
+    if (spin > 4096) std::this_thread::yield();
+    if ((spin & 255u) == 0) {
+      const hipError_t e = hipStreamQuery(c->stream);
+      if (e == hipSuccess) {
+        if (status_word(c, 0) > g.seen) continue;
+        return fail(c, OFDFT_E_DEVICE, "graph CG: the stream drained without a status update");
+      }
+      if (e != hipErrorNotReady) return fail(c, OFDFT_E_DEVICE, std::string("graph CG: ") + hipGetErrorString(e));
+    }
+    __builtin_ia32_pause();
+  }
+}
+
+// The final state: report and return code from the device CG state.
+int graph_finish(GraphRun& g, ofdft_report* rep) {
+  ofdft_ctx* c = g.c;
+  double st[CG_COUNT], h[SC_COUNT];
+  int rc;
+  if ((rc = dev_read(c, c->cgst, CG_COUNT, st))) return rc;
+  if ((rc = dev_read(c, c->scalars, SC_COUNT, h))) return rc;
+  const bool converged = st[CG_CONVERGED] != 0.0;
+  if ((rc = fill_report(c, h, st[CG_RESID], rep, (int)st[CG_ITERS], (int)st[CG_EVALS], converged ? 1 : 0)))
+    return rc;
+  c->converged = converged;
+  if (st[CG_STATUS] == CGS_NONFINITE)
+    return fail(c, OFDFT_E_NONFINITE, "non-finite energy: the last finite state is kept");
+  if (converged) return OFDFT_OK;
+  char msg[160];
+  std::snprintf(msg, sizeof(msg), "minimisation did not converge (graph CG: %s after %d iterations, residual %.3e)",
+                st[CG_STATUS] == CGS_MAXITER ? "max_iter reached" : "no lower F found", (int)st[CG_ITERS],
+                st[CG_RESID]);
+  return fail(c, OFDFT_E_NOT_CONVERGED, msg);
+}
+
+int minimize_cg_graph(ofdft_ctx* c, ofdft_report* rep) {
+  GraphRun g;
+  g.c = c;
+  int rc = graph_begin(g);
+  while (!rc && !g.done) rc = graph_step(g, true);
+  if (rc) {
+    (void)dev_sync(c);
+    return rc;
+  }
+  return graph_finish(g, rep);
 }
 
 // ---------------------------------------------------------------- truncated Newton
@@ -461,7 +600,7 @@ int minimize_tn(ofdft_ctx* c, ofdft_report* rep) {
     LS ls;
     if ((rc = line_search(c, F, dF0, r, std::sqrt(phinorm2), dn, theta1, nevals, ls))) return rc;
     if (!ls.ok) {
-      converged = stalled_converged(c, small, last_dF, F, resid);
+      converged = stalled_converged(c, small, last_dF < 1e300 ? last_dF : ls.bound, F, resid);
       break;
     }
     accept_trial(c);
@@ -479,6 +618,26 @@ int minimize_tn(ofdft_ctx* c, ofdft_report* rep) {
 }
 
 }  // namespace
+
+namespace ofdft {
+
+hipError_t ctx_malloc(ofdft_ctx* c, void** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 1;
+  if (c->opt.alloc) {
+    *p = c->opt.alloc(bytes, c->opt.alloc_ctx);
+    return *p ? hipSuccess : hipErrorOutOfMemory;
+  }
+  return hipMalloc(p, bytes);
+}
+
+void ctx_free(ofdft_ctx* c, void* p) {
+  if (!p) return;
+  if (c->opt.alloc) c->opt.free_(p, c->opt.alloc_ctx);
+  else (void)hipFree(p);
+}
+
+}  // namespace ofdft
 
 // ==================================================================== C ABI
 extern "C" {
@@ -511,7 +670,8 @@ int ofdft_create(const ofdft_options* opt, ofdft_ctx** out) {
   if (opt) o = *opt;
   else ofdft_default_options(&o);
   if (o.functional < OFDFT_TF || o.functional > OFDFT_APBEF) return fail(nullptr, OFDFT_E_ARG, "unknown functional");
-  if (o.xc != OFDFT_XC_NONE && o.xc != OFDFT_XC_PZ81) return fail(nullptr, OFDFT_E_ARG, "unknown xc");
+  if (o.xc != OFDFT_XC_NONE && o.xc != OFDFT_XC_PZ81 && o.xc != OFDFT_XC_KSDT)
+    return fail(nullptr, OFDFT_E_ARG, "unknown xc");
   if (o.lpp != OFDFT_LPP_GAUSS && o.lpp != OFDFT_LPP_HA) return fail(nullptr, OFDFT_E_ARG, "unknown pseudopotential");
   if (!(o.lpp_rc > 0.0)) return fail(nullptr, OFDFT_E_ARG, "lpp_rc must be > 0");
   if (o.lpp == OFDFT_LPP_HA && !(o.lpp_qc > 0.0)) return fail(nullptr, OFDFT_E_ARG, "lpp_qc must be > 0");
@@ -523,6 +683,8 @@ int ofdft_create(const ofdft_options* opt, ofdft_ctx** out) {
   if (!(o.cg_precond >= 0.0) || !std::isfinite(o.cg_precond))
     return fail(nullptr, OFDFT_E_ARG, "cg_precond must be finite and >= 0");
   if (o.extrapolate < 0 || o.extrapolate > 2) return fail(nullptr, OFDFT_E_ARG, "extrapolate must be 0, 1 or 2");
+  if ((o.alloc == nullptr) != (o.free_ == nullptr))
+    return fail(nullptr, OFDFT_E_ARG, "alloc and free_ must be set together");
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(nullptr, OFDFT_E_DEVICE, "no HIP device");
   if (o.device < 0 || o.device >= ndev) return fail(nullptr, OFDFT_E_ARG, "device ordinal out of range");
@@ -533,6 +695,7 @@ int ofdft_create(const ofdft_options* opt, ofdft_ctx** out) {
   c->rsize = (o.precision == OFDFT_MIXED) ? 4 : 8;
   if (const char* pp = std::getenv("OFDFT_PLANE_PASSES")) c->plane_passes = std::atoi(pp) != 0;
   if (const char* pf = std::getenv("OFDFT_ION_FORCES")) c->ion_forces = std::atoi(pf) != 0 ? 1 : 0;
+  if (const char* pn = std::getenv("OFDFT_TEST_NONFINITE")) c->test_nonfinite = std::atoi(pn);
   if (o.stream) {
     c->stream = (hipStream_t)o.stream;
   } else {
@@ -552,10 +715,10 @@ int ofdft_destroy(ofdft_ctx* c) {
   (void)hipSetDevice(c->opt.device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   dev_free_grid(c);
-  if (c->phase) (void)hipFree(c->phase);
-  if (c->dZ) (void)hipFree(c->dZ);
-  if (c->fpart) (void)hipFree(c->fpart);
-  if (c->dforces) (void)hipFree(c->dforces);
+  ctx_free(c, c->phase);
+  ctx_free(c, c->dZ);
+  ctx_free(c, c->fpart);
+  ctx_free(c, c->dforces);
   if (c->hmap) (void)hipHostFree(c->hmap);
   for (hipEvent_t e : c->timing.events) (void)hipEventDestroy(e);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -632,6 +795,10 @@ int ofdft_set_ions(ofdft_ctx* c, int nat, const double* tau, const double* Z) {
   }
   if (hipSetDevice(c->opt.device) != hipSuccess) return fail(c, OFDFT_E_DEVICE, "hipSetDevice");
   join_ewald(c);
+  // the ion state is rebuilt below; until the structure factor and E_rec exist for
+  // the new ions the context has no valid ions (a failure leaves it that way)
+  c->have_ions = false;
+  c->converged = false;
   // positions are given in the frame of the unscaled lattice (cellScale, Sec. V B)
   const double Ne_old = c->Ne;
   c->nat = nat;
@@ -673,7 +840,9 @@ int ofdft_minimize_density(ofdft_ctx* c, ofdft_report* rep) {
   int rc = check_ready(c);
   if (rc) return rc;
   c->converged = false;
-  rc = c->opt.minimizer == OFDFT_TN ? minimize_tn(c, rep) : minimize_cg(c, rep);
+  rc = c->opt.minimizer == OFDFT_TN ? minimize_tn(c, rep)
+       : c->opt.graph_cg          ? minimize_cg_graph(c, rep)
+                                  : minimize_cg(c, rep);
   if (rc == OFDFT_OK && c->opt.extrapolate > 0 && (rc = save_history(c))) return rc;
   return rc;
 }
@@ -926,11 +1095,68 @@ int ofdft_batch_minimize(ofdft_ctx* const* ctxs, int n, ofdft_report* reps) {
   if (!ctxs || n < 0) return fail(nullptr, OFDFT_E_ARG, "invalid batch");
   for (int i = 0; i < n; ++i)
     if (!ctxs[i]) return fail(nullptr, OFDFT_E_ARG, "null context in batch");
-  std::vector<int> rcs(n, OFDFT_OK);
-  std::vector<std::thread> th;
-  th.reserve(n);
   for (int i = 0; i < n; ++i)
-    th.emplace_back([&, i]() { rcs[i] = ofdft_minimize_density(ctxs[i], reps ? reps + i : nullptr); });
+    for (int j = 0; j < i; ++j)
+      if (ctxs[i] == ctxs[j]) return fail(nullptr, OFDFT_E_ARG, "a context appears twice in the batch");
+  std::vector<int> rcs(n, OFDFT_OK);
+  // graph-mode CG contexts: one host thread replays every cell's captured iteration
+  std::vector<GraphRun> runs;
+  std::vector<int> run_of(n, -1);
+  for (int i = 0; i < n; ++i) {
+    ofdft_ctx* c = ctxs[i];
+    if (c->opt.graph_cg && c->opt.minimizer == OFDFT_CG) {
+      int rc = check_ready(c);
+      if (rc) { rcs[i] = rc; continue; }
+      c->converged = false;
+      GraphRun g;
+      g.c = c;
+      run_of[i] = (int)runs.size();
+      runs.push_back(g);
+    }
+  }
+  for (GraphRun& g : runs) {
+    if (hipSetDevice(g.c->opt.device) != hipSuccess) g.rc = fail(g.c, OFDFT_E_DEVICE, "hipSetDevice");
+    if (!g.rc) g.rc = graph_begin(g);
+  }
+  // other contexts: one host thread each (the host-driven minimisers block on readbacks)
+  std::vector<std::thread> th;
+  for (int i = 0; i < n; ++i)
+    if (run_of[i] < 0 && rcs[i] == OFDFT_OK)
+      th.emplace_back([&, i]() { rcs[i] = ofdft_minimize_density(ctxs[i], reps ? reps + i : nullptr); });
+  for (bool busy = true; busy;) {
+    busy = false;
+    bool progress = false;
+    for (GraphRun& g : runs) {
+      if (g.rc || g.done) continue;
+      const double before = g.seen;
+      g.rc = graph_step(g, false);
+      progress |= g.seen != before || g.done;
+      busy |= !g.rc && !g.done;
+    }
+    if (busy && !progress) {
+      std::this_thread::yield();
+      // a failed launch or a drained stream shows up here rather than as a silent spin
+      for (GraphRun& g : runs) {
+        if (g.rc || g.done) continue;
+        const hipError_t e = hipStreamQuery(g.c->stream);
+        if (e != hipSuccess && e != hipErrorNotReady)
+          g.rc = fail(g.c, OFDFT_E_DEVICE, std::string("graph CG: ") + hipGetErrorString(e));
+        else if (e == hipSuccess && status_word(g.c, 0) <= g.seen)
+          g.rc = fail(g.c, OFDFT_E_DEVICE, "graph CG: the stream drained without a status update");
+      }
+    }
+  }
+  for (int i = 0; i < n; ++i) {
+    if (run_of[i] < 0) continue;
+    GraphRun& g = runs[run_of[i]];
+    if (g.rc) {
+      (void)dev_sync(g.c);
+      rcs[i] = g.rc;
+    } else {
+      rcs[i] = graph_finish(g, reps ? reps + i : nullptr);
+    }
+    if (rcs[i] == OFDFT_OK && g.c->opt.extrapolate > 0) rcs[i] = save_history(g.c);
+  }
   for (auto& t : th) t.join();
   for (int i = 0; i < n; ++i)
     if (rcs[i]) {

@@ -12,6 +12,10 @@
 
 namespace ofdft {
 
+// Device copies of the t-factor tables, stored coefficient-major within a piece:
+// c[(piece * NC + k) * NF + f] (the generated tables are function-major), so the k-th
+// Chebyshev coefficients of all NF functions of a piece are one contiguous 8 NF-byte run
+// that a single wide scalar load fetches.
 __constant__ double c_t_gga[OFDFT_T_NP * 8 * OFDFT_T_NC];
 __constant__ double c_t_tf[OFDFT_T_NP * 3 * OFDFT_T_NC];
 
@@ -65,19 +69,19 @@ __device__ __forceinline__ double ln_pos(double x) {
   return fma(ed, kLn2Hi, f - (hfsq - fma(s, hfsq + R, ed * kLn2Lo)));
 }
 
-// NF Chebyshev series (coefficients c[f * OFDFT_T_NC + k], first K terms used)
+// NF Chebyshev series of one piece (coefficients c[k * NF + f], first K terms used)
 // at one x, sharing the T_k recurrence.
 template <int NF, int K>
 __device__ __forceinline__ void cheb_series(const double* __restrict__ c, double x, double* s) {
 #pragma unroll
-  for (int f = 0; f < NF; ++f) s[f] = fma(c[f * OFDFT_T_NC + 1], x, c[f * OFDFT_T_NC]);
+  for (int f = 0; f < NF; ++f) s[f] = fma(c[NF + f], x, c[f]);
   double t0 = 1.0, t1 = x;
   const double x2 = 2.0 * x;
-#pragma unroll 2
+#pragma unroll
   for (int k = 2; k < K; ++k) {
     const double t2 = fma(x2, t1, -t0);
 #pragma unroll
-    for (int f = 0; f < NF; ++f) s[f] = fma(c[f * OFDFT_T_NC + k], t2, s[f]);
+    for (int f = 0; f < NF; ++f) s[f] = fma(c[k * NF + f], t2, s[f]);
     t0 = t1;
     t1 = t2;
   }
@@ -219,6 +223,95 @@ __device__ __forceinline__ void pz81(double ln_n, R& eps, R& v) {
   }
   eps = ex + ec;
   v = R(4.0 / 3.0) * ex + ec - rs * dec * R(1.0 / 3.0);
+}
+
+// ---------------------------------------------------------------- KSDT finite-T LDA XC
+// Eq. fit2 (spin-unpolarised, omega = 1):
+//   f_xc = -(1/rs) (a + b rs^(1/2) + c rs) / (1 + d rs^(1/2) + e rs),
+// with a(t)..e(t) and their parameters from the publication the paper cites for the fit
+// (Karasiev, Sjostrom, Dufty, Trickey, PRL 112, 076403 (2014), unpolarised set):
+//   a = 0.610887 tanh(1/t) (0.75 + 3.04363 t^2 - 0.09227 t^3 + 1.7035 t^4)/(1 + 8.31051 t^2 + 5.1105 t^4)
+//   b, d = tanh(1/sqrt t) (p0 + p1 t^2 + p2 t^4)/(1 + q1 t^2 + q2 t^4);  e the same with tanh(1/t)
+//   c = (c1 + c2 exp(-c3/t)) e.
+// The potential is Eq. vxc1, v = f - (rs/3) df/drs - (2t/3) df/dt, and the entropy term
+// T s_xc = -t df/dt.  Everything here is FP64 in both paths: t reaches ~1e10 at nearly
+// empty points (t^4 overflows FP32) and the fit carries exponentially small terms.
+struct KsdtRat {
+  double p0, p1, p2, q1, q2;
+};
+constexpr KsdtRat kKsdtB{0.283997, 48.932154, 0.370919, 61.095357, 0.871837};
+constexpr KsdtRat kKsdtD{0.579824, 94.537454, 97.839603, 59.939999, 24.388037};
+constexpr KsdtRat kKsdtE{0.212036, 16.731249, 28.485792, 34.028876, 17.235515};
+constexpr double kKsdtC1 = 0.870089, kKsdtC2 = 0.193077, kKsdtC3 = 2.414644;
+
+// r = P(u)/Q(u) in u = t^2 and t dr/dt
+__device__ __forceinline__ void ksdt_ratio(const KsdtRat& k, double u, double& r, double& tr) {
+  const double P = k.p0 + u * (k.p1 + u * k.p2);
+  const double Q = 1.0 + u * (k.q1 + u * k.q2);
+  const double tP = u * (2.0 * k.p1 + 4.0 * k.p2 * u);
+  const double tQ = u * (2.0 * k.q1 + 4.0 * k.q2 * u);
+  const double iQ = 1.0 / Q;
+  r = P * iQ;
+  tr = (tP - r * tQ) * iQ;
+}
+
+// f_xc, v_xc and T s_xc per electron from ln n and l = ln t.
+__device__ __forceinline__ void ksdt_point(double ln_n, double l, double& f, double& v, double& ts) {
+  const double t = exp(l);
+  const double u = t * t;
+  const double rs = exp((kLn3Over4Pi - ln_n) * (1.0 / 3.0));
+  const double q = sqrt(rs);
+  const double it = 1.0 / t;
+  const double th1 = tanh(it);                      // tanh(1/t) and t d/dt of it
+  const double tth1 = -(1.0 - th1 * th1) * it;
+  const double isq = 1.0 / sqrt(t);
+  const double th2 = tanh(isq);                     // tanh(1/sqrt t) and t d/dt of it
+  const double tth2 = -0.5 * (1.0 - th2 * th2) * isq;
+  // a(t): its numerator has a t^3 term
+  const double Pa = 0.75 + u * (3.04363 - 0.09227 * t + 1.7035 * u);
+  const double tPa = u * (2.0 * 3.04363 - 3.0 * 0.09227 * t + 4.0 * 1.7035 * u);
+  const double Qa = 1.0 + u * (8.31051 + 5.1105 * u);
+  const double tQa = u * (2.0 * 8.31051 + 4.0 * 5.1105 * u);
+  const double ra = Pa / Qa, tra = (tPa - ra * tQa) / Qa;
+  const double a = 0.610887 * th1 * ra, ta = 0.610887 * (tth1 * ra + th1 * tra);
+  double rb, trb, rd, trd, re, tre;
+  ksdt_ratio(kKsdtB, u, rb, trb);
+  ksdt_ratio(kKsdtD, u, rd, trd);
+  ksdt_ratio(kKsdtE, u, re, tre);
+  const double b = th2 * rb, tb = tth2 * rb + th2 * trb;
+  const double d = th2 * rd, td = tth2 * rd + th2 * trd;
+  const double e = th1 * re, te = tth1 * re + th1 * tre;
+  const double ex = exp(-kKsdtC3 * it);
+  const double cp = kKsdtC1 + kKsdtC2 * ex;
+  const double c = cp * e, tc = kKsdtC2 * ex * kKsdtC3 * it * e + cp * te;
+  const double N = a + b * q + c * rs;
+  const double D = 1.0 + d * q + e * rs;
+  const double iD = 1.0 / D, irs = 1.0 / rs;
+  f = -N * irs * iD;
+  // rs df/drs and t df/dt
+  const double rs_frs = -f - ((0.5 * b * q + c * rs) * D - N * (0.5 * d * q + e * rs)) * irs * iD * iD;
+  const double t_ft = -((ta + tb * q + tc * rs) * D - N * (td * q + te * rs)) * irs * iD * iD;
+  v = f - (1.0 / 3.0) * rs_frs - (2.0 / 3.0) * t_ft;
+  ts = -t_ft;
+}
+
+// XC at one point: PZ81 (xc == 1, in R) or KSDT (xc == 2, FP64); adds the potential to
+// vl and n eps (the XC free energy density) and n T s_xc to the sums.
+template <typename R, typename V>
+__device__ __forceinline__ void xc_point(int xc, double n, double ln_n, double lt0, V& vl, double& exc,
+                                         double& tsxc) {
+  if (xc == 1) {
+    R eps, vxc;
+    pz81<R>(ln_n, eps, vxc);
+    vl += V(vxc);
+    exc += n * double(eps);
+  } else if (xc == 2) {
+    double fx, vx, tsx;
+    ksdt_point(ln_n, lt0 - (2.0 / 3.0) * ln_n, fx, vx, tsx);
+    vl += V(vx);
+    exc += n * fx;
+    tsxc += n * tsx;
+  }
 }
 
 // ---------------------------------------------------------------- pointwise F_s

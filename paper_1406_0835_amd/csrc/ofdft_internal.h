@@ -13,7 +13,8 @@ namespace ofdft {
 // Slots of the per-block partial sums written by the evaluation kernels.
 // SL_DT1, SL_DT2: sums phi_t v_t q and phi_t q of a line-search trial (q = ms phi + mc d),
 // from which the reduction forms dF/dtheta once mu is known.
-enum Slot { SL_PHI2 = 0, SL_FS, SL_TS, SL_EXC, SL_EH, SL_EEXT, SL_NV, SL_DT1, SL_DT2, SL_COUNT };
+// SL_TSXC: n T s_xc of a temperature-dependent XC (KSDT), zero otherwise.
+enum Slot { SL_PHI2 = 0, SL_FS, SL_TS, SL_EXC, SL_EH, SL_EEXT, SL_NV, SL_DT1, SL_DT2, SL_TSXC, SL_COUNT };
 // Reduced scalars of one evaluation (double[SC_COUNT] on the device).  On the device
 // SC_FTOT is the electronic part of F (E_ion, a constant of the minimisation, is
 // added on the host) and SC_EION is 0.
@@ -30,7 +31,35 @@ enum Scal {
   SC_SB = 22,
   SC_MS = 23,
   SC_MC = 24,
-  SC_COUNT = 25
+  SC_TSXC = 25,   // T S_xc = -T dF_xc/dT (KSDT; 0 for PZ81)
+  SC_COUNT = 26
+};
+
+// State of the device-resident CG iteration (HIP-graph mode), doubles in device memory.
+// The control kernels of an iteration read and write it; every other kernel of the
+// iteration reads one of the gate words on entry.
+enum CgSlot {
+  CG_ACTIVE = 0,   // 1 while the minimisation runs (gate of the CG-step kernels)
+  CG_GATE1,        // the direction descends: evaluate the first trial
+  CG_GATE2,        // the first trial failed the line-search test: evaluate a second one
+  CG_GATEACC,      // a trial was accepted: copy it into the current state
+  CG_SRC,          // the trial taken (1 or 2; 0 none)
+  CG_HAVE_PREV, CG_GG_PREV, CG_CPROJ, CG_F, CG_F_PREV, CG_KAPPA, CG_SMALL, CG_LAST_DF,
+  CG_ITERS, CG_EVALS, CG_CONVERGED, CG_STATUS, CG_NF_USED, CG_LSR_USED, CG_TRIALS,
+  CG_DF0, CG_DN, CG_RESID, CG_GG, CG_LAUNCHES, CG_F1, CG_D1, CG_TH2,
+  CG_COEF2,        // ca, sb, ms, mc of the second trial (4 doubles)
+  CG_COUNT = CG_COEF2 + 4
+};
+enum CgStatus { CGS_RUNNING = 0, CGS_CONVERGED = 1, CGS_STALLED = 2, CGS_MAXITER = 3, CGS_NONFINITE = 4 };
+// Where the control kernel publishes an iteration's status in the context's mapped host
+// memory (hmap[kMapStatus + k]): launches, active, status, iterations, evaluations, F.
+constexpr int kMapStatus = 54;
+
+// Constants of one graph-mode minimisation, captured with the graph.
+struct CgConst {
+  double r;           // sphere radius sqrt(N_e / dv)
+  double dv, tol_energy, tol_residual;
+  int max_iter, pcg, mixed, inject_at;
 };
 
 // Largest tiles the kernels stage through registers: a contiguous-axis tile
@@ -51,6 +80,9 @@ struct GridDesc {
   int tr;         // rows per block in the contiguous-axis pass (power of two >= 2, divides n2)
   int tc;         // columns per block in the strided pass (power of two, divides n2)
   int rb;         // rows per block in the x2 pass (power of two)
+  // Device flag the evaluation and CG kernels read on entry: 0.0 makes the whole launch
+  // return at once (the HIP-graph CG iteration skips work this way); nullptr: always run.
+  const double* gate;
 };
 
 struct LppParams {
@@ -65,6 +97,18 @@ struct EvalParams {
   double lt0;         // ln t = lt0 - (2/3) ln n
   double alpha_sum;   // sum_I alpha_I (G = 0 remainder of the pseudopotential)
   double enh_kind, enh_c1, enh_a1;   // enhancement-factor parameters (kind as double)
+  const double* gate;                // as GridDesc::gate
+};
+
+// What a captured CG-iteration graph depends on: the launches bake in the grid and tiles,
+// the evaluation parameters, the minimisation constants and the buffers the line search
+// alternates between (their pointers are swapped by the host-driven minimisers).
+struct GraphKey {
+  GridDesc g;
+  EvalParams ep;
+  CgConst k;
+  const void* bufs[9];
+  int pcg, plane;
 };
 
 struct Timing {
@@ -146,6 +190,11 @@ struct ofdft_ctx {
   // force kernel: -1 picks by ion count, 0 the G-parallel one, 1 one thread per ion
   // (OFDFT_ION_FORCES in the environment at ofdft_create)
   int ion_forces = -1;
+  // recovery tests (OFDFT_TEST_NONFINITE at ofdft_create): the host treats line-search trial
+  // number test_nonfinite (counted from 1 over the context's life; < 0: every trial) as
+  // non-finite.  0 = off.
+  int test_nonfinite = 0;
+  long long trials_seen = 0;
   double* hmap = nullptr;
   double* dmap = nullptr;      // the same memory as seen by kernels
   unsigned long long read_seq = 0;
@@ -157,7 +206,14 @@ struct ofdft_ctx {
   double* dZ = nullptr;
   double* fpart = nullptr;
   double* dforces = nullptr;
-  int phase_cap = 0;
+  long long phase_cap = 0;   // entries of the phase tables (nat * (n1 + n2 + n3h))
+  int ion_cap = 0;           // ions that dZ, fpart and dforces are sized for
+
+  // HIP-graph CG (options.graph_cg): device state (CgSlot doubles) and the captured iteration
+  double* cgst = nullptr;
+  hipGraph_t cg_graph = nullptr;
+  hipGraphExec_t cg_exec = nullptr;
+  ofdft::GraphKey cg_key{};
 
   ofdft::Timing timing;
   ofdft_report last{};
@@ -182,7 +238,14 @@ double grid_ewald_split(const ofdft_ctx* c);
 void start_ewald(ofdft_ctx* c);
 bool join_ewald(ofdft_ctx* c);
 
+// Device memory of a context: the caller's allocator (options.alloc / free_) when
+// one is set, else hipMalloc / hipFree.  ctx_malloc returns hipErrorOutOfMemory
+// when the callback returns NULL; ctx_free ignores NULL.
+hipError_t ctx_malloc(ofdft_ctx* c, void** p, size_t bytes);
+void ctx_free(ofdft_ctx* c, void* p);
+
 // kernels (ofdft_kernels.hip)
+// Uploads the t-factor tables, once per device.
 int dev_upload_tables(int device);
 int dev_alloc_grid(ofdft_ctx* c);
 void dev_free_grid(ofdft_ctx* c);
@@ -225,6 +288,12 @@ int dev_cg_step(ofdft_ctx* c, bool pcg, bool have_prev, double gg_prev, double c
                 double kappa);
 // The same direction with beta = 0 (after a step that was not a descent direction).
 int dev_cg_restart(ofdft_ctx* c, bool pcg);
+// HIP-graph CG: capture one device-resident CG iteration (when the key changed), start a
+// minimisation from the evaluation in c->scalars (k_cg_init), replay the iteration.
+int dev_cg_graph_prepare(ofdft_ctx* c, bool pcg, const CgConst& k);
+int dev_cg_graph_start(ofdft_ctx* c);
+int dev_cg_graph_launch(ofdft_ctx* c);
+void dev_cg_graph_release(ofdft_ctx* c);
 int dev_rotate(ofdft_ctx* c, double* dst, const double* phi, double ca, const double* dir, double sb);
 // dF/dtheta at the trial point, written to out[0]
 int dev_dtheta(ofdft_ctx* c, const double* phi_t, const void* v_t, const double* sc_t, const double* phi,

@@ -45,6 +45,8 @@
 namespace ofdft {
 
 constexpr int NT = 256;
+// block sums of a final pass: f_s, T s_s, XC, T s_xc, sum n v and the two slope sums of a trial
+constexpr int kFinalSums = 7;
 constexpr double kFourPi = 12.566370614359172953850573533118;
 
 // ---------------------------------------------------------------- helpers
@@ -89,6 +91,12 @@ __device__ __forceinline__ void block_sum(double* v, double* red) {
   }
   __syncthreads();
 }
+
+// Uniform early exit of a whole launch when its gate flag (device memory) is 0.
+#define OFDFT_GATE(gp)                         \
+  do {                                         \
+    if ((gp) != nullptr && *(gp) == 0.0) return; \
+  } while (0)
 
 __device__ __forceinline__ int signed_freq(int k, int n) { return (2 * k <= n) ? k : k - n; }
 
@@ -243,6 +251,7 @@ template <typename R, int L, bool ROT>
 __global__ void __launch_bounds__(NT) k_rpass_fwd_density(const double* __restrict__ phi, cplx<R>* __restrict__ out,
                                                           const cplx<R>* __restrict__ tw_g, GridDesc g,
                                                           double* __restrict__ partials, int maxb, Rotation rot) {
+  OFDFT_GATE(g.gate);
   extern __shared__ __align__(16) char smem_raw[];
   const int tr = g.tr;
   Smem sm(smem_raw);
@@ -298,7 +307,9 @@ struct Arr3 {
 
 // One tile of rb rows per block; U staged elements per thread (U * NT >= rb * L).
 template <typename R, int L, int SIGN, int U>
-__global__ void __launch_bounds__(NT) k_cpass_x2(Arr3 arrs, const cplx<R>* __restrict__ tw_g, int nrows, int rb) {
+__global__ void __launch_bounds__(NT) k_cpass_x2(Arr3 arrs, const cplx<R>* __restrict__ tw_g, int nrows, int rb,
+                                                  const double* __restrict__ gate) {
+  OFDFT_GATE(gate);
   extern __shared__ __align__(16) char smem_raw[];
   Smem sm(smem_raw);
   cplx<R>* a = sm.take<cplx<R>>(rb * Lay<L>::RS);
@@ -367,6 +378,7 @@ __global__ void __launch_bounds__(NT) k_x1_density(const cplx<R>* __restrict__ A
                                                    cplx<R>* __restrict__ out2, cplx<R>* __restrict__ s0,
                                                    const cplx<R>* __restrict__ tw_g, GridDesc g,
                                                    double* __restrict__ partials, int maxb) {
+  OFDFT_GATE(g.gate);
   extern __shared__ __align__(16) char smem_raw[];
   const int tc = g.tc, tcl = ilog2(tc);
   Smem sm(smem_raw);
@@ -485,6 +497,7 @@ struct RealArr3 {
 template <typename R, int L>
 __global__ void __launch_bounds__(NT) k_rpass_inv_real(Arr3 in, RealArr3 out, const cplx<R>* __restrict__ tw_g,
                                                        GridDesc g) {
+  OFDFT_GATE(g.gate);
   extern __shared__ __align__(16) char smem_raw[];
   const int tr = g.tr;
   Smem sm(smem_raw);
@@ -523,14 +536,15 @@ static inline int pw_blocks(const GridDesc& g) {
 
 // Finite-T GGA + PZ81 at every point: v_loc = df/dn + v_xc, W = 2 df/dsigma grad n
 // (written over grad n), energy partial sums per block.
-template <typename R>
+template <typename R, int XC>
 __global__ void __launch_bounds__(NT) k_pointwise_gga(const double* __restrict__ phi, R* __restrict__ g0,
                                                       R* __restrict__ g1, R* __restrict__ g2, R* __restrict__ vloc,
                                                       long long npts, EvalParams ep, double* __restrict__ partials,
                                                       int maxb) {
-  __shared__ double red[3 * NT / 64];
+  OFDFT_GATE(ep.gate);
+  __shared__ double red[4 * NT / 64];
   EnhParams enh{(int)ep.enh_kind, ep.enh_c1, ep.enh_a1};
-  double fs = 0.0, ts = 0.0, exc = 0.0;
+  double fs = 0.0, ts = 0.0, exc = 0.0, tsxc = 0.0;
   for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < npts; i += (long long)gridDim.x * NT) {
     const double p = phi[i];
     const double n = p * p;
@@ -542,12 +556,7 @@ __global__ void __launch_bounds__(NT) k_pointwise_gga(const double* __restrict__
     const double ln_n = ln_pos(nf);
     gga_point<R>(nf, ln_n, sigma, ep.lt0, enh, f, dfdn, dfds, tsl);
     R vl = dfdn;
-    if (ep.xc) {
-      R eps, vxc;
-      pz81<R>(ln_n, eps, vxc);
-      vl += vxc;
-      exc += n * double(eps);
-    }
+    xc_point<R>(XC, n, ln_n, ep.lt0, vl, exc, tsxc);   // XC fixed at compile time: no registers for the others
     vloc[i] = vl;
     fs += f;
     ts += tsl;
@@ -556,18 +565,20 @@ __global__ void __launch_bounds__(NT) k_pointwise_gga(const double* __restrict__
     g1[i] = w2 * gy;
     g2[i] = w2 * gz;
   }
-  double v[3] = {fs, ts, exc};
-  block_sum<3>(v, red);
+  double v[4] = {fs, ts, exc, tsxc};
+  block_sum<4>(v, red);
   if (threadIdx.x == 0) {
     partials[SL_FS * maxb + blockIdx.x] = v[0];
     partials[SL_TS * maxb + blockIdx.x] = v[1];
     partials[SL_EXC * maxb + blockIdx.x] = v[2];
+    partials[SL_TSXC * maxb + blockIdx.x] = v[3];
   }
 }
 
 template <typename R, int L>
 __global__ void __launch_bounds__(NT) k_rpass_fwd_real(RealArr3 in, Arr3 out, const cplx<R>* __restrict__ tw_g,
                                                        GridDesc g) {
+  OFDFT_GATE(g.gate);
   extern __shared__ __align__(16) char smem_raw[];
   const int tr = g.tr;
   Smem sm(smem_raw);
@@ -604,6 +615,7 @@ __global__ void __launch_bounds__(NT) k_rpass_fwd_grad(const double* __restrict_
                                                        const double* __restrict__ sc, double two_dv,
                                                        cplx<R>* __restrict__ out, const cplx<R>* __restrict__ tw_g,
                                                        GridDesc g) {
+  OFDFT_GATE(g.gate);
   extern __shared__ __align__(16) char smem_raw[];
   const int tr = g.tr;
   Smem sm(smem_raw);
@@ -644,6 +656,7 @@ __global__ void __launch_bounds__(NT) k_x1_divergence(const cplx<R>* __restrict_
                                                       const cplx<R>* __restrict__ C2, const cplx<R>* __restrict__ s0,
                                                       cplx<R>* __restrict__ out, const cplx<R>* __restrict__ tw_g,
                                                       GridDesc g) {
+  OFDFT_GATE(g.gate);
   extern __shared__ __align__(16) char smem_raw[];
   const int tc = g.tc, tcl = ilog2(tc);
   Smem sm(smem_raw);
@@ -716,6 +729,7 @@ struct ReduceParams {
   int nb_fs;         // partial count of the free-energy slots (pointwise kernel or final pass)
   int trial;         // 1: also dF/dtheta of a line-search trial into SC_DOT0
   double dv, volume, alpha_sum;
+  const double* gate;
 };
 
 // Destination of a device-written readback: dst[0..n) and then the sequence
@@ -749,7 +763,7 @@ __device__ __forceinline__ void reduce_scalars(const double* __restrict__ partia
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int s = w; s < SL_COUNT; s += NTH / 64) {
     const int cnt = (s == SL_EH || s == SL_EEXT) ? rp.nb_x1
-                    : (s == SL_FS || s == SL_TS || s == SL_EXC) ? rp.nb_fs
+                    : (s == SL_FS || s == SL_TS || s == SL_EXC || s == SL_TSXC) ? rp.nb_fs
                     : (s == SL_DT1 || s == SL_DT2) ? (rp.trial ? rp.nb_r : 0) : rp.nb_r;
     const double* ps = partials + (size_t)s * maxb;
     double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -779,6 +793,7 @@ __device__ __forceinline__ void reduce_scalars(const double* __restrict__ partia
     out[SC_FTOT] = out[SC_FS] + out[SC_EXC] + out[SC_EH] + out[SC_EEXT] + out[SC_EAZ];
     for (int k = SC_FTOT + 1; k < SC_COUNT; ++k) out[k] = 0.0;   // dot slots cleared
     if (rp.trial) out[SC_DOT0] = 2.0 * rp.dv * (raw[SL_DT1] - out[SC_MU] * raw[SL_DT2]);
+    out[SC_TSXC] = rp.dv * raw[SL_TSXC];
   }
   __syncthreads();
   if (threadIdx.x < SC_COUNT) sc[threadIdx.x] = out[threadIdx.x];
@@ -803,13 +818,14 @@ __global__ void __launch_bounds__(NT) k_rpass_final(const cplx<R>* __restrict__ 
                                                     const R* __restrict__ vloc, R* __restrict__ vout,
                                                     const cplx<R>* __restrict__ tw_g, GridDesc g, EvalParams ep,
                                                     double* __restrict__ partials, int maxb, Slope sl) {
+  OFDFT_GATE(g.gate);
   extern __shared__ __align__(16) char smem_raw[];
   const int tr = g.tr;
   Smem sm(smem_raw);
   cplx<R>* za = sm.take<cplx<R>>((tr / 2) * Lay<L>::RS);
   cplx<R>* zb = sm.take<cplx<R>>(zb_elems<L>(tr));
   cplx<R>* tw = sm.take<cplx<R>>(L);
-  double* red = sm.take<double>(6 * NT / 64);
+  double* red = sm.take<double>(kFinalSums * NT / 64);
   const int i1 = blockIdx.y, i2_0 = blockIdx.x * tr;
   const size_t base = ((size_t)i1 * g.n2 + i2_0) * L;
   const int cnt = tr * L;
@@ -836,7 +852,7 @@ __global__ void __launch_bounds__(NT) k_rpass_final(const cplx<R>* __restrict__ 
     for (int u = 0; u < MAXU; ++u) q[u] = ms * p0[u] + mc * dd[u];
   }
   const cplx<R>* res = lds_fft<R, +1, L, NT>(za, zb, tw, tr / 2, threadIdx.x);
-  double fs = 0.0, ts = 0.0, exc = 0.0, nv = 0.0, dt1 = 0.0, dt2 = 0.0;
+  double fs = 0.0, ts = 0.0, exc = 0.0, tsxc = 0.0, nv = 0.0, dt1 = 0.0, dt2 = 0.0;
 #pragma unroll
   for (int u = 0; u < MAXU; ++u) {
     const int e = threadIdx.x + u * NT;
@@ -855,12 +871,7 @@ __global__ void __launch_bounds__(NT) k_rpass_final(const cplx<R>* __restrict__ 
       vl = vt;
       fs += f;
       ts += tsl;
-      if (ep.xc) {
-        R eps, vxc;
-        pz81<R>(ln_n, eps, vxc);
-        vl += double(vxc);
-        exc += n * double(eps);
-      }
+      xc_point<R>(ep.xc, n, ln_n, ep.lt0, vl, exc, tsxc);
     } else {
       vl = double(lv[u]);
     }
@@ -872,7 +883,7 @@ __global__ void __launch_bounds__(NT) k_rpass_final(const cplx<R>* __restrict__ 
       dt2 += p * q[u];
     }
   }
-  constexpr int K = (TF ? 4 : 1) + (DT ? 2 : 0);
+  constexpr int K = (TF ? 5 : 1) + (DT ? 2 : 0);
   double v[K];
   int slot[K];
   int k = 0;
@@ -880,6 +891,7 @@ __global__ void __launch_bounds__(NT) k_rpass_final(const cplx<R>* __restrict__ 
     v[k] = fs; slot[k++] = SL_FS;
     v[k] = ts; slot[k++] = SL_TS;
     v[k] = exc; slot[k++] = SL_EXC;
+    v[k] = tsxc; slot[k++] = SL_TSXC;
   }
   v[k] = nv; slot[k++] = SL_NV;
   if constexpr (DT) {
@@ -908,6 +920,9 @@ constexpr int NTP = 1024;   // threads of a plane block
 // Elements per thread of the in-place transforms of a half plane ((L/2) L points).
 template <int L, int NTH>
 __host__ __device__ constexpr int plane_maxe() { return ((L / 2) * L + NTH - 1) / NTH; }
+// The same for a quarter of the rows (the half-plane transforms of the split passes).
+template <int L, int NTH>
+__host__ __device__ constexpr int plane_maxe_q() { return ((L / 4) * L + NTH - 1) / NTH; }
 
 template <typename R, int L>
 __host__ __device__ constexpr size_t lds_plane(int nred) {
@@ -1035,21 +1050,122 @@ __device__ __forceinline__ R plane_real(const cplx<R>* buf, int e) {
 // Chunk of the plane's real elements per thread in the load and store loops.
 constexpr int PCH = 8;
 
+// The density and final passes split each i1 plane over two blocks (at 128^3 one block per
+// plane gives 128 workgroups for 256 CUs).  Block b takes plane i1 and half h; the two halves
+// of a plane are 8 block indices apart, so the round-robin dispatch of workgroups over the
+// 8 XCDs places them on the same XCD, whose L2 then serves the second read of the plane.
+__device__ __forceinline__ void plane_half(int b, int n1, int& i1, int& h) {
+  if ((n1 & 7) == 0) {
+    i1 = (b >> 4) * 8 + (b & 7);
+    h = (b >> 3) & 1;
+  } else {
+    i1 = b >> 1;
+    h = b & 1;
+  }
+}
+
+// x3 forward transform of the packed rows, then the half spectra written transposed into
+// T[k3][i2] for k3 in [k0, k0 + L/4) only (the rows this block's x2 transform takes).
+template <typename R, int L, int NTH>
+__device__ __forceinline__ void plane_x3_fwd_to_T_half(cplx<R>* buf, const cplx<R>* tw, int k0) {
+  lds_fft_inplace<R, -1, L, NTH, plane_maxe<L, NTH>()>(buf, tw, L / 2, threadIdx.x);
+  constexpr int H = L / 2, Q = L / 4, ITEMS = H * Q, MI = (ITEMS + NTH - 1) / NTH;
+  cplx<R> xa[MI], xb[MI];
+#pragma unroll
+  for (int m = 0; m < MI; ++m) {
+    const int it = threadIdx.x + m * NTH;
+    if (it < ITEMS) {
+      const int p = it / Q, k3 = k0 + (it - p * Q);
+      const cplx<R> z = buf[Lay<L>::at(p, k3)];
+      const cplx<R> zc = cconj(buf[Lay<L>::at(p, (L - k3) % L)]);
+      xa[m] = {R(0.5) * (z.x + zc.x), R(0.5) * (z.y + zc.y)};
+      xb[m] = {R(0.5) * (z.y - zc.y), R(-0.5) * (z.x - zc.x)};
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < MI; ++m) {
+    const int it = threadIdx.x + m * NTH;
+    if (it < ITEMS) {
+      const int p = it / Q, k3 = k0 + (it - p * Q);
+      buf[Lay<L>::at(k3, 2 * p)] = xa[m];
+      buf[Lay<L>::at(k3, 2 * p + 1)] = xb[m];
+    }
+  }
+  __syncthreads();
+}
+
+// x2 forward transform of the T rows k3 in [k0, k0 + L/4), stored as S[k3][i1][k2].
+template <typename R, int L, int NTH>
+__device__ __forceinline__ void plane_x2_fwd_store_half(cplx<R>* buf, const cplx<R>* tw, cplx<R>* out,
+                                                        const GridDesc& g, int i1, int k0) {
+  cplx<R>* rows = buf + k0 * Lay<L>::RS;
+  lds_fft_inplace<R, -1, L, NTH, plane_maxe_q<L, NTH>()>(rows, tw, L / 4, threadIdx.x);
+  const size_t plane = (size_t)g.n1 * L;
+  constexpr int CNT = (L / 4) * L;
+  for (int e = threadIdx.x; e < CNT; e += NTH) {
+    const int r = e / L, k2 = e - r * L;
+    out[(k0 + r) * plane + (size_t)i1 * L + k2] = rows[Lay<L>::at(r, k2)];
+  }
+}
+
+// Inverse of a half plane: x2 inverse of all T rows, the packed rows z_p (p in [p0, p0 + L/4))
+// and their x3 inverse; real element (i2, i3) with i2 in [2 p0, 2 p0 + L/2) is then Re or Im of
+// P[i2/2][i3].
+template <typename R, int L, int NTH>
+__device__ __forceinline__ void plane_inv_half(cplx<R>* buf, const cplx<R>* tw, int p0) {
+  lds_fft_inplace<R, +1, L, NTH, plane_maxe<L, NTH>()>(buf, tw, L / 2, threadIdx.x);
+  constexpr int Q = L / 4, ITEMS = Q * L, MI = (ITEMS + NTH - 1) / NTH;
+  cplx<R> z[MI];
+#pragma unroll
+  for (int m = 0; m < MI; ++m) {
+    const int it = threadIdx.x + m * NTH;
+    if (it < ITEMS) {
+      const int p = p0 + it / L, k = it % L;
+      cplx<R> xa = {R(0), R(0)}, xb = {R(0), R(0)};
+      if (2 * k < L) {
+        xa = buf[Lay<L>::at(k, 2 * p)];
+        xb = buf[Lay<L>::at(k, 2 * p + 1)];
+      } else if (2 * k > L) {
+        xa = cconj(buf[Lay<L>::at(L - k, 2 * p)]);
+        xb = cconj(buf[Lay<L>::at(L - k, 2 * p + 1)]);
+      }
+      z[m] = {xa.x - xb.y, xa.y + xb.x};
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < MI; ++m) {
+    const int it = threadIdx.x + m * NTH;
+    if (it < ITEMS) {
+      const int p = p0 + it / L, k = it % L;
+      buf[Lay<L>::at(p, k)] = z[m];
+    }
+  }
+  __syncthreads();
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
+  lds_fft_inplace<R, +1, L, NTH, plane_maxe_q<L, NTH>()>(buf + p0 * Lay<L>::RS, tw, L / 4, tid);
+}
+
 // F1: n = phi^2 (phi_t = ca phi + sb dir for a line-search trial), x3 and x2
 // forward; sum phi^2 per plane.
 template <typename R, int L, bool ROT>
 __global__ void __launch_bounds__(NTP) k_plane_fwd_density(const double* __restrict__ phi, cplx<R>* __restrict__ out,
                                                            const cplx<R>* __restrict__ tw_g, GridDesc g,
                                                            double* __restrict__ partials, int maxb, Rotation rot) {
+  OFDFT_GATE(g.gate);
   static_assert(plane_maxe<L, NTP>() <= 16, "plane too large for the in-place FFT registers");
   extern __shared__ __align__(16) char smem_raw[];
   Smem sm(smem_raw);
   cplx<R>* buf = sm.take<cplx<R>>((L / 2) * Lay<L>::RS);
   cplx<R>* tw = sm.take<cplx<R>>(L);
   double* red = sm.take<double>(NTP / 64);
-  const int i1 = blockIdx.x;
+  int i1, h;
+  plane_half(blockIdx.x, g.n1, i1, h);
   const size_t base = (size_t)i1 * L * L;
   constexpr int CNT = L * L;
+  const int e_lo = h * (CNT / 2), e_hi = e_lo + CNT / 2;   // this block's half of the plane's points
   const cplx<R> twv = twiddle_load<R, L>(tw_g);
   R* zr = reinterpret_cast<R*>(buf);
   double acc = 0.0;
@@ -1066,7 +1182,7 @@ __global__ void __launch_bounds__(NTP) k_plane_fwd_density(const double* __restr
       for (int u = 0; u < PCH; ++u) {
         pv[u] = ca * pv[u] + sb * dv_[u];
         const int e = c0 + threadIdx.x + u * NTP;
-        if (e < CNT) rot.phi_out[base + e] = pv[u];
+        if (e >= e_lo && e < e_hi) rot.phi_out[base + e] = pv[u];   // each half stores its points
       }
     }
 #pragma unroll
@@ -1075,24 +1191,26 @@ __global__ void __launch_bounds__(NTP) k_plane_fwd_density(const double* __restr
       if (e < CNT) {
         const int i2 = e / L, i3 = e - i2 * L;
         const double n = pv[u] * pv[u];
-        acc += n;
+        if (e >= e_lo && e < e_hi) acc += n;
         zr[2 * Lay<L>::at(i2 >> 1, i3) + (i2 & 1)] = R(n);
       }
     }
   }
   twiddle_store<R, L>(tw, twv);
   __syncthreads();
-  plane_x3_fwd_to_T<R, L, NTP>(buf, tw);
-  plane_x2_fwd_store<R, L, NTP>(buf, tw, out, g, i1);
+  // the x3 transform needs every row; the x2 transform and the store take this half's k3 rows
+  plane_x3_fwd_to_T_half<R, L, NTP>(buf, tw, h * (L / 4));
+  plane_x2_fwd_store_half<R, L, NTP>(buf, tw, out, g, i1, h * (L / 4));
   double v[1] = {acc};
   block_sum<1, NTP>(v, red);
-  if (threadIdx.x == 0) partials[SL_PHI2 * maxb + i1] = v[0];
+  if (threadIdx.x == 0) partials[SL_PHI2 * maxb + 2 * i1 + h] = v[0];
 }
 
 // F3: forward x3 and x2 transforms of real arrays (component blockIdx.y).
 template <typename R, int L, int NTH>
 __global__ void __launch_bounds__(NTH, sizeof(R) == 4 ? 8 : 4) k_plane_fwd_real(RealArr3 in, Arr3 out, const cplx<R>* __restrict__ tw_g,
                                                         GridDesc g) {
+  OFDFT_GATE(g.gate);
   static_assert(plane_maxe<L, NTH>() <= 16, "plane too large for the in-place FFT registers");
   extern __shared__ __align__(16) char smem_raw[];
   Smem sm(smem_raw);
@@ -1129,6 +1247,7 @@ __global__ void __launch_bounds__(NTP) k_plane_fwd_grad(const double* __restrict
                                                         const double* __restrict__ sc, double two_dv,
                                                         cplx<R>* __restrict__ out, const cplx<R>* __restrict__ tw_g,
                                                         GridDesc g) {
+  OFDFT_GATE(g.gate);
   static_assert(plane_maxe<L, NTP>() <= 16, "plane too large for the in-place FFT registers");
   extern __shared__ __align__(16) char smem_raw[];
   Smem sm(smem_raw);
@@ -1168,6 +1287,7 @@ __global__ void __launch_bounds__(NTP) k_plane_fwd_grad(const double* __restrict
 template <typename R, int L, int NTH>
 __global__ void __launch_bounds__(NTH, sizeof(R) == 4 ? 8 : 4) k_plane_inv_real(Arr3 in, RealArr3 out, const cplx<R>* __restrict__ tw_g,
                                                         GridDesc g) {
+  OFDFT_GATE(g.gate);
   static_assert(plane_maxe<L, NTH>() <= 16, "plane too large for the in-place FFT registers");
   extern __shared__ __align__(16) char smem_raw[];
   Smem sm(smem_raw);
@@ -1189,18 +1309,22 @@ __global__ void __launch_bounds__(NTP) k_plane_final(const cplx<R>* __restrict__
                                                      const R* __restrict__ vloc, R* __restrict__ vout,
                                                      const cplx<R>* __restrict__ tw_g, GridDesc g, EvalParams ep,
                                                      double* __restrict__ partials, int maxb, Slope sl) {
+  OFDFT_GATE(g.gate);
   static_assert(plane_maxe<L, NTP>() <= 16, "plane too large for the in-place FFT registers");
   extern __shared__ __align__(16) char smem_raw[];
   Smem sm(smem_raw);
   cplx<R>* buf = sm.take<cplx<R>>((L / 2) * Lay<L>::RS);
   cplx<R>* tw = sm.take<cplx<R>>(L);
-  double* red = sm.take<double>(6 * NTP / 64);
-  const int i1 = blockIdx.x;
-  const size_t base = (size_t)i1 * L * L;
-  constexpr int CNT = L * L;
+  double* red = sm.take<double>(kFinalSums * NTP / 64);
+  int i1, h;
+  plane_half(blockIdx.x, g.n1, i1, h);
+  // this block's half: real rows i2 in [h L/2, (h + 1) L/2), i.e. points [h CNT/2, (h + 1) CNT/2)
+  const size_t base = (size_t)i1 * L * L + (size_t)h * (L * L / 2);
+  constexpr int CNT = L * L / 2;
   plane_load_T<R, L, NTP>(buf, tw, D, tw_g, g, i1);
-  plane_inv<R, L, NTP>(buf, tw);
-  double fs = 0.0, ts = 0.0, exc = 0.0, nv = 0.0, dt1 = 0.0, dt2 = 0.0;
+  plane_inv_half<R, L, NTP>(buf, tw, h * (L / 4));
+  const cplx<R>* hbuf = buf + h * (L / 4) * Lay<L>::RS;   // packed rows of this half
+  double fs = 0.0, ts = 0.0, exc = 0.0, tsxc = 0.0, nv = 0.0, dt1 = 0.0, dt2 = 0.0;
   constexpr int CH = TF ? 2 : PCH;   // the inlined ftTF point is register-heavy
   for (int c0 = 0; c0 < CNT; c0 += CH * NTP) {
     double pv[CH], q[CH];
@@ -1227,7 +1351,7 @@ __global__ void __launch_bounds__(NTP) k_plane_final(const cplx<R>* __restrict__
     for (int u = 0; u < CH; ++u) {
       const int e = c0 + threadIdx.x + u * NTP;
       if (e >= CNT) continue;
-      const double S = double(plane_real<R, L>(buf, e));
+      const double S = double(plane_real<R, L>(hbuf, e));
       const double p = pv[u];
       const double n = p * p;
       double vl;
@@ -1239,12 +1363,7 @@ __global__ void __launch_bounds__(NTP) k_plane_final(const cplx<R>* __restrict__
         vl = vt;
         fs += f;
         ts += tsl;
-        if (ep.xc) {
-          R eps, vxc;
-          pz81<R>(ln_n, eps, vxc);
-          vl += double(vxc);
-          exc += n * double(eps);
-        }
+        xc_point<R>(ep.xc, n, ln_n, ep.lt0, vl, exc, tsxc);
       } else {
         vl = double(lv[u]);
       }
@@ -1257,7 +1376,7 @@ __global__ void __launch_bounds__(NTP) k_plane_final(const cplx<R>* __restrict__
       }
     }
   }
-  constexpr int K = (TF ? 4 : 1) + (DT ? 2 : 0);
+  constexpr int K = (TF ? 5 : 1) + (DT ? 2 : 0);
   double v[K];
   int slot[K];
   int k = 0;
@@ -1265,6 +1384,7 @@ __global__ void __launch_bounds__(NTP) k_plane_final(const cplx<R>* __restrict__
     v[k] = fs; slot[k++] = SL_FS;
     v[k] = ts; slot[k++] = SL_TS;
     v[k] = exc; slot[k++] = SL_EXC;
+    v[k] = tsxc; slot[k++] = SL_TSXC;
   }
   v[k] = nv; slot[k++] = SL_NV;
   if constexpr (DT) {
@@ -1274,7 +1394,7 @@ __global__ void __launch_bounds__(NTP) k_plane_final(const cplx<R>* __restrict__
   block_sum<K, NTP>(v, red);
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int m = 0; m < K; ++m) partials[slot[m] * maxb + i1] = v[m];
+    for (int m = 0; m < K; ++m) partials[slot[m] * maxb + 2 * i1 + h] = v[m];
   }
 }
 
@@ -1283,6 +1403,7 @@ constexpr int RED_NT = 64 * SL_COUNT;   // one wavefront per slot
 
 __global__ void __launch_bounds__(RED_NT) k_reduce_scalars(const double* __restrict__ partials, int maxb,
                                                            ReduceParams rp, double* __restrict__ sc, Publish pub) {
+  OFDFT_GATE(rp.gate);
   __shared__ double raw[SL_COUNT];
   __shared__ double out[SC_COUNT];
   reduce_scalars<RED_NT>(partials, maxb, rp, sc, pub, raw, out);
@@ -1300,7 +1421,9 @@ __global__ void __launch_bounds__(64) k_publish(const double* __restrict__ src, 
 constexpr int VEC_BLOCKS = 512;
 
 template <int K, class Op>
-__global__ void __launch_bounds__(NT) k_vec(long long n, Op op, double* __restrict__ part) {
+__global__ void __launch_bounds__(NT) k_vec(long long n, Op op, double* __restrict__ part,
+                                             const double* __restrict__ gate) {
+  OFDFT_GATE(gate);
   __shared__ double red[(K > 0 ? K : 1) * NT / 64];
   double acc[K > 0 ? K : 1];
 #pragma unroll
@@ -1333,11 +1456,18 @@ __global__ void __launch_bounds__(NT) k_vec_final(const double* __restrict__ par
 struct CgCoef {
   int pcg, have_prev;
   double gg_prev, dv;
+  const double* st;   // graph mode: have_prev and gg_prev come from the device CG state
+  const double* gate;
 };
 
 template <int K>
 __global__ void __launch_bounds__(NT) k_cg_dots_final(const double* __restrict__ part, int nb,
                                                       double* __restrict__ sc, CgCoef cf) {
+  OFDFT_GATE(cf.gate);
+  if (cf.st) {
+    cf.have_prev = cf.st[CG_HAVE_PREV] != 0.0;
+    cf.gg_prev = cf.st[CG_GG_PREV];
+  }
   __shared__ double red[NT / 64];
   double dots[K];
   for (int k = 0; k < K; ++k) {
@@ -1369,10 +1499,18 @@ struct TrialCoef {
   double F_prev;
   int have_prev;
   double r, dv, kappa;
+  const double* st;   // graph mode: F_prev, have_prev and kappa come from the device CG state
+  const double* gate;
 };
 
 __global__ void __launch_bounds__(NT) k_dir_final(const double* __restrict__ part, int nb, double* __restrict__ sc,
                                                   TrialCoef tc) {
+  OFDFT_GATE(tc.gate);
+  if (tc.st) {
+    tc.F_prev = tc.st[CG_F_PREV];
+    tc.have_prev = tc.st[CG_HAVE_PREV] != 0.0;
+    tc.kappa = tc.st[CG_KAPPA];
+  }
   __shared__ double red[NT / 64];
   double dots[2];
   for (int k = 0; k < 2; ++k) {
@@ -1402,17 +1540,20 @@ __global__ void __launch_bounds__(NT) k_dir_final(const double* __restrict__ par
 }
 
 // g = 2 dv phi (v - mu): dots g.g, g.gprev, g.d and sum n (v - mu)^2
+// st (graph mode): gprev and d count only while the device CG state has a previous step.
 template <typename R>
 struct OpGradDots {
   const double* phi; const R* v; const double* sc; const double* gprev; const double* d; double two_dv;
+  const double* st;
   __device__ void operator()(long long i, double* acc) const {
+    const bool prev = !st || st[CG_HAVE_PREV] != 0.0;
     const double mu = sc[SC_MU];
     const double p = phi[i];
     const double dvm = double(v[i]) - mu;
     const double gi = two_dv * p * dvm;
     acc[0] += gi * gi;
-    acc[1] += gprev ? gi * gprev[i] : 0.0;
-    acc[2] += d ? gi * d[i] : 0.0;
+    acc[1] += (gprev && prev) ? gi * gprev[i] : 0.0;
+    acc[2] += (d && prev) ? gi * d[i] : 0.0;
     acc[3] += p * p * dvm * dvm;
   }
 };
@@ -1422,17 +1563,19 @@ struct OpGradDots {
 template <typename R>
 struct OpPrecDots {
   const double* phi; const R* v; const R* w; const double* sc; const double* gprev; double two_dv;
+  const double* st;
   __device__ void operator()(long long i, double* acc) const {
+    const bool prev = gprev && (!st || st[CG_HAVE_PREV] != 0.0);
     const double mu = sc[SC_MU];
     const double p = phi[i];
     const double dvm = double(v[i]) - mu;
     const double gi = two_dv * p * dvm;
     const double zi = gi + double(w[i]);
     acc[0] += zi * gi;
-    acc[1] += gprev ? zi * gprev[i] : 0.0;
+    acc[1] += prev ? zi * gprev[i] : 0.0;
     acc[2] += zi * p;
     acc[3] += p * p * dvm * dvm;
-    acc[4] += gprev ? p * gprev[i] : 0.0;
+    acc[4] += prev ? p * gprev[i] : 0.0;
   }
 };
 
@@ -1442,8 +1585,10 @@ template <typename R>
 struct OpPrecDirection {
   const double* phi; const R* v; const R* w; const double* sc; double* gprev; double* d;
   double two_dv, cproj; int restart;
+  const double* st;   // graph mode: cproj from the device CG state
   __device__ void operator()(long long i, double* acc) const {
     const double beta = restart ? 0.0 : sc[SC_BETA], cz = sc[SC_CZ];
+    const double cproj = st ? st[CG_CPROJ] : this->cproj;
     const double p = phi[i];
     const double gi = two_dv * p * (double(v[i]) - sc[SC_MU]);
     const double di = -(gi + double(w[i]) - cz * p) + beta * (d[i] - cproj * p);
@@ -1460,8 +1605,10 @@ template <typename R>
 struct OpDirection {
   const double* phi; const R* v; const double* sc; double* gprev; double* d; double two_dv, beta_host, cproj;
   int dev_beta;
+  const double* st;   // graph mode: cproj from the device CG state
   __device__ void operator()(long long i, double* acc) const {
     const double beta = dev_beta ? sc[SC_BETA] : beta_host;
+    const double cproj = st ? st[CG_CPROJ] : this->cproj;
     const double p = phi[i];
     const double gi = two_dv * p * (double(v[i]) - sc[SC_MU]);
     const double di = -gi + beta * (d[i] - cproj * p);
@@ -1883,11 +2030,10 @@ __global__ void __launch_bounds__(NT) k_stress_local(const double* __restrict__ 
       acc[6] += w2 * dy * dz;
       acc[7] += w2 * dx * dz;
     }
-    if (ep.xc) {
-      R eps, vxc;
-      pz81<R>(ln_n, eps, vxc);
-      acc[1] += n * (double(eps) - double(vxc));
-    }
+    // LDA XC term delta_ab int n (f_xc - v_xc) (PZ81, or KSDT by Eq. stressLSDAxc)
+    double vx = 0.0, ex = 0.0, tx = 0.0;
+    xc_point<R>(ep.xc, n, ln_n, ep.lt0, vx, ex, tx);
+    acc[1] += ex - n * vx;
   }
   block_sum<8>(acc, red);
   if (threadIdx.x == 0) {
@@ -1920,11 +2066,22 @@ int dev_upload_tables(int device) {
   if (device < 0) return OFDFT_E_ARG;
   if ((int)uploaded.size() <= device) uploaded.resize(device + 1, 0);
   if (uploaded[device]) return OFDFT_OK;
-  if (hipMemcpyToSymbol(HIP_SYMBOL(c_t_gga), kTGga, sizeof(kTGga)) != hipSuccess) return OFDFT_E_DEVICE;
-  if (hipMemcpyToSymbol(HIP_SYMBOL(c_t_tf), kTTf, sizeof(kTTf)) != hipSuccess) return OFDFT_E_DEVICE;
+  // function-major (as generated) -> coefficient-major within each piece
+  auto k_major = [](const double* src, int nf) {
+    std::vector<double> out((size_t)OFDFT_T_NP * nf * OFDFT_T_NC);
+    for (int p = 0; p < OFDFT_T_NP; ++p)
+      for (int f = 0; f < nf; ++f)
+        for (int k = 0; k < OFDFT_T_NC; ++k)
+          out[((size_t)p * OFDFT_T_NC + k) * nf + f] = src[((size_t)p * nf + f) * OFDFT_T_NC + k];
+    return out;
+  };
+  const std::vector<double> gga = k_major(kTGga, 8), tf = k_major(kTTf, 3);
+  if (hipMemcpyToSymbol(HIP_SYMBOL(c_t_gga), gga.data(), sizeof(kTGga)) != hipSuccess) return OFDFT_E_DEVICE;
+  if (hipMemcpyToSymbol(HIP_SYMBOL(c_t_tf), tf.data(), sizeof(kTTf)) != hipSuccess) return OFDFT_E_DEVICE;
   uploaded[device] = 1;
   return OFDFT_OK;
 }
+
 
 template <typename R, int L>
 static size_t lds_rpass_fwd(int tr) {
@@ -1978,7 +2135,7 @@ static void launch_x2_u(ofdft_ctx* c, void* a0, void* a1, void* a2, int narr) {
   dim3 grid((unsigned)((nrows + g.rb - 1) / g.rb), narr);
   Arr3 arr{{a0, a1, a2}};
   hipLaunchKernelGGL((k_cpass_x2<R, L, SIGN, U>), grid, dim3(NT), (lds_x2<R, L>(g.rb)), c->stream, arr,
-                     (const cplx<R>*)c->tw[1], nrows, g.rb);
+                     (const cplx<R>*)c->tw[1], nrows, g.rb, g.gate);
 }
 
 // Staged elements per thread of an x1 tile of L * tc elements: 1, 2, 4 or 8.
@@ -2052,10 +2209,10 @@ template <typename R, int L>
 static void launch_plane_fwd_density(ofdft_ctx* c, const double* phi, void* out, const Rotation* rot) {
   const GridDesc& g = c->g;
   if (rot)
-    hipLaunchKernelGGL((k_plane_fwd_density<R, L, true>), dim3(g.n1), dim3(NTP), (lds_plane<R, L>(1)), c->stream,
+    hipLaunchKernelGGL((k_plane_fwd_density<R, L, true>), dim3(2 * g.n1), dim3(NTP), (lds_plane<R, L>(1)), c->stream,
                        phi, (cplx<R>*)out, (const cplx<R>*)c->tw[2], g, c->partials, c->max_blocks, *rot);
   else
-    hipLaunchKernelGGL((k_plane_fwd_density<R, L, false>), dim3(g.n1), dim3(NTP), (lds_plane<R, L>(1)), c->stream,
+    hipLaunchKernelGGL((k_plane_fwd_density<R, L, false>), dim3(2 * g.n1), dim3(NTP), (lds_plane<R, L>(1)), c->stream,
                        phi, (cplx<R>*)out, (const cplx<R>*)c->tw[2], g, c->partials, c->max_blocks, Rotation{});
 }
 
@@ -2090,19 +2247,20 @@ template <typename R, int L, bool TF>
 static void launch_plane_final(ofdft_ctx* c, const double* phi, void* v_out, const EvalParams& ep, const Slope* sl) {
   const GridDesc& g = c->g;
   if (sl)
-    hipLaunchKernelGGL((k_plane_final<R, L, TF, true>), dim3(g.n1), dim3(NTP), (lds_plane<R, L>(6)), c->stream,
+    hipLaunchKernelGGL((k_plane_final<R, L, TF, true>), dim3(2 * g.n1), dim3(NTP), (lds_plane<R, L>(kFinalSums)), c->stream,
                        (const cplx<R>*)c->D, phi, (const R*)c->vloc, (R*)v_out, (const cplx<R>*)c->tw[2], g, ep,
                        c->partials, c->max_blocks, *sl);
   else
-    hipLaunchKernelGGL((k_plane_final<R, L, TF, false>), dim3(g.n1), dim3(NTP), (lds_plane<R, L>(6)), c->stream,
+    hipLaunchKernelGGL((k_plane_final<R, L, TF, false>), dim3(2 * g.n1), dim3(NTP), (lds_plane<R, L>(kFinalSums)), c->stream,
                        (const cplx<R>*)c->D, phi, (const R*)c->vloc, (R*)v_out, (const cplx<R>*)c->tw[2], g, ep,
                        c->partials, c->max_blocks, Slope{});
 }
 
 template <typename R>
 static void launch_pointwise_gga(ofdft_ctx* c, const double* phi, const EvalParams& ep) {
-  hipLaunchKernelGGL((k_pointwise_gga<R>), dim3(pw_blocks(c->g)), dim3(NT), 0, c->stream, phi, (R*)c->gr[0],
-                     (R*)c->gr[1], (R*)c->gr[2], (R*)c->vloc, c->g.N, ep, c->partials, c->max_blocks);
+  auto k = ep.xc == 1 ? k_pointwise_gga<R, 1> : ep.xc == 2 ? k_pointwise_gga<R, 2> : k_pointwise_gga<R, 0>;
+  hipLaunchKernelGGL(k, dim3(pw_blocks(c->g)), dim3(NT), 0, c->stream, phi, (R*)c->gr[0], (R*)c->gr[1],
+                     (R*)c->gr[2], (R*)c->vloc, c->g.N, ep, c->partials, c->max_blocks);
 }
 
 template <typename R, int L>
@@ -2134,11 +2292,11 @@ static void launch_rpass_final(ofdft_ctx* c, const double* phi, void* v_out, con
   const GridDesc& g = c->g;
   dim3 grid(g.n2 / g.tr, g.n1);
   if (sl)
-    hipLaunchKernelGGL((k_rpass_final<R, L, TF, true>), grid, dim3(NT), (lds_rpass_inv<R, L>(g.tr, 0, 6)),
+    hipLaunchKernelGGL((k_rpass_final<R, L, TF, true>), grid, dim3(NT), (lds_rpass_inv<R, L>(g.tr, 0, kFinalSums)),
                        c->stream, (const cplx<R>*)c->D, phi, (const R*)c->vloc, (R*)v_out, (const cplx<R>*)c->tw[2],
                        g, ep, c->partials, c->max_blocks, *sl);
   else
-    hipLaunchKernelGGL((k_rpass_final<R, L, TF, false>), grid, dim3(NT), (lds_rpass_inv<R, L>(g.tr, 0, 6)),
+    hipLaunchKernelGGL((k_rpass_final<R, L, TF, false>), grid, dim3(NT), (lds_rpass_inv<R, L>(g.tr, 0, kFinalSums)),
                        c->stream, (const cplx<R>*)c->D, phi, (const R*)c->vloc, (R*)v_out, (const cplx<R>*)c->tw[2],
                        g, ep, c->partials, c->max_blocks, Slope{});
 }
@@ -2184,10 +2342,11 @@ static bool plane_mode(const ofdft_ctx* c) {
 static EvalParams make_params(ofdft_ctx* c) {
   EvalParams ep{};
   ep.functional = c->opt.functional;
-  ep.xc = c->opt.xc == OFDFT_XC_PZ81 ? 1 : 0;
+  ep.xc = c->opt.xc == OFDFT_XC_PZ81 ? 1 : c->opt.xc == OFDFT_XC_KSDT ? 2 : 0;
   ep.T = c->T_ha;
   ep.lt0 = lt_offset(c->T_ha);
   ep.alpha_sum = c->alpha_sum;
+  ep.gate = c->g.gate;
   switch (c->opt.functional) {
     case OFDFT_SGA: ep.enh_kind = 0; ep.enh_c1 = c->opt.mu_sga; break;
     case OFDFT_VWTF: ep.enh_kind = 0; ep.enh_c1 = 5.0 / 3.0; break;
@@ -2270,9 +2429,9 @@ static int eval_impl(ofdft_ctx* c, const double* phi, void* v_out, double* sc, c
     }
   }
   // partial sums of the density and final passes: one per block
-  const int nb_r = plane ? g.n1 : (g.n2 / g.tr) * g.n1;
+  const int nb_r = plane ? 2 * g.n1 : (g.n2 / g.tr) * g.n1;   // plane passes: two blocks per i1 plane
   const ReduceParams rp{nb_r, (g.n2 / g.tc) * g.n3k, tf ? nb_r : pw_blocks(g), sl ? 1 : 0, g.dv, g.volume,
-                        c->alpha_sum};
+                        c->alpha_sum, g.gate};
   tmark(c, "reduce_scalars");
   hipLaunchKernelGGL(k_reduce_scalars, dim3(1), dim3(RED_NT), 0, c->stream, c->partials, c->max_blocks, rp, sc,
                      pub);
@@ -2289,7 +2448,7 @@ static size_t max_lds_impl(const ofdft_ctx* c) {
   switch (g.n3) {
 #define OFDFT_LDS3(LEN) \
     case LEN: upd(lds_rpass_fwd<R, LEN>(g.tr)); upd(lds_rpass_inv<R, LEN>(g.tr, 0, 0)); \
-              upd(lds_rpass_inv<R, LEN>(g.tr, 0, 6)); break;
+              upd(lds_rpass_inv<R, LEN>(g.tr, 0, kFinalSums)); break;
     OFDFT_LENGTHS(OFDFT_LDS3)
 #undef OFDFT_LDS3
     default: break;
@@ -2308,7 +2467,7 @@ static size_t max_lds_impl(const ofdft_ctx* c) {
   }
   if (plane_mode(c)) {
     switch (g.n3) {
-#define OFDFT_LDSP(LEN) case LEN: upd(lds_plane<R, LEN>(6)); break;
+#define OFDFT_LDSP(LEN) case LEN: upd(lds_plane<R, LEN>(kFinalSums)); break;
       OFDFT_PLANE_LENGTHS(OFDFT_LDSP)
 #undef OFDFT_LDSP
       default: break;
@@ -2388,13 +2547,13 @@ int dev_eval_trial(ofdft_ctx* c, const double* phi, const double* dir, double ca
 // ---------------------------------------------------------------- allocation
 template <typename T>
 static bool dalloc(ofdft_ctx* c, T** p, size_t n) {
-  *p = nullptr;
-  if (n == 0) n = 1;
-  return hip_ok(c, hipMalloc((void**)p, n * sizeof(T)), "hipMalloc");
+  void* q = nullptr;
+  const bool ok = hip_ok(c, ctx_malloc(c, &q, (n ? n : 1) * sizeof(T)), "device allocation");
+  *p = reinterpret_cast<T*>(q);
+  return ok;
 }
 static bool dalloc_bytes(ofdft_ctx* c, void** p, size_t bytes) {
-  *p = nullptr;
-  return hip_ok(c, hipMalloc(p, bytes ? bytes : 1), "hipMalloc");
+  return hip_ok(c, ctx_malloc(c, p, bytes), "device allocation");
 }
 
 template <typename R>
@@ -2502,7 +2661,7 @@ int dev_alloc_grid(ofdft_ctx* c) {
   for (int k = 0; k < 3 && ok; ++k) ok = dalloc_bytes(c, &c->gr[k], N * rs);
   ok = ok && dalloc(c, &c->partials, (size_t)SL_COUNT * c->max_blocks) && dalloc(c, &c->scalars, SC_COUNT) &&
        dalloc(c, &c->scalars_t, SC_COUNT) && dalloc(c, &c->scalars_t2, SC_COUNT) &&
-       dalloc(c, &c->vpart, 8 * VEC_BLOCKS) && dalloc(c, &c->vout, 32);
+       dalloc(c, &c->vpart, 8 * VEC_BLOCKS) && dalloc(c, &c->vout, 32) && dalloc(c, &c->cgst, CG_COUNT);
   if (ok && !c->hmap) {
     ok = hip_ok(c, hipHostMalloc((void**)&c->hmap, (kMapDoubles + 1) * sizeof(double),
                                  hipHostMallocMapped | hipHostMallocCoherent), "hipHostMalloc (mapped)");
@@ -2528,34 +2687,51 @@ int dev_alloc_grid(ofdft_ctx* c) {
 }
 
 void dev_free_grid(ofdft_ctx* c) {
+  // a caller's allocator may hand the memory out again at once: let pending work finish
+  // (hipFree waits by itself)
+  if (c->opt.alloc && c->stream) (void)hipStreamSynchronize(c->stream);
+  dev_cg_graph_release(c);   // its launches refer to the buffers freed here
   void** ps[] = {(void**)&c->phi, (void**)&c->phi_t, (void**)&c->d, (void**)&c->gprev, (void**)&c->tn[0],
                  (void**)&c->tn[1], (void**)&c->tn[2], (void**)&c->tn[3], &c->v, &c->v_t, &c->vloc, &c->A,
                  &c->S0, &c->D, &c->Vext, &c->B[0], &c->B[1], &c->B[2], &c->tw[0], &c->tw[1], &c->tw[2],
                  (void**)&c->partials, (void**)&c->scalars, (void**)&c->scalars_t, (void**)&c->vpart,
                  (void**)&c->vout, &c->gr[0], &c->gr[1], &c->gr[2], (void**)&c->phi_hist[0],
                  (void**)&c->phi_hist[1], (void**)&c->phi_hist[2], (void**)&c->phi_t2, &c->v_t2,
-                 (void**)&c->scalars_t2, (void**)&c->sfac};
+                 (void**)&c->scalars_t2, (void**)&c->sfac, (void**)&c->cgst};
   for (void** p : ps) {
-    if (*p) (void)hipFree(*p);
+    ctx_free(c, *p);
     *p = nullptr;
   }
   c->n_hist = 0;
 }
 
+// Ion buffers: the phase tables hold nat * (n1 + n2 + n3h) entries, which depends on
+// the grid; the charges/coordinates, force partials and forces depend on nat alone.
+// Each has its own capacity, so a smaller grid with more ions still reallocates.
 int dev_alloc_ions(ofdft_ctx* c) {
-  const int M = c->g.n1 + c->g.n2 + c->g.n3h;
-  if (c->phase_cap < c->nat * M) {
-    if (c->phase) (void)hipFree(c->phase);
-    if (c->dZ) (void)hipFree(c->dZ);
-    if (c->fpart) (void)hipFree(c->fpart);
-    if (c->dforces) (void)hipFree(c->dforces);
-    c->phase = nullptr; c->dZ = nullptr; c->fpart = nullptr; c->dforces = nullptr;
-    const int cap = c->nat * M;
-    bool ok = dalloc(c, &c->phase, 2 * (size_t)cap) && dalloc(c, &c->dZ, c->nat + 4 * (size_t)c->nat) &&
-              dalloc(c, &c->fpart, std::max<size_t>((size_t)3 * c->nat * 1024, 8 * PW_BLOCKS + 12 * 1024)) &&
-              dalloc(c, &c->dforces, 3 * (size_t)c->nat);
+  const long long M = c->g.n1 + c->g.n2 + c->g.n3h;
+  const long long need_phase = (long long)c->nat * M;
+  if (c->opt.alloc && c->stream && (c->phase_cap < need_phase || c->ion_cap < c->nat))
+    (void)hipStreamSynchronize(c->stream);
+  if (c->phase_cap < need_phase) {
+    ctx_free(c, c->phase);
+    c->phase = nullptr;
+    c->phase_cap = 0;
+    if (!dalloc(c, &c->phase, 2 * (size_t)need_phase)) return OFDFT_E_DEVICE;
+    c->phase_cap = need_phase;
+  }
+  if (c->ion_cap < c->nat) {
+    ctx_free(c, c->dZ);
+    ctx_free(c, c->fpart);
+    ctx_free(c, c->dforces);
+    c->dZ = nullptr; c->fpart = nullptr; c->dforces = nullptr;
+    c->ion_cap = 0;
+    const size_t nat = (size_t)c->nat;
+    bool ok = dalloc(c, &c->dZ, nat + 4 * nat) &&
+              dalloc(c, &c->fpart, std::max<size_t>(3 * nat * 1024, 8 * PW_BLOCKS + 12 * 1024)) &&
+              dalloc(c, &c->dforces, 3 * nat);
     if (!ok) return OFDFT_E_DEVICE;
-    c->phase_cap = cap;
+    c->ion_cap = c->nat;
   }
   return OFDFT_OK;
 }
@@ -2715,7 +2891,7 @@ int dev_stress(ofdft_ctx* c, double* sums) {
 // ---------------------------------------------------------------- vector-op launchers
 template <int K, class Op>
 static int run_vec(ofdft_ctx* c, const Op& op, double* out = nullptr) {
-  hipLaunchKernelGGL((k_vec<K, Op>), dim3(VEC_BLOCKS), dim3(NT), 0, c->stream, c->g.N, op, c->vpart);
+  hipLaunchKernelGGL((k_vec<K, Op>), dim3(VEC_BLOCKS), dim3(NT), 0, c->stream, c->g.N, op, c->vpart, c->g.gate);
   if constexpr (K > 0)
     hipLaunchKernelGGL((k_vec_final<K>), dim3(1), dim3(NT), 0, c->stream, c->vpart, VEC_BLOCKS,
                        out ? out : c->vout);
@@ -2749,7 +2925,7 @@ static void launch_rpass_fwd_grad(ofdft_ctx* c, const double* phi, const void* v
 // Reduce the K dots the op accumulates and form the CG coefficients (k_cg_dots_final).
 template <int K, class Op>
 static int run_cg_dots(ofdft_ctx* c, const Op& op, const CgCoef& cf) {
-  hipLaunchKernelGGL((k_vec<K, Op>), dim3(VEC_BLOCKS), dim3(NT), 0, c->stream, c->g.N, op, c->vpart);
+  hipLaunchKernelGGL((k_vec<K, Op>), dim3(VEC_BLOCKS), dim3(NT), 0, c->stream, c->g.N, op, c->vpart, c->g.gate);
   hipLaunchKernelGGL((k_cg_dots_final<K>), dim3(1), dim3(NT), 0, c->stream, c->vpart, VEC_BLOCKS, c->scalars, cf);
   return hip_ok(c, hipGetLastError(), "CG dots") ? OFDFT_OK : OFDFT_E_DEVICE;
 }
@@ -2757,21 +2933,23 @@ static int run_cg_dots(ofdft_ctx* c, const Op& op, const CgCoef& cf) {
 // The direction pass of a CG step: d, gprev and its dots reduced by k_dir_final.
 template <class Op>
 static int run_direction(ofdft_ctx* c, const Op& op, const TrialCoef& tc) {
-  hipLaunchKernelGGL((k_vec<2, Op>), dim3(VEC_BLOCKS), dim3(NT), 0, c->stream, c->g.N, op, c->vpart);
+  hipLaunchKernelGGL((k_vec<2, Op>), dim3(VEC_BLOCKS), dim3(NT), 0, c->stream, c->g.N, op, c->vpart, c->g.gate);
   hipLaunchKernelGGL(k_dir_final, dim3(1), dim3(NT), 0, c->stream, c->vpart, VEC_BLOCKS, c->scalars, tc);
   return hip_ok(c, hipGetLastError(), "CG direction") ? OFDFT_OK : OFDFT_E_DEVICE;
 }
 
+// st (graph mode): have_prev, gg_prev, cproj, F_prev and kappa are read on the device from
+// the CG state instead of the host arguments.
 template <typename R>
 static int cg_step_impl(ofdft_ctx* c, bool pcg, bool have_prev, double gg_prev, double cproj, double F_prev,
-                        double r, double kappa) {
-  const TrialCoef tc{F_prev, have_prev ? 1 : 0, r, c->g.dv, kappa};
+                        double r, double kappa, const double* st = nullptr) {
+  const TrialCoef tc{F_prev, have_prev ? 1 : 0, r, c->g.dv, kappa, st, c->g.gate};
   const GridDesc& g = c->g;
   const double two_dv = 2.0 * g.dv;
   const double* phi = c->phi;
   const R* v = (const R*)c->v;
-  const double* gprev = have_prev ? c->gprev : nullptr;
-  const CgCoef cf{pcg ? 1 : 0, have_prev ? 1 : 0, gg_prev, g.dv};
+  const double* gprev = (have_prev || st) ? c->gprev : nullptr;
+  const CgCoef cf{pcg ? 1 : 0, have_prev ? 1 : 0, gg_prev, g.dv, st, c->g.gate};
   int rc;
   if (pcg) {
     // w = (P - 1) g: forward 3D FFT of g, filter in the x1 pass, inverse 3D FFT into gr[0];
@@ -2789,14 +2967,15 @@ static int cg_step_impl(ofdft_ctx* c, bool pcg, bool have_prev, double gg_prev, 
       OFDFT_DISPATCH(g.n3, (launch_rpass_inv_real1<R, L_>(c, c->B[0], c->gr[0])));
     }
 
-    rc = run_cg_dots<5>(c, OpPrecDots<R>{phi, v, (const R*)c->gr[0], c->scalars, gprev, two_dv}, cf);
+    rc = run_cg_dots<5>(c, OpPrecDots<R>{phi, v, (const R*)c->gr[0], c->scalars, gprev, two_dv, st}, cf);
     if (rc) return rc;
-    return run_direction(c, OpPrecDirection<R>{phi, v, (const R*)c->gr[0], c->scalars, c->gprev, c->d, two_dv, cproj, 0},
-                         tc);
+    return run_direction(
+        c, OpPrecDirection<R>{phi, v, (const R*)c->gr[0], c->scalars, c->gprev, c->d, two_dv, cproj, 0, st}, tc);
   }
-  rc = run_cg_dots<4>(c, OpGradDots<R>{phi, v, c->scalars, gprev, have_prev ? c->d : nullptr, two_dv}, cf);
+  rc = run_cg_dots<4>(c, OpGradDots<R>{phi, v, c->scalars, gprev, (have_prev || st) ? c->d : nullptr, two_dv, st},
+                      cf);
   if (rc) return rc;
-  return run_direction(c, OpDirection<R>{phi, v, c->scalars, c->gprev, c->d, two_dv, 0.0, cproj, 1}, tc);
+  return run_direction(c, OpDirection<R>{phi, v, c->scalars, c->gprev, c->d, two_dv, 0.0, cproj, 1, st}, tc);
 }
 
 int dev_cg_step(ofdft_ctx* c, bool pcg, bool have_prev, double gg_prev, double cproj, double F_prev, double r,
@@ -2854,6 +3033,346 @@ int dev_tn_hess_finish(ofdft_ctx* c, double* hs, const double* phi, const double
   (void)s;
   (void)mu_term;
   return run_vec<1>(c, OpHessScale{hs, phi, inv2e});
+}
+
+// ---------------------------------------------------------------- HIP-graph CG iteration
+// One CG iteration as a fixed sequence of launches that a HIP graph can replay, every
+// decision taken on the device in FP64 from the CG state st (CgSlot):
+//   CG step (gate ACTIVE)      preconditioned gradient, PR+ coefficients, direction d and
+//                              the first trial angle theta1 (the rule of the host CG)
+//   k_cg_check                 stop rule on the residual, max_iter, descent check
+//   trial 1 (gate GATE1)       evaluation at theta1 with dF/dtheta
+//   k_ls_decide1               accept theta1 (strong-Wolfe test of the host line search)
+//                              or place theta2 by the secant of the slopes at 0 and theta1
+//                              (or the quadratic through F(0), F'(0), F(theta1))
+//   trial 2 (gate GATE2)       evaluation at theta2
+//   k_ls_decide2               take the lower of the trials that decrease F, update the CG
+//                              history and the energy-change stop, handle a stall; publish
+//                              the status to the host
+//   k_accept (gate GATEACC)    copy the taken trial (phi, v, scalars) into the current state
+// A converged or failed minimisation clears ACTIVE, and every later launch returns at once.
+
+__device__ __forceinline__ bool fin(double x) { return isfinite(x); }
+
+// Resolution of F: FP64 rounding (1e-14 |F|), or in the mixed path the FP32 rounding of its
+// terms, ~5e-10 of S = |F_s| + |E_xc| + |E_H| + |E_ext| + |E_alphaZ| (the magnitudes that are
+// summed; a change of F below this is no resolvable progress).
+__device__ __forceinline__ double term_scale(const double* sc) {
+  return fabs(sc[SC_FS]) + fabs(sc[SC_EXC]) + fabs(sc[SC_EH]) + fabs(sc[SC_EEXT]) + fabs(sc[SC_EAZ]);
+}
+__device__ __forceinline__ double f_resolution(const double* sc, double F0, const CgConst& k) {
+  return k.mixed ? 5e-10 * term_scale(sc) : 1e-14 * fabs(F0);
+}
+
+__global__ void k_cg_init(double* __restrict__ st, const double* __restrict__ sc) {
+  if (threadIdx.x != 0) return;
+  for (int k = 0; k < CG_COUNT; ++k) st[k] = 0.0;
+  st[CG_F] = sc[SC_FTOT];
+  st[CG_EVALS] = 1.0;   // the starting evaluation
+  if (isfinite(sc[SC_FTOT])) {
+    st[CG_ACTIVE] = 1.0;
+  } else {
+    st[CG_STATUS] = CGS_NONFINITE;
+  }
+}
+
+// Stop rule and descent check after the direction kernels.
+__global__ void k_cg_check(double* __restrict__ st, const double* __restrict__ sc, CgConst k) {
+  if (threadIdx.x != 0) return;
+  st[CG_GATE1] = 0.0;
+  st[CG_GATE2] = 0.0;
+  st[CG_GATEACC] = 0.0;
+  st[CG_SRC] = 0.0;
+  if (st[CG_ACTIVE] == 0.0) return;
+  const double gg = sc[SC_DOT0];
+  const double resid = sqrt(sc[SC_DOT0 + 3] / (sc[SC_NE] / k.dv));
+  st[CG_GG] = gg;
+  st[CG_RESID] = resid;
+  if (gg <= 0.0 || (st[CG_SMALL] >= 2.0 && (k.tol_residual <= 0.0 || resid < k.tol_residual))) {
+    st[CG_ACTIVE] = 0.0;
+    st[CG_CONVERGED] = 1.0;
+    st[CG_STATUS] = CGS_CONVERGED;
+    return;
+  }
+  if (st[CG_ITERS] >= k.max_iter) {
+    st[CG_ACTIVE] = 0.0;
+    st[CG_STATUS] = CGS_MAXITER;
+    return;
+  }
+  const double dd = sc[SC_DD], dg = sc[SC_DG];
+  if (!(dg < 0.0) || !(dd > 0.0)) {
+    // not a descent direction: the next iteration restarts along -g (-z)
+    st[CG_HAVE_PREV] = 0.0;
+    st[CG_KAPPA] = 0.0;
+    st[CG_ITERS] += 1.0;
+    return;
+  }
+  const double dn = sqrt(dd);
+  st[CG_DN] = dn;
+  st[CG_DF0] = k.r * dg / dn;
+  st[CG_GATE1] = 1.0;
+  st[CG_EVALS] += 1.0;
+}
+
+__device__ __forceinline__ void trial_coefs(double th, double r, double dn, double ne_over_dv, double* out) {
+  const double ratio = r / sqrt(ne_over_dv);
+  const double ct = cos(th), st_ = sin(th);
+  out[0] = ct * ratio;
+  out[1] = st_ * r / dn;
+  out[2] = -st_ * ratio;
+  out[3] = ct * r / dn;
+}
+
+// First trial: accept it, or place the second one.  Non-finite trial: restart once.
+__global__ void k_ls_decide1(double* __restrict__ st, const double* __restrict__ sc,
+                             const double* __restrict__ sc1, CgConst k) {
+  if (threadIdx.x != 0) return;
+  if (st[CG_GATE1] == 0.0) return;
+  const double F0 = st[CG_F], dF0 = st[CG_DF0], th1 = sc[SC_TH1];
+  double F1 = sc1[SC_FTOT];
+  const double d1 = sc1[SC_DOT0];
+  st[CG_TRIALS] += 1.0;
+  if (k.inject_at != 0 && (k.inject_at < 0 || st[CG_TRIALS] == (double)k.inject_at)) F1 = NAN;
+  if (!fin(F1) || !fin(d1)) {
+    if (st[CG_NF_USED] == 0.0) {
+      st[CG_NF_USED] = 1.0;
+      st[CG_HAVE_PREV] = 0.0;
+      st[CG_KAPPA] = 0.0;
+      st[CG_SMALL] = 0.0;
+    } else {
+      st[CG_ACTIVE] = 0.0;
+      st[CG_STATUS] = CGS_NONFINITE;
+    }
+    st[CG_GATE1] = 0.0;   // nothing to take from this iteration
+    st[CG_ITERS] += 1.0;
+    return;
+  }
+  st[CG_F1] = F1;
+  st[CG_D1] = d1;
+  const bool armijo = F1 <= F0 + 1e-4 * th1 * dF0;
+  const bool flat = F1 <= F0 + f_resolution(sc, F0, k);
+  if ((armijo || flat) && fabs(d1) <= 0.1 * fabs(dF0)) {
+    st[CG_SRC] = 1.0;
+    return;
+  }
+  double th2;
+  if (armijo && d1 < 0.0) {
+    // still descending at theta1: extrapolate with the secant of the slope
+    th2 = d1 > dF0 ? th1 * dF0 / (dF0 - d1) : 4.0 * th1;
+    th2 = fmin(fmax(th2, 1.5 * th1), 4.0 * th1);
+  } else {
+    // the minimum lies inside (0, theta1).  With only one more trial the secant is trusted
+    // down to 1e-6 theta1: a first trial far past the minimum (a restart near convergence)
+    // is then corrected in one step, where a bisecting search would need many.
+    if (d1 > 0.0) {
+      th2 = th1 * dF0 / (dF0 - d1);
+    } else {
+      const double curv = F1 - F0 - dF0 * th1;
+      th2 = curv > 0.0 ? -0.5 * dF0 * th1 * th1 / curv : 0.5 * th1;
+    }
+    th2 = fmin(fmax(th2, 1e-6 * th1), 0.9 * th1);
+  }
+  st[CG_TH2] = th2;
+  trial_coefs(th2, k.r, st[CG_DN], sc[SC_NE] / k.dv, st + CG_COEF2);
+  st[CG_GATE2] = 1.0;
+  st[CG_EVALS] += 1.0;
+}
+
+// Take a trial (or handle the stall), update the history and the stop rule, publish.
+__global__ void k_ls_decide2(double* __restrict__ st, const double* __restrict__ sc,
+                             const double* __restrict__ sc1, const double* __restrict__ sc2, CgConst k,
+                             double* __restrict__ hmap) {
+  if (threadIdx.x != 0) return;
+  st[CG_LAUNCHES] += 1.0;
+  if (st[CG_ACTIVE] != 0.0 && st[CG_GATE1] != 0.0) {
+    const double F0 = st[CG_F], dF0 = st[CG_DF0];
+    const double th1 = sc[SC_TH1];
+    int take = (int)st[CG_SRC];
+    double Ft = 0.0, dt = 0.0, tht = 0.0;
+    if (take == 1) {
+      Ft = st[CG_F1];
+      dt = st[CG_D1];
+      tht = th1;
+    } else if (st[CG_GATE2] != 0.0) {
+      // candidates: a trial that does not raise F beyond its rounding level; between two,
+      // the lower F, or the smaller slope once both F sit at the rounding level (there the
+      // slope, not F, still carries the information)
+      const double F1 = st[CG_F1], d1 = st[CG_D1], F2 = sc2[SC_FTOT], d2 = sc2[SC_DOT0];
+      const double th2 = st[CG_TH2];
+      const double tol_flat = f_resolution(sc, F0, k);
+      const bool ok1 = F1 <= F0 + tol_flat;
+      const bool ok2 = fin(F2) && fin(d2) && F2 <= F0 + tol_flat;
+      bool two;
+      if (ok1 && ok2) {
+        two = fabs(F2 - F1) <= tol_flat ? fabs(d2) <= fabs(d1) : F2 < F1;
+      } else {
+        two = ok2;
+      }
+      if (two) {
+        take = 2; Ft = F2; dt = d2; tht = th2;
+      } else if (ok1) {
+        take = 1; Ft = F1; dt = d1; tht = th1;
+      }
+    }
+    st[CG_ITERS] += 1.0;
+    if (take) {
+      const double dF = F0 - Ft;
+      st[CG_LAST_DF] = dF;
+      st[CG_F_PREV] = F0;
+      st[CG_F] = Ft;
+      st[CG_GG_PREV] = st[CG_GG];
+      st[CG_KAPPA] = (tht > 0.0 && dt > dF0) ? (dt - dF0) / tht : 0.0;
+      st[CG_CPROJ] = sin(tht) * st[CG_DN] / k.r;
+      st[CG_HAVE_PREV] = 1.0;
+      // mixed path: a change below the resolution of F counts toward the stop like a change
+      // below tol_energy
+      const double resolvable = k.mixed ? f_resolution(sc, F0, k) : 0.0;
+      st[CG_SMALL] = fabs(dF) < fmax(k.tol_energy, resolvable) ? st[CG_SMALL] + 1.0 : 0.0;
+      st[CG_SRC] = take;
+      st[CG_GATEACC] = 1.0;
+      if (st[CG_SMALL] >= 2.0 && k.tol_residual <= 0.0) {
+        st[CG_ACTIVE] = 0.0;
+        st[CG_CONVERGED] = 1.0;
+        st[CG_STATUS] = CGS_CONVERGED;
+      }
+    } else {
+      // no trial lowers F: converged at the resolution of F, else restart along -g once
+      const bool had_prev = st[CG_HAVE_PREV] != 0.0;
+      const double last = had_prev ? st[CG_LAST_DF] : fabs(dF0) * th1;
+      // the mixed path's noise floor (the host CG's 1e-6 |F_tot| in terms of the summed magnitudes)
+      const bool floor_ok = k.mixed && fabs(last) < 1e-7 * term_scale(sc);
+      const bool conv = k.tol_residual > 0.0 ? (st[CG_RESID] < k.tol_residual || floor_ok)
+                                             : (st[CG_SMALL] >= 1.0 || floor_ok);
+      if (conv) {
+        st[CG_ACTIVE] = 0.0;
+        st[CG_CONVERGED] = 1.0;
+        st[CG_STATUS] = CGS_CONVERGED;
+      } else if (had_prev && st[CG_LSR_USED] == 0.0) {
+        // restart along -g; the last measured curvature still sets the first angle
+        st[CG_LSR_USED] = 1.0;
+        st[CG_HAVE_PREV] = 0.0;
+      } else {
+        st[CG_ACTIVE] = 0.0;
+        st[CG_STATUS] = CGS_STALLED;
+      }
+    }
+  }
+  // status to the host: the data first, then the launch counter with a system-scope release
+  hmap[kMapStatus + 1] = st[CG_ACTIVE];
+  hmap[kMapStatus + 2] = st[CG_STATUS];
+  hmap[kMapStatus + 3] = st[CG_ITERS];
+  hmap[kMapStatus + 4] = st[CG_EVALS];
+  hmap[kMapStatus + 5] = st[CG_F];
+  __threadfence_system();
+  __hip_atomic_store(hmap + kMapStatus, st[CG_LAUNCHES], __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Copy the taken trial into the current state: phi and v (grid-stride), scalars (block 0).
+template <typename R>
+__global__ void __launch_bounds__(NT) k_accept(const double* __restrict__ st, double* __restrict__ phi,
+                                               R* __restrict__ v, double* __restrict__ sc,
+                                               const double* __restrict__ phi1, const R* __restrict__ v1,
+                                               const double* __restrict__ sc1, const double* __restrict__ phi2,
+                                               const R* __restrict__ v2, const double* __restrict__ sc2, long long n) {
+  if (st[CG_GATEACC] == 0.0) return;
+  const bool two = st[CG_SRC] == 2.0;
+  const double* ps = two ? phi2 : phi1;
+  const R* vs = two ? v2 : v1;
+  for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT) {
+    phi[i] = ps[i];
+    v[i] = vs[i];
+  }
+  if (blockIdx.x == 0 && threadIdx.x < SC_COUNT) sc[threadIdx.x] = (two ? sc2 : sc1)[threadIdx.x];
+}
+
+template <typename R>
+static int cg_graph_iteration(ofdft_ctx* c, bool pcg, const CgConst& k) {
+  double* st = c->cgst;
+  const GridDesc saved = c->g;
+  int rc;
+  // CG step
+  c->g.gate = st + CG_ACTIVE;
+  rc = cg_step_impl<R>(c, pcg, false, 0.0, 0.0, 0.0, k.r, 0.0, st);
+  c->g.gate = nullptr;
+  if (rc) { c->g = saved; return rc; }
+  hipLaunchKernelGGL(k_cg_check, dim3(1), dim3(64), 0, c->stream, st, (const double*)c->scalars, k);
+  // trial 1 at the device angle theta1 (coefficients in scalars[SC_CA..SC_MC])
+  {
+    c->g.gate = st + CG_GATE1;
+    const Rotation rot{c->d, 0.0, 0.0, c->phi_t, c->scalars + SC_CA};
+    const Slope sl{c->phi, c->d, 0.0, 0.0, c->scalars + SC_CA};
+    rc = eval_impl<R>(c, c->phi, c->v_t, c->scalars_t, &rot, &sl, Publish{nullptr, nullptr, 0, nullptr, 0});
+    c->g.gate = nullptr;
+    if (rc) { c->g = saved; return rc; }
+  }
+  hipLaunchKernelGGL(k_ls_decide1, dim3(1), dim3(64), 0, c->stream, st, (const double*)c->scalars,
+                     (const double*)c->scalars_t, k);
+  {
+    c->g.gate = st + CG_GATE2;
+    const Rotation rot{c->d, 0.0, 0.0, c->phi_t2, st + CG_COEF2};
+    const Slope sl{c->phi, c->d, 0.0, 0.0, st + CG_COEF2};
+    rc = eval_impl<R>(c, c->phi, c->v_t2, c->scalars_t2, &rot, &sl, Publish{nullptr, nullptr, 0, nullptr, 0});
+    c->g.gate = nullptr;
+    if (rc) { c->g = saved; return rc; }
+  }
+  hipLaunchKernelGGL(k_ls_decide2, dim3(1), dim3(64), 0, c->stream, st, (const double*)c->scalars,
+                     (const double*)c->scalars_t, (const double*)c->scalars_t2, k, c->dmap);
+  const int nb = (int)std::min<long long>(2048, (c->g.N + NT - 1) / NT);
+  hipLaunchKernelGGL((k_accept<R>), dim3(nb), dim3(NT), 0, c->stream, (const double*)st, c->phi, (R*)c->v,
+                     c->scalars, (const double*)c->phi_t, (const R*)c->v_t, (const double*)c->scalars_t,
+                     (const double*)c->phi_t2, (const R*)c->v_t2, (const double*)c->scalars_t2, c->g.N);
+  c->g = saved;
+  return hip_ok(c, hipGetLastError(), "graph CG iteration") ? OFDFT_OK : OFDFT_E_DEVICE;
+}
+
+void dev_cg_graph_release(ofdft_ctx* c) {
+  if (c->cg_exec) (void)hipGraphExecDestroy(c->cg_exec);
+  if (c->cg_graph) (void)hipGraphDestroy(c->cg_graph);
+  c->cg_exec = nullptr;
+  c->cg_graph = nullptr;
+}
+
+int dev_cg_graph_prepare(ofdft_ctx* c, bool pcg, const CgConst& k) {
+  // the captured launches bake in the grid, tiles, evaluation parameters and constants
+  GraphKey key{};
+  key.g = c->g;
+  key.ep = make_params(c);
+  key.k = k;
+  key.pcg = pcg;
+  key.plane = plane_mode(c);
+  const void* bufs[9] = {c->phi, c->v, c->scalars, c->phi_t, c->v_t, c->scalars_t, c->phi_t2, c->v_t2,
+                         c->scalars_t2};
+  for (int i = 0; i < 9; ++i) key.bufs[i] = bufs[i];
+  if (c->cg_exec && std::memcmp(&key, &c->cg_key, sizeof(GraphKey)) == 0) return OFDFT_OK;
+  dev_cg_graph_release(c);
+  if (!hip_ok(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal), "graph capture"))
+    return OFDFT_E_DEVICE;
+  const int rc = c->rsize == 4 ? cg_graph_iteration<float>(c, pcg, k) : cg_graph_iteration<double>(c, pcg, k);
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(c->stream, &graph);
+  if (rc) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  if (!hip_ok(c, e, "graph capture end")) return OFDFT_E_DEVICE;
+  hipGraphExec_t exec = nullptr;
+  if (!hip_ok(c, hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "graph instantiate")) {
+    (void)hipGraphDestroy(graph);
+    return OFDFT_E_DEVICE;
+  }
+  c->cg_graph = graph;
+  c->cg_exec = exec;
+  c->cg_key = key;
+  return OFDFT_OK;
+}
+
+int dev_cg_graph_start(ofdft_ctx* c) {
+  hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(64), 0, c->stream, c->cgst, (const double*)c->scalars);
+  return hip_ok(c, hipGetLastError(), "CG state init") ? OFDFT_OK : OFDFT_E_DEVICE;
+}
+
+int dev_cg_graph_launch(ofdft_ctx* c) {
+  return hip_ok(c, hipGraphLaunch(c->cg_exec, c->stream), "graph launch") ? OFDFT_OK : OFDFT_E_DEVICE;
 }
 
 int dev_read(ofdft_ctx* c, const double* dptr, int n, double* host) {

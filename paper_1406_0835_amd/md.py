@@ -1,6 +1,6 @@
 """Born-Oppenheimer molecular dynamics driven through the C ABI.
 
-Each ionic step follows the paper's coupling (Sec. I flow chart, Sec. V C):
+Each ionic step follows the paper's coupling (Sec. I flow chart, Sec. V D):
 new ion positions in, density re-minimised from the previous density (warm
 start), free energy and forces out, velocity-Verlet update of the ions.
 Energy conservation is monitored with E_cons = sum M v^2/2 + F_tot (the
@@ -9,7 +9,7 @@ thermostat (as the paper's AIMD runs do, Sec. VI): after each step every ion,
 with probability 1 - exp(-nu dt), draws a new velocity from the
 Maxwell-Boltzmann distribution at the ion temperature (Andersen, J. Chem.
 Phys. 72, 2384 (1980)).  output_block() prints the per-step energies in the
-layout of the paper's output sample (Sec. V), write_xyz() the trajectory (md.xyz).
+layout of the paper's output sample (Sec. V D), write_xyz() the trajectory (md.xyz).
 """
 from __future__ import annotations
 
@@ -36,9 +36,10 @@ class MDRecord:
     iterations: int
     evaluations: int
     wall_ms: float
-    E_internal: float = 0.0      # F_tot + T S_s (EinternEl)
-    TS: float = 0.0              # T S_s
-    E_xc: float = 0.0
+    E_internal: float = 0.0      # F_tot + T S_s + T S_xc (EinternEl)
+    TS: float = 0.0              # T S = T S_s + T S_xc
+    E_xc: float = 0.0            # XC free energy F_xc
+    TS_xc: float = 0.0           # T S_xc (KSDT; 0 for the T-independent PZ81)
     T_ion: float = 0.0           # kelvin, from the kinetic energy
     pressure: Optional[float] = None   # hartree/bohr^3 (electrons + ions' potential part)
 
@@ -97,7 +98,8 @@ def velocity_verlet(ctx: Context, positions, velocities, charges, masses, dt: fl
         P = ctx.pressure() if (pressure and step is None) else None
         return MDRecord(k, F, float(0.5 * np.sum(m * v * v)), rep.iterations, rep.evaluations,
                         1e3 * (time.perf_counter() - t0), E_internal=getattr(rep, "E_internal", 0.0),
-                        TS=getattr(rep, "TS_s", 0.0), E_xc=getattr(rep, "E_xc", 0.0),
+                        TS=getattr(rep, "TS_s", 0.0) + getattr(rep, "TS_xc", 0.0), E_xc=getattr(rep, "E_xc", 0.0),
+                        TS_xc=getattr(rep, "TS_xc", 0.0),
                         T_ion=ion_temperature(v, masses), pressure=P)
 
     t0 = time.perf_counter()
@@ -119,14 +121,15 @@ def velocity_verlet(ctx: Context, positions, velocities, charges, masses, dt: fl
 
 
 def output_block(rec: MDRecord) -> str:
-    """The per-step energy block of the paper's output sample (Sec. V), in hartree (Fxc = Exc:
-    the XC here does not depend on T)."""
+    """The per-step energy block of the paper's output sample (Sec. V D), in hartree.  Fxc is
+    the XC free energy and Exc = Fxc + T S_xc its internal energy (equal for the T-independent
+    PZ81, different for KSDT)."""
     lines = [f"     MD step {rec.step}"]
     if rec.pressure is not None:
         lines.append(f"     P          = {rec.pressure:20.10f} Ha/bohr^3")
     lines += [
         f"     Fxc        = {rec.E_xc:20.10f} Ha",
-        f"     Exc        = {rec.E_xc:20.10f} Ha",
+        f"     Exc        = {rec.E_xc + rec.TS_xc:20.10f} Ha",
         f"     Ekin       = {rec.kinetic:20.10f} Ha",
         f"     T_ion      = {rec.T_ion:20.4f} K",
         f"     Ekin+Etot  = {rec.kinetic + rec.F_total:20.10f} Ha",

@@ -22,6 +22,31 @@ def make_ctx(cell, functional="TF", precision="fp64", minimizer="cg", xc="PZ81",
     return ctx
 
 
+def fcc_al_symmetric_minimum(precision="fp64", rounds=80):
+    """The minimum of one conventional fcc-Al cell (4 ions, 16^3, VT84F, HA LPP, 100 K) over
+    densities with the lattice's symmetry: CG runs of at most 25 iterations, each followed by
+    the projection onto symmetric amplitudes (wl.fcc_symmetrize), until F changes by less
+    than 1e-14 relative.  Returns the report, the amplitude and the stress (after a last,
+    converged CG run from the projected density).  Unconstrained runs leave the symmetric
+    densities at the ion-site points, where the 100 K density vanishes and F is not convex."""
+    cell = wl.fcc_al_cell(1, 16)
+    c = make_ctx(cell, "VT84F", precision=precision, lpp=wl.AL_HA_LPP, tol_energy=1e-14, max_iter=25,
+                 cg_precond=8.0)
+    F_prev = None
+    for _ in range(rounds):
+        c.minimize_density(check=False)
+        c.set_density(wl.fcc_symmetrize(c.get_density()))
+        rep = c.eval()
+        if F_prev is not None and abs(rep.F_total - F_prev) <= 1e-14 * abs(F_prev):
+            break
+        F_prev = rep.F_total
+    phi = c.get_density()
+    c.minimize_density()
+    sig = c.stress()
+    c.close()
+    return rep, phi, sig
+
+
 def oracle_system(cell, functional="TF", xc="PZ81", lpp=None, mu_sga=5.0 / 27.0):
     lpp = lpp or {"kind": "gauss", "rc": 0.5}
     return oracle.System(cell.lattice, cell.grid, cell.positions, cell.charges, cell.temperature_K,
@@ -44,3 +69,30 @@ def normalized_phi(sysm, seed, contrast=0.5):
 
 def rel(a, b):
     return abs(a - b) / max(abs(b), 1e-300)
+
+
+def assert_pointwise(v, v_ref, tol):
+    """|v - v_ref| <= tol * max|v_ref| at every grid point (reports the worst point)."""
+    v = np.asarray(v)
+    v_ref = np.asarray(v_ref)
+    assert v.shape == v_ref.shape, (v.shape, v_ref.shape)
+    diff = np.abs(v - v_ref)
+    scale = float(np.max(np.abs(v_ref)))
+    worst = int(np.argmax(diff))
+    err = float(diff.flat[worst]) / scale
+    assert err <= tol, (f"max |v - v_ref| = {err:.3e} of max|v_ref| at flat index {worst} "
+                        f"(v = {v.flat[worst]!r}, v_ref = {v_ref.flat[worst]!r}); tolerance {tol:.1e}")
+
+
+# Potential tolerances.  FP64: every point within 1e-10 of max|v_ref|.  Mixed (FP32 FFTs and
+# gradient terms): the RMS error within 1e-5 of the RMS, and every point within 5e-5 of
+# max|v_ref|.  The pointwise bound is ~800 FP32 roundings (u = 6e-8): the three-pass FFTs
+# add ~log2(N) roundings of the largest term at every point, and the divergence of W and
+# df/dn cancel to a few per cent of their size at the worst points.
+def assert_potential(v, v_ref, precision, fp64_tol=1e-10):
+    if precision == "fp64":
+        assert_pointwise(v, v_ref, fp64_tol)
+    else:
+        assert_pointwise(v, v_ref, 5e-5)
+        rms = float(np.sqrt(np.mean((np.asarray(v) - v_ref) ** 2)) / np.sqrt(np.mean(np.asarray(v_ref) ** 2)))
+        assert rms <= 1e-5, f"RMS error {rms:.3e} of the RMS potential; tolerance 1e-5"

@@ -10,8 +10,15 @@ potential residual is below the stated value.
   c3eval_<functional>_<T>   1024 H, 4.0 g/cm^3, 128^3: one evaluation at the
        seeded benchmark phi (no minimisation): energy components and the
        potential at 4096 seeded sample points.
+  al1_sym   fcc Al, one conventional cell (4 ions, 2.7 g/cm^3, 16^3, 100 K), VT84F
+       + PZ81, HA local pseudopotential: the minimum over densities with the
+       lattice's symmetry (the amplitude and the gradient projected after every
+       CG step onto functions invariant under the fcc translations and the
+       inversion through an ion).  Unconstrained runs leave this subspace at the
+       four ion-site grid points, where the 100 K density vanishes and F is not
+       convex in phi; the projection removes that freedom.
 
-Usage: python tests/golden/make_golden.py c1 [c2_2000 c2_50000 c2_1000000] [c3eval_VT84F_100000]
+Usage: python tests/golden/make_golden.py c1 [c2_2000 c2_50000 c2_1000000] [c3eval_VT84F_100000] [al1_sym]
 """
 import json
 import os
@@ -59,9 +66,38 @@ def run_c3eval(name):
     print("wrote", name, out["F_tot"], out["seconds"])
 
 
+def run_al1_sym(name):
+    cell = wl.fcc_al_cell(1, 16)
+    sysm = oracle.System(cell.lattice, cell.grid, cell.positions, cell.charges, cell.temperature_K,
+                         functional="VT84F", lpp=wl.AL_HA_LPP)
+
+    def project(i, phi, ev):
+        phi[...] = wl.fcc_symmetrize(phi)
+        ev.grad[...] = wl.fcc_symmetrize(ev.grad)
+
+    t0 = time.time()
+    r = mn.minimize_cg(sysm, tol_energy=1e-14, tol_residual=1e-8, max_iter=2000, callback=project)
+    ev = oracle.evaluate(r.phi, sysm)
+    F = frc.total_forces(sysm, ev.nhat)
+    out = {
+        "target": name, "functional": "VT84F", "lpp": "HA", "temperature_K": cell.temperature_K,
+        "grid": list(cell.grid), "nat": cell.nat, "rho_gcc": cell.rho_gcc,
+        "converged": bool(r.converged), "iterations": r.iterations, "residual": ev.residual(r.phi),
+        "F_tot": ev.F_tot, "F_per_ion": ev.F_tot / cell.nat, "F_s": ev.F_s, "E_xc": ev.E_xc, "E_H": ev.E_H,
+        "E_ext": ev.E_ext, "E_ion": ev.E_ion, "mu": ev.mu, "max_abs_force": float(np.max(np.abs(F))),
+        "seconds": time.time() - t0,
+        "source": "oracle.minimize.minimize_cg (projected onto fcc-symmetric amplitudes) + oracle.forces",
+    }
+    with open(os.path.join(HERE, f"{name}.json"), "w") as fh:
+        json.dump(out, fh, indent=1)
+    print("wrote", name, out["F_per_ion"], out["residual"], out["seconds"])
+
+
 def run(name):
     if name.startswith("c3eval_"):
         return run_c3eval(name)
+    if name == "al1_sym":
+        return run_al1_sym(name)
     if name == "c1":
         cell = wl.small_tf_cell()
         functional = "TF"

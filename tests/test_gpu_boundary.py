@@ -1,0 +1,164 @@
+"""The C ABI's contracts on the GPU: context reuse across grids, the caller's device
+allocator and stream, the pressure output of ofdft_free_energy_and_forces, and the
+failure paths of the minimiser (max_iter exhaustion, a non-finite trial forced from
+the host, an allocator that fails)."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from paper_1406_0835_amd import binding as B
+
+from _gpu_common import make_ctx, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(ctx):
+    rep = ctx.minimize_density()
+    F, E, f, P = ctx.free_energy_and_forces(forces=True, pressure=True)
+    return rep, F, f, P
+
+
+def test_context_reused_on_a_smaller_grid_with_more_ions():
+    """A context set up at 64^3 with 128 ions, then at 32^3 with 200 ions: the phase tables
+    shrink while the per-ion buffers must grow; the result equals a fresh context's."""
+    first = wl.h_cell(128, 1.0, 64, 5e4, seed=901)
+    second = wl.h_cell(200, 2.0, 32, 5e4, seed=902)
+    ctx = make_ctx(first, "VT84F", tol_energy=1e-9, cg_precond=8.0)
+    _run(ctx)
+    ctx.set_cell(second.lattice, second.grid)
+    ctx.set_ions(second.positions, second.charges)
+    r1, F1, f1, P1 = _run(ctx)
+    fresh = make_ctx(second, "VT84F", tol_energy=1e-9, cg_precond=8.0)
+    r2, F2, f2, P2 = _run(fresh)
+    assert f1.shape == (200, 3)
+    assert rel(F1, F2) <= 1e-12
+    assert np.max(np.abs(f1 - f2)) <= 1e-10
+    assert abs(P1 - P2) <= 1e-12 * abs(P2)
+    # and back to more phase-table entries with fewer ions
+    ctx.set_cell(first.lattice, first.grid)
+    ctx.set_ions(first.positions[:64], first.charges[:64])
+    _, F3, f3, _ = _run(ctx)
+    assert f3.shape == (64, 3) and np.all(np.isfinite(f3))
+
+
+def test_torch_allocator_and_stream():
+    """Every device buffer of the context comes from PyTorch's caching allocator and the
+    kernels run on PyTorch's current stream; results equal those of a default context."""
+    torch = pytest.importorskip("torch")
+    dev = 0
+    stream = torch.cuda.current_stream(dev)
+    live = {}
+
+    @B.ALLOC_FN
+    def alloc(nbytes, _ctx):
+        p = torch.cuda.caching_allocator_alloc(int(nbytes), dev, stream)
+        live[p] = int(nbytes)
+        return p
+
+    @B.FREE_FN
+    def free(ptr, _ctx):
+        live.pop(ptr)
+        torch.cuda.caching_allocator_delete(ptr)
+
+    cell = wl.h_cell(32, 1.0, 32, 5e4, seed=903)
+    base = torch.cuda.memory_allocated(dev)
+    ctx = B.Context(functional="VT84F", precision="mixed", tol_energy=1e-8, stream=stream.cuda_stream,
+                    alloc=alloc, free_=free)
+    ctx.set_cell(cell.lattice, cell.grid)
+    ctx.set_ions(cell.positions, cell.charges)
+    ctx.set_temperature(cell.temperature_K)
+    r1, F1, f1, P1 = _run(ctx)
+    held = torch.cuda.memory_allocated(dev) - base
+    assert len(live) > 10 and held >= sum(live.values())
+    ref = B.Context(functional="VT84F", precision="mixed", tol_energy=1e-8)
+    ref.set_cell(cell.lattice, cell.grid)
+    ref.set_ions(cell.positions, cell.charges)
+    ref.set_temperature(cell.temperature_K)
+    r2, F2, f2, P2 = _run(ref)
+    assert F1 == F2 and np.array_equal(f1, f2) and P1 == P2
+    assert r1.iterations == r2.iterations
+    ctx.close()
+    ref.close()
+    assert not live
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated(dev) == base
+
+
+def test_failing_allocator_is_a_device_error():
+    @B.ALLOC_FN
+    def alloc(nbytes, _ctx):
+        return None
+
+    @B.FREE_FN
+    def free(ptr, _ctx):
+        raise AssertionError("nothing was allocated")
+
+    cell = wl.h_cell(4, 1.0, 16, 5e4, seed=904)
+    ctx = B.Context(functional="TF", alloc=alloc, free_=free)
+    with pytest.raises(B.OFDFTError) as e:
+        ctx.set_cell(cell.lattice, cell.grid)
+    assert e.value.code == B.E_DEVICE
+    ctx.close()
+
+
+def test_allocator_callbacks_come_in_pairs():
+    @B.ALLOC_FN
+    def alloc(nbytes, _ctx):
+        return None
+
+    with pytest.raises(B.OFDFTError) as e:
+        B.Context(functional="TF", alloc=alloc)
+    assert e.value.code == B.E_ARG
+
+
+def test_pressure_output_is_minus_a_third_of_the_stress_trace():
+    cell = wl.h_cell(16, 1.0, 32, 5e4, seed=905)
+    ctx = make_ctx(cell, "VT84F", tol_energy=1e-10, cg_precond=8.0)
+    ctx.minimize_density()
+    P = ctx.pressure()
+    sig = ctx.stress()
+    assert P == pytest.approx(-np.trace(sig) / 3.0, rel=1e-14)
+
+
+def test_max_iter_keeps_the_best_state():
+    cell = wl.h_cell(16, 1.0, 32, 5e4, seed=906)
+    ctx = make_ctx(cell, "VT84F", tol_energy=1e-10, max_iter=3)
+    F0 = ctx.eval().F_total
+    rep = ctx.minimize_density(check=False)
+    assert ctx.last_rc == B.E_NOT_CONVERGED
+    assert rep.converged == 0 and rep.iterations == 3
+    assert rep.F_total < F0
+    # the kept state is the reported one
+    assert ctx.eval().F_total == pytest.approx(rep.F_total, rel=1e-13)
+    with pytest.raises(B.OFDFTError) as e:
+        ctx.free_energy_and_forces()
+    assert e.value.code == B.E_STATE
+
+
+def test_one_nonfinite_trial_is_recovered(monkeypatch):
+    cell = wl.h_cell(16, 1.0, 32, 5e4, seed=907)
+    ref = make_ctx(cell, "VT84F", tol_energy=1e-10, cg_precond=8.0)
+    F_ref = ref.minimize_density().F_total
+    monkeypatch.setenv("OFDFT_TEST_NONFINITE", "3")
+    ctx = make_ctx(cell, "VT84F", tol_energy=1e-10, cg_precond=8.0)
+    monkeypatch.delenv("OFDFT_TEST_NONFINITE")
+    rep = ctx.minimize_density()
+    assert rep.converged == 1
+    assert rel(rep.F_total, F_ref) <= 1e-9
+
+
+def test_repeated_nonfinite_trials_end_with_the_last_finite_state(monkeypatch):
+    cell = wl.h_cell(16, 1.0, 32, 5e4, seed=908)
+    monkeypatch.setenv("OFDFT_TEST_NONFINITE", "-1")
+    ctx = make_ctx(cell, "VT84F", tol_energy=1e-10, cg_precond=8.0)
+    monkeypatch.delenv("OFDFT_TEST_NONFINITE")
+    F0 = ctx.eval().F_total
+    rep = ctx.minimize_density(check=False)
+    assert ctx.last_rc == B.E_NONFINITE
+    assert rep.converged == 0
+    # no trial was accepted: the state and the report are the starting point's
+    assert rep.F_total == pytest.approx(F0, rel=1e-13)
+    assert np.isfinite(ctx.eval().F_total)

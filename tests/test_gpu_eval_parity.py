@@ -1,9 +1,11 @@
 """GPU evaluation parity: the HIP path (through the C ABI) against the FP64 oracle.
 
 One F[n] + gradient evaluation at the same seeded phi: every energy component
-and the potential on every grid point.  FP64 path: 1e-10 relative.  Mixed path
-(FP32 FFTs and gradient terms, FP64 Fermi-Dirac inversion and sums): 1e-6
-relative in F_tot, potential RMS error below 1e-5 of its RMS.
+and the potential on every grid point.  FP64 path: 1e-10 relative, and at every
+grid point |v - v_oracle| <= 1e-10 max|v_oracle|.  Mixed path (FP32 FFTs and
+gradient terms, FP64 Fermi-Dirac inversion and sums): 1e-6 relative in F_tot,
+the potential's RMS error within 1e-5 of its RMS and every point within 5e-5 of
+max|v_oracle| (the bounds of _gpu_common.assert_potential).
 """
 import numpy as np
 import pytest
@@ -11,7 +13,7 @@ import pytest
 import oracle
 import workloads as wl
 
-from _gpu_common import make_pair, normalized_phi, rel
+from _gpu_common import assert_potential, make_pair, normalized_phi, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -19,7 +21,7 @@ COMPONENTS = [("F_total", "F_tot"), ("F_s", "F_s"), ("TS_s", "TS_s"), ("E_xc", "
               ("E_ext", "E_ext"), ("E_alphaZ", "E_alphaZ"), ("E_ion", "E_ion"), ("N_e", "N_e"), ("mu", "mu")]
 
 
-def _compare(ctx, sysm, phi, tol_e, tol_v):
+def _compare(ctx, sysm, phi, tol_e, precision="fp64"):
     ctx.set_density(phi)
     rep, v = ctx.eval(potential=True)
     ev = oracle.evaluate(phi, sysm)
@@ -27,8 +29,7 @@ def _compare(ctx, sysm, phi, tol_e, tol_v):
         got, ref = getattr(rep, a), getattr(ev, b)
         scale = max(abs(ref), 1e-3 * abs(ev.F_tot))
         assert abs(got - ref) <= tol_e * scale, (a, got, ref)
-    err = np.sqrt(np.mean((v - ev.v) ** 2)) / np.sqrt(np.mean(ev.v ** 2))
-    assert err <= tol_v, err
+    assert_potential(v, ev.v, precision)
     return rep, ev, v
 
 
@@ -43,7 +44,7 @@ def test_eval_fp64_matches_oracle(functional, shape, nat):
     cell = wl.h_cell(nat, 1.0, shape, 3e4, seed=500 + nat)
     ctx, sysm = make_pair(cell, functional)
     phi = normalized_phi(sysm, seed=nat)
-    _compare(ctx, sysm, phi, 1e-10, 1e-10)
+    _compare(ctx, sysm, phi, 1e-10)
 
 
 @pytest.mark.parametrize("T_K", [2e3, 5e4, 1e6, 4e6])
@@ -51,7 +52,7 @@ def test_eval_fp64_temperature_range(T_K):
     cell = wl.h_cell(4, 2.0, (16, 16, 16), T_K, seed=600)
     ctx, sysm = make_pair(cell, "VT84F")
     phi = normalized_phi(sysm, seed=7, contrast=0.8)
-    _compare(ctx, sysm, phi, 1e-10, 1e-10)
+    _compare(ctx, sysm, phi, 1e-10)
 
 
 def test_eval_fp64_triclinic_cell_and_ha_pseudopotential():
@@ -60,20 +61,57 @@ def test_eval_fp64_triclinic_cell_and_ha_pseudopotential():
     cell.positions = np.random.default_rng(1).random((3, 3)) @ cell.lattice
     lpp = {"kind": "ha", "rc": 0.25, "A": 6.18, "qc": 29.97}
     ctx, sysm = make_pair(cell, "SGA", lpp=lpp)
-    _compare(ctx, sysm, normalized_phi(sysm, seed=3), 1e-10, 1e-10)
+    _compare(ctx, sysm, normalized_phi(sysm, seed=3), 1e-10)
 
 
 def test_eval_without_xc():
     cell = wl.h_cell(2, 1.0, (12, 12, 12), 1e5, seed=602)
     ctx, sysm = make_pair(cell, "VT84F", xc="NONE")
-    _compare(ctx, sysm, normalized_phi(sysm, seed=5), 1e-10, 1e-10)
+    _compare(ctx, sysm, normalized_phi(sysm, seed=5), 1e-10)
+
+
+@pytest.mark.parametrize("functional,T_K,precision", [
+    ("TF", 1e4, "fp64"), ("VT84F", 2e3, "fp64"), ("VT84F", 5e4, "fp64"), ("SGA", 1e6, "fp64"),
+    ("VT84F", 4e6, "fp64"), ("VT84F", 5e4, "mixed"), ("TF", 1e6, "mixed"),
+])
+def test_eval_ksdt_matches_oracle(functional, T_K, precision):
+    """The finite-T LDA XC of Sec. IV A (Eq. fit2, potential Eq. vxc1) in place of PZ81:
+    energies, T S_xc, the internal energy and the potential at every point."""
+    # the mixed path's 1e-6 is relative to F: its cell (16 H on 32^3) has a free energy that
+    # is not a near cancellation of its terms, unlike the small FP64 cell (F ~ 1e-3 Ha)
+    cell = (wl.h_cell(4, 1.0, (16, 16, 16), T_K, seed=610) if precision == "fp64"
+            else wl.h_cell(16, 1.0, (32, 32, 32), T_K, seed=603))
+    ctx, sysm = make_pair(cell, functional, precision=precision, xc="KSDT")
+    phi = normalized_phi(sysm, seed=13, contrast=0.7)
+    tol = 1e-10 if precision == "fp64" else 1e-6
+    rep, ev, _ = _compare(ctx, sysm, phi, tol, precision)
+    assert ev.TS_xc != 0.0
+    assert abs(rep.TS_xc - ev.TS_xc) <= tol * max(abs(ev.TS_xc), 1e-3 * abs(ev.F_tot))
+    # E_internal = F + T S_s + T S_xc carries F's absolute error; scale it as F's
+    assert abs(rep.E_internal - ev.E_internal) <= tol * max(abs(ev.E_internal), abs(ev.F_tot))
+
+
+def test_ksdt_minimisation_matches_oracle():
+    """Converged FP64 density with KSDT (ftTF, 8 H on 16^3 at 10 kK) against the oracle's CG."""
+    from oracle import minimize as om
+    cell = wl.h_cell(8, 1.0, (16, 16, 16), 1e4, seed=611)
+    ctx, sysm = make_pair(cell, "TF", xc="KSDT", tol_energy=1e-12, tol_residual=1e-9)
+    rep = ctx.minimize_density()
+    res = om.minimize_cg(sysm, tol_energy=1e-12, tol_residual=1e-9)
+    assert rep.converged and res.converged
+    assert rel(rep.F_total, res.result.F_tot) <= 1e-10
+    assert rel(rep.E_internal, res.result.E_internal) <= 1e-10
+    _, _, f = ctx.free_energy_and_forces()
+    from oracle import forces as ofo
+    f_ref = ofo.total_forces(sysm, res.result.nhat)
+    assert np.max(np.abs(f - f_ref)) <= 1e-7
 
 
 @pytest.mark.parametrize("functional", ["TF", "VT84F", "SGA"])
 def test_eval_mixed_precision(functional):
     cell = wl.h_cell(16, 1.0, (32, 32, 32), 5e4, seed=603)
     ctx, sysm = make_pair(cell, functional, precision="mixed")
-    _compare(ctx, sysm, normalized_phi(sysm, seed=9), 1e-6, 1e-5)
+    _compare(ctx, sysm, normalized_phi(sysm, seed=9), 1e-6, "mixed")
 
 
 def test_eval_is_deterministic():
@@ -107,7 +145,7 @@ def test_fft_tiles_do_not_change_results(precision, functional):
     tiles = ctx.autotune(2)
     rep, v = ctx.eval(potential=True)
     assert rel(rep.F_total, ev.F_tot) <= tol_e, tiles
-    assert np.sqrt(np.mean((v - ev.v) ** 2)) / np.sqrt(np.mean(ev.v ** 2)) <= tol_v, tiles
+    assert_potential(v, ev.v, precision)
 
 
 @pytest.mark.parametrize("precision,functional,shape", [
@@ -119,9 +157,13 @@ def test_plane_passes_match_row_passes(precision, functional, shape, monkeypatch
     per i1; with it switched off (row passes and a separate x2 pass) the evaluation, a
     line-search trial and the forces agree, and the oracle pins the plane path."""
     cell = wl.h_cell(4, 1.0, shape, 5e4, seed=606)
-    ctx, sysm = make_pair(cell, functional, precision=precision)
+    fp64 = precision == "fp64"
+    # FP64 minimises to a residual target: two energy-stopped runs whose paths differ in
+    # rounding stop up to ~1e-9 apart, a convergence difference and not a pass difference
+    stop = dict(tol_energy=1e-12, tol_residual=1e-8) if fp64 else {}
+    ctx, sysm = make_pair(cell, functional, precision=precision, **stop)
     monkeypatch.setenv("OFDFT_PLANE_PASSES", "0")
-    ctx_row, _ = make_pair(cell, functional, precision=precision)
+    ctx_row, _ = make_pair(cell, functional, precision=precision, **stop)
     monkeypatch.delenv("OFDFT_PLANE_PASSES")
     phi = normalized_phi(sysm, seed=12, contrast=0.6)
     tol_f, tol_v = (1e-12, 1e-11) if precision == "fp64" else (1e-6, 1e-5)
@@ -136,11 +178,11 @@ def test_plane_passes_match_row_passes(precision, functional, shape, monkeypatch
     if shape[1] <= 48:
         ev = oracle.evaluate(phi, sysm)
         assert rel(rep.F_total, ev.F_tot) <= (1e-10 if precision == "fp64" else 1e-6)
-        assert np.sqrt(np.mean((v - ev.v) ** 2)) / np.sqrt(np.mean(ev.v ** 2)) <= tol_v * 10
+        assert_potential(v, ev.v, precision)
     # a minimisation (line-search trials, preconditioned directions) and the forces
     r1 = ctx.minimize_density()
     r2 = ctx_row.minimize_density()
-    assert abs(r1.F_total - r2.F_total) <= (1e-9 if precision == "fp64" else 1e-5) * abs(r2.F_total)
+    assert abs(r1.F_total - r2.F_total) <= (1e-11 if fp64 else 1e-5) * abs(r2.F_total)
     _, _, f1 = ctx.free_energy_and_forces()
     _, _, f2 = ctx_row.free_energy_and_forces()
-    assert np.max(np.abs(f1 - f2)) <= (1e-6 if precision == "fp64" else 1e-4)
+    assert np.max(np.abs(f1 - f2)) <= (1e-7 if fp64 else 1e-4)

@@ -16,7 +16,7 @@ from oracle import forces as frc
 from oracle import minimize as mn
 from paper_1406_0835_amd import binding as B
 
-from _gpu_common import make_pair, rel
+from _gpu_common import fcc_al_symmetric_minimum, make_pair, rel
 
 pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -222,11 +222,22 @@ def test_restart_at_the_converged_density_reports_convergence(kind, precision):
     else:
         cell, lpp, fn = wl.fcc_al_cell(2, 32), wl.AL_HA_LPP, "VT84F"
     tol = 1e-10 if precision == "fp64" else 1e-8
-    ctx, _ = make_pair(cell, fn, precision=precision, lpp=lpp, tol_energy=tol * cell.nat, cg_precond=PRECOND)
-    F1 = ctx.minimize_density().F_total
+    # FP64 hydrogen: a residual target converges the first minimisation to where a restart
+    # cannot move F beyond 1e-10.  FP64 fcc Al: energy-stopped runs end on a slowly descending
+    # path away from the symmetric minimum (the ion-site points, see test_gpu_al.py), so the
+    # restart starts at the symmetric minimum of one cell, tiled.
+    tol_res = 1e-9 if (precision == "fp64" and kind == "h") else 0.0
+    ctx, _ = make_pair(cell, fn, precision=precision, lpp=lpp, tol_energy=tol * cell.nat, tol_residual=tol_res,
+                       cg_precond=PRECOND)
+    if precision == "fp64" and kind == "al":
+        _, phi1, _ = fcc_al_symmetric_minimum()
+        ctx.set_density(np.tile(phi1, (2, 2, 2)))
+        F1 = ctx.eval().F_total
+    else:
+        F1 = ctx.minimize_density().F_total
     ctx.set_density(ctx.get_density())
     rep = ctx.minimize_density()
     assert rep.converged
-    # FP64 may keep descending by what the first stop left (~1e-9 relative here)
-    assert rel(rep.F_total, F1) <= (1e-8 if precision == "fp64" else 1e-6)
+    bound = 1e-10 if precision == "fp64" else 1e-6
+    assert rel(rep.F_total, F1) <= bound
     assert rep.F_total <= F1 + (1e-12 if precision == "fp64" else 1e-6) * abs(F1)

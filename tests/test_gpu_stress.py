@@ -27,17 +27,20 @@ def _cell(shape, triclinic, nat=4, seed=820):
     return cell
 
 
-@pytest.mark.parametrize("functional,precision,shape,triclinic,lpp", [
-    ("TF", "fp64", (16, 16, 16), False, None),
-    ("VT84F", "fp64", (16, 16, 16), False, None),
-    ("SGA", "fp64", (12, 16, 12), True, HA),
-    ("VT84F", "fp64", (24, 24, 24), True, None),
-    ("VT84F", "mixed", (32, 32, 32), False, None),
-    ("TF", "mixed", (24, 24, 24), True, None),
+@pytest.mark.parametrize("functional,precision,shape,triclinic,lpp,xc", [
+    ("TF", "fp64", (16, 16, 16), False, None, "PZ81"),
+    ("VT84F", "fp64", (16, 16, 16), False, None, "PZ81"),
+    ("SGA", "fp64", (12, 16, 12), True, HA, "PZ81"),
+    ("VT84F", "fp64", (24, 24, 24), True, None, "PZ81"),
+    ("VT84F", "mixed", (32, 32, 32), False, None, "PZ81"),
+    ("TF", "mixed", (24, 24, 24), True, None, "PZ81"),
+    ("VT84F", "fp64", (16, 16, 16), True, None, "KSDT"),
+    ("TF", "fp64", (16, 16, 16), False, HA, "KSDT"),
+    ("VT84F", "mixed", (24, 24, 24), False, None, "KSDT"),
 ])
-def test_stress_matches_oracle(functional, precision, shape, triclinic, lpp):
+def test_stress_matches_oracle(functional, precision, shape, triclinic, lpp, xc):
     cell = _cell(shape, triclinic)
-    ctx, sysm = make_pair(cell, functional, precision=precision, lpp=lpp,
+    ctx, sysm = make_pair(cell, functional, precision=precision, lpp=lpp, xc=xc,
                           tol_energy=1e-10 if precision == "fp64" else 1e-8)
     ctx.minimize_density()
     sig = ctx.stress()

@@ -56,11 +56,12 @@ def _fd(system, phi, a, b, h=1e-5):
     return (E[0] - E[1]) / (2 * h) / V0 / (1.0 if a == b else 2.0)
 
 
-@pytest.mark.parametrize("functional,lpp,triclinic", [
-    ("TF", GAUSS, False), ("VT84F", GAUSS, True), ("SGA", HA, True), ("KST2", GAUSS, False),
+@pytest.mark.parametrize("functional,lpp,triclinic,xc", [
+    ("TF", GAUSS, False, "PZ81"), ("VT84F", GAUSS, True, "PZ81"), ("SGA", HA, True, "PZ81"),
+    ("KST2", GAUSS, False, "PZ81"), ("VT84F", GAUSS, True, "KSDT"), ("TF", HA, False, "KSDT"),
 ])
-def test_stress_is_strain_derivative_of_the_energy(functional, lpp, triclinic):
-    s = _system(functional, lpp, triclinic)
+def test_stress_is_strain_derivative_of_the_energy(functional, lpp, triclinic, xc):
+    s = _system(functional, lpp, triclinic, xc=xc)
     phi = _phi(s)
     sig = st.stress(phi, s)
     assert np.allclose(sig, sig.T, atol=1e-15)

@@ -143,6 +143,22 @@ def fcc_al_cell(n_rep: int, grid, temperature_K: float = 100.0, rho_gcc: float =
                  seed=0)
 
 
+def fcc_symmetrize(a: np.ndarray) -> np.ndarray:
+    """Project a field on the grid of ONE conventional fcc cell (ions at the origin and the
+    face centres, even grid) onto the fields with the lattice's symmetry: the average over
+    the three face-centring translations and the inversion through the ion at the origin
+    (grid index i -> -i mod n).  A geometric helper for checks at the symmetric density."""
+    if a.ndim != 3 or any(m % 2 for m in a.shape):
+        raise ValueError("a 3-D field on an even grid is required")
+    h1, h2, h3 = (m // 2 for m in a.shape)
+    acc = np.zeros_like(a)
+    for sh in [(0, 0, 0), (h1, h2, 0), (h1, 0, h3), (0, h2, h3)]:
+        r = np.roll(a, sh, axis=(0, 1, 2))
+        acc += r
+        acc += np.roll(np.flip(r, axis=(0, 1, 2)), 1, axis=(0, 1, 2))
+    return acc / 8.0
+
+
 def smooth_field(shape, n_modes: int, seed: int, max_freq: int = 3) -> np.ndarray:
     """A smooth real field on a periodic grid: a sum of random low-order cosines, max |.| = 1."""
     rng = np.random.Generator(np.random.PCG64(seed))
