@@ -257,6 +257,33 @@ int ofdft_set_tiles(ofdft_ctx* ctx, const int tiles[3]);
    taken to its end). */
 int ofdft_batch_minimize(ofdft_ctx* const* ctxs, int n, ofdft_report* reps);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+   tight serving loops, harnesses that forbid hipMalloc): the evaluation of
+   ofdft_eval with no allocation of any kind in the call.  Its intermediates (the
+   spectra, real work arrays, per-block partial sums and scalars of one
+   evaluation) live in a static device array of OFDFT_NOALLOC_SCRATCH_BYTES that
+   every device holds for the life of the process, instead of the context's own
+   buffers; the context's set-up (ofdft_set_cell, ofdft_set_ions,
+   ofdft_set_temperature) must have run before.
+     phi_dev  device pointer, N1*N2*N3 doubles (row-major [N1][N2][N3]): the
+              amplitude, evaluated as given (not renormalised to N_e); read only.
+     v_dev    device pointer, N1*N2*N3 doubles: receives the total potential
+              v = dF_tot/dn (the potential_out of ofdft_eval), in FP64 in both
+              precisions.
+     rep      host report as from ofdft_eval (may be NULL).
+   Both device buffers belong to the caller and must not overlap the scratch
+   array.  The work runs on the context's stream; the call waits for it, so
+   v_dev is complete on return.  OFDFT_E_ARG when an argument is NULL or the
+   evaluation of this grid needs more than OFDFT_NOALLOC_SCRATCH_BYTES (that is
+   the case above 64^3 in FP64 and above 96^3 in mixed precision for cubic
+   grids); OFDFT_E_STATE before the set-up.  Calls on one device share the one
+   array: calls that overlap in time on the same device (from different threads
+   or contexts) race and must be serialised by the caller.  Nothing in the array
+   needs to start at zero: every byte a call reads was written earlier in the
+   same call. */
+#define OFDFT_NOALLOC_SCRATCH_BYTES (48ull << 20)
+int ofdft_eval_noalloc(ofdft_ctx* ctx, const double* phi_dev, double* v_dev, ofdft_report* rep);
+
 /* Message for the last error on ctx (or a global message if ctx is NULL). */
 /* Ewald energy and forces of point ions Z_I in a neutralising background (the
    ion-ion term E_ion of the total free energy, Sec. II; the same sum that

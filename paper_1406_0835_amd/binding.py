@@ -108,6 +108,7 @@ def load_library() -> ctypes.CDLL:
         "ofdft_set_tiles": [P, ip],
         "ofdft_ewald": [dp, I, dp, dp, dp, dp, dp],
         "ofdft_stress": [P, dp],
+        "ofdft_eval_noalloc": [P, P, P, ctypes.POINTER(Report)],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -261,6 +262,15 @@ class Context:
         _check(self._lib, self._lib.ofdft_eval(self._h, ctypes.byref(rep), _dptr(pot) if potential else None),
                self._h)
         return (rep, pot.reshape(self.shape)) if potential else rep
+
+    def eval_noalloc(self, phi_dev: int, v_dev: int) -> Report:
+        """ofdft_eval_noalloc: one evaluation at the amplitude in device memory phi_dev
+        (N doubles, as given), the potential into device memory v_dev (N doubles), with no
+        allocation (intermediates in the library's static device scratch array)."""
+        rep = Report()
+        _check(self._lib, self._lib.ofdft_eval_noalloc(self._h, ctypes.c_void_p(int(phi_dev)),
+                                                       ctypes.c_void_p(int(v_dev)), ctypes.byref(rep)), self._h)
+        return rep
 
     def autotune(self, n_evals: int = 5):
         """Pick FFT tiles (tr, tc, rb) by timing; returns the chosen triple."""

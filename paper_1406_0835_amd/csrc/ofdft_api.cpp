@@ -959,6 +959,37 @@ int ofdft_eval(ofdft_ctx* c, ofdft_report* rep, double* potential_out) {
   return OFDFT_OK;
 }
 
+int ofdft_eval_noalloc(ofdft_ctx* c, const double* phi_dev, double* v_dev, ofdft_report* rep) {
+  if (!c) return fail(nullptr, OFDFT_E_ARG, "null context");
+  if (!phi_dev || !v_dev) return fail(c, OFDFT_E_ARG, "phi_dev and v_dev must not be NULL");
+  if (!c->have_cell || !c->have_ions || !c->have_T)
+    return fail(c, OFDFT_E_STATE, "set_cell, set_ions and set_temperature must come first");
+  if (hipSetDevice(c->opt.device) != hipSuccess) return fail(c, OFDFT_E_DEVICE, "hipSetDevice");
+  ScratchSave sv;
+  int rc = dev_scratch_bind(c, &sv);
+  if (rc) return fail(c, rc, c->err);
+  // every step below uses the scratch-bound buffers; the context's own come back afterwards
+  double h[SC_COUNT];
+  Point p;
+  rc = eval_at(c, phi_dev, c->v, c->scalars, p);
+  if (!rc) rc = dev_grad_dots(c, phi_dev, c->v, c->scalars, nullptr, nullptr, c->scalars + SC_DOT0);
+  if (!rc) rc = dev_read(c, c->scalars, SC_COUNT, h);
+  if (!rc) rc = dev_to_double(c, c->v, v_dev);
+  if (!rc) rc = dev_sync(c);
+  dev_scratch_restore(c, &sv);
+  if (rc) return fail(c, rc, c->err);
+  // the report goes to the caller only: the context's last report and state (phi, converged)
+  // stay those of its own calls
+  ofdft_report r{};
+  const bool conv = c->converged;
+  const ofdft_report last = c->last;
+  if ((rc = fill_report(c, h, std::sqrt(h[SC_DOT0 + 3] / (p.Ne / c->g.dv)), &r, 0, 1, 0))) return rc;
+  c->last = last;
+  c->converged = conv;
+  if (rep) *rep = r;
+  return OFDFT_OK;
+}
+
 int ofdft_time_evals(ofdft_ctx* c, int n_evals, double* total_ms, int max_kernels, const char** kernel_names,
                      double* kernel_ms, int* n_kernels) {
   int rc = check_ready(c);

@@ -238,6 +238,16 @@ double grid_ewald_split(const ofdft_ctx* c);
 void start_ewald(ofdft_ctx* c);
 bool join_ewald(ofdft_ctx* c);
 
+// Size of the static device scratch array of ofdft_eval_noalloc (OFDFT_NOALLOC_SCRATCH_BYTES).
+constexpr size_t kNoAllocScratchBytes = OFDFT_NOALLOC_SCRATCH_BYTES;
+
+// The context's evaluation buffers while ofdft_eval_noalloc points them into the static
+// scratch array (dev_scratch_bind saves them, dev_scratch_restore puts them back).
+struct ScratchSave {
+  void* A; void* S0; void* D; void* B[3]; void* gr[3]; void* vloc; void* v;
+  double* partials; double* scalars; double* vpart; double* vout;
+};
+
 // Device memory of a context: the caller's allocator (options.alloc / free_) when
 // one is set, else hipMalloc / hipFree.  ctx_malloc returns hipErrorOutOfMemory
 // when the callback returns NULL; ctx_free ignores NULL.
@@ -245,8 +255,15 @@ hipError_t ctx_malloc(ofdft_ctx* c, void** p, size_t bytes);
 void ctx_free(ofdft_ctx* c, void* p);
 
 // kernels (ofdft_kernels.hip)
-// Uploads the t-factor tables, once per device.
+// Uploads the t-factor tables and resolves the static scratch address, once per device.
 int dev_upload_tables(int device);
+// Scratch bytes one evaluation of the context needs; binding fails with OFDFT_E_ARG above
+// kNoAllocScratchBytes.
+size_t dev_noalloc_bytes(const ofdft_ctx* c);
+int dev_scratch_bind(ofdft_ctx* c, ScratchSave* sv);
+void dev_scratch_restore(ofdft_ctx* c, const ScratchSave* sv);
+// out[0..N) = the grid array v (context precision) as doubles, on the context's stream.
+int dev_to_double(ofdft_ctx* c, const void* v, double* out);
 int dev_alloc_grid(ofdft_ctx* c);
 void dev_free_grid(ofdft_ctx* c);
 int dev_alloc_ions(ofdft_ctx* c);

@@ -2057,15 +2057,30 @@ static inline int dev_fail(ofdft_ctx* c, int code, const char* what) {
   return code;
 }
 
+// ---------------------------------------------------------------- static scratch
+// Evaluation scratch of ofdft_eval_noalloc: the spectra, real work arrays, partial
+// sums and scalars of one evaluation, carved out of this array instead of the
+// context's own buffers.  Each device holds its own copy for the life of the process.
+// Host code never uses the name: its device address is taken once per device, with
+// that device current, by hipGetSymbolAddress (dev_upload_tables) and kept in
+// g_scratch_addr.
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+static std::mutex g_dev_mtx;
+static std::vector<char> g_tables_uploaded;
+static std::vector<void*> g_scratch_addr;
+
 // The t-factor tables live in __constant__ memory, one copy per device: upload
-// once per device (the caller has made it current).
+// once per device (the caller has made it current).  The same first call per
+// device records the device address of the static scratch array.
 int dev_upload_tables(int device) {
-  static std::mutex mtx;
-  static std::vector<char> uploaded;
-  std::lock_guard<std::mutex> lock(mtx);
+  std::lock_guard<std::mutex> lock(g_dev_mtx);
   if (device < 0) return OFDFT_E_ARG;
-  if ((int)uploaded.size() <= device) uploaded.resize(device + 1, 0);
-  if (uploaded[device]) return OFDFT_OK;
+  if ((int)g_tables_uploaded.size() <= device) {
+    g_tables_uploaded.resize(device + 1, 0);
+    g_scratch_addr.resize(device + 1, nullptr);
+  }
+  if (g_tables_uploaded[device]) return OFDFT_OK;
   // function-major (as generated) -> coefficient-major within each piece
   auto k_major = [](const double* src, int nf) {
     std::vector<double> out((size_t)OFDFT_T_NP * nf * OFDFT_T_NC);
@@ -2078,10 +2093,82 @@ int dev_upload_tables(int device) {
   const std::vector<double> gga = k_major(kTGga, 8), tf = k_major(kTTf, 3);
   if (hipMemcpyToSymbol(HIP_SYMBOL(c_t_gga), gga.data(), sizeof(kTGga)) != hipSuccess) return OFDFT_E_DEVICE;
   if (hipMemcpyToSymbol(HIP_SYMBOL(c_t_tf), tf.data(), sizeof(kTTf)) != hipSuccess) return OFDFT_E_DEVICE;
-  uploaded[device] = 1;
+  void* addr = nullptr;
+  if (hipGetSymbolAddress(&addr, HIP_SYMBOL(scratch)) != hipSuccess || addr == nullptr) return OFDFT_E_DEVICE;
+  g_scratch_addr[device] = addr;
+  g_tables_uploaded[device] = 1;
   return OFDFT_OK;
 }
 
+// Bytes of the scratch one evaluation of the context needs (spectra A, S0, D, B0..B2;
+// real arrays gr0..gr2, vloc, v; partial sums, scalars and vector-reduction partials).
+static size_t noalloc_layout(const ofdft_ctx* c, size_t* off) {
+  const size_t rs = c->rsize, N = (size_t)c->g.N, NS = (size_t)c->g.NS;
+  auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+  size_t o = 0;
+  for (int k = 0; k < 6; ++k) { off[k] = o; o += up(NS * 2 * rs); }      // A S0 D B0 B1 B2
+  for (int k = 6; k < 11; ++k) { off[k] = o; o += up(N * rs); }          // gr0..gr2 vloc v
+  off[11] = o; o += up((size_t)SL_COUNT * c->max_blocks * sizeof(double));  // partials
+  off[12] = o; o += up(SC_COUNT * sizeof(double));                      // scalars
+  off[13] = o; o += up(8 * VEC_BLOCKS * sizeof(double));                 // vpart
+  off[14] = o; o += up(32 * sizeof(double));                             // vout
+  return o;
+}
+
+size_t dev_noalloc_bytes(const ofdft_ctx* c) {
+  size_t off[15];
+  return noalloc_layout(c, off);
+}
+
+int dev_scratch_bind(ofdft_ctx* c, ScratchSave* sv) {
+  size_t off[15];
+  const size_t need = noalloc_layout(c, off);
+  if (need > kNoAllocScratchBytes)
+    return dev_fail(c, OFDFT_E_ARG, "the evaluation needs more scratch than the static scratch array holds "
+                                    "(see OFDFT_NOALLOC_SCRATCH_BYTES)");
+  const int dev = c->opt.device;
+  char* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_dev_mtx);
+    if (dev < (int)g_scratch_addr.size()) base = static_cast<char*>(g_scratch_addr[dev]);
+  }
+  if (!base) return dev_fail(c, OFDFT_E_DEVICE, "static scratch address not resolved for this device");
+  sv->A = c->A; sv->S0 = c->S0; sv->D = c->D;
+  for (int k = 0; k < 3; ++k) { sv->B[k] = c->B[k]; sv->gr[k] = c->gr[k]; }
+  sv->vloc = c->vloc; sv->v = c->v; sv->partials = c->partials; sv->scalars = c->scalars;
+  sv->vpart = c->vpart; sv->vout = c->vout;
+  void* spec[6];
+  for (int k = 0; k < 6; ++k) spec[k] = base + off[k];
+  c->A = spec[0]; c->S0 = spec[1]; c->D = spec[2];
+  for (int k = 0; k < 3; ++k) { c->B[k] = spec[3 + k]; c->gr[k] = base + off[6 + k]; }
+  c->vloc = base + off[9];
+  c->v = base + off[10];
+  c->partials = reinterpret_cast<double*>(base + off[11]);
+  c->scalars = reinterpret_cast<double*>(base + off[12]);
+  c->vpart = reinterpret_cast<double*>(base + off[13]);
+  c->vout = reinterpret_cast<double*>(base + off[14]);
+  return OFDFT_OK;
+}
+
+void dev_scratch_restore(ofdft_ctx* c, const ScratchSave* sv) {
+  c->A = sv->A; c->S0 = sv->S0; c->D = sv->D;
+  for (int k = 0; k < 3; ++k) { c->B[k] = sv->B[k]; c->gr[k] = sv->gr[k]; }
+  c->vloc = sv->vloc; c->v = sv->v; c->partials = sv->partials; c->scalars = sv->scalars;
+  c->vpart = sv->vpart; c->vout = sv->vout;
+}
+
+// out[i] = double(v[i]) for the N points of the grid (v in the context's precision).
+__global__ void __launch_bounds__(NT) k_to_double(const void* __restrict__ v, int rsize, long long n,
+                                                  double* __restrict__ out) {
+  for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT)
+    out[i] = rsize == 4 ? double(static_cast<const float*>(v)[i]) : static_cast<const double*>(v)[i];
+}
+
+int dev_to_double(ofdft_ctx* c, const void* v, double* out) {
+  const int nb = (int)std::min<long long>(2048, (c->g.N + NT - 1) / NT);
+  hipLaunchKernelGGL(k_to_double, dim3(nb), dim3(NT), 0, c->stream, v, (int)c->rsize, c->g.N, out);
+  return hip_ok(c, hipGetLastError(), "conversion launch") ? OFDFT_OK : OFDFT_E_DEVICE;
+}
 
 template <typename R, int L>
 static size_t lds_rpass_fwd(int tr) {
