@@ -197,7 +197,8 @@ def md_run(P, wl, precision, n_steps):
 
 def al_static(P, wl, precision, n_rep=8):
     """The static fcc-Al workload: n_rep^3 conventional cells (2048 ions on 128^3 for n_rep = 8,
-    16384 ions on 256^3 for 16; 16 grid points per cell edge), 2.70 g/cm^3, 100 K, VT84F + PZ81,
+    16384 on 256^3 for 16, 32000 on 320^3 for 20, 62500 on 400^3 for 25; 16 grid points per
+    cell edge), 2.70 g/cm^3, 100 K, VT84F + PZ81,
     Heine-Abarenkov Al pseudopotential; one density optimisation from the uniform density,
     then forces and stress.  setup_ms covers set_ions (the structure factor on the device; the
     Ewald sum starts on a host thread and overlaps the optimisation)."""
@@ -522,6 +523,12 @@ def main():
         al = {"mixed": al_static(P, wl, "mixed"), "fp64": al_static(P, wl, "fp64")}
         log("static fcc-Al: 16384 ions, 256^3, mixed and FP64")
         al["16384"] = {"mixed": al_static(P, wl, "mixed", 16), "fp64": al_static(P, wl, "fp64", 16)}
+        # the paper's largest cells (radix-5 grids): one density optimisation of 32 000 ions took
+        # about 17 h on 128 CPU cores there (context, not the same machine or stopping rule)
+        log("static fcc-Al: 32000 ions, 320^3, mixed and FP64")
+        al["32000"] = {"mixed": al_static(P, wl, "mixed", 20), "fp64": al_static(P, wl, "fp64", 20)}
+        log("static fcc-Al: 62500 ions, 400^3, mixed")
+        al["62500"] = {"mixed": al_static(P, wl, "mixed", 25)}
 
     batch = None
     if args.batch > 0:

@@ -47,7 +47,7 @@ extern "C" {
 /* status codes */
 #define OFDFT_OK 0
 #define OFDFT_E_ARG (-1)           /* invalid argument (NULL, nat <= 0, T <= 0, singular cell, ...) */
-#define OFDFT_E_GRID (-2)          /* grid size not an even 2^a 3^b in [8, 256] */
+#define OFDFT_E_GRID (-2)          /* grid size not one of the supported lengths (ofdft_set_cell) */
 #define OFDFT_E_NOT_CONVERGED (-3) /* minimisation hit max_iter; the best state is kept */
 #define OFDFT_E_NONFINITE (-4)     /* a non-finite energy or gradient appeared */
 #define OFDFT_E_DEVICE (-5)        /* HIP runtime or allocation failure */
@@ -165,8 +165,11 @@ int ofdft_create(const ofdft_options* opt, ofdft_ctx** out);
 int ofdft_destroy(ofdft_ctx* ctx);
 
 /* Cell (Sec. V B): lattice = rows a1, a2, a3 (9 doubles, bohr), scaled by
-   cell_scale (> 0, the cellScale keyword); grid = {N1, N2, N3}, each even and
-   2^a 3^b in [8, 256].  Invalidates the ions' structure factor and the density. */
+   cell_scale (> 0, the cellScale keyword); grid = {N1, N2, N3}, each one of
+   8, 12, 16, 20, 24, 32, 40, 48, 64, 80, 96, 128, 160, 192, 256, 320, 400 (even
+   2^a 3^b 5^c lengths; 320 and 400 hold the 32 000- and 62 500-ion fcc-Al cells
+   of Sec. VI A at 16 points per cell edge).  Invalidates the ions' structure
+   factor and the density. */
 int ofdft_set_cell(ofdft_ctx* ctx, const double lattice[9], double cell_scale, const int grid[3]);
 
 /* Ions: nat >= 1 Cartesian positions tau[3*nat] (bohr, multiplied by the

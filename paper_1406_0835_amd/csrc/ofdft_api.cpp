@@ -36,14 +36,16 @@ int fail(ofdft_ctx* c, int code, const std::string& msg) {
 }
 
 bool grid_ok(int n) {
-  static const int allowed[] = {8, 12, 16, 24, 32, 48, 64, 96, 128, 256};
+  static const int allowed[] = {8, 12, 16, 20, 24, 32, 40, 48, 64, 80, 96, 128, 160, 192, 256, 320, 400};
   for (int a : allowed)
     if (a == n) return true;
   return false;
 }
 
+// Largest power of two that divides n and is at most cap (1 if cap < 2).
 int largest_pow2_divisor_upto(int n, int cap) {
-  int t = cap;
+  int t = 1;
+  while (2 * t <= cap) t *= 2;
   while (t > 1 && n % t) t >>= 1;
   return t;
 }
@@ -733,7 +735,9 @@ int ofdft_set_cell(ofdft_ctx* c, const double lattice[9], double cell_scale, con
   for (int k = 0; k < 9; ++k)
     if (!is_fin(lattice[k])) return fail(c, OFDFT_E_ARG, "non-finite lattice");
   for (int k = 0; k < 3; ++k)
-    if (!grid_ok(grid[k])) return fail(c, OFDFT_E_GRID, "grid sizes must be one of 8,12,16,24,32,48,64,96,128,256");
+    if (!grid_ok(grid[k])) return fail(c, OFDFT_E_GRID,
+                                         "grid sizes must be one of 8,12,16,20,24,32,40,48,64,80,96,128,160,192,"
+                                         "256,320,400");
   double lat[9];
   for (int k = 0; k < 9; ++k) lat[k] = lattice[k] * cell_scale;
   const double* a1 = lat;
@@ -765,8 +769,9 @@ int ofdft_set_cell(ofdft_ctx* c, const double lattice[9], double cell_scale, con
   g.volume = std::fabs(det);
   g.dv = g.volume / (double)g.N;
   g.inv_n = 1.0 / (double)g.N;
-  g.tr = std::max(2, largest_pow2_divisor_upto(g.n2, g.n3 >= 256 ? 8 : 16));
-  const int tc_cap = (g.n1 >= 256) ? 8 : 16;
+  // default tiles: at most 16 rows or columns, within the register-staged tile size
+  g.tr = std::max(2, largest_pow2_divisor_upto(g.n2, std::min(g.n3 >= 256 ? 8 : 16, kStageElems / g.n3)));
+  const int tc_cap = std::min((g.n1 >= 256) ? 8 : 16, kStageElems / g.n1);
   g.tc = largest_pow2_divisor_upto(g.n2, tc_cap);
   g.rb = 1;
   while (2 * g.rb * g.n2 <= 1024) g.rb *= 2;   // largest power of two with rb * n2 <= 1024

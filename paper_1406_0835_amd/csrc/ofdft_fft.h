@@ -7,7 +7,7 @@
 //   * a contiguous-axis pass that packs two real rows into one complex row,
 //   * passes along the two other axes on the transposed half spectrum
 //     S[k3][i1][i2] (k3 slowest), so both are rows of N1 or N2 points.
-// Plans are compile-time (radix 8, 4, 2, 3 in that order of preference), so
+// Plans are compile-time (radix 8, 4, 2, 3, 5 in that order of preference), so
 // every index division in the butterflies is by a constant.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -41,7 +41,7 @@ __device__ __forceinline__ cplx<R> mul_si(cplx<R> a) {
 
 // ---------------------------------------------------------------- plans
 __host__ __device__ constexpr int first_radix(int L) {
-  return (L % 8 == 0) ? 8 : (L % 4 == 0) ? 4 : (L % 2 == 0) ? 2 : (L % 3 == 0) ? 3 : 0;
+  return (L % 8 == 0) ? 8 : (L % 4 == 0) ? 4 : (L % 2 == 0) ? 2 : (L % 3 == 0) ? 3 : (L % 5 == 0) ? 5 : 0;
 }
 // radix of stage s for length L: stages peel the preferred radix off L
 __host__ __device__ constexpr int radix_at(int L, int s) {
@@ -59,6 +59,7 @@ __host__ __device__ constexpr bool supported_length(int L) {
   int rem = L;
   while (rem % 2 == 0) rem /= 2;
   while (rem % 3 == 0) rem /= 3;
+  while (rem % 5 == 0) rem /= 5;
   return rem == 1;
 }
 
@@ -86,6 +87,31 @@ struct Bfly<R, SIGN, 3> {
     v[0] = v[0] + t1;
     v[1] = {m.x - s * t2.y, m.y + s * t2.x};
     v[2] = {m.x + s * t2.y, m.y - s * t2.x};
+  }
+};
+
+// Five-point DFT y_k = sum_j x_j W^{jk}, W = exp(SIGN 2 pi i / 5), from the pairs
+// x1 +- x4 and x2 +- x3: W^1, W^4 = c1 +- i SIGN s1 and W^2, W^3 = c2 +- i SIGN s2 with
+// c1 = cos(2 pi/5), s1 = sin(2 pi/5), c2 = cos(4 pi/5), s2 = sin(4 pi/5).
+template <typename R, int SIGN>
+struct Bfly<R, SIGN, 5> {
+  __device__ __forceinline__ static void run(cplx<R>* v) {
+    const R c1 = R(0.30901699437494742410229341718281906);
+    const R c2 = R(-0.80901699437494742410229341718281906);
+    const R s1 = R(SIGN) * R(0.95105651629515357211643933337938214);
+    const R s2 = R(SIGN) * R(0.58778525229247312916870595463907277);
+    const cplx<R> t1 = v[1] + v[4], t2 = v[2] + v[3];
+    const cplx<R> t3 = v[1] - v[4], t4 = v[2] - v[3];
+    const cplx<R> a1 = {v[0].x + c1 * t1.x + c2 * t2.x, v[0].y + c1 * t1.y + c2 * t2.y};
+    const cplx<R> a2 = {v[0].x + c2 * t1.x + c1 * t2.x, v[0].y + c2 * t1.y + c1 * t2.y};
+    // b1 = i (s1 t3 + s2 t4), b2 = i (s2 t3 - s1 t4)
+    const cplx<R> u1 = {s1 * t3.x + s2 * t4.x, s1 * t3.y + s2 * t4.y};
+    const cplx<R> u2 = {s2 * t3.x - s1 * t4.x, s2 * t3.y - s1 * t4.y};
+    v[0] = v[0] + t1 + t2;
+    v[1] = {a1.x - u1.y, a1.y + u1.x};
+    v[4] = {a1.x + u1.y, a1.y - u1.x};
+    v[2] = {a2.x - u2.y, a2.y + u2.x};
+    v[3] = {a2.x + u2.y, a2.y - u2.x};
   }
 };
 

@@ -80,6 +80,7 @@ struct GridDesc {
   int tr;         // rows per block in the contiguous-axis pass (power of two >= 2, divides n2)
   int tc;         // columns per block in the strided pass (power of two, divides n2)
   int rb;         // rows per block in the x2 pass (power of two)
+  int pwb;        // blocks of the pointwise kernels: one resident round on the device (0: default)
   // Device flag the evaluation and CG kernels read on entry: 0.0 makes the whole launch
   // return at once (the HIP-graph CG iteration skips work this way); nullptr: always run.
   const double* gate;
@@ -207,7 +208,8 @@ struct ofdft_ctx {
   double* fpart = nullptr;
   double* dforces = nullptr;
   long long phase_cap = 0;   // entries of the phase tables (nat * (n1 + n2 + n3h))
-  int ion_cap = 0;           // ions that dZ, fpart and dforces are sized for
+  int ion_cap = 0;           // ions that dZ and dforces are sized for
+  long long fpart_cap = 0;   // doubles in fpart (force, stress and energy partial sums)
 
   // HIP-graph CG (options.graph_cg): device state (CgSlot doubles) and the captured iteration
   double* cgst = nullptr;

@@ -144,14 +144,29 @@ __device__ __forceinline__ void x1_offsets(unsigned* off, int cnt, int n2, int t
 // Twiddles of one transform length go to LDS once per block.  The global load
 // is issued before the tile loads and stored after them, so waiting for it
 // does not wait for the tile.
+// Twiddle m is held by thread m mod NT (lengths above NT take two or more per thread).
 template <typename R, int L>
-__device__ __forceinline__ cplx<R> twiddle_load(const cplx<R>* tw_g) {
-  static_assert(L <= NT, "one twiddle per thread");
-  return tw_g[threadIdx.x < L ? threadIdx.x : L - 1];
+struct TwReg {
+  static constexpr int K = (L + NT - 1) / NT;
+  cplx<R> v[K];
+};
+template <typename R, int L>
+__device__ __forceinline__ TwReg<R, L> twiddle_load(const cplx<R>* tw_g) {
+  TwReg<R, L> r;
+#pragma unroll
+  for (int m = 0; m < TwReg<R, L>::K; ++m) {
+    const int i = (int)threadIdx.x + m * NT;
+    r.v[m] = tw_g[i < L ? i : L - 1];
+  }
+  return r;
 }
 template <typename R, int L>
-__device__ __forceinline__ void twiddle_store(cplx<R>* tw, cplx<R> v) {
-  if (threadIdx.x < L) tw[threadIdx.x] = v;
+__device__ __forceinline__ void twiddle_store(cplx<R>* tw, const TwReg<R, L>& r) {
+#pragma unroll
+  for (int m = 0; m < TwReg<R, L>::K; ++m) {
+    const int i = (int)threadIdx.x + m * NT;
+    if (i < L) tw[i] = r.v[m];
+  }
 }
 
 // ---------------------------------------------------------------- contiguous-axis helpers
@@ -194,7 +209,7 @@ __device__ __forceinline__ void store_half_spectra(const cplx<R>* res, cplx<R>* 
 template <typename R, int L>
 __device__ __forceinline__ void load_pack_half_spectra(const cplx<R>* in, cplx<R>* stage, cplx<R>* z,
                                                        const GridDesc& g, int i1, int i2_0, int tr,
-                                                       cplx<R>* tw, cplx<R> twv) {
+                                                       cplx<R>* tw, const TwReg<R, L>& twv) {
   const int trl = ilog2(tr);
   const int plane = g.n1 * g.n2;
   const int cnt = (L / 2) * tr;
@@ -262,7 +277,7 @@ __global__ void __launch_bounds__(NT) k_rpass_fwd_density(const double* __restri
   const int i1 = blockIdx.y, i2_0 = blockIdx.x * tr;
   const double* src = phi + ((size_t)i1 * g.n2 + i2_0) * L;
   const int cnt = tr * L;
-  const cplx<R> twv = twiddle_load<R, L>(tw_g);
+  const auto twv = twiddle_load<R, L>(tw_g);
   double pv[MAXU];
 #pragma unroll
   for (int u = 0; u < MAXU; ++u) pv[u] = src[tile_elem(u, cnt)];
@@ -319,7 +334,7 @@ __global__ void __launch_bounds__(NT) k_cpass_x2(Arr3 arrs, const cplx<R>* __res
   const int nr = min(rb, nrows - row0);
   const int cnt = nr * L;
   cplx<R>* x = reinterpret_cast<cplx<R>*>(arrs.p[blockIdx.y]) + (size_t)row0 * L;
-  const cplx<R> twv = twiddle_load<R, L>(tw_g);
+  const auto twv = twiddle_load<R, L>(tw_g);
   cplx<R> v[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) v[u] = x[tile_elem(u, cnt)];
@@ -391,7 +406,7 @@ __global__ void __launch_bounds__(NT) k_x1_density(const cplx<R>* __restrict__ A
   // element e of the tile: row k1 = e >> tcl (x1 index), column c = e & (tc - 1)
   const size_t tile0 = (size_t)k3 * g.n1 * g.n2 + i2_0;
   const int cnt = L * tc;
-  const cplx<R> twv = twiddle_load<R, L>(tw_g);
+  const auto twv = twiddle_load<R, L>(tw_g);
   unsigned off[U];
   x1_offsets<U>(off, cnt, g.n2, tc, tcl);
   cplx<R> av[U], ve[U];
@@ -531,16 +546,28 @@ constexpr int PW_BLOCKS = 2048;   // at most; four points per thread at 128^3
 // too small to give every thread of PW_BLOCKS blocks a point.
 static inline int pw_blocks(const GridDesc& g) {
   const long long b = (g.N + NT - 1) / NT;
-  return (int)std::max(1LL, std::min<long long>(PW_BLOCKS, b));
+  const int cap = g.pwb > 0 ? std::min(g.pwb, PW_BLOCKS) : PW_BLOCKS;
+  return (int)std::max(1LL, std::min<long long>(cap, b));
+}
+
+// Waves per SIMD the register allocation of k_pointwise_gga must allow: 5 for the FP32 point
+// with PZ81 or no XC (96 VGPRs, no spills), fewer where the FP64 point or the KSDT fit need
+// more registers.  With NT = 256 a block is one wave per SIMD, so this is also the number of
+// resident blocks per CU.
+constexpr int pointwise_waves_of(int rsize, int xc) {
+  return rsize == 4 ? (xc == 2 ? 3 : 5) : (xc == 2 ? 2 : 3);
+}
+template <typename R, int XC>
+constexpr int pointwise_waves() {
+  return pointwise_waves_of((int)sizeof(R), XC);
 }
 
 // Finite-T GGA + PZ81 at every point: v_loc = df/dn + v_xc, W = 2 df/dsigma grad n
 // (written over grad n), energy partial sums per block.
 template <typename R, int XC>
-__global__ void __launch_bounds__(NT) k_pointwise_gga(const double* __restrict__ phi, R* __restrict__ g0,
-                                                      R* __restrict__ g1, R* __restrict__ g2, R* __restrict__ vloc,
-                                                      long long npts, EvalParams ep, double* __restrict__ partials,
-                                                      int maxb) {
+__global__ void __launch_bounds__(NT, (pointwise_waves<R, XC>()))
+    k_pointwise_gga(const double* __restrict__ phi, R* __restrict__ g0, R* __restrict__ g1, R* __restrict__ g2,
+                    R* __restrict__ vloc, long long npts, EvalParams ep, double* __restrict__ partials, int maxb) {
   OFDFT_GATE(ep.gate);
   __shared__ double red[4 * NT / 64];
   EnhParams enh{(int)ep.enh_kind, ep.enh_c1, ep.enh_a1};
@@ -589,7 +616,7 @@ __global__ void __launch_bounds__(NT) k_rpass_fwd_real(RealArr3 in, Arr3 out, co
   const R* src = reinterpret_cast<const R*>(in.p[blockIdx.z]) + ((size_t)i1 * g.n2 + i2_0) * L;
   cplx<R>* dst = reinterpret_cast<cplx<R>*>(out.p[blockIdx.z]);
   const int cnt = tr * L;
-  const cplx<R> twv = twiddle_load<R, L>(tw_g);
+  const auto twv = twiddle_load<R, L>(tw_g);
   R xv[MAXU];
 #pragma unroll
   for (int u = 0; u < MAXU; ++u) xv[u] = src[tile_elem(u, cnt)];
@@ -625,7 +652,7 @@ __global__ void __launch_bounds__(NT) k_rpass_fwd_grad(const double* __restrict_
   const int i1 = blockIdx.y, i2_0 = blockIdx.x * tr;
   const size_t base = ((size_t)i1 * g.n2 + i2_0) * L;
   const int cnt = tr * L;
-  const cplx<R> twv = twiddle_load<R, L>(tw_g);
+  const auto twv = twiddle_load<R, L>(tw_g);
   double pv[MAXU];
   R vv[MAXU];
 #pragma unroll
@@ -668,7 +695,7 @@ __global__ void __launch_bounds__(NT) k_x1_divergence(const cplx<R>* __restrict_
   const size_t tile0 = (size_t)k3 * g.n1 * g.n2 + i2_0;
   const int cnt = L * tc;
   const cplx<R>* Cs[3] = {C0, C1, C2};
-  const cplx<R> twv = twiddle_load<R, L>(tw_g);
+  const auto twv = twiddle_load<R, L>(tw_g);
   // S0 and the first component are loaded together; each later component is
   // loaded into registers while the previous one is transformed
   unsigned off[U];
@@ -979,7 +1006,7 @@ __device__ __forceinline__ void plane_load_T(cplx<R>* buf, cplx<R>* tw, const cp
                                              const cplx<R>* tw_g, const GridDesc& g, int i1) {
   const size_t plane = (size_t)g.n1 * L;
   constexpr int CNT = (L / 2) * L, MU = (CNT + NTH - 1) / NTH;
-  const cplx<R> twv = twiddle_load<R, L>(tw_g);
+  const auto twv = twiddle_load<R, L>(tw_g);
   cplx<R> v[MU];
 #pragma unroll
   for (int m = 0; m < MU; ++m) {
@@ -1166,7 +1193,7 @@ __global__ void __launch_bounds__(NTP) k_plane_fwd_density(const double* __restr
   const size_t base = (size_t)i1 * L * L;
   constexpr int CNT = L * L;
   const int e_lo = h * (CNT / 2), e_hi = e_lo + CNT / 2;   // this block's half of the plane's points
-  const cplx<R> twv = twiddle_load<R, L>(tw_g);
+  const auto twv = twiddle_load<R, L>(tw_g);
   R* zr = reinterpret_cast<R*>(buf);
   double acc = 0.0;
   for (int c0 = 0; c0 < CNT; c0 += PCH * NTP) {
@@ -1219,7 +1246,7 @@ __global__ void __launch_bounds__(NTH, sizeof(R) == 4 ? 8 : 4) k_plane_fwd_real(
   const int i1 = blockIdx.x;
   constexpr int CNT = L * L;
   const R* src = reinterpret_cast<const R*>(in.p[blockIdx.y]) + (size_t)i1 * CNT;
-  const cplx<R> twv = twiddle_load<R, L>(tw_g);
+  const auto twv = twiddle_load<R, L>(tw_g);
   R* zr = reinterpret_cast<R*>(buf);
   for (int c0 = 0; c0 < CNT; c0 += PCH * NTH) {
     R xv[PCH];
@@ -1256,7 +1283,7 @@ __global__ void __launch_bounds__(NTP) k_plane_fwd_grad(const double* __restrict
   const int i1 = blockIdx.x;
   const size_t base = (size_t)i1 * L * L;
   constexpr int CNT = L * L;
-  const cplx<R> twv = twiddle_load<R, L>(tw_g);
+  const auto twv = twiddle_load<R, L>(tw_g);
   const double mu = sc[SC_MU];
   R* zr = reinterpret_cast<R*>(buf);
   for (int c0 = 0; c0 < CNT; c0 += PCH * NTP) {
@@ -1839,7 +1866,7 @@ __global__ void __launch_bounds__(NT) k_forces(int nat, const double* __restrict
 // the phase tables every FRC_RESEED steps and where the signed frequency wraps
 // (k2 = n2/2 + 1).
 constexpr int FRC_RESEED = 32;
-constexpr int FRC_MAX_N2 = 256;
+constexpr int FRC_MAX_N2 = 512;
 
 template <typename R>
 __global__ void __launch_bounds__(NT) k_forces_ions(int nat, const double* __restrict__ Z,
@@ -2043,8 +2070,9 @@ __global__ void __launch_bounds__(NT) k_stress_local(const double* __restrict__ 
 }
 
 // ---------------------------------------------------------------- host side
-#define OFDFT_LENGTHS(X) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(256)
-#define OFDFT_PLANE_LENGTHS(X) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128)
+#define OFDFT_LENGTHS(X) \
+  X(8) X(12) X(16) X(20) X(24) X(32) X(40) X(48) X(64) X(80) X(96) X(128) X(160) X(192) X(256) X(320) X(400)
+#define OFDFT_PLANE_LENGTHS(X) X(8) X(12) X(16) X(20) X(24) X(32) X(40) X(48) X(64) X(80) X(96) X(128)
 
 static inline bool hip_ok(ofdft_ctx* c, hipError_t e, const char* what) {
   if (e == hipSuccess) return true;
@@ -2389,34 +2417,32 @@ static void launch_rpass_final(ofdft_ctx* c, const double* phi, void* v_out, con
 }
 
 // Dispatch on a runtime length.
-#define OFDFT_DISPATCH(LEN, CALL)                        \
-  switch (LEN) {                                         \
-    case 8: { constexpr int L_ = 8; CALL; } break;       \
-    case 12: { constexpr int L_ = 12; CALL; } break;     \
-    case 16: { constexpr int L_ = 16; CALL; } break;     \
-    case 24: { constexpr int L_ = 24; CALL; } break;     \
-    case 32: { constexpr int L_ = 32; CALL; } break;     \
-    case 48: { constexpr int L_ = 48; CALL; } break;     \
-    case 64: { constexpr int L_ = 64; CALL; } break;     \
-    case 96: { constexpr int L_ = 96; CALL; } break;     \
-    case 128: { constexpr int L_ = 128; CALL; } break;   \
-    case 256: { constexpr int L_ = 256; CALL; } break;   \
-    default: return OFDFT_E_GRID;                        \
+#define OFDFT_DISPATCH(LEN, CALL)              \
+  switch (LEN) {                               \
+    OFDFT_LENGTHS_CALL(CALL)                   \
+    default: return OFDFT_E_GRID;              \
   }
+#define OFDFT_LENGTHS_CALL(CALL)                                                                         \
+  case 8: { constexpr int L_ = 8; CALL; } break; case 12: { constexpr int L_ = 12; CALL; } break;       \
+  case 16: { constexpr int L_ = 16; CALL; } break; case 20: { constexpr int L_ = 20; CALL; } break;     \
+  case 24: { constexpr int L_ = 24; CALL; } break; case 32: { constexpr int L_ = 32; CALL; } break;     \
+  case 40: { constexpr int L_ = 40; CALL; } break; case 48: { constexpr int L_ = 48; CALL; } break;     \
+  case 64: { constexpr int L_ = 64; CALL; } break; case 80: { constexpr int L_ = 80; CALL; } break;     \
+  case 96: { constexpr int L_ = 96; CALL; } break; case 128: { constexpr int L_ = 128; CALL; } break;   \
+  case 160: { constexpr int L_ = 160; CALL; } break; case 192: { constexpr int L_ = 192; CALL; } break; \
+  case 256: { constexpr int L_ = 256; CALL; } break; case 320: { constexpr int L_ = 320; CALL; } break; \
+  case 400: { constexpr int L_ = 400; CALL; } break;
 
 // Dispatch of the plane passes (lengths up to 128).
-#define OFDFT_DISPATCH_PLANE(LEN, CALL)                  \
-  switch (LEN) {                                         \
-    case 8: { constexpr int L_ = 8; CALL; } break;       \
-    case 12: { constexpr int L_ = 12; CALL; } break;     \
-    case 16: { constexpr int L_ = 16; CALL; } break;     \
-    case 24: { constexpr int L_ = 24; CALL; } break;     \
-    case 32: { constexpr int L_ = 32; CALL; } break;     \
-    case 48: { constexpr int L_ = 48; CALL; } break;     \
-    case 64: { constexpr int L_ = 64; CALL; } break;     \
-    case 96: { constexpr int L_ = 96; CALL; } break;     \
-    case 128: { constexpr int L_ = 128; CALL; } break;   \
-    default: return OFDFT_E_GRID;                        \
+#define OFDFT_DISPATCH_PLANE(LEN, CALL)                                                                  \
+  switch (LEN) {                                                                                         \
+    case 8: { constexpr int L_ = 8; CALL; } break; case 12: { constexpr int L_ = 12; CALL; } break;     \
+    case 16: { constexpr int L_ = 16; CALL; } break; case 20: { constexpr int L_ = 20; CALL; } break;   \
+    case 24: { constexpr int L_ = 24; CALL; } break; case 32: { constexpr int L_ = 32; CALL; } break;   \
+    case 40: { constexpr int L_ = 40; CALL; } break; case 48: { constexpr int L_ = 48; CALL; } break;   \
+    case 64: { constexpr int L_ = 64; CALL; } break; case 80: { constexpr int L_ = 80; CALL; } break;   \
+    case 96: { constexpr int L_ = 96; CALL; } break; case 128: { constexpr int L_ = 128; CALL; } break; \
+    default: return OFDFT_E_GRID;                                                                        \
   }
 
 // The x3 and x2 transforms run as plane passes when the (i2, i3) planes are
@@ -2731,6 +2757,14 @@ static void configure_lds() {
 
 int dev_alloc_grid(ofdft_ctx* c) {
   dev_free_grid(c);
+  {
+    // the pointwise kernels run one resident round of blocks over a grid-stride loop
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->opt.device) != hipSuccess || cus <= 0)
+      cus = 256;
+    const int xc = c->opt.xc == OFDFT_XC_PZ81 ? 1 : c->opt.xc == OFDFT_XC_KSDT ? 2 : 0;
+    c->g.pwb = cus * pointwise_waves_of(c->rsize, xc);
+  }
   const GridDesc& g = c->g;
   const size_t rs = c->rsize;
   const size_t N = g.N, NS = g.NS;
@@ -2795,10 +2829,22 @@ void dev_free_grid(ofdft_ctx* c) {
 // Ion buffers: the phase tables hold nat * (n1 + n2 + n3h) entries, which depends on
 // the grid; the charges/coordinates, force partials and forces depend on nat alone.
 // Each has its own capacity, so a smaller grid with more ions still reallocates.
+// Force kernels: whether one thread per ion runs (many ions), and the row chunks per ion
+// (partial sums per ion and component) of that launch: about 4096 blocks in all, at most 1024.
+static bool force_per_ion(const ofdft_ctx* c) {
+  return c->nat > 0 && (c->ion_forces == 1 || (c->ion_forces < 0 && c->nat >= NT));
+}
+static int force_part_cap(const ofdft_ctx* c) {
+  if (!force_per_ion(c)) return 1024;
+  const int nby = (c->nat + NT - 1) / NT;
+  return std::min(1024, std::max(1, (4096 + nby - 1) / nby));
+}
+
 int dev_alloc_ions(ofdft_ctx* c) {
   const long long M = c->g.n1 + c->g.n2 + c->g.n3h;
   const long long need_phase = (long long)c->nat * M;
-  if (c->opt.alloc && c->stream && (c->phase_cap < need_phase || c->ion_cap < c->nat))
+  const long long need_part = std::max<long long>(3LL * c->nat * force_part_cap(c), 8LL * PW_BLOCKS + 12 * 1024);
+  if (c->opt.alloc && c->stream && (c->phase_cap < need_phase || c->ion_cap < c->nat || c->fpart_cap < need_part))
     (void)hipStreamSynchronize(c->stream);
   if (c->phase_cap < need_phase) {
     ctx_free(c, c->phase);
@@ -2809,16 +2855,19 @@ int dev_alloc_ions(ofdft_ctx* c) {
   }
   if (c->ion_cap < c->nat) {
     ctx_free(c, c->dZ);
-    ctx_free(c, c->fpart);
     ctx_free(c, c->dforces);
-    c->dZ = nullptr; c->fpart = nullptr; c->dforces = nullptr;
+    c->dZ = nullptr; c->dforces = nullptr;
     c->ion_cap = 0;
     const size_t nat = (size_t)c->nat;
-    bool ok = dalloc(c, &c->dZ, nat + 4 * nat) &&
-              dalloc(c, &c->fpart, std::max<size_t>(3 * nat * 1024, 8 * PW_BLOCKS + 12 * 1024)) &&
-              dalloc(c, &c->dforces, 3 * nat);
-    if (!ok) return OFDFT_E_DEVICE;
+    if (!(dalloc(c, &c->dZ, nat + 4 * nat) && dalloc(c, &c->dforces, 3 * nat))) return OFDFT_E_DEVICE;
     c->ion_cap = c->nat;
+  }
+  if (c->fpart_cap < need_part) {
+    ctx_free(c, c->fpart);
+    c->fpart = nullptr;
+    c->fpart_cap = 0;
+    if (!dalloc(c, &c->fpart, (size_t)need_part)) return OFDFT_E_DEVICE;
+    c->fpart_cap = need_part;
   }
   return OFDFT_OK;
 }
@@ -2890,13 +2939,12 @@ static int forces_impl(ofdft_ctx* c, double* out_host) {
   }
   OFDFT_DISPATCH(g.n1, (launch_x1_density<R, L_, X1_NHAT>(c, c->A, c->D, nullptr, nullptr)));
   int nbx;
-  const bool per_ion = c->nat > 0 && (c->ion_forces == 1 || (c->ion_forces < 0 && c->nat >= NT));
-  if (per_ion) {
+  if (force_per_ion(c)) {
     // one tile of NT ions per block row; enough row chunks for about 4096 blocks (at most
-    // 1024, the partial-sum capacity per force component)
+    // force_part_cap, the partial-sum capacity per force component)
     const int nby = (c->nat + NT - 1) / NT;
     const int nrows = g.n1 * g.n3h;
-    const int want = (int)std::min<long long>(std::min(1024, nrows), std::max(1, (4096 + nby - 1) / nby));
+    const int want = std::min(nrows, force_part_cap(c));
     const int rows_per_chunk = (nrows + want - 1) / want;
     nbx = (nrows + rows_per_chunk - 1) / rows_per_chunk;
     hipLaunchKernelGGL(k_forces_ions<R>, dim3(nbx, nby), dim3(NT), 0, c->stream, c->nat, c->dZ,
