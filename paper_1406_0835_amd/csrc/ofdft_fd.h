@@ -28,11 +28,13 @@ constexpr double kLn3Pi2 = 3.38807206036691003968;     // ln(3 pi^2)
 constexpr double kDensityFloor = 1.0e-12;
 constexpr double kLn3Over4Pi = -1.43241195830118110158;  // ln(3/(4 pi))
 
-// Chebyshev terms used in the FP32 path.  Its t-factors are rounded to FP32,
-// and the coefficients beyond the 14th sum to less than 5e-9 of the factor
-// they belong to (of xi, zeta, P_tau or P_sigma for the t-derivatives) on
-// every piece, below FP32 rounding.
-constexpr int kTermsFp32 = 14;
+// Chebyshev terms per GGA t-factor in the FP32 path, in table order (xi, zeta,
+// t xi', t zeta', P_tau, P_sigma, t P_tau', t P_sigma').  Its t-factors are
+// rounded to FP32, and on every piece the dropped coefficients sum to less than
+// 3e-8 of the factor each entry belongs to (xi, zeta, P_tau or P_sigma for the
+// t-derivatives), below FP32 unit roundoff (6e-8).
+constexpr int kTermsFp32[8] = {8, 9, 9, 10, 11, 12, 12, 14};
+constexpr int kTermsFp32Max = 14;
 
 // ln x for a positive normal double.  Reduction x = 2^e (1 + f) with 1 + f in
 // [sqrt(1/2), sqrt(2)) and s = f/(2 + f), so ln(1 + f) = 2 atanh(s) =
@@ -71,8 +73,10 @@ __device__ __forceinline__ double ln_pos(double x) {
 
 // NF Chebyshev series of one piece (coefficients c[k * NF + f], first K terms used)
 // at one x, sharing the T_k recurrence.
-template <int NF, int K>
+// With TRIM (the FP32 path of the GGA table) function f takes its first kTermsFp32[f] terms.
+template <int NF, int K, bool TRIM = false>
 __device__ __forceinline__ void cheb_series(const double* __restrict__ c, double x, double* s) {
+  static_assert(!TRIM || NF == 8, "trimmed series are defined for the GGA table");
 #pragma unroll
   for (int f = 0; f < NF; ++f) s[f] = fma(c[NF + f], x, c[f]);
   double t0 = 1.0, t1 = x;
@@ -81,7 +85,8 @@ __device__ __forceinline__ void cheb_series(const double* __restrict__ c, double
   for (int k = 2; k < K; ++k) {
     const double t2 = fma(x2, t1, -t0);
 #pragma unroll
-    for (int f = 0; f < NF; ++f) s[f] = fma(c[k * NF + f], t2, s[f]);
+    for (int f = 0; f < NF; ++f)
+      if (!TRIM || k < kTermsFp32[f]) s[f] = fma(c[k * NF + f], t2, s[f]);
     t0 = t1;
     t1 = t2;
   }
@@ -106,7 +111,7 @@ __device__ __forceinline__ int min_pending_cell(int cell, bool pending_lane, uns
 // lane inside the piece takes the result.  Neighbouring points have similar
 // densities, so one pass usually serves the whole wavefront (always, when the
 // spread of l across the wavefront is at most H).
-template <int NF, int K = OFDFT_T_NC>
+template <int NF, int K = OFDFT_T_NC, bool TRIM = false>
 __device__ __forceinline__ void t_table(const double* __restrict__ table, double l, double* s) {
   static_assert(K >= 2 && K <= OFDFT_T_NC, "series length");
   l = fmin(fmax(l, OFDFT_T_LLO), OFDFT_T_LHI);
@@ -119,7 +124,7 @@ __device__ __forceinline__ void t_table(const double* __restrict__ table, double
   int pm = min_pending_cell(cell, true, pending);
   double a = OFDFT_T_LLO + pm * OFDFT_T_H;
   double x = (l - a) * (2.0 / OFDFT_T_W) - 1.0;
-  cheb_series<NF, K>(table + pm * NF * OFDFT_T_NC, x, s);
+  cheb_series<NF, K, TRIM>(table + pm * NF * OFDFT_T_NC, x, s);
   bool done = x <= 1.0;
   pending = __ballot(!done);
   for (int pass = 1; pending != 0ull && pass < 64; ++pass) {
@@ -127,7 +132,7 @@ __device__ __forceinline__ void t_table(const double* __restrict__ table, double
     a = OFDFT_T_LLO + pm * OFDFT_T_H;
     x = (l - a) * (2.0 / OFDFT_T_W) - 1.0;
     double r[NF];
-    cheb_series<NF, K>(table + pm * NF * OFDFT_T_NC, x, r);
+    cheb_series<NF, K, TRIM>(table + pm * NF * OFDFT_T_NC, x, r);
     if (!done && x <= 1.0) {
 #pragma unroll
       for (int f = 0; f < NF; ++f) s[f] = r[f];
@@ -335,7 +340,7 @@ template <typename R>
 __device__ __forceinline__ void gga_point(double n, double ln_n, R sigma, double lt0, const EnhParams& ep,
                                           double& f_out, R& dfdn, R& dfds, double& ts_out) {
   double a[8];   // xi, zeta, t xi', t zeta', P_tau, P_sigma, t P_tau', t P_sigma'
-  t_table<8, sizeof(R) == 4 ? kTermsFp32 : OFDFT_T_NC>(c_t_gga, lt0 - (2.0 / 3.0) * ln_n, a);
+  t_table<8, sizeof(R) == 4 ? kTermsFp32Max : OFDFT_T_NC, sizeof(R) == 4>(c_t_gga, lt0 - (2.0 / 3.0) * ln_n, a);
   const R nr = R(n);
   const R n23 = exp(R((2.0 / 3.0) * ln_n));
   const R A = R(kCTF) * nr * n23;

@@ -32,8 +32,10 @@ def _header():
 
 
 def _terms_fp32():
+    """Terms per GGA factor of the FP32 path (kTermsFp32 in ofdft_fd.h)."""
     text = open(os.path.join(CSRC, "ofdft_fd.h")).read()
-    return int(re.search(r"constexpr int kTermsFp32 = (\d+);", text).group(1))
+    body = re.search(r"constexpr int kTermsFp32\[8\] = \{([\d, ]+)\};", text).group(1)
+    return [int(v) for v in body.split(",")]
 
 
 def _cheb(c, x, k):
@@ -104,19 +106,25 @@ def test_full_series_matches_oracle(tables):
 
 
 def test_fp32_series_below_fp32_rounding(tables):
-    """The shorter series of the FP32 path stays well below FP32 rounding (6e-8)."""
+    """The shorter series of the FP32 path (a term count per factor) stay below FP32 unit
+    roundoff (6e-8) relative to the factor each entry belongs to."""
     d, gga, _ = tables
     k = _terms_fp32()
-    assert 2 <= k <= gga.shape[2]
+    assert len(k) == 8 and all(2 <= v <= gga.shape[2] for v in k)
     for piece in _pieces(d, L_WIDE):
         full = _eval(d, gga, L_WIDE, piece, gga.shape[2])
-        got = _eval(d, gga, L_WIDE, piece, k)
+        got = np.stack([_eval(d, gga[:, f:f + 1, :], L_WIDE, piece, k[f])[0] for f in range(8)])
         err = np.abs(got - full) / np.abs(full[PARENT])
-        assert err.max() < 1e-8, err.max(axis=1)
-    # the dropped tail on every piece, which bounds the truncation anywhere in the piece
-    tail = np.abs(gga[:, :, k:]).sum(axis=2)
-    scale = np.abs(gga[:, PARENT, 0])
-    assert (tail / scale).max() < 1e-8
+        assert err.max() < 5e-8, err.max(axis=1)
+    # the dropped tail on every piece bounds the truncation anywhere in the piece: against the
+    # parent's sum of |coefficients| (a bound of the parent on the piece), below 3e-8
+    tail = np.stack([np.abs(gga[:, f, k[f]:]).sum(axis=1) for f in range(8)], axis=1)
+    scale = np.abs(gga[:, PARENT, :]).sum(axis=2)
+    assert (tail / scale).max() < 3e-8
+    # one term fewer for any factor would break that bound somewhere
+    for f in range(8):
+        short = np.abs(gga[:, f, k[f] - 1:]).sum(axis=1) / scale[:, f]
+        assert short.max() > 3e-8, f
 
 
 def test_tables_cover_the_documented_range(tables):
