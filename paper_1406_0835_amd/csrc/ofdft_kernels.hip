@@ -1618,7 +1618,9 @@ struct OpPrecDirection {
     const double cproj = st ? st[CG_CPROJ] : this->cproj;
     const double p = phi[i];
     const double gi = two_dv * p * (double(v[i]) - sc[SC_MU]);
-    const double di = -(gi + double(w[i]) - cz * p) + beta * (d[i] - cproj * p);
+    // with beta = 0 the previous direction is not read: before the first step it has never
+    // been written (a fresh allocation may hold non-finite bit patterns, and 0 * NaN = NaN)
+    const double di = -(gi + double(w[i]) - cz * p) + (beta != 0.0 ? beta * (d[i] - cproj * p) : 0.0);
     d[i] = di;
     gprev[i] = gi;
     acc[0] += di * di;
@@ -1638,7 +1640,8 @@ struct OpDirection {
     const double cproj = st ? st[CG_CPROJ] : this->cproj;
     const double p = phi[i];
     const double gi = two_dv * p * (double(v[i]) - sc[SC_MU]);
-    const double di = -gi + beta * (d[i] - cproj * p);
+    // with beta = 0 the previous direction is not read (see OpPrecDirection)
+    const double di = -gi + (beta != 0.0 ? beta * (d[i] - cproj * p) : 0.0);
     d[i] = di;
     gprev[i] = gi;
     acc[0] += di * di;
@@ -2798,7 +2801,11 @@ int dev_alloc_grid(ofdft_ctx* c) {
     static bool lds_f = false, lds_d = false;
     if (rs == 4 && !lds_f) { configure_lds<float>(); lds_f = true; }
     if (rs == 8 && !lds_d) { configure_lds<double>(); lds_d = true; }
-    ok = hip_ok(c, hipMemsetAsync(c->Vext, 0, NS * 2 * rs, c->stream), "memset");
+    // the CG direction and previous gradient start at zero (they are read only with a nonzero
+    // coefficient, but a fresh allocation is no valid state)
+    ok = hip_ok(c, hipMemsetAsync(c->Vext, 0, NS * 2 * rs, c->stream), "memset") &&
+         hip_ok(c, hipMemsetAsync(c->d, 0, N * sizeof(double), c->stream), "memset") &&
+         hip_ok(c, hipMemsetAsync(c->gprev, 0, N * sizeof(double), c->stream), "memset");
   }
   if (!ok) {
     dev_free_grid(c);
