@@ -47,6 +47,7 @@ enum CgSlot {
   CG_HAVE_PREV, CG_GG_PREV, CG_CPROJ, CG_F, CG_F_PREV, CG_KAPPA, CG_SMALL, CG_LAST_DF,
   CG_ITERS, CG_EVALS, CG_CONVERGED, CG_STATUS, CG_NF_USED, CG_LSR_USED, CG_TRIALS,
   CG_DF0, CG_DN, CG_RESID, CG_GG, CG_LAUNCHES, CG_F1, CG_D1, CG_TH2,
+  CG_THCAP,        // cap on the next first trial angle after a failed line search (0: none)
   CG_COEF2,        // ca, sb, ms, mc of the second trial (4 doubles)
   CG_COUNT = CG_COEF2 + 4
 };

@@ -1556,6 +1556,7 @@ __global__ void __launch_bounds__(NT) k_dir_final(const double* __restrict__ par
     double th = 0.05;
     if (tc.kappa > 0.0 && dF0 < 0.0) th = fmin(fmax(-dF0 / tc.kappa, 1e-6), 0.3);
     else if (tc.have_prev && dF0 < 0.0 && tc.F_prev > F) th = fmin(fmax(2.0 * (tc.F_prev - F) / (-dF0), 1e-6), 0.3);
+    if (tc.st && tc.st[CG_THCAP] > 0.0) th = fmin(th, tc.st[CG_THCAP]);   // after a failed line search
     const double ratio = tc.r / sqrt(sc[SC_NE] / tc.dv);
     const double ct = cos(th), st = sin(th);
     sc[SC_TH1] = th;
@@ -3372,27 +3373,36 @@ __global__ void k_ls_decide2(double* __restrict__ st, const double* __restrict__
       st[CG_SMALL] = fabs(dF) < fmax(k.tol_energy, resolvable) ? st[CG_SMALL] + 1.0 : 0.0;
       st[CG_SRC] = take;
       st[CG_GATEACC] = 1.0;
+      st[CG_THCAP] = 0.0;
       if (st[CG_SMALL] >= 2.0 && k.tol_residual <= 0.0) {
         st[CG_ACTIVE] = 0.0;
         st[CG_CONVERGED] = 1.0;
         st[CG_STATUS] = CGS_CONVERGED;
       }
     } else {
-      // no trial lowers F: converged at the resolution of F, else restart along -g once
+      // no trial lowers F.  If F is convex along the line it lies nowhere below
+      // F0 - |dF0| th_min (th_min the smallest angle tried): below the energy tolerance (or
+      // the resolution of F) that counts as converged, like a small last step.  Otherwise
+      // restart along -g with the first angle capped at a tenth of th_min, up to three times.
       const bool had_prev = st[CG_HAVE_PREV] != 0.0;
-      const double last = had_prev ? st[CG_LAST_DF] : fabs(dF0) * th1;
+      const double th_min = st[CG_GATE2] != 0.0 ? fmin(th1, st[CG_TH2]) : th1;
+      const double bound = fabs(dF0) * th_min;
+      const double last = had_prev ? st[CG_LAST_DF] : bound;
       // the mixed path's noise floor (the host CG's 1e-6 |F_tot| in terms of the summed magnitudes)
       const bool floor_ok = k.mixed && fabs(last) < 1e-7 * term_scale(sc);
-      const bool conv = k.tol_residual > 0.0 ? (st[CG_RESID] < k.tol_residual || floor_ok)
-                                             : (st[CG_SMALL] >= 1.0 || floor_ok);
+      const double resolvable = k.mixed ? f_resolution(sc, F0, k) : 0.0;
+      const bool conv = k.tol_residual > 0.0
+                            ? (st[CG_RESID] < k.tol_residual || floor_ok)
+                            : (st[CG_SMALL] >= 1.0 || floor_ok || bound < fmax(k.tol_energy, resolvable));
       if (conv) {
         st[CG_ACTIVE] = 0.0;
         st[CG_CONVERGED] = 1.0;
         st[CG_STATUS] = CGS_CONVERGED;
-      } else if (had_prev && st[CG_LSR_USED] == 0.0) {
-        // restart along -g; the last measured curvature still sets the first angle
-        st[CG_LSR_USED] = 1.0;
+      } else if (st[CG_LSR_USED] < 3.0) {
+        // the last measured curvature still sets the first angle, within the cap
+        st[CG_LSR_USED] += 1.0;
         st[CG_HAVE_PREV] = 0.0;
+        st[CG_THCAP] = 0.1 * th_min;
       } else {
         st[CG_ACTIVE] = 0.0;
         st[CG_STATUS] = CGS_STALLED;
