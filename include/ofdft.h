@@ -188,11 +188,17 @@ int ofdft_set_temperature(ofdft_ctx* ctx, double T_kelvin);
 /* Minimises F_tot over phi at fixed N_e.  Starts from the current density
    (uniform if none).  rep may be NULL.  Returns OFDFT_E_NOT_CONVERGED (and
    keeps the best state, whose energies rep receives) if max_iter is reached.
-   Recovery in the CG minimiser, each at most once per call: a line-search trial
-   with a non-finite energy or slope restarts the CG along the steepest-descent
-   direction from the last finite point (a second one ends the call with
-   OFDFT_E_NONFINITE, the last finite state kept and reported); a line search
-   that finds no lower F before the stopping rule is met restarts along -g.
+   Recovery in the CG minimiser: a line-search trial with a non-finite energy or
+   slope restarts the CG along the steepest-descent direction from the last finite
+   point, once (a second one ends the call with OFDFT_E_NONFINITE, the last finite
+   state kept and reported).  A line search that finds no lower F ends the call
+   as converged when a residual target is set and met, or, without one, when the
+   last accepted step changed F by less than tol_energy or the decrease still
+   possible along the line (|dF/dtheta(0)| times the smallest angle tried, F
+   convex along the line) is below it (the host-driven CG uses that bound only
+   before its first step).  Otherwise it restarts along -g: once in the
+   host-driven CG, up to three times in the graph CG with the first angle capped
+   at a tenth of the smallest angle tried.
    A non-finite energy at the starting density is OFDFT_E_NONFINITE at once. */
 int ofdft_minimize_density(ofdft_ctx* ctx, ofdft_report* rep);
 
