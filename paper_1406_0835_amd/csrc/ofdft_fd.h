@@ -89,6 +89,9 @@ __device__ __forceinline__ void cheb_series(const double* __restrict__ c, double
       if (!TRIM || k < kTermsFp32[f]) s[f] = fma(c[k * NF + f], t2, s[f]);
     t0 = t1;
     t1 = t2;
+    // keeps the wave-uniform coefficient loads of later terms from being hoisted above this
+    // one: all of them live at once overflow the scalar registers into VGPR lanes
+    asm volatile("" ::: "memory");
   }
 }
 
