@@ -156,8 +156,11 @@ def test_plane_passes_match_row_passes(precision, functional, shape, monkeypatch
     """Square (i2, i3) planes up to 128 run the x3 and x2 transforms as one plane pass
     per i1; with it switched off (row passes and a separate x2 pass) the evaluation, a
     line-search trial and the forces agree, and the oracle pins the plane path."""
-    cell = wl.h_cell(4, 1.0, shape, 5e4, seed=606)
     fp64 = precision == "fp64"
+    # mixed: the two paths round differently, so they agree only to the mixed path's own error,
+    # which on a cubic 4-atom cell squeezed onto 8 x 128 x 128 points (0.034 bohr along two axes)
+    # reaches 2e-4 of max|v| (the G^2 weight of the gradient terms); its cells keep 0.15 bohr
+    cell = wl.h_cell(4, 1.0, shape, 5e4, seed=606) if fp64 else wl.h_cell_spaced(shape, seed=606)
     # FP64 minimises to a residual target: two energy-stopped runs whose paths differ in
     # rounding stop up to ~1e-9 apart, a convergence difference and not a pass difference
     stop = dict(tol_energy=1e-12, tol_residual=1e-8) if fp64 else {}
@@ -185,4 +188,13 @@ def test_plane_passes_match_row_passes(precision, functional, shape, monkeypatch
     assert abs(r1.F_total - r2.F_total) <= (1e-11 if fp64 else 1e-5) * abs(r2.F_total)
     _, _, f1 = ctx.free_energy_and_forces()
     _, _, f2 = ctx_row.free_energy_and_forces()
-    assert np.max(np.abs(f1 - f2)) <= (1e-7 if fp64 else 1e-4)
+    if fp64:
+        assert np.max(np.abs(f1 - f2)) <= 1e-7
+    else:
+        # each mixed run carries its own force error of up to the mixed tolerance (1e-4
+        # hartree/bohr): both are held to the FP64 minimum of the same cell
+        ref, _ = make_pair(cell, functional, precision="fp64", tol_energy=1e-12, tol_residual=1e-8)
+        ref.minimize_density()
+        _, _, f64 = ref.free_energy_and_forces()
+        assert np.max(np.abs(f1 - f64)) <= 1e-4
+        assert np.max(np.abs(f2 - f64)) <= 1e-4

@@ -25,19 +25,10 @@ COMPONENTS = [("F_total", "F_tot"), ("F_s", "F_s"), ("TS_s", "TS_s"), ("E_xc", "
 AL_FP64_V_TOL = 1e-9   # the oracle's own rounding at t ~ 7e-4 (see test_gpu_al.py)
 
 
-def _spaced_h_cell(shape, seed, h=0.15, rho_gcc=1.0):
-    """Hydrogen at rho in an orthorhombic cell with grid spacing h on every axis.  The mixed
-    path's FP32 potential error grows as the spacing shrinks (the gradient and divergence
-    terms weight the spectrum by G^2: RMS 1.7e-6 of the RMS potential at h = 0.16 bohr,
-    8e-6 at 0.08, 2.2e-5 at 0.04, measured on radix-2, -3 and -5 grids alike), so every axis
-    keeps the spacing of the workloads instead of a cubic cell squeezed onto a long axis."""
-    lengths = np.array(shape, dtype=float) * h
-    n_per_bohr3 = rho_gcc / 1.00794 * 6.02214076e23 * (0.529177210903e-8) ** 3
-    nat = max(2, int(round(n_per_bohr3 * np.prod(lengths))))
-    rng = np.random.Generator(np.random.PCG64(seed))
-    pos = rng.random((nat, 3)) * lengths
-    return wl.HCell(lattice=np.diag(lengths), positions=pos, charges=np.ones(nat), grid=tuple(shape),
-                    temperature_K=5e4, rho_gcc=rho_gcc, seed=seed)
+# The mixed path's FP32 potential error grows as the grid spacing shrinks (the gradient and
+# divergence terms weight the spectrum by G^2: RMS 1.7e-6 of the RMS potential at h = 0.16 bohr,
+# 8e-6 at 0.08, 2.2e-5 at 0.04, measured on radix-2, -3 and -5 grids alike), so every axis keeps
+# the spacing of the workloads instead of a cubic cell squeezed onto a long axis.
 
 
 @pytest.mark.parametrize("shape", [
@@ -46,7 +37,7 @@ def _spaced_h_cell(shape, seed, h=0.15, rho_gcc=1.0):
 ])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_radix5_and_long_axes_match_oracle(shape, precision):
-    cell = _spaced_h_cell(shape, seed=1300 + sum(shape))
+    cell = wl.h_cell_spaced(shape, seed=1300 + sum(shape))
     ctx, sysm = make_pair(cell, "VT84F", precision=precision)
     phi = normalized_phi(sysm, seed=13, contrast=0.6)
     ctx.set_density(phi)

@@ -87,6 +87,20 @@ def h_cell(n_atoms: int, rho_gcc: float, grid, temperature_K: float,
                  temperature_K=float(temperature_K), rho_gcc=float(rho_gcc), seed=seed)
 
 
+def h_cell_spaced(shape, seed: int, spacing: float = 0.15, rho_gcc: float = 1.0,
+                  temperature_K: float = 5.0e4) -> HCell:
+    """A seeded hydrogen cell on an orthorhombic box with the same grid spacing (bohr) along
+    every axis, for grids whose axes differ in length: the atom count follows from rho."""
+    lengths = np.array(shape, dtype=float) * spacing
+    n_per_bohr3 = rho_gcc / 1.00794 * 6.02214076e23 * (0.529177210903e-8) ** 3
+    nat = max(2, int(round(n_per_bohr3 * float(np.prod(lengths)))))
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pos = rng.random((nat, 3)) * lengths
+    return HCell(lattice=np.diag(lengths), positions=pos, charges=np.ones(nat),
+                 grid=tuple(int(g) for g in shape), temperature_K=float(temperature_K),
+                 rho_gcc=float(rho_gcc), seed=seed)
+
+
 # The five benchmark workloads (seed = SEED_BASE + index).
 def small_tf_cell() -> HCell:
     """16 H, 1.0 g/cm^3, 32^3, 10 kK (plain FP64 ftTF minimization)."""
