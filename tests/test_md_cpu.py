@@ -28,6 +28,23 @@ def test_nve_conserves_energy():
     assert np.ptp(e) < 1e-3 * abs(e.mean())
 
 
+def test_nve_positions_follow_the_closed_form_of_the_harmonic_map():
+    # velocity Verlet in a harmonic well: x_n = x_0 cos(na) + (dt v_0 / sin a) sin(na),
+    # cos a = 1 - (w dt)^2 / 2 (the discrete map's exact solution)
+    nat, dt = 6, 12.0
+    m = np.full(nat, md.H_MASS_ME)
+    rng = np.random.default_rng(3)
+    x0 = rng.normal(0, 0.3, (nat, 3))
+    v0 = rng.normal(0, 1e-3, (nat, 3))
+    seen = []
+    md.velocity_verlet(None, x0, v0, np.ones(nat), m, dt, 120, step=_harmonic,
+                       callback=lambda rec, x, v, f: seen.append((rec.step, x.copy())))
+    a = np.arccos(1.0 - 0.5 * (K_SPRING / md.H_MASS_ME) * dt * dt)
+    for k, x in seen:
+        ref = x0 * np.cos(k * a) + (dt * v0 / np.sin(a)) * np.sin(k * a)
+        assert np.max(np.abs(x - ref)) < 1e-12, k
+
+
 def test_andersen_thermostat_reaches_the_target_temperature():
     nat = 64
     m = np.full(nat, md.H_MASS_ME)
