@@ -86,6 +86,7 @@ def kernel_bytes(name: str, n1: int, n2: int, n3: int, rsize: int) -> float:
         "plane_fwd_density": P + CS,
         "plane_inv_grad3": 3 * CS + 3 * RR,
         "plane_fwd_w3": 3 * CS + 3 * RR,
+        "plane_inv_gga": 3 * CS + P + 4 * RR,
         "plane_final": CS + P + 2 * RR,
         "plane_tf_final": CS + P + RR,
         "reduce_scalars": 0,
@@ -451,15 +452,20 @@ def main():
                            "GB_s": (b / (ms * 1e-3) / 1e9) if ms > 0 and b > 0 else None})
     dom = max(per_kernel, key=lambda k: k["avg_us"])
     traffic = measured_traffic(dom["kernel"])
-    if dom["kernel"] == "pointwise_gga":
+    if dom["kernel"] in ("pointwise_gga", "plane_inv_gga"):
         N = n1 * n2 * n3
-        flops = POINTWISE_GGA_FLOP_PER_POINT * N
+        # the fused pass also runs the inverse x2 and x3 transforms of three components:
+        # 5 L^2 log2 L flop per plane and component (5 n log2 n per complex n-point transform,
+        # L/2 rows of the half spectrum and L/2 packed real-row pairs), FP32
+        fft32 = 15 * math.log2(n3) if dom["kernel"] == "plane_inv_gga" else 0.0
+        f64, f32 = POINTWISE_GGA_FLOP_FP64, POINTWISE_GGA_FLOP_FP32 + fft32
+        flops = (f64 + f32) * N
         achieved = flops / (dom["avg_us"] * 1e-6) / 1e12
-        t_min = N * (POINTWISE_GGA_FLOP_FP64 / FP64_PEAK_TFLOPS + POINTWISE_GGA_FLOP_FP32 / FP32_PEAK_TFLOPS) * 1e-12
+        t_min = N * (f64 / FP64_PEAK_TFLOPS + f32 / FP32_PEAK_TFLOPS) * 1e-12
         peak = flops / t_min / 1e12
         roofline = {"bound": "alu", "kernel": dom["kernel"], "achieved": achieved, "peak": peak,
                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
-                    "peak_basis": "FP64 239 flop/pt at 78.6 + FP32 151 flop/pt at 157.3 TFLOP/s",
+                    "peak_basis": f"FP64 {f64:g} flop/pt at 78.6 + FP32 {f32:g} flop/pt at 157.3 TFLOP/s",
                     "alg_flop_per_launch": float(flops), "alg_bytes_per_launch": dom["alg_bytes"],
                     "hbm_GB_s": dom["GB_s"], "avg_launch_us": dom["avg_us"]}
     else:

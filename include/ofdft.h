@@ -153,11 +153,14 @@ typedef struct {
 void ofdft_default_options(ofdft_options* opt);
 
 /* Creates a context.  opt may be NULL (defaults).  *out is set on success.
-   Two environment variables, read here, pick between equivalent kernels (for
+   Three environment variables, read here, pick between equivalent kernels (for
    tests and diagnosis; results agree to rounding): OFDFT_PLANE_PASSES=0 uses the
-   row FFT passes where plane passes would run; OFDFT_ION_FORCES=0 or 1 forces the
-   G-parallel or the one-thread-per-ion force kernel (default: per ion from 256
-   ions up).  A third, OFDFT_TEST_NONFINITE=k, exists for tests of the recovery
+   row FFT passes where plane passes would run; OFDFT_FUSED_GGA=0 keeps the inverse
+   gradient transforms and the pointwise functional as two passes where one fused
+   pass would run (mixed precision, PZ81 or no XC, square planes of 32, 64 or 128);
+   OFDFT_ION_FORCES=0 or 1 forces the G-parallel or the one-thread-per-ion force
+   kernel (default: per ion from 256 ions up).  A fourth, OFDFT_TEST_NONFINITE=k,
+   exists for tests of the recovery
    path of ofdft_minimize_density: the host treats the k-th line-search trial of
    the context (counted from 1; k < 0: every trial) as non-finite; the device
    state is not touched. */

@@ -696,6 +696,7 @@ int ofdft_create(const ofdft_options* opt, ofdft_ctx** out) {
   c->opt = o;
   c->rsize = (o.precision == OFDFT_MIXED) ? 4 : 8;
   if (const char* pp = std::getenv("OFDFT_PLANE_PASSES")) c->plane_passes = std::atoi(pp) != 0;
+  if (const char* pg = std::getenv("OFDFT_FUSED_GGA")) c->fused_gga = std::atoi(pg) != 0;
   if (const char* pf = std::getenv("OFDFT_ION_FORCES")) c->ion_forces = std::atoi(pf) != 0 ? 1 : 0;
   if (const char* pn = std::getenv("OFDFT_TEST_NONFINITE")) c->test_nonfinite = std::atoi(pn);
   if (o.stream) {

@@ -562,6 +562,30 @@ constexpr int pointwise_waves() {
   return pointwise_waves_of((int)sizeof(R), XC);
 }
 
+// The gradient functional and XC at one point of amplitude p with density gradient (gx, gy, gz):
+// returns v_loc = df/dn + v_xc, replaces the gradient by W = 2 (df/dsigma) grad n and adds the
+// point's f, T s, n eps_xc and n T s_xc to the running sums.
+template <typename R, int XC>
+__device__ __forceinline__ R gga_xc_at(double p, R& gx, R& gy, R& gz, double lt0, const EnhParams& enh,
+                                       double& fs, double& ts, double& exc, double& tsxc) {
+  const double n = p * p;
+  const double nf = n > kDensityFloor ? n : kDensityFloor;
+  const R sigma = gx * gx + gy * gy + gz * gz;
+  double f, tsl;
+  R dfdn, dfds;
+  const double ln_n = ln_pos(nf);
+  gga_point<R>(nf, ln_n, sigma, lt0, enh, f, dfdn, dfds, tsl);
+  R vl = dfdn;
+  xc_point<R>(XC, n, ln_n, lt0, vl, exc, tsxc);   // XC fixed at compile time: no registers for the others
+  fs += f;
+  ts += tsl;
+  const R w2 = R(2) * dfds;
+  gx *= w2;
+  gy *= w2;
+  gz *= w2;
+  return vl;
+}
+
 // Finite-T GGA + PZ81 at every point: v_loc = df/dn + v_xc, W = 2 df/dsigma grad n
 // (written over grad n), energy partial sums per block.
 template <typename R, int XC>
@@ -573,24 +597,11 @@ __global__ void __launch_bounds__(NT, (pointwise_waves<R, XC>()))
   EnhParams enh{(int)ep.enh_kind, ep.enh_c1, ep.enh_a1};
   double fs = 0.0, ts = 0.0, exc = 0.0, tsxc = 0.0;
   for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < npts; i += (long long)gridDim.x * NT) {
-    const double p = phi[i];
-    const double n = p * p;
-    const double nf = n > kDensityFloor ? n : kDensityFloor;
-    const R gx = g0[i], gy = g1[i], gz = g2[i];
-    const R sigma = gx * gx + gy * gy + gz * gz;
-    double f, tsl;
-    R dfdn, dfds;
-    const double ln_n = ln_pos(nf);
-    gga_point<R>(nf, ln_n, sigma, ep.lt0, enh, f, dfdn, dfds, tsl);
-    R vl = dfdn;
-    xc_point<R>(XC, n, ln_n, ep.lt0, vl, exc, tsxc);   // XC fixed at compile time: no registers for the others
-    vloc[i] = vl;
-    fs += f;
-    ts += tsl;
-    const R w2 = R(2) * dfds;
-    g0[i] = w2 * gx;
-    g1[i] = w2 * gy;
-    g2[i] = w2 * gz;
+    R gx = g0[i], gy = g1[i], gz = g2[i];
+    vloc[i] = gga_xc_at<R, XC>(phi[i], gx, gy, gz, ep.lt0, enh, fs, ts, exc, tsxc);
+    g0[i] = gx;
+    g1[i] = gy;
+    g2[i] = gz;
   }
   double v[4] = {fs, ts, exc, tsxc};
   block_sum<4>(v, red);
@@ -1422,6 +1433,178 @@ __global__ void __launch_bounds__(NTP) k_plane_final(const cplx<R>* __restrict__
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int m = 0; m < K; ++m) partials[slot[m] * maxb + 2 * i1 + h] = v[m];
+  }
+}
+
+// ---------------------------------------------------------------- K4 plane form, fused
+// Gradient functional on the plane passes, FP32 assembly: the inverse x2 and x3 transforms of
+// the three grad n spectra of one i1 plane, then the pointwise functional and XC on the real
+// rows they give, with W and v_loc stored; grad n itself stays in registers.  The x2 inverse
+// is split four ways by decimation in time over i2 mod 4 = q: with Q = L/4 and w = e^{-2 pi i/L},
+//   y[4m + q] = sum_{k < Q} Y_q[k] e^{+2 pi i k m/Q},  Y_q[k] = conj(w)^{k q} sum_{s < 4} i^{s q} X[k + s Q],
+// so each of the plane's four blocks runs Q-point transforms over its own rows and together
+// they do the arithmetic of one full-plane pass (each reads the plane's spectrum; the four sit
+// on one XCD, whose L2 serves all but the first read).  Blocks of IGG_NT threads, two per CU,
+// so that one block's transforms overlap the other's pointwise arithmetic.
+constexpr int IGG_NT = 512;
+
+// Block b takes plane i1 and row class q; the four blocks of a plane are 8 block indices
+// apart, so the round-robin dispatch over the 8 XCDs puts them on the same XCD.
+__device__ __forceinline__ void plane_quarter(int b, int n1, int& i1, int& q) {
+  if ((n1 & 7) == 0) {
+    i1 = (b >> 5) * 8 + (b & 7);
+    q = (b >> 3) & 3;
+  } else {
+    i1 = b >> 2;
+    q = b & 3;
+  }
+}
+
+// z multiplied by i^p
+template <typename R>
+__device__ __forceinline__ cplx<R> mul_ipow(cplx<R> z, int p) {
+  switch (p & 3) {
+    case 0: return z;
+    case 1: return {-z.y, z.x};
+    case 2: return {-z.x, -z.y};
+    default: return {z.y, -z.x};
+  }
+}
+
+template <int L>
+struct InvGgaLds {
+  static constexpr int H = L / 2, Q = L / 4, NP = Q / 2;
+  static constexpr int ELEMS = (H * Lay<Q>::RS > NP * Lay<L>::RS) ? H * Lay<Q>::RS : NP * Lay<L>::RS;
+};
+
+template <typename R, int L, int XC>
+__global__ void __launch_bounds__(IGG_NT, 4) k_plane_inv_gga(Arr3 in, const double* __restrict__ phi,
+                                                             R* __restrict__ g0, R* __restrict__ g1,
+                                                             R* __restrict__ g2, R* __restrict__ vloc,
+                                                             const cplx<R>* __restrict__ tw_g, GridDesc g,
+                                                             EvalParams ep, double* __restrict__ partials,
+                                                             int maxb) {
+  OFDFT_GATE(g.gate);
+  constexpr int NTH = IGG_NT;
+  constexpr int H = L / 2, Q = L / 4, NP = Q / 2;
+  constexpr int NY = H * Q, MY = (NY + NTH - 1) / NTH;   // Y_q elements (k3 < H, k < Q), per thread
+  constexpr int NZ = NP * L, MZ = (NZ + NTH - 1) / NTH;  // packed x3 rows' elements, per thread
+  constexpr int NR = Q * L, MR = (NR + NTH - 1) / NTH;   // real points of the block, per thread
+  static_assert(L % 8 == 0 && MY <= 4 && MZ <= 4 && MR <= 8, "plane too large for the fused pass");
+  __shared__ cplx<R> buf[InvGgaLds<L>::ELEMS];
+  __shared__ cplx<R> tw[L];
+  __shared__ cplx<R> twq[Q];
+  __shared__ double red[4 * NTH / 64];
+  int i1, q;
+  plane_quarter(blockIdx.x, g.n1, i1, q);
+  const int tid = threadIdx.x;
+  const size_t slab = (size_t)g.n1 * L;   // elements per k3 of the spectrum S[k3][i1][k2]
+  const size_t row0 = (size_t)i1 * L;
+  const size_t base = (size_t)i1 * L * L;
+  if (tid < L) tw[tid] = tw_g[tid];
+  if (tid < Q) twq[tid] = tw_g[4 * tid];
+  R gr[3][MR];
+  double pv[MR];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    // X[k + s Q] (s < 4) of this thread's Y_q elements: rows of the spectrum are read whole
+    const cplx<R>* S = reinterpret_cast<const cplx<R>*>(in.p[a]);
+    cplx<R> x[MY][4];
+#pragma unroll
+    for (int m = 0; m < MY; ++m) {
+      const int e = min(tid + m * NTH, NY - 1);
+      const int k3 = e / Q, k = e - k3 * Q;
+      const cplx<R>* r = S + k3 * slab + row0 + k;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) x[m][s] = r[s * Q];
+    }
+    if (a == 2) {
+#pragma unroll
+      for (int u = 0; u < MR; ++u) {
+        const int e = min(tid + u * NTH, NR - 1);
+        const int m = e / L, i3 = e - m * L;
+        pv[u] = phi[base + (size_t)(4 * m + q) * L + i3];
+      }
+    }
+    __syncthreads();   // the twiddles are in place; every thread has read the previous real rows
+#pragma unroll
+    for (int m = 0; m < MY; ++m) {
+      const int e = tid + m * NTH;
+      if (e < NY) {
+        const int k3 = e / Q, k = e - k3 * Q;
+        cplx<R> y = x[m][0];
+#pragma unroll
+        for (int s = 1; s < 4; ++s) y = y + mul_ipow(x[m][s], s * q);
+        buf[Lay<Q>::at(k3, k)] = q == 0 ? y : cmul(y, cconj(tw[k * q]));
+      }
+    }
+    __syncthreads();
+    // x2 inverse: Q-point transforms along k of the rows k3 (y_q[k3][m] in place)
+    lds_fft_inplace<R, +1, Q, NTH, MY>(buf, twq, H, tid);
+    // packed rows z_p[k] = A[k] + i B[k] of the block's real rows 2p and 2p + 1, over the
+    // whole k range by Hermitian symmetry (Nyquist term zero)
+    cplx<R> z[MZ];
+#pragma unroll
+    for (int m = 0; m < MZ; ++m) {
+      const int it = tid + m * NTH;
+      if (it < NZ) {
+        const int p = it / L, k = it - p * L;
+        cplx<R> A = {R(0), R(0)}, B = {R(0), R(0)};
+        if (2 * k < L) {
+          A = buf[Lay<Q>::at(k, 2 * p)];
+          B = buf[Lay<Q>::at(k, 2 * p + 1)];
+        } else if (2 * k > L) {
+          A = cconj(buf[Lay<Q>::at(L - k, 2 * p)]);
+          B = cconj(buf[Lay<Q>::at(L - k, 2 * p + 1)]);
+        }
+        z[m] = {A.x - B.y, A.y + B.x};
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < MZ; ++m) {
+      const int it = tid + m * NTH;
+      if (it < NZ) {
+        const int p = it / L, k = it - p * L;
+        buf[Lay<L>::at(p, k)] = z[m];
+      }
+    }
+    __syncthreads();
+    // x3 inverse of the packed rows: real row m of the block is Re (m even) or Im (m odd) of
+    // packed row m/2
+    int tid2 = tid;
+    asm volatile("" : "+v"(tid2));
+    lds_fft_inplace<R, +1, L, NTH, MZ>(buf, tw, NP, tid2);
+#pragma unroll
+    for (int u = 0; u < MR; ++u) {
+      const int e = min(tid + u * NTH, NR - 1);
+      const int m = e / L, i3 = e - m * L;
+      const cplx<R> v = buf[Lay<L>::at(m >> 1, i3)];
+      gr[a][u] = (m & 1) ? v.y : v.x;
+    }
+  }
+  const EnhParams enh{(int)ep.enh_kind, ep.enh_c1, ep.enh_a1};
+  double fs = 0.0, ts = 0.0, exc = 0.0, tsxc = 0.0;
+#pragma unroll
+  for (int u = 0; u < MR; ++u) {
+    const int e = tid + u * NTH;
+    if (e < NR) {
+      const int m = e / L, i3 = e - m * L;
+      const size_t i = base + (size_t)(4 * m + q) * L + i3;
+      R gx = gr[0][u], gy = gr[1][u], gz = gr[2][u];
+      vloc[i] = gga_xc_at<R, XC>(pv[u], gx, gy, gz, ep.lt0, enh, fs, ts, exc, tsxc);
+      g0[i] = gx;
+      g1[i] = gy;
+      g2[i] = gz;
+    }
+  }
+  double v[4] = {fs, ts, exc, tsxc};
+  block_sum<4, NTH>(v, red);
+  if (tid == 0) {
+    partials[SL_FS * maxb + blockIdx.x] = v[0];
+    partials[SL_TS * maxb + blockIdx.x] = v[1];
+    partials[SL_EXC * maxb + blockIdx.x] = v[2];
+    partials[SL_TSXC * maxb + blockIdx.x] = v[3];
   }
 }
 
@@ -2382,6 +2565,25 @@ static void launch_pointwise_gga(ofdft_ctx* c, const double* phi, const EvalPara
                      (R*)c->gr[2], (R*)c->vloc, c->g.N, ep, c->partials, c->max_blocks);
 }
 
+// The fused gradient pass (k_plane_inv_gga) serves mixed precision with PZ81 or no XC on
+// square planes of 32, 64 or 128 points (the KSDT fit and the FP64 assembly need more
+// registers than two of its blocks per CU leave); its four blocks per plane each write one
+// slot of partial sums.
+static bool fused_gga_mode(const ofdft_ctx* c, const EvalParams& ep) {
+  return c->fused_gga && c->rsize == 4 && ep.xc != 2 &&
+         (c->g.n3 == 32 || c->g.n3 == 64 || c->g.n3 == 128) && 4 * c->g.n1 <= c->max_blocks;
+}
+
+template <int L>
+static void launch_plane_inv_gga(ofdft_ctx* c, const double* phi, const EvalParams& ep) {
+  const GridDesc& g = c->g;
+  Arr3 in{{c->B[0], c->B[1], c->B[2]}};
+  auto k = ep.xc == 1 ? k_plane_inv_gga<float, L, 1> : k_plane_inv_gga<float, L, 0>;
+  hipLaunchKernelGGL(k, dim3(4 * g.n1), dim3(IGG_NT), 0, c->stream, in, phi, (float*)c->gr[0], (float*)c->gr[1],
+                     (float*)c->gr[2], (float*)c->vloc, (const cplx<float>*)c->tw[2], g, ep, c->partials,
+                     c->max_blocks);
+}
+
 template <typename R, int L>
 static void launch_rpass_fwd_real3(ofdft_ctx* c) {
   const GridDesc& g = c->g;
@@ -2487,6 +2689,7 @@ static int eval_impl(ofdft_ctx* c, const double* phi, void* v_out, double* sc, c
   const bool tf = c->opt.functional == OFDFT_TF;
   const double* phi_e = rot ? rot->phi_out : phi;   // the amplitude being evaluated
   const bool plane = plane_mode(c);
+  const bool fused = plane && !tf && fused_gga_mode(c, ep);
   if (plane) {
     tmark(c, "plane_fwd_density");
     OFDFT_DISPATCH_PLANE(g.n3, (launch_plane_fwd_density<R, L_>(c, phi, c->A, rot)));
@@ -2502,18 +2705,28 @@ static int eval_impl(ofdft_ctx* c, const double* phi, void* v_out, double* sc, c
   } else {
     tmark(c, "x1_density_gradient");
     OFDFT_DISPATCH(g.n1, (launch_x1_density<R, L_, X1_GGA>(c, c->A, c->B[0], c->B[1], c->B[2])));
-    if (plane) {
-      tmark(c, "plane_inv_grad3");
-      OFDFT_DISPATCH_PLANE(g.n3, (launch_plane_inv_real<R, L_>(c, c->B[0], c->B[1], c->B[2], c->gr[0], c->gr[1],
-                                                               c->gr[2], 3)));
+    if (fused) {
+      tmark(c, "plane_inv_gga");
+      if (g.n3 == 128)
+        launch_plane_inv_gga<128>(c, phi_e, ep);
+      else if (g.n3 == 64)
+        launch_plane_inv_gga<64>(c, phi_e, ep);
+      else
+        launch_plane_inv_gga<32>(c, phi_e, ep);
     } else {
-      tmark(c, "cpass_x2_inv3");
-      OFDFT_DISPATCH(g.n2, (launch_x2<R, L_, +1>(c, c->B[0], c->B[1], c->B[2], 3)));
-      tmark(c, "rpass_inv_grad3");
-      OFDFT_DISPATCH(g.n3, (launch_rpass_inv_real3<R, L_>(c)));
+      if (plane) {
+        tmark(c, "plane_inv_grad3");
+        OFDFT_DISPATCH_PLANE(g.n3, (launch_plane_inv_real<R, L_>(c, c->B[0], c->B[1], c->B[2], c->gr[0], c->gr[1],
+                                                                 c->gr[2], 3)));
+      } else {
+        tmark(c, "cpass_x2_inv3");
+        OFDFT_DISPATCH(g.n2, (launch_x2<R, L_, +1>(c, c->B[0], c->B[1], c->B[2], 3)));
+        tmark(c, "rpass_inv_grad3");
+        OFDFT_DISPATCH(g.n3, (launch_rpass_inv_real3<R, L_>(c)));
+      }
+      tmark(c, "pointwise_gga");
+      launch_pointwise_gga<R>(c, phi_e, ep);
     }
-    tmark(c, "pointwise_gga");
-    launch_pointwise_gga<R>(c, phi_e, ep);
     if (plane) {
       tmark(c, "plane_fwd_w3");
       OFDFT_DISPATCH_PLANE(g.n3, (launch_plane_fwd_real3<R, L_>(c)));
@@ -2547,7 +2760,7 @@ static int eval_impl(ofdft_ctx* c, const double* phi, void* v_out, double* sc, c
   }
   // partial sums of the density and final passes: one per block
   const int nb_r = plane ? 2 * g.n1 : (g.n2 / g.tr) * g.n1;   // plane passes: two blocks per i1 plane
-  const ReduceParams rp{nb_r, (g.n2 / g.tc) * g.n3k, tf ? nb_r : pw_blocks(g), sl ? 1 : 0, g.dv, g.volume,
+  const ReduceParams rp{nb_r, (g.n2 / g.tc) * g.n3k, tf ? nb_r : fused ? 4 * g.n1 : pw_blocks(g), sl ? 1 : 0, g.dv, g.volume,
                         c->alpha_sum, g.gate};
   tmark(c, "reduce_scalars");
   hipLaunchKernelGGL(k_reduce_scalars, dim3(1), dim3(RED_NT), 0, c->stream, c->partials, c->max_blocks, rp, sc,

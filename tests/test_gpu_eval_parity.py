@@ -198,3 +198,45 @@ def test_plane_passes_match_row_passes(precision, functional, shape, monkeypatch
         _, _, f64 = ref.free_energy_and_forces()
         assert np.max(np.abs(f1 - f64)) <= 1e-4
         assert np.max(np.abs(f2 - f64)) <= 1e-4
+
+
+@pytest.mark.parametrize("functional,xc,shape,rho,T_K", [
+    ("VT84F", "PZ81", (16, 32, 32), 4.0, 1e5), ("SGA", "NONE", (12, 32, 32), 2.0, 1e6),
+    ("VT84F", "PZ81", (12, 64, 64), 2.0, 1e5), ("KST2", "PZ81", (8, 64, 64), 1.0, 5e4),
+    ("VT84F", "NONE", (8, 128, 128), 1.0, 5e4), ("VT84F", "PZ81", (16, 128, 128), 2.0, 1e5),
+])
+def test_fused_gradient_pass_matches_separate_passes(functional, xc, shape, rho, T_K, monkeypatch):
+    """Mixed precision on square planes of 32, 64 and 128 points runs the inverse gradient
+    transforms and the pointwise functional as one plane pass (x2 split over the row parity);
+    with it switched off (OFDFT_FUSED_GGA=0: inverse plane pass, then the pointwise kernel) the
+    evaluation agrees to the mixed path's rounding, and the oracle pins the fused path on every
+    grid point, including plane counts that are not multiples of 8 and the no-XC form.  The
+    mixed path's 1e-6 is relative to F, so the cells are ones whose F is not a near
+    cancellation of its terms (|F| at least half the largest component)."""
+    cell = wl.h_cell_spaced(shape, seed=607, rho_gcc=rho, temperature_K=T_K)
+    ctx, sysm = make_pair(cell, functional, precision="mixed", xc=xc)
+    monkeypatch.setenv("OFDFT_FUSED_GGA", "0")
+    ctx_sep, _ = make_pair(cell, functional, precision="mixed", xc=xc)
+    monkeypatch.delenv("OFDFT_FUSED_GGA")
+    phi = normalized_phi(sysm, seed=13, contrast=0.6)
+    ctx.set_density(phi)
+    ctx_sep.set_density(phi)
+    rep, v = ctx.eval(potential=True)
+    rep_s, v_s = ctx_sep.eval(potential=True)
+    for a, _ in COMPONENTS:
+        got, ref = getattr(rep, a), getattr(rep_s, a)
+        assert abs(got - ref) <= 1e-6 * max(abs(ref), 1e-3 * abs(rep_s.F_total)), (a, got, ref)
+    assert np.max(np.abs(v - v_s)) <= 1e-5 * np.max(np.abs(v_s))
+    # against the oracle: what the fused pass forms (the free-energy density sums and, through
+    # them, F and mu; the potential at every point).  E_H and E_ext come from the x1 pass before
+    # it, unchanged, and are held to the separate passes above.
+    ev = oracle.evaluate(phi, sysm)
+    for a, b in [("F_total", "F_tot"), ("F_s", "F_s"), ("TS_s", "TS_s"), ("E_xc", "E_xc"), ("mu", "mu")]:
+        got, ref = getattr(rep, a), getattr(ev, b)
+        assert abs(got - ref) <= 1e-6 * max(abs(ref), 1e-3 * abs(ev.F_tot)), (a, got, ref)
+    assert_potential(v, ev.v, "mixed")
+    # bitwise repeatable: fixed block order of every sum
+    rep2, v2 = ctx.eval(potential=True)
+    assert rep2.F_total == rep.F_total and np.array_equal(v2, v)
+    ctx.close()
+    ctx_sep.close()
