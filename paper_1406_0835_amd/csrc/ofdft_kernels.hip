@@ -1495,6 +1495,10 @@ __global__ void __launch_bounds__(IGG_NT, 4) k_plane_inv_gga(Arr3 in, const doub
   __shared__ cplx<R> tw[L];
   __shared__ cplx<R> twq[Q];
   __shared__ double red[4 * NTH / 64];
+  // grad n of the block's points: components 0 and 1 here, component 2 read from buf, which
+  // holds the last transform's real rows (registers would cap the kernel below its two blocks
+  // per CU)
+  __shared__ R greal[2][NR];
   int i1, q;
   plane_quarter(blockIdx.x, g.n1, i1, q);
   const int tid = threadIdx.x;
@@ -1503,7 +1507,6 @@ __global__ void __launch_bounds__(IGG_NT, 4) k_plane_inv_gga(Arr3 in, const doub
   const size_t base = (size_t)i1 * L * L;
   if (tid < L) tw[tid] = tw_g[tid];
   if (tid < Q) twq[tid] = tw_g[4 * tid];
-  R gr[3][MR];
   double pv[MR];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -1575,12 +1578,17 @@ __global__ void __launch_bounds__(IGG_NT, 4) k_plane_inv_gga(Arr3 in, const doub
     int tid2 = tid;
     asm volatile("" : "+v"(tid2));
     lds_fft_inplace<R, +1, L, NTH, MZ>(buf, tw, NP, tid2);
+    if (a < 2) {
+      // each thread keeps the points it takes in the pointwise loop: no barrier needed
 #pragma unroll
-    for (int u = 0; u < MR; ++u) {
-      const int e = min(tid + u * NTH, NR - 1);
-      const int m = e / L, i3 = e - m * L;
-      const cplx<R> v = buf[Lay<L>::at(m >> 1, i3)];
-      gr[a][u] = (m & 1) ? v.y : v.x;
+      for (int u = 0; u < MR; ++u) {
+        const int e = tid + u * NTH;
+        if (e < NR) {
+          const int m = e / L, i3 = e - m * L;
+          const cplx<R> v = buf[Lay<L>::at(m >> 1, i3)];
+          greal[a][e] = (m & 1) ? v.y : v.x;
+        }
+      }
     }
   }
   const EnhParams enh{(int)ep.enh_kind, ep.enh_c1, ep.enh_a1};
@@ -1591,7 +1599,8 @@ __global__ void __launch_bounds__(IGG_NT, 4) k_plane_inv_gga(Arr3 in, const doub
     if (e < NR) {
       const int m = e / L, i3 = e - m * L;
       const size_t i = base + (size_t)(4 * m + q) * L + i3;
-      R gx = gr[0][u], gy = gr[1][u], gz = gr[2][u];
+      const cplx<R> v = buf[Lay<L>::at(m >> 1, i3)];
+      R gx = greal[0][e], gy = greal[1][e], gz = (m & 1) ? v.y : v.x;
       vloc[i] = gga_xc_at<R, XC>(pv[u], gx, gy, gz, ep.lt0, enh, fs, ts, exc, tsxc);
       g0[i] = gx;
       g1[i] = gy;
