@@ -397,9 +397,10 @@ __global__ void __launch_bounds__(NT) k_x1_density(const cplx<R>* __restrict__ A
   extern __shared__ __align__(16) char smem_raw[];
   const int tc = g.tc, tcl = ilog2(tc);
   Smem sm(smem_raw);
+  // two tile buffers and in-place transforms: at 128 points and 16 columns a block takes 38 KB,
+  // so four blocks share a CU
   cplx<R>* b0 = sm.take<cplx<R>>(tc * Lay<L>::RS);
   cplx<R>* b1 = sm.take<cplx<R>>(tc * Lay<L>::RS);
-  cplx<R>* b2 = sm.take<cplx<R>>(tc * Lay<L>::RS);
   cplx<R>* tw = sm.take<cplx<R>>(L);
   double* red = sm.take<double>(2 * NT / 64);
   const int k3 = blockIdx.y, i2_0 = blockIdx.x * tc;
@@ -426,9 +427,9 @@ __global__ void __launch_bounds__(NT) k_x1_density(const cplx<R>* __restrict__ A
   }
   twiddle_store<R, L>(tw, twv);
   __syncthreads();
-  cplx<R>* res = lds_fft<R, -1, L, NT>(b0, b1, tw, tc, threadIdx.x);
-  cplx<R>* fa = (res == b0) ? b1 : b0;   // free buffers
-  cplx<R>* fb = b2;
+  lds_fft_inplace<R, -1, L, NT, U>(b0, tw, tc, threadIdx.x);
+  cplx<R>* res = b0;
+  cplx<R>* fa = b1;   // work buffer of the gradient components
   const R inv_n = R(g.inv_n);
   const double wk = (k3 == 0) ? 1.0 : 2.0;
   double eh = 0.0, ee = 0.0;
@@ -479,8 +480,8 @@ __global__ void __launch_bounds__(NT) k_x1_density(const cplx<R>* __restrict__ A
     __syncthreads();
   }
   if constexpr (MODE == X1_TF || MODE == X1_PREC) {
-    const cplx<R>* o = lds_fft<R, +1, L, NT>(res, fa, tw, tc, threadIdx.x);
-    store_x1_tile<R, L, U>(o, out0 + tile0, off, tc, tcl, cnt);
+    lds_fft_inplace<R, +1, L, NT, U>(res, tw, tc, threadIdx.x);
+    store_x1_tile<R, L, U>(res, out0 + tile0, off, tc, tcl, cnt);
   } else if constexpr (MODE == X1_GGA) {
     cplx<R>* outs[3] = {out0, out1, out2};
 #pragma unroll 1
@@ -495,8 +496,8 @@ __global__ void __launch_bounds__(NT) k_x1_density(const cplx<R>* __restrict__ A
         fa[idx] = {-ga * z.y, ga * z.x};
       }
       __syncthreads();
-      const cplx<R>* o = lds_fft<R, +1, L, NT>(fa, fb, tw, tc, threadIdx.x);
-      store_x1_tile<R, L, U>(o, outs[a] + tile0, off, tc, tcl, cnt);
+      lds_fft_inplace<R, +1, L, NT, U>(fa, tw, tc, threadIdx.x);
+      store_x1_tile<R, L, U>(fa, outs[a] + tile0, off, tc, tcl, cnt);
       __syncthreads();
     }
   }
@@ -700,7 +701,6 @@ __global__ void __launch_bounds__(NT) k_x1_divergence(const cplx<R>* __restrict_
   Smem sm(smem_raw);
   cplx<R>* acc = sm.take<cplx<R>>(tc * Lay<L>::RS);
   cplx<R>* b0 = sm.take<cplx<R>>(tc * Lay<L>::RS);
-  cplx<R>* b1 = sm.take<cplx<R>>(tc * Lay<L>::RS);
   cplx<R>* tw = sm.take<cplx<R>>(L);
   const int k3 = blockIdx.y, i2_0 = blockIdx.x * tc;
   const size_t tile0 = (size_t)k3 * g.n1 * g.n2 + i2_0;
@@ -741,7 +741,8 @@ __global__ void __launch_bounds__(NT) k_x1_divergence(const cplx<R>* __restrict_
       for (int u = 0; u < U; ++u) cv[u] = nxt[off[u]];
     }
     __syncthreads();
-    const cplx<R>* res = lds_fft<R, -1, L, NT>(b0, b1, tw, tc, threadIdx.x);
+    lds_fft_inplace<R, -1, L, NT, U>(b0, tw, tc, threadIdx.x);
+    const cplx<R>* res = b0;
     for (int e = threadIdx.x; e < cnt; e += NT) {
       const int c = e / L, k1 = e - c * L;
       const int k2 = i2_0 + c;
@@ -757,8 +758,8 @@ __global__ void __launch_bounds__(NT) k_x1_divergence(const cplx<R>* __restrict_
     }
     __syncthreads();
   }
-  const cplx<R>* o = lds_fft<R, +1, L, NT>(acc, b0, tw, tc, threadIdx.x);
-  store_x1_tile<R, L, U>(o, out + tile0, off, tc, tcl, cnt);
+  lds_fft_inplace<R, +1, L, NT, U>(acc, tw, tc, threadIdx.x);
+  store_x1_tile<R, L, U>(acc, out + tile0, off, tc, tcl, cnt);
 }
 
 // ---------------------------------------------------------------- scalar reduction
@@ -2405,7 +2406,7 @@ static size_t lds_rpass_inv(int tr, int extra_real, int nred) {
 }
 template <typename R, int L>
 static size_t lds_x1(int tc, int nred) {
-  return 3 * pad16<cplx<R>>((size_t)tc * Lay<L>::RS) + pad16<cplx<R>>(L) + pad16<double>((size_t)nred * NT / 64);
+  return 2 * pad16<cplx<R>>((size_t)tc * Lay<L>::RS) + pad16<cplx<R>>(L) + pad16<double>((size_t)nred * NT / 64);
 }
 template <typename R, int L>
 static size_t lds_x2(int rb) {
