@@ -769,6 +769,7 @@ struct ReduceParams {
   int trial;         // 1: also dF/dtheta of a line-search trial into SC_DOT0
   double dv, volume, alpha_sum;
   const double* gate;
+  int nb_fin;        // partial count of the final pass's slots (n v, dF/dtheta)
 };
 
 // Destination of a device-written readback: dst[0..n) and then the sequence
@@ -803,7 +804,8 @@ __device__ __forceinline__ void reduce_scalars(const double* __restrict__ partia
   for (int s = w; s < SL_COUNT; s += NTH / 64) {
     const int cnt = (s == SL_EH || s == SL_EEXT) ? rp.nb_x1
                     : (s == SL_FS || s == SL_TS || s == SL_EXC || s == SL_TSXC) ? rp.nb_fs
-                    : (s == SL_DT1 || s == SL_DT2) ? (rp.trial ? rp.nb_r : 0) : rp.nb_r;
+                    : (s == SL_DT1 || s == SL_DT2) ? (rp.trial ? rp.nb_fin : 0)
+                    : (s == SL_NV) ? rp.nb_fin : rp.nb_r;
     const double* ps = partials + (size_t)s * maxb;
     double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     int i = lane;
@@ -1478,6 +1480,78 @@ struct InvGgaLds {
   static constexpr int ELEMS = (H * Lay<Q>::RS > NP * Lay<L>::RS) ? H * Lay<Q>::RS : NP * Lay<L>::RS;
 };
 
+// The four-way split inverse of one plane's half spectrum S (component rows S[k3][i1][.]) for
+// row class q: on return buf holds the block's Q real rows packed in pairs (Lay<L> rows p),
+// real row m (i2 = 4m + q) being Re (m even) or Im (m odd) of packed row m/2.  tw (L entries)
+// and twq (Q entries) are written by the caller before the call; the first barrier here
+// publishes them, and also orders this call's writes of buf after earlier reads of it.
+template <typename R, int L, int NTH>
+__device__ __forceinline__ void plane_inv_quarter(const cplx<R>* __restrict__ S, cplx<R>* buf, const cplx<R>* tw,
+                                                  const cplx<R>* twq, size_t slab, size_t row0, int q, int tid) {
+  constexpr int H = L / 2, Q = L / 4, NP = Q / 2;
+  constexpr int NY = H * Q, MY = (NY + NTH - 1) / NTH;   // Y_q elements (k3 < H, k < Q), per thread
+  constexpr int NZ = NP * L, MZ = (NZ + NTH - 1) / NTH;  // packed x3 rows' elements, per thread
+  static_assert(L % 8 == 0 && MY <= 4 && MZ <= 4, "plane too large for the split inverse");
+  // X[k + s Q] (s < 4) of this thread's Y_q elements: rows of the spectrum are read whole
+  cplx<R> x[MY][4];
+#pragma unroll
+  for (int m = 0; m < MY; ++m) {
+    const int e = min(tid + m * NTH, NY - 1);
+    const int k3 = e / Q, k = e - k3 * Q;
+    const cplx<R>* r = S + k3 * slab + row0 + k;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) x[m][s] = r[s * Q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < MY; ++m) {
+    const int e = tid + m * NTH;
+    if (e < NY) {
+      const int k3 = e / Q, k = e - k3 * Q;
+      cplx<R> y = x[m][0];
+#pragma unroll
+      for (int s = 1; s < 4; ++s) y = y + mul_ipow(x[m][s], s * q);
+      buf[Lay<Q>::at(k3, k)] = q == 0 ? y : cmul(y, cconj(tw[k * q]));
+    }
+  }
+  __syncthreads();
+  // x2 inverse: Q-point transforms along k of the rows k3 (y_q[k3][m] in place)
+  lds_fft_inplace<R, +1, Q, NTH, MY>(buf, twq, H, tid);
+  // packed rows z_p[k] = A[k] + i B[k] of the block's real rows 2p and 2p + 1, over the
+  // whole k range by Hermitian symmetry (Nyquist term zero)
+  cplx<R> z[MZ];
+#pragma unroll
+  for (int m = 0; m < MZ; ++m) {
+    const int it = tid + m * NTH;
+    if (it < NZ) {
+      const int p = it / L, k = it - p * L;
+      cplx<R> A = {R(0), R(0)}, B = {R(0), R(0)};
+      if (2 * k < L) {
+        A = buf[Lay<Q>::at(k, 2 * p)];
+        B = buf[Lay<Q>::at(k, 2 * p + 1)];
+      } else if (2 * k > L) {
+        A = cconj(buf[Lay<Q>::at(L - k, 2 * p)]);
+        B = cconj(buf[Lay<Q>::at(L - k, 2 * p + 1)]);
+      }
+      z[m] = {A.x - B.y, A.y + B.x};
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < MZ; ++m) {
+    const int it = tid + m * NTH;
+    if (it < NZ) {
+      const int p = it / L, k = it - p * L;
+      buf[Lay<L>::at(p, k)] = z[m];
+    }
+  }
+  __syncthreads();
+  // x3 inverse of the packed rows
+  int tid2 = tid;
+  asm volatile("" : "+v"(tid2));
+  lds_fft_inplace<R, +1, L, NTH, MZ>(buf, tw, NP, tid2);
+}
+
 template <typename R, int L, int XC>
 __global__ void __launch_bounds__(IGG_NT, 4) k_plane_inv_gga(Arr3 in, const double* __restrict__ phi,
                                                              R* __restrict__ g0, R* __restrict__ g1,
@@ -1487,11 +1561,9 @@ __global__ void __launch_bounds__(IGG_NT, 4) k_plane_inv_gga(Arr3 in, const doub
                                                              int maxb) {
   OFDFT_GATE(g.gate);
   constexpr int NTH = IGG_NT;
-  constexpr int H = L / 2, Q = L / 4, NP = Q / 2;
-  constexpr int NY = H * Q, MY = (NY + NTH - 1) / NTH;   // Y_q elements (k3 < H, k < Q), per thread
-  constexpr int NZ = NP * L, MZ = (NZ + NTH - 1) / NTH;  // packed x3 rows' elements, per thread
+  constexpr int Q = L / 4;
   constexpr int NR = Q * L, MR = (NR + NTH - 1) / NTH;   // real points of the block, per thread
-  static_assert(L % 8 == 0 && MY <= 4 && MZ <= 4 && MR <= 8, "plane too large for the fused pass");
+  static_assert(MR <= 8, "plane too large for the fused pass");
   __shared__ cplx<R> buf[InvGgaLds<L>::ELEMS];
   __shared__ cplx<R> tw[L];
   __shared__ cplx<R> twq[Q];
@@ -1511,17 +1583,6 @@ __global__ void __launch_bounds__(IGG_NT, 4) k_plane_inv_gga(Arr3 in, const doub
   double pv[MR];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    // X[k + s Q] (s < 4) of this thread's Y_q elements: rows of the spectrum are read whole
-    const cplx<R>* S = reinterpret_cast<const cplx<R>*>(in.p[a]);
-    cplx<R> x[MY][4];
-#pragma unroll
-    for (int m = 0; m < MY; ++m) {
-      const int e = min(tid + m * NTH, NY - 1);
-      const int k3 = e / Q, k = e - k3 * Q;
-      const cplx<R>* r = S + k3 * slab + row0 + k;
-#pragma unroll
-      for (int s = 0; s < 4; ++s) x[m][s] = r[s * Q];
-    }
     if (a == 2) {
 #pragma unroll
       for (int u = 0; u < MR; ++u) {
@@ -1530,55 +1591,8 @@ __global__ void __launch_bounds__(IGG_NT, 4) k_plane_inv_gga(Arr3 in, const doub
         pv[u] = phi[base + (size_t)(4 * m + q) * L + i3];
       }
     }
-    __syncthreads();   // the twiddles are in place; every thread has read the previous real rows
-#pragma unroll
-    for (int m = 0; m < MY; ++m) {
-      const int e = tid + m * NTH;
-      if (e < NY) {
-        const int k3 = e / Q, k = e - k3 * Q;
-        cplx<R> y = x[m][0];
-#pragma unroll
-        for (int s = 1; s < 4; ++s) y = y + mul_ipow(x[m][s], s * q);
-        buf[Lay<Q>::at(k3, k)] = q == 0 ? y : cmul(y, cconj(tw[k * q]));
-      }
-    }
-    __syncthreads();
-    // x2 inverse: Q-point transforms along k of the rows k3 (y_q[k3][m] in place)
-    lds_fft_inplace<R, +1, Q, NTH, MY>(buf, twq, H, tid);
-    // packed rows z_p[k] = A[k] + i B[k] of the block's real rows 2p and 2p + 1, over the
-    // whole k range by Hermitian symmetry (Nyquist term zero)
-    cplx<R> z[MZ];
-#pragma unroll
-    for (int m = 0; m < MZ; ++m) {
-      const int it = tid + m * NTH;
-      if (it < NZ) {
-        const int p = it / L, k = it - p * L;
-        cplx<R> A = {R(0), R(0)}, B = {R(0), R(0)};
-        if (2 * k < L) {
-          A = buf[Lay<Q>::at(k, 2 * p)];
-          B = buf[Lay<Q>::at(k, 2 * p + 1)];
-        } else if (2 * k > L) {
-          A = cconj(buf[Lay<Q>::at(L - k, 2 * p)]);
-          B = cconj(buf[Lay<Q>::at(L - k, 2 * p + 1)]);
-        }
-        z[m] = {A.x - B.y, A.y + B.x};
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int m = 0; m < MZ; ++m) {
-      const int it = tid + m * NTH;
-      if (it < NZ) {
-        const int p = it / L, k = it - p * L;
-        buf[Lay<L>::at(p, k)] = z[m];
-      }
-    }
-    __syncthreads();
-    // x3 inverse of the packed rows: real row m of the block is Re (m even) or Im (m odd) of
-    // packed row m/2
-    int tid2 = tid;
-    asm volatile("" : "+v"(tid2));
-    lds_fft_inplace<R, +1, L, NTH, MZ>(buf, tw, NP, tid2);
+    // (its first barrier: the twiddles are in place, every thread has read the previous rows)
+    plane_inv_quarter<R, L, NTH>(reinterpret_cast<const cplx<R>*>(in.p[a]), buf, tw, twq, slab, row0, q, tid);
     if (a < 2) {
       // each thread keeps the points it takes in the pointwise loop: no barrier needed
 #pragma unroll
@@ -1615,6 +1629,81 @@ __global__ void __launch_bounds__(IGG_NT, 4) k_plane_inv_gga(Arr3 in, const doub
     partials[SL_TS * maxb + blockIdx.x] = v[1];
     partials[SL_EXC * maxb + blockIdx.x] = v[2];
     partials[SL_TSXC * maxb + blockIdx.x] = v[3];
+  }
+}
+
+// Final pass of the gradient functionals on the same four-way split (mixed precision, planes of
+// 32, 64 or 128): the inverse x2 and x3 of D for the block's rows i2 = 4m + q, then
+// v = v_loc + S + alpha_sum and the sums of k_plane_final (n v; a trial's phi_t v_t q and
+// phi_t q).  One slot of partial sums per block.
+template <typename R, int L, bool DT>
+__global__ void __launch_bounds__(IGG_NT, 4) k_plane_final_q(const cplx<R>* __restrict__ D,
+                                                             const double* __restrict__ phi,
+                                                             const R* __restrict__ vloc, R* __restrict__ vout,
+                                                             const cplx<R>* __restrict__ tw_g, GridDesc g,
+                                                             EvalParams ep, double* __restrict__ partials,
+                                                             int maxb, Slope sl) {
+  OFDFT_GATE(g.gate);
+  constexpr int NTH = IGG_NT;
+  constexpr int Q = L / 4;
+  constexpr int NR = Q * L, MR = (NR + NTH - 1) / NTH;   // real points of the block, per thread
+  static_assert(MR <= 8, "plane too large for the split final pass");
+  __shared__ cplx<R> buf[InvGgaLds<L>::ELEMS];
+  __shared__ cplx<R> tw[L];
+  __shared__ cplx<R> twq[Q];
+  constexpr int K = DT ? 3 : 1;
+  __shared__ double red[K * NTH / 64];
+  int i1, q;
+  plane_quarter(blockIdx.x, g.n1, i1, q);
+  const int tid = threadIdx.x;
+  const size_t base = (size_t)i1 * L * L;
+  if (tid < L) tw[tid] = tw_g[tid];
+  if (tid < Q) twq[tid] = tw_g[4 * tid];
+  plane_inv_quarter<R, L, NTH>(D, buf, tw, twq, (size_t)g.n1 * L, (size_t)i1 * L, q, tid);
+  double pv[MR], qv[MR];
+  R lv[MR];
+#pragma unroll
+  for (int u = 0; u < MR; ++u) {
+    const int e = min(tid + u * NTH, NR - 1);
+    const int m = e / L, i3 = e - m * L;
+    const size_t i = base + (size_t)(4 * m + q) * L + i3;
+    pv[u] = phi[i];
+    lv[u] = vloc[i];
+    if constexpr (DT) qv[u] = sl.ms_part() * sl.phi0[i] + sl.mc_part() * sl.dir[i];
+  }
+  double nv = 0.0, dt1 = 0.0, dt2 = 0.0;
+#pragma unroll
+  for (int u = 0; u < MR; ++u) {
+    const int e = tid + u * NTH;
+    if (e < NR) {
+      const int m = e / L, i3 = e - m * L;
+      const size_t i = base + (size_t)(4 * m + q) * L + i3;
+      const cplx<R> z = buf[Lay<L>::at(m >> 1, i3)];
+      const double S = double((m & 1) ? z.y : z.x);
+      const double p = pv[u];
+      const double n = p * p;
+      const R vv = R(double(lv[u]) + S + ep.alpha_sum);
+      vout[i] = vv;
+      nv += n * double(vv);
+      if constexpr (DT) {
+        dt1 += p * double(vv) * qv[u];
+        dt2 += p * qv[u];
+      }
+    }
+  }
+  double v[K];
+  v[0] = nv;
+  if constexpr (DT) {
+    v[1] = dt1;
+    v[2] = dt2;
+  }
+  block_sum<K, NTH>(v, red);
+  if (tid == 0) {
+    partials[SL_NV * maxb + blockIdx.x] = v[0];
+    if constexpr (DT) {
+      partials[SL_DT1 * maxb + blockIdx.x] = v[1];
+      partials[SL_DT2 * maxb + blockIdx.x] = v[2];
+    }
   }
 }
 
@@ -2555,6 +2644,19 @@ static void launch_plane_fwd_grad(ofdft_ctx* c, const double* phi, const void* v
                      (const R*)v, sc, two_dv, (cplx<R>*)out, (const cplx<R>*)c->tw[2], g);
 }
 
+template <int L>
+static void launch_plane_final_q(ofdft_ctx* c, const double* phi, void* v_out, const EvalParams& ep, const Slope* sl) {
+  const GridDesc& g = c->g;
+  if (sl)
+    hipLaunchKernelGGL((k_plane_final_q<float, L, true>), dim3(4 * g.n1), dim3(IGG_NT), 0, c->stream,
+                       (const cplx<float>*)c->D, phi, (const float*)c->vloc, (float*)v_out,
+                       (const cplx<float>*)c->tw[2], g, ep, c->partials, c->max_blocks, *sl);
+  else
+    hipLaunchKernelGGL((k_plane_final_q<float, L, false>), dim3(4 * g.n1), dim3(IGG_NT), 0, c->stream,
+                       (const cplx<float>*)c->D, phi, (const float*)c->vloc, (float*)v_out,
+                       (const cplx<float>*)c->tw[2], g, ep, c->partials, c->max_blocks, Slope{});
+}
+
 template <typename R, int L, bool TF>
 static void launch_plane_final(ofdft_ctx* c, const double* phi, void* v_out, const EvalParams& ep, const Slope* sl) {
   const GridDesc& g = c->g;
@@ -2753,6 +2855,14 @@ static int eval_impl(ofdft_ctx* c, const double* phi, void* v_out, double* sc, c
     if (tf) {
       tmark(c, "plane_tf_final");
       OFDFT_DISPATCH_PLANE(g.n3, (launch_plane_final<R, L_, true>(c, phi_e, v_out, ep, sl)));
+    } else if (fused) {
+      tmark(c, "plane_final");
+      if (g.n3 == 128)
+        launch_plane_final_q<128>(c, phi_e, v_out, ep, sl);
+      else if (g.n3 == 64)
+        launch_plane_final_q<64>(c, phi_e, v_out, ep, sl);
+      else
+        launch_plane_final_q<32>(c, phi_e, v_out, ep, sl);
     } else {
       tmark(c, "plane_final");
       OFDFT_DISPATCH_PLANE(g.n3, (launch_plane_final<R, L_, false>(c, phi_e, v_out, ep, sl)));
@@ -2771,7 +2881,7 @@ static int eval_impl(ofdft_ctx* c, const double* phi, void* v_out, double* sc, c
   // partial sums of the density and final passes: one per block
   const int nb_r = plane ? 2 * g.n1 : (g.n2 / g.tr) * g.n1;   // plane passes: two blocks per i1 plane
   const ReduceParams rp{nb_r, (g.n2 / g.tc) * g.n3k, tf ? nb_r : fused ? 4 * g.n1 : pw_blocks(g), sl ? 1 : 0, g.dv, g.volume,
-                        c->alpha_sum, g.gate};
+                        c->alpha_sum, g.gate, fused ? 4 * g.n1 : nb_r};
   tmark(c, "reduce_scalars");
   hipLaunchKernelGGL(k_reduce_scalars, dim3(1), dim3(RED_NT), 0, c->stream, c->partials, c->max_blocks, rp, sc,
                      pub);
