@@ -1707,6 +1707,136 @@ __global__ void __launch_bounds__(IGG_NT, 4) k_plane_final_q(const cplx<R>* __re
   }
 }
 
+// Density pass split by the parity r of k3 (mixed precision, planes of 32, 64 or 128): both
+// blocks of a plane form the packed rows z_p = n_{2p} + i n_{2p+1} of the whole plane, and block
+// r keeps the x3 outputs k3 = 2j + r by decimation in frequency,
+//   Z_p[2j + r] = sum_{m < H} (z_p[m] + (-1)^r z_p[m + H]) w^{r m} e^{-2 pi i j m/H},  H = L/2,
+// so each block runs H-point transforms on its own half of the frequencies.  The Hermitian
+// partner L - k3 of k3 has the same parity, so the half spectra of the two real rows separate
+// within the block; the x2 transform of its L/4 k3 rows follows.  Together the two blocks do the
+// butterflies of one full-plane pass (the split density pass above repeats the x3 transform).
+// Block r sums phi^2 (and stores a trial's phi_t) on the points i3 in [r H, (r + 1) H).
+template <int L>
+struct FwdParLds {
+  static constexpr int H = L / 2;
+  static constexpr int ELEMS = (H * Lay<H>::RS > (L / 4) * Lay<L>::RS) ? H * Lay<H>::RS : (L / 4) * Lay<L>::RS;
+};
+
+template <typename R, int L, bool ROT>
+__global__ void __launch_bounds__(NTP) k_plane_fwd_density_par(const double* __restrict__ phi,
+                                                               cplx<R>* __restrict__ out,
+                                                               const cplx<R>* __restrict__ tw_g, GridDesc g,
+                                                               double* __restrict__ partials, int maxb,
+                                                               Rotation rot) {
+  OFDFT_GATE(g.gate);
+  constexpr int H = L / 2, QK = L / 4;                   // x3 outputs per block: k3 = 2j + r, j < QK
+  constexpr int NE = H * H, ME = (NE + NTP - 1) / NTP;   // (p, m) elements, per thread
+  constexpr int NU = H * QK, MU = (NU + NTP - 1) / NTP;  // (p, j) unpack items, per thread
+  constexpr int NT2 = QK * L, MT = (NT2 + NTP - 1) / NTP;
+  static_assert(L % 8 == 0 && ME <= 4 && MU <= 2 && MT <= 4, "plane too large for the parity-split pass");
+  __shared__ cplx<R> buf[FwdParLds<L>::ELEMS];
+  __shared__ cplx<R> tw[L];
+  __shared__ cplx<R> twh[H];
+  __shared__ double red[NTP / 64];
+  int i1, r;
+  plane_half(blockIdx.x, g.n1, i1, r);
+  const int tid = threadIdx.x;
+  const size_t base = (size_t)i1 * L * L;
+  // amplitudes of rows 2p, 2p + 1 at columns m and m + H
+  double pa[ME][4];
+#pragma unroll
+  for (int u = 0; u < ME; ++u) {
+    const int e = min(tid + u * NTP, NE - 1);
+    const int pp = e / H, m = e - pp * H;
+    const size_t i0 = base + (size_t)(2 * pp) * L + m;
+    pa[u][0] = phi[i0];
+    pa[u][1] = phi[i0 + H];
+    pa[u][2] = phi[i0 + L];
+    pa[u][3] = phi[i0 + L + H];
+  }
+  if constexpr (ROT) {
+    const double ca = rot.cos_part(), sb = rot.sin_part();
+#pragma unroll
+    for (int u = 0; u < ME; ++u) {
+      const int e = min(tid + u * NTP, NE - 1);
+      const int pp = e / H, m = e - pp * H;
+      const size_t i0 = base + (size_t)(2 * pp) * L + m;
+      double dv[4] = {rot.dir[i0], rot.dir[i0 + H], rot.dir[i0 + L], rot.dir[i0 + L + H]};
+#pragma unroll
+      for (int t = 0; t < 4; ++t) pa[u][t] = ca * pa[u][t] + sb * dv[t];
+      if (tid + u * NTP < NE) {   // each block stores the points of its column half
+        const size_t j0 = i0 + (size_t)r * H;
+        rot.phi_out[j0] = pa[u][r];
+        rot.phi_out[j0 + L] = pa[u][2 + r];
+      }
+    }
+  }
+  if (tid < L) tw[tid] = tw_g[tid];
+  if (tid < H) twh[tid] = tw_g[2 * tid];
+  __syncthreads();
+  double acc = 0.0;
+#pragma unroll
+  for (int u = 0; u < ME; ++u) {
+    const int e = tid + u * NTP;
+    if (e < NE) {
+      const int pp = e / H, m = e - pp * H;
+      double n[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) n[t] = pa[u][t] * pa[u][t];
+      acc += n[r] + n[2 + r];
+      // z_p[m] = n(2p, m) + i n(2p + 1, m), z_p[m + H] likewise
+      const cplx<R> zl = {R(n[0]), R(n[2])}, zh = {R(n[1]), R(n[3])};
+      const cplx<R> zc = r == 0 ? zl + zh : cmul(zl - zh, tw[m]);
+      buf[Lay<H>::at(pp, m)] = zc;
+    }
+  }
+  __syncthreads();
+  // x3: H-point forward transforms of the packed rows, Zr[p][j] = Z_p[2j + r]
+  lds_fft_inplace<R, -1, H, NTP, ME>(buf, twh, H, tid);
+  // separate the two real rows of each packed row: X_{2p}[k] = (Z[k] + conj Z[L - k]) / 2,
+  // X_{2p+1}[k] = (Z[k] - conj Z[L - k]) / (2i), with L - k = 2 j' + r, j' = (H - j - r) mod H
+  cplx<R> xa[MU], xb[MU];
+#pragma unroll
+  for (int u = 0; u < MU; ++u) {
+    const int it = tid + u * NTP;
+    if (it < NU) {
+      const int pp = it / QK, j = it - pp * QK;
+      const int jc = (H - j - r) & (H - 1);
+      const cplx<R> z = buf[Lay<H>::at(pp, j)];
+      const cplx<R> zc = cconj(buf[Lay<H>::at(pp, jc)]);
+      xa[u] = {R(0.5) * (z.x + zc.x), R(0.5) * (z.y + zc.y)};
+      xb[u] = {R(0.5) * (z.y - zc.y), R(-0.5) * (z.x - zc.x)};
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < MU; ++u) {
+    const int it = tid + u * NTP;
+    if (it < NU) {
+      const int pp = it / QK, j = it - pp * QK;
+      buf[Lay<L>::at(j, 2 * pp)] = xa[u];
+      buf[Lay<L>::at(j, 2 * pp + 1)] = xb[u];
+    }
+  }
+  __syncthreads();
+  // x2 forward of the block's QK k3 rows, stored as S[k3][i1][k2]
+  int tid2 = tid;
+  asm volatile("" : "+v"(tid2));
+  lds_fft_inplace<R, -1, L, NTP, MT>(buf, tw, QK, tid2);
+  const size_t plane = (size_t)g.n1 * L;
+#pragma unroll
+  for (int u = 0; u < MT; ++u) {
+    const int e = tid + u * NTP;
+    if (e < NT2) {
+      const int j = e / L, k2 = e - j * L;
+      out[(size_t)(2 * j + r) * plane + (size_t)i1 * L + k2] = buf[Lay<L>::at(j, k2)];
+    }
+  }
+  double v[1] = {acc};
+  block_sum<1, NTP>(v, red);
+  if (tid == 0) partials[SL_PHI2 * maxb + 2 * i1 + r] = v[0];
+}
+
 // ---------------------------------------------------------------- K7: scalar reduction
 constexpr int RED_NT = 64 * SL_COUNT;   // one wavefront per slot
 
@@ -2609,6 +2739,17 @@ static void launch_rpass_inv_real1(ofdft_ctx* c, void* in_spec, void* out_real) 
 template <typename R, int L>
 static void launch_plane_fwd_density(ofdft_ctx* c, const double* phi, void* out, const Rotation* rot) {
   const GridDesc& g = c->g;
+  if constexpr (sizeof(R) == 4 && (L == 32 || L == 64 || L == 128)) {
+    if (c->fused_gga) {   // the parity-split form (same switch as the fused gradient pass)
+      if (rot)
+        hipLaunchKernelGGL((k_plane_fwd_density_par<R, L, true>), dim3(2 * g.n1), dim3(NTP), 0, c->stream, phi,
+                           (cplx<R>*)out, (const cplx<R>*)c->tw[2], g, c->partials, c->max_blocks, *rot);
+      else
+        hipLaunchKernelGGL((k_plane_fwd_density_par<R, L, false>), dim3(2 * g.n1), dim3(NTP), 0, c->stream, phi,
+                           (cplx<R>*)out, (const cplx<R>*)c->tw[2], g, c->partials, c->max_blocks, Rotation{});
+      return;
+    }
+  }
   if (rot)
     hipLaunchKernelGGL((k_plane_fwd_density<R, L, true>), dim3(2 * g.n1), dim3(NTP), (lds_plane<R, L>(1)), c->stream,
                        phi, (cplx<R>*)out, (const cplx<R>*)c->tw[2], g, c->partials, c->max_blocks, *rot);
