@@ -157,7 +157,8 @@ void ofdft_default_options(ofdft_options* opt);
    tests and diagnosis; results agree to rounding): OFDFT_PLANE_PASSES=0 uses the
    row FFT passes where plane passes would run; OFDFT_FUSED_GGA=0 keeps the inverse
    gradient transforms and the pointwise functional as two passes where one fused
-   pass would run (mixed precision, PZ81 or no XC, square planes of 32, 64 or 128);
+   pass would run (mixed precision, PZ81 or no XC, square planes of 32, 64 or 128),
+   and the whole-plane density and final passes where their split forms would run;
    OFDFT_ION_FORCES=0 or 1 forces the G-parallel or the one-thread-per-ion force
    kernel (default: per ion from 256 ions up).  A fourth, OFDFT_TEST_NONFINITE=k,
    exists for tests of the recovery

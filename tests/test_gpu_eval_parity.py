@@ -207,9 +207,10 @@ def test_plane_passes_match_row_passes(precision, functional, shape, monkeypatch
 ])
 def test_fused_gradient_pass_matches_separate_passes(functional, xc, shape, rho, T_K, monkeypatch):
     """Mixed precision on square planes of 32, 64 and 128 points runs the inverse gradient
-    transforms and the pointwise functional as one plane pass (x2 split over the row parity);
-    with it switched off (OFDFT_FUSED_GGA=0: inverse plane pass, then the pointwise kernel) the
-    evaluation agrees to the mixed path's rounding, and the oracle pins the fused path on every
+    transforms and the pointwise functional as one plane pass (x2 split four ways over i2 mod 4),
+    the final pass on the same split and the density pass split by the parity of k3; with them
+    switched off (OFDFT_FUSED_GGA=0: whole-plane passes and the separate pointwise kernel) the
+    evaluation agrees to the mixed path's rounding, and the oracle pins the split path on every
     grid point, including plane counts that are not multiples of 8 and the no-XC form.  The
     mixed path's 1e-6 is relative to F, so the cells are ones whose F is not a near
     cancellation of its terms (|F| at least half the largest component)."""
