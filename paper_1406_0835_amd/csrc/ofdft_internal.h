@@ -189,9 +189,10 @@ struct ofdft_ctx {
   // x3 and x2 transforms as one plane pass where the grid allows (on unless
   // OFDFT_PLANE_PASSES=0 in the environment at ofdft_create)
   bool plane_passes = true;
-  // mixed-precision gradient functionals on square planes of 32, 64 or 128: the inverse
-  // gradient transforms and the pointwise functional as one fused plane pass (on unless
-  // OFDFT_FUSED_GGA=0 in the environment at ofdft_create)
+  // mixed precision on square planes of 32, 64 or 128: the inverse gradient transforms and
+  // the pointwise functional as one fused plane pass, and the density and final passes split
+  // without repeated transform work (on unless OFDFT_FUSED_GGA=0 in the environment at
+  // ofdft_create)
   bool fused_gga = true;
   // force kernel: -1 picks by ion count, 0 the G-parallel one, 1 one thread per ion
   // (OFDFT_ION_FORCES in the environment at ofdft_create)

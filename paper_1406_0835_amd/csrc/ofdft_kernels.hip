@@ -1447,8 +1447,8 @@ __global__ void __launch_bounds__(NTP) k_plane_final(const cplx<R>* __restrict__
 //   y[4m + q] = sum_{k < Q} Y_q[k] e^{+2 pi i k m/Q},  Y_q[k] = conj(w)^{k q} sum_{s < 4} i^{s q} X[k + s Q],
 // so each of the plane's four blocks runs Q-point transforms over its own rows and together
 // they do the arithmetic of one full-plane pass (each reads the plane's spectrum; the four sit
-// on one XCD, whose L2 serves all but the first read).  Blocks of IGG_NT threads, two per CU,
-// so that one block's transforms overlap the other's pointwise arithmetic.
+// on one XCD, whose L2 serves all but the first read).  Blocks of IGG_NT threads, two per CU
+// (the point functional's registers allow no more).
 constexpr int IGG_NT = 512;
 
 // Block b takes plane i1 and row class q; the four blocks of a plane are 8 block indices
