@@ -229,6 +229,21 @@ def al_static(P, wl, precision, n_rep=8):
             "pressure_Ha_per_bohr3": P_el, "forces_and_stress_ms": 1e3 * t_fs, "setup_ms": 1e3 * t_set}
 
 
+def c1_minimize(P, wl):
+    """C1: plain FP64 ftTF minimisation of 16 H on 32^3 (1.0 g/cm^3, 10 kK, Gaussian LPP, PZ81),
+    CG to 1e-8 Ha from the uniform density; the time of ofdft_minimize_density alone."""
+    cell = wl.small_tf_cell()
+    ctx = make_context(P, cell, "TF", "fp64", tol_energy=1e-8)
+    sync()
+    t0 = time.perf_counter()
+    rep = ctx.minimize_density()
+    sync()
+    t = time.perf_counter() - t0
+    ctx.close()
+    return {"minimize_ms": 1e3 * t, "iterations": rep.iterations, "evaluations": rep.evaluations,
+            "F_Ha": rep.F_total, "workload": "16 H, 1.0 g/cm^3, 32^3 grid, T=10 kK, ftTF+PZ81, FP64, CG to 1e-8 Ha"}
+
+
 def batch_run(P, wl, n_cells):
     """C4: the heterogeneous batch (16-256 H, grids {32,48,64,96}^3, 0.5-5 g/cm^3, 2 kK-4 MK,
     VT84F + PZ81, CG to 1e-8 Ha).  Three runs over the same cells:
@@ -352,10 +367,29 @@ def _oracle_eval_seconds(wl, n, threads, functional="VT84F"):
     return float(out.stdout.strip().splitlines()[-1])
 
 
+def _oracle_c1_seconds(threads):
+    """The oracle's converged C1 minimisation (its CG from the uniform density, 1e-8 Ha) in a
+    child process with OFDFT_ORACLE_THREADS = threads: (seconds, iterations)."""
+    import subprocess
+    code = (
+        "import sys, time; sys.path.insert(0, %r)\n"
+        "import oracle, workloads as wl\n"
+        "from oracle import minimize as om\n"
+        "c = wl.small_tf_cell()\n"
+        "s = oracle.System(c.lattice, c.grid, c.positions, c.charges, c.temperature_K, functional='TF')\n"
+        "t0 = time.perf_counter(); r = om.minimize_cg(s, tol_energy=1e-8)\n"
+        "print(time.perf_counter() - t0, r.iterations)\n"
+    ) % (ROOT,)
+    env = dict(os.environ, OFDFT_ORACLE_THREADS=str(threads), OMP_NUM_THREADS=str(threads))
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=600)
+    sec, it = out.stdout.strip().splitlines()[-1].split()
+    return float(sec), int(it)
+
+
 def cpu_baseline(wl, cell, phi):
     """The FP64 oracle (numpy/scipy, not tuned) on the host: one 128^3 evaluation of the benchmark
-    cell on all host threads (the reported value), plus 32^3 and 64^3 evaluations on all threads
-    and a 64^3 evaluation on one core."""
+    cell on all host threads (the reported value), plus 32^3 and 64^3 evaluations on all threads,
+    a 64^3 evaluation on one core and the converged C1 minimisation (16 H, 32^3, ftTF)."""
     os.environ.setdefault("OFDFT_ORACLE_THREADS", str(host_threads()))
     import numpy as np
     import oracle
@@ -372,6 +406,7 @@ def cpu_baseline(wl, cell, phi):
         extra["eval_s_32cubed"] = _oracle_eval_seconds(wl, 32, threads)
         extra["eval_s_64cubed"] = _oracle_eval_seconds(wl, 64, threads)
         extra["eval_s_64cubed_one_core"] = _oracle_eval_seconds(wl, 64, 1)
+        extra["c1_minimize_s"], extra["c1_iterations"] = _oracle_c1_seconds(threads)
     except Exception as e:  # the headline baseline stands without these
         extra["error"] = str(e)
     return {"value": 1.0 / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
@@ -546,6 +581,9 @@ def main():
         log(f"MD trajectory: {args.md_long} steps mixed and FP64")
         mdl = md_long(P, wl, args.md_long, args.graph_cg)
 
+    log("C1: FP64 ftTF minimisation, 16 H on 32^3")
+    c1 = c1_minimize(P, wl)
+
     cpu = None
     if not args.no_cpu:
         log("CPU oracle baseline (one 128^3 evaluation)")
@@ -580,6 +618,7 @@ def main():
         "al_static": al,
         "batch": batch,
         "md_trajectory": mdl,
+        "c1_fp64_minimize": c1,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
