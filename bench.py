@@ -14,8 +14,10 @@ roofline of the dominant kernel, milliseconds per converged MD step (128 H,
 1.0 g/cm^3, 64^3, 50 kK, VT84F, warm-started velocity Verlet) in mixed and FP64
 precision with the stress tensor timed at the last step, one density optimisation
 of the static fcc-Al workload (2048 ions on 128^3 and 16384 ions on 256^3, 100 K,
-Heine-Abarenkov Al pseudopotential) in mixed and FP64 with its forces and pressure, and the FP64
-CPU oracle timed on the host as a baseline.
+Heine-Abarenkov Al pseudopotential) in mixed and FP64 with its forces and pressure (also the
+32 000- and 62 500-ion cells), the heterogeneous 64-cell batch and a 200-step MD trajectory,
+the converged FP64 ftTF minimisation of 16 H on 32^3, and the FP64 CPU oracle timed on the host
+as a baseline (one 128^3 evaluation; 32^3 and 64^3 evaluations; the converged 16 H minimisation).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--md-steps M] [--no-md] [--no-al] [--no-cpu]
 """
