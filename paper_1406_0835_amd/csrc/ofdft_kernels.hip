@@ -1442,7 +1442,7 @@ __global__ void __launch_bounds__(NTP) k_plane_final(const cplx<R>* __restrict__
 // ---------------------------------------------------------------- K4 plane form, fused
 // Gradient functional on the plane passes, FP32 assembly: the inverse x2 and x3 transforms of
 // the three grad n spectra of one i1 plane, then the pointwise functional and XC on the real
-// rows they give, with W and v_loc stored; grad n itself stays in registers.  The x2 inverse
+// rows they give, with W and v_loc stored; grad n itself stays on the CU.  The x2 inverse
 // is split four ways by decimation in time over i2 mod 4 = q: with Q = L/4 and w = e^{-2 pi i/L},
 //   y[4m + q] = sum_{k < Q} Y_q[k] e^{+2 pi i k m/Q},  Y_q[k] = conj(w)^{k q} sum_{s < 4} i^{s q} X[k + s Q],
 // so each of the plane's four blocks runs Q-point transforms over its own rows and together
