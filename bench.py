@@ -584,7 +584,10 @@ def main():
         mdl = md_long(P, wl, args.md_long, args.graph_cg)
 
     log("C1: FP64 ftTF minimisation, 16 H on 32^3")
-    c1 = c1_minimize(P, wl)
+    try:
+        c1 = c1_minimize(P, wl)
+    except Exception as e:  # the headline line stands without it
+        c1 = {"error": str(e)}
 
     cpu = None
     if not args.no_cpu:
