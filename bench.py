@@ -473,7 +473,7 @@ def main():
     ctx.set_density(phi)
     tiles = None
     if not args.no_tune:
-        tiles = ctx.autotune(5)
+        tiles = ctx.autotune(20)
         log(f"autotuned tiles (tr, tc, rb) = {tiles}")
     log(f"timing {args.steps} mixed-precision evaluations")
     value, ms_per_step, dev_ms = eval_rate(ctx, args.steps, args.warmup)
@@ -549,7 +549,7 @@ def main():
         log("FP64 evaluation rate")
         c64 = make_context(P, cell, "VT84F", "fp64")
         c64.set_density(phi)
-        tiles64 = c64.autotune(3) if not args.no_tune else None
+        tiles64 = c64.autotune(10) if not args.no_tune else None
         v64, ms64, _ = eval_rate(c64, max(20, args.steps // 4), max(2, args.warmup // 2))
         c64.close()
         fp64 = {"evals_per_s": v64, "ms_per_eval": ms64, "tiles": tiles64}
